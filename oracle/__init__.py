@@ -1,0 +1,266 @@
+"""FP64 CPU oracle for MPWoS -- TEST INFRASTRUCTURE ONLY.
+
+Plain ctypes marshalling around ``libmpwos_oracle.so`` (built from
+``mpwos_oracle.c`` by ``oracle/build.py``).  Only the test suite, the smoke
+check and the CPU-baseline leg of the benchmark may import this module; the
+solver itself never does.
+
+Problems are plain dicts (the same dict a test also hands to the GPU binding):
+
+    {"manifold": "sphere" | "sphere_cap" | "torus" | "point_cloud",
+     "n": int, "p": [R, h_or_a, ...], "sigma": float,
+     "f": {"kind": "sph_pair", "idx": [0, 1], "coef": [8.0]},
+     "g": {...} (boundary only), "eps": float, "theta": 0.95, "c_kappa": 1.2,
+     "tau_w": 1e-8, "n_v": 1, "compensation": "exact" | "none",
+     "max_steps": int, "points": ndarray (point cloud), "k_nn": 16,
+     "radius_rule": "curvature" | "spacing" | "curvature_fit", "c_h": 2.4}
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "libmpwos_oracle.so")
+
+MANIFOLDS = {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3}
+FN_KINDS = {"zero": 0, "const": 1, "sph_pair": 2, "circle_mode": 3, "legendre": 4,
+            "torus_mode": 5, "table_s1": 6}
+COMP = {"none": 0, "exact": 1}
+RADIUS_RULES = {"curvature": 0, "spacing": 1, "curvature_fit": 2}
+STATUS = {0: "OK", -1: "EINVAL", -2: "EOFFMANIFOLD", -3: "ENOMEM", 1: "WTRUNC"}
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("manifold", ctypes.c_int32), ("n", ctypes.c_int32), ("p", ctypes.c_double * 4),
+        ("points", ctypes.c_void_p), ("n_points", ctypes.c_int64), ("k_nn", ctypes.c_int32),
+        ("radius_rule", ctypes.c_int32),
+        ("f_kind", ctypes.c_int32), ("f_idx", ctypes.c_int32 * 3), ("f_coef", ctypes.c_double * 8),
+        ("f_values", ctypes.c_void_p), ("f_nvalues", ctypes.c_int64),
+        ("g_kind", ctypes.c_int32), ("g_idx", ctypes.c_int32 * 3), ("g_coef", ctypes.c_double * 8),
+        ("sigma", ctypes.c_double), ("eps", ctypes.c_double), ("theta", ctypes.c_double),
+        ("c_kappa", ctypes.c_double), ("c_h", ctypes.c_double), ("tau_w", ctypes.c_double),
+        ("n_v", ctypes.c_int32), ("compensation", ctypes.c_int32), ("max_steps", ctypes.c_int64),
+        ("k_spacing", ctypes.c_int32), ("newton_iters", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIBPATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(_LIBPATH)
+        d, i32, u32, i64, u64, vp = (ctypes.c_double, ctypes.c_int32, ctypes.c_uint32,
+                                     ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p)
+        L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        L.orc_uniform.argtypes = [u32]; L.orc_uniform.restype = d
+        L.orc_box_muller.argtypes = [u32, u32, vp]
+        L.orc_normals.argtypes = [u64, u32, u32, u32, u32, ctypes.c_int, vp]
+        L.orc_radius_uniform.argtypes = [u64, u32, u32, u32, u32, ctypes.c_int]
+        L.orc_radius_uniform.restype = d
+        for nm in ("orc_c_sigma_r", "orc_omega"):
+            getattr(L, nm).argtypes = [ctypes.c_int, d, d]
+            getattr(L, nm).restype = d
+        for nm in ("orc_radial_cdf", "orc_radial_pdf", "orc_radial_inv"):
+            getattr(L, nm).argtypes = [ctypes.c_int, d, d]
+            getattr(L, nm).restype = d
+        L.orc_radial_xmax.argtypes = [ctypes.c_int]; L.orc_radial_xmax.restype = d
+        L.orc_knn.argtypes = [vp, i64, vp, ctypes.c_int, vp, vp]; L.orc_knn.restype = ctypes.c_int
+        L.orc_cp.argtypes = [vp, vp, vp]; L.orc_cp.restype = ctypes.c_int
+        L.orc_delta_gamma.argtypes = [vp, vp]; L.orc_delta_gamma.restype = d
+        L.orc_source.argtypes = [vp, vp]; L.orc_source.restype = d
+        L.orc_radius.argtypes = [vp, vp]; L.orc_radius.restype = d
+        L.orc_solve.argtypes = [vp, vp, i64, i64, u64, ctypes.c_int, vp, vp, vp, vp, vp]
+        L.orc_solve.restype = ctypes.c_int
+        L.orc_walk_one.argtypes = [vp, vp, u32, u32, u64, vp, vp, vp]
+        L.orc_walk_one.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Problem:
+    """Marshals a problem dict into the oracle's struct; keeps arrays alive."""
+
+    def __init__(self, d):
+        self.d = d
+        s = _Problem()
+        s.manifold = MANIFOLDS[d["manifold"]]
+        s.n = int(d["n"])
+        for i, v in enumerate(d.get("p", [1.0])):
+            s.p[i] = float(v)
+        self._keep = []
+        if d["manifold"] == "point_cloud":
+            pts = np.ascontiguousarray(d["points"], dtype=np.float64)
+            self._keep.append(pts)
+            s.points = pts.ctypes.data
+            s.n_points = pts.shape[0]
+        s.k_nn = int(d.get("k_nn", 16))
+        s.radius_rule = RADIUS_RULES[d.get("radius_rule", "curvature")]
+        f = d.get("f", {"kind": "zero"})
+        s.f_kind = FN_KINDS[f["kind"]]
+        for i, v in enumerate(f.get("idx", [])):
+            s.f_idx[i] = int(v)
+        for i, v in enumerate(f.get("coef", [])):
+            s.f_coef[i] = float(v)
+        if "values" in f:
+            vals = np.ascontiguousarray(f["values"], dtype=np.float64)
+            self._keep.append(vals)
+            s.f_values = vals.ctypes.data
+            s.f_nvalues = vals.size
+        g = d.get("g", {"kind": "zero"})
+        s.g_kind = FN_KINDS[g["kind"]]
+        for i, v in enumerate(g.get("idx", [])):
+            s.g_idx[i] = int(v)
+        for i, v in enumerate(g.get("coef", [])):
+            s.g_coef[i] = float(v)
+        s.sigma = float(d["sigma"])
+        s.eps = float(d.get("eps", 1e-3))
+        s.theta = float(d.get("theta", 0.95))
+        s.c_kappa = float(d.get("c_kappa", 1.2))
+        s.c_h = float(d.get("c_h", 2.4))
+        s.tau_w = float(d.get("tau_w", 1e-8))
+        s.n_v = int(d.get("n_v", 1))
+        s.compensation = COMP[d.get("compensation", "exact")]
+        s.max_steps = int(d.get("max_steps", 10_000_000))
+        s.k_spacing = int(d.get("k_spacing", d.get("k_nn", 16)))
+        s.newton_iters = int(d.get("newton_iters", 6))
+        self.s = s
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def normals(seed, q, w, k, sub, n):
+    g = np.zeros(n, dtype=np.float64)
+    lib().orc_normals(seed, q, w, k, sub, n, _ptr(g))
+    return g
+
+
+def radius_uniform(seed, q, w, k, sub, n):
+    return lib().orc_radius_uniform(seed, q, w, k, sub, n)
+
+
+def uniform(x):
+    return lib().orc_uniform(int(x))
+
+
+def box_muller(x0, x1):
+    out = np.zeros(2)
+    lib().orc_box_muller(int(x0), int(x1), _ptr(out))
+    return out
+
+
+def c_sigma_r(n, sigma, r):
+    return lib().orc_c_sigma_r(n, sigma, r)
+
+
+def omega(n, sigma, r):
+    return lib().orc_omega(n, sigma, r)
+
+
+def radial_cdf(n, X, s):
+    return lib().orc_radial_cdf(n, X, s)
+
+
+def radial_pdf(n, X, s):
+    return lib().orc_radial_pdf(n, X, s)
+
+
+def radial_inv(n, X, u):
+    return lib().orc_radial_inv(n, X, u)
+
+
+def radial_xmax(n):
+    return lib().orc_radial_xmax(n)
+
+
+def knn(points, x, k):
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    idx = np.zeros(k, dtype=np.int64)
+    d2 = np.zeros(k, dtype=np.float64)
+    st = lib().orc_knn(_ptr(pts), pts.shape[0], _ptr(xx), k, _ptr(idx), _ptr(d2))
+    if st:
+        raise ValueError(STATUS.get(st, st))
+    return idx, d2
+
+
+def cp(problem, x):
+    P = problem if isinstance(problem, Problem) else Problem(problem)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.zeros_like(xx)
+    st = lib().orc_cp(P.ref, _ptr(xx), _ptr(y))
+    if st:
+        raise ValueError(STATUS.get(st, st))
+    return y
+
+
+def delta_gamma(problem, y):
+    P = problem if isinstance(problem, Problem) else Problem(problem)
+    yy = np.ascontiguousarray(y, dtype=np.float64)
+    return lib().orc_delta_gamma(P.ref, _ptr(yy))
+
+
+def source(problem, z):
+    P = problem if isinstance(problem, Problem) else Problem(problem)
+    zz = np.ascontiguousarray(z, dtype=np.float64)
+    return lib().orc_source(P.ref, _ptr(zz))
+
+
+def radius(problem, y):
+    P = problem if isinstance(problem, Problem) else Problem(problem)
+    yy = np.ascontiguousarray(y, dtype=np.float64)
+    return lib().orc_radius(P.ref, _ptr(yy))
+
+
+def walk(problem, y0, q, w, seed):
+    P = problem if isinstance(problem, Problem) else Problem(problem)
+    yy = np.ascontiguousarray(y0, dtype=np.float64)
+    S = ctypes.c_double()
+    K = ctypes.c_int32()
+    tr = ctypes.c_int()
+    st = lib().orc_walk_one(P.ref, _ptr(yy), q, w, seed, ctypes.byref(S), ctypes.byref(K),
+                            ctypes.byref(tr))
+    if st:
+        raise ValueError(STATUS.get(st, st))
+    return S.value, K.value, bool(tr.value)
+
+
+def solve(problem, queries, n_walks, seed, threads=None):
+    """Run every walk; returns dict(u, stderr, walk_S (nq, nw), walk_K, status, truncated)."""
+    P = problem if isinstance(problem, Problem) else Problem(problem)
+    Q = np.ascontiguousarray(queries, dtype=np.float64)
+    nq = Q.shape[0]
+    nw = int(n_walks)
+    if threads is None:
+        threads = os.cpu_count() or 1
+    wS = np.zeros((nq, nw), dtype=np.float64)
+    wK = np.zeros((nq, nw), dtype=np.int32)
+    u = np.zeros(nq, dtype=np.float64)
+    se = np.zeros(nq, dtype=np.float64)
+    ntr = ctypes.c_int64(0)
+    st = lib().orc_solve(P.ref, _ptr(Q), nq, nw, seed, int(threads), _ptr(wS), _ptr(wK), _ptr(u),
+                         _ptr(se), ctypes.byref(ntr))
+    if st < 0:
+        raise ValueError(STATUS.get(st, st))
+    return {"u": u, "stderr": se, "walk_S": wS, "walk_K": wK, "status": STATUS[st],
+            "truncated": ntr.value, "threads": int(threads)}

@@ -1,0 +1,1004 @@
+/*
+ * mpwos_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 CPU oracle for the modified projected Walk on Spheres
+ * (MPWoS) estimator of the screened Poisson equation -Lap_Omega u + sigma u = f
+ * on an embedded manifold (Sec. 2.1, eq. surface_pde / surface_bc).
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this library.  It shares no code, header, table or
+ * constant generator with the GPU path; it is written from the paper's
+ * formulas and from the published definitions it names:
+ *   - Philox4x32-10: Salmon, Moraes, Dror, Shaw, "Parallel random numbers:
+ *     as easy as 1, 2, 3", SC'11.
+ *   - Box-Muller transform (Box & Muller 1958).
+ *   - Jacobi eigenvalue iteration (textbook) for the point-cloud frame.
+ *
+ * Floating point: IEEE binary64, built with -ffp-contract=off and no
+ * fast-math, so every multiply-add is rounded twice, as written.
+ *
+ * Parity status of each function is stated in its comment; every function
+ * here is pinned by a CPU test unless it says "parity unpinned".
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* Codes (numeric values fixed by the solver's public interface).             */
+/* ------------------------------------------------------------------------- */
+enum { ORC_SPHERE = 0, ORC_SPHERE_CAP = 1, ORC_TORUS = 2, ORC_POINT_CLOUD = 3 };
+enum {
+  ORC_FN_ZERO = 0, ORC_FN_CONST = 1, ORC_FN_SPH_PAIR = 2, ORC_FN_CIRCLE_MODE = 3,
+  ORC_FN_LEGENDRE = 4, ORC_FN_TORUS_MODE = 5, ORC_FN_TABLE_S1 = 6
+};
+enum { ORC_COMP_NONE = 0, ORC_COMP_EXACT = 1 };
+enum { ORC_RADIUS_CURVATURE = 0, ORC_RADIUS_SPACING = 1, ORC_RADIUS_CURVATURE_FIT = 2 };
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_EOFFMANIFOLD = -2, ORC_ENOMEM = -3, ORC_WTRUNC = 1 };
+
+#define ORC_MAXN 4096
+#define ORC_NSERIES 160
+#define ORC_MAXK 64
+
+typedef struct {
+  int32_t manifold;      /* ORC_SPHERE ... */
+  int32_t n;             /* ambient dimension */
+  double p[4];           /* sphere: R; cap: R, h; torus: R, a */
+  const double* points;  /* point cloud, n_points x 3, row-major */
+  int64_t n_points;
+  int32_t k_nn;          /* neighbours used by the local reconstruction */
+  int32_t radius_rule;   /* ORC_RADIUS_* */
+  int32_t f_kind; int32_t f_idx[3]; double f_coef[8];
+  const double* f_values; int64_t f_nvalues;
+  int32_t g_kind; int32_t g_idx[3]; double g_coef[8];
+  double sigma, eps, theta, c_kappa, c_h, tau_w;
+  int32_t n_v, compensation;
+  int64_t max_steps;
+  int32_t k_spacing;     /* neighbours for the spacing rule h(y) */
+  int32_t newton_iters;  /* foot-point Newton iterations on the fitted patch */
+} orc_problem;
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon et al., SC'11): 10 rounds of the 4x32 Philox S-box,  */
+/* multipliers 0xD2511F53 / 0xCD9E8D57, Weyl key increments 0x9E3779B9 /      */
+/* 0xBB67AE85, key bumped between rounds.                                     */
+/* ------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+  uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Random stream of one walk: Philox block `block` of sub-stream `sub` at step
+ * k of walk w of query q.  counter = (q, w, k, sub<<24 | block),
+ * key = (seed_lo, seed_hi).  sub 0 = sphere direction, sub l = Green sample l. */
+static void orc_block(uint64_t seed, uint32_t q, uint32_t w, uint32_t k, uint32_t sub,
+                      uint32_t block, uint32_t out[4]) {
+  uint32_t ctr[4] = {q, w, k, (sub << 24) | block};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  orc_philox4x32_10(ctr, key, out);
+}
+
+/* 32-bit word -> uniform in (0,1): (x + 1/2) 2^-32. */
+double orc_uniform(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
+
+/* Box-Muller on one word pair. */
+void orc_box_muller(uint32_t x0, uint32_t x1, double out[2]) {
+  double u0 = orc_uniform(x0), u1 = orc_uniform(x1);
+  double rad = sqrt(-2.0 * log(u0));
+  double ang = 6.283185307179586 * u1;
+  out[0] = rad * cos(ang);
+  out[1] = rad * sin(ang);
+}
+
+/* n standard normals of sub-stream `sub`: normal i comes from words
+ * (2*floor(i/2), 2*floor(i/2)+1) of the sub-stream, word j being word j%4
+ * of block j/4. */
+void orc_normals(uint64_t seed, uint32_t q, uint32_t w, uint32_t k, uint32_t sub, int n,
+                 double* g) {
+  int nblocks = (n + 3) / 4;
+  for (int b = 0; b < nblocks; ++b) {
+    uint32_t x[4];
+    orc_block(seed, q, w, k, sub, (uint32_t)b, x);
+    double pr[2];
+    orc_box_muller(x[0], x[1], pr);
+    if (4 * b + 0 < n) g[4 * b + 0] = pr[0];
+    if (4 * b + 1 < n) g[4 * b + 1] = pr[1];
+    orc_box_muller(x[2], x[3], pr);
+    if (4 * b + 2 < n) g[4 * b + 2] = pr[0];
+    if (4 * b + 3 < n) g[4 * b + 3] = pr[1];
+  }
+}
+
+/* The uniform that picks the radius of Green sample `sub`: the first word
+ * after the direction pairs, word index 2*ceil(n/2). */
+double orc_radius_uniform(uint64_t seed, uint32_t q, uint32_t w, uint32_t k, uint32_t sub, int n) {
+  int word = 2 * ((n + 1) / 2);
+  uint32_t x[4];
+  orc_block(seed, q, w, k, sub, (uint32_t)(word / 4), x);
+  return orc_uniform(x[word % 4]);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Screening factor c_{sigma,r} and omega = (1-c)/sigma.                      */
+/* Lemma 3.1 series: c = [sum_j (sigma r^2/4)^j / (j! (nu+1)_j)]^-1,          */
+/* nu = (n-2)/2 (eq. def_c_sigma_r); omega from Theorem 2.2                   */
+/* (eq. omega_explicit_formula).  s1 = sum_{j>=1}, so 1-c = s1/(1+s1) has no  */
+/* cancellation.                                                              */
+/* ------------------------------------------------------------------------- */
+static double orc_s1(int n, double sigma, double r) {
+  double nu = 0.5 * (double)(n - 2);
+  double q = sigma * r * r / 4.0;
+  double term = 1.0, s1 = 0.0;
+  for (int j = 1; j < 100000; ++j) {
+    term = term * q / ((double)j * (nu + (double)j));
+    s1 += term;
+    if (term <= 1e-18 * s1) break;
+  }
+  return s1;
+}
+double orc_c_sigma_r(int n, double sigma, double r) { return 1.0 / (1.0 + orc_s1(n, sigma, r)); }
+double orc_omega(int n, double sigma, double r) {
+  double s1 = orc_s1(n, sigma, r);
+  return s1 / (sigma * (1.0 + s1));
+}
+
+/* ------------------------------------------------------------------------- */
+/* Radial law of the normalised Green density rho = G/omega (eq. omega_of_y,  */
+/* eq. Z_sampling_density).  With lambda = sqrt(sigma), X = lambda r,         */
+/* s = t/r, x = X s, S_nu(x) = Gamma(nu+1)(2/x)^nu I_nu(x) = sum_j            */
+/* (x^2/4)^j/(j!(nu+1)_j) and sum_j b_j y^{2j} = S_nu(y)^-2, the flux of G    */
+/* through the sphere of radius t gives the CDF of |Z-Y|/r:                    */
+/*   (1-c) F(s) = (1 - 1/S_nu(x)) + x^2 S_{nu+1}(x)/(2(nu+1)) D(s),           */
+/*   (1-c) F'(s) = X^2 s S_nu(x) D(s),                                        */
+/*   D(s) = sum_{j != nu} b_j X^{2j} (s^{2j} - s^{2nu})/(2(nu-j))             */
+/*          + [nu integer] b_nu X^{2nu} (-s^{2nu} ln s).                      */
+/* Derived from the Green function of the Remark after Lemma 2.1 by reduction */
+/* of order on the regular radial solution (proof of Lemma 2.1).              */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  int n;
+  double nu;
+  int nu_int;            /* nu is an integer (n even): index of the log term, else -1 */
+  double alpha[ORC_NSERIES];   /* S_nu coefficients in z = y^2 */
+  double alpha1[ORC_NSERIES];  /* S_{nu+1} coefficients */
+  double beta[ORC_NSERIES];    /* coefficients of S_nu^-2 */
+} orc_radial;
+
+static void orc_radial_init(orc_radial* R, int n) {
+  R->n = n;
+  R->nu = 0.5 * (double)(n - 2);
+  R->nu_int = (n % 2 == 0) ? (n - 2) / 2 : -1;
+  R->alpha[0] = 1.0;
+  R->alpha1[0] = 1.0;
+  for (int j = 1; j < ORC_NSERIES; ++j) {
+    R->alpha[j] = R->alpha[j - 1] / (4.0 * (double)j * (R->nu + (double)j));
+    R->alpha1[j] = R->alpha1[j - 1] / (4.0 * (double)j * (R->nu + 1.0 + (double)j));
+  }
+  double gam[ORC_NSERIES];
+  for (int j = 0; j < ORC_NSERIES; ++j) {
+    double acc = 0.0;
+    for (int i = 0; i <= j; ++i) acc += R->alpha[i] * R->alpha[j - i];
+    gam[j] = acc;
+  }
+  R->beta[0] = 1.0;
+  for (int j = 1; j < ORC_NSERIES; ++j) {
+    double acc = 0.0;
+    for (int i = 1; i <= j; ++i) acc += gam[i] * R->beta[j - i];
+    R->beta[j] = -acc;
+  }
+}
+
+/* Largest X for which the b_j series is used: 0.8 sqrt((nu+1)(nu+5)), a lower
+ * bound of the first zero j_{nu,1} of J_nu (the radius of convergence). */
+double orc_radial_xmax(int n) {
+  double nu = 0.5 * (double)(n - 2);
+  return 0.8 * sqrt((nu + 1.0) * (nu + 5.0));
+}
+
+/* sum_{j>=1} a_j z^j */
+static double orc_series_tail(const double* a, double z) {
+  double zp = 1.0, acc = 0.0;
+  for (int j = 1; j < ORC_NSERIES; ++j) {
+    zp *= z;
+    double t = a[j] * zp;
+    acc += t;
+    if (fabs(t) <= 1e-19 * fabs(acc)) break;
+  }
+  return acc;
+}
+static double orc_series(const double* a, double z) { return 1.0 + orc_series_tail(a, z); }
+
+static double orc_radial_D(const orc_radial* R, double X, double s) {
+  double X2 = X * X;
+  double s2 = s * s;
+  double s2nu = (R->n == 2) ? 1.0 : pow(s, (double)(R->n - 2));
+  double acc = 0.0, Xp = 1.0, sp = 1.0;
+  for (int j = 0; j < ORC_NSERIES; ++j) {
+    if (j > 0) { Xp *= X2; sp *= s2; }
+    double bx = R->beta[j] * Xp;
+    double t;
+    if (j == R->nu_int) t = bx * (-s2nu * log(s));
+    else t = bx * (sp - s2nu) / (2.0 * (R->nu - (double)j));
+    acc += t;
+    if (j > R->nu + 2 && fabs(bx) <= 1e-19 * fabs(acc)) break;
+  }
+  return acc;
+}
+
+static double orc_radial_cdf_r(const orc_radial* R, double X, double s) {
+  if (s <= 0.0) return 0.0;
+  if (s >= 1.0) return 1.0;
+  double z = X * X * s * s;
+  double s1x = orc_series_tail(R->alpha, z);
+  double S1 = orc_series(R->alpha1, z);
+  double s1X = orc_series_tail(R->alpha, X * X);
+  double D = orc_radial_D(R, X, s);
+  double num = s1x / (1.0 + s1x) + z * S1 / (2.0 * (R->nu + 1.0)) * D;
+  return num * (1.0 + s1X) / s1X;
+}
+
+static double orc_radial_pdf_r(const orc_radial* R, double X, double s) {
+  if (s <= 0.0 || s >= 1.0) return 0.0;
+  double z = X * X * s * s;
+  double Sx = orc_series(R->alpha, z);
+  double s1X = orc_series_tail(R->alpha, X * X);
+  double D = orc_radial_D(R, X, s);
+  return X * X * s * Sx * D * (1.0 + s1X) / s1X;
+}
+
+/* Inverse CDF by bisection on [0,1] until the bracket cannot shrink. */
+static double orc_radial_inv_r(const orc_radial* R, double X, double u) {
+  double lo = 0.0, hi = 1.0;
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (orc_radial_cdf_r(R, X, mid) < u) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+double orc_radial_cdf(int n, double X, double s) {
+  orc_radial R; orc_radial_init(&R, n);
+  return orc_radial_cdf_r(&R, X, s);
+}
+double orc_radial_pdf(int n, double X, double s) {
+  orc_radial R; orc_radial_init(&R, n);
+  return orc_radial_pdf_r(&R, X, s);
+}
+double orc_radial_inv(int n, double X, double u) {
+  orc_radial R; orc_radial_init(&R, n);
+  return orc_radial_inv_r(&R, X, u);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Small vector helpers.                                                      */
+/* ------------------------------------------------------------------------- */
+static double orc_dot(const double* a, const double* b, int n) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += a[i] * b[i];
+  return s;
+}
+static double orc_norm(const double* a, int n) { return sqrt(orc_dot(a, a, n)); }
+
+/* ------------------------------------------------------------------------- */
+/* Point cloud: exact kNN by brute force, ties by index, then the local       */
+/* reconstruction (centroid, PCA frame, least-squares quadratic height field, */
+/* Newton foot point).  The paper names "nearest-neighbour search with local  */
+/* reconstruction" for point clouds (Sec. 2.3.2); the reconstruction used is  */
+/* this quadratic patch.                                                      */
+/* ------------------------------------------------------------------------- */
+typedef struct { double d2; int64_t idx; } orc_nb;
+
+static int orc_nb_less(const orc_nb* a, const orc_nb* b) {
+  return (a->d2 < b->d2) || (a->d2 == b->d2 && a->idx < b->idx);
+}
+
+/* k nearest points of x (sorted by (distance^2, index)). */
+int orc_knn(const double* pts, int64_t np, const double* x, int k, int64_t* idx_out, double* d2_out) {
+  if (k > ORC_MAXK || k > np || k < 1) return ORC_EINVAL;
+  orc_nb best[ORC_MAXK];
+  int cnt = 0;
+  for (int64_t i = 0; i < np; ++i) {
+    double dx = pts[3 * i] - x[0], dy = pts[3 * i + 1] - x[1], dz = pts[3 * i + 2] - x[2];
+    orc_nb c = {dx * dx + dy * dy + dz * dz, i};
+    if (cnt < k) {
+      int j = cnt++;
+      while (j > 0 && orc_nb_less(&c, &best[j - 1])) { best[j] = best[j - 1]; --j; }
+      best[j] = c;
+    } else if (orc_nb_less(&c, &best[k - 1])) {
+      int j = k - 1;
+      while (j > 0 && orc_nb_less(&c, &best[j - 1])) { best[j] = best[j - 1]; --j; }
+      best[j] = c;
+    }
+  }
+  for (int j = 0; j < k; ++j) { idx_out[j] = best[j].idx; d2_out[j] = best[j].d2; }
+  return ORC_OK;
+}
+
+/* Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations (textbook).
+ * Eigenvalues ascending in w, eigenvectors as columns of V. */
+static void orc_jacobi3(const double A_in[9], double w[3], double V[9]) {
+  double A[9];
+  memcpy(A, A_in, sizeof(A));
+  for (int i = 0; i < 9; ++i) V[i] = (i % 4 == 0) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
+    double diag = A[0] * A[0] + A[4] * A[4] + A[8] * A[8];
+    if (off <= 1e-34 * diag || off == 0.0) break;
+    for (int p = 0; p < 2; ++p) {
+      for (int q = p + 1; q < 3; ++q) {
+        double apq = A[3 * p + q];
+        if (apq == 0.0) continue;
+        double app = A[3 * p + p], aqq = A[3 * q + q];
+        double tau = (aqq - app) / (2.0 * apq);
+        double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+        /* A <- J^T A J with J the (p,q) rotation */
+        for (int k = 0; k < 3; ++k) {
+          double akp = A[3 * k + p], akq = A[3 * k + q];
+          A[3 * k + p] = c * akp - s * akq;
+          A[3 * k + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) {
+          double apk = A[3 * p + k], aqk = A[3 * q + k];
+          A[3 * p + k] = c * apk - s * aqk;
+          A[3 * q + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < 3; ++k) {
+          double vkp = V[3 * k + p], vkq = V[3 * k + q];
+          V[3 * k + p] = c * vkp - s * vkq;
+          V[3 * k + q] = s * vkp + c * vkq;
+        }
+      }
+    }
+  }
+  int order[3] = {0, 1, 2};
+  double d[3] = {A[0], A[4], A[8]};
+  for (int i = 0; i < 3; ++i)
+    for (int j = i + 1; j < 3; ++j)
+      if (d[order[j]] < d[order[i]]) { int t = order[i]; order[i] = order[j]; order[j] = t; }
+  double Vs[9];
+  for (int c = 0; c < 3; ++c) {
+    w[c] = d[order[c]];
+    for (int r = 0; r < 3; ++r) Vs[3 * r + c] = V[3 * r + order[c]];
+  }
+  memcpy(V, Vs, sizeof(Vs));
+}
+
+/* Solve the 6x6 SPD system M a = b by Gaussian elimination with partial pivoting. */
+static int orc_solve6(double M[36], double b[6], double a[6]) {
+  for (int c = 0; c < 6; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 6; ++r) if (fabs(M[6 * r + c]) > fabs(M[6 * piv + c])) piv = r;
+    if (M[6 * piv + c] == 0.0) return ORC_EINVAL;
+    if (piv != c) {
+      for (int k = 0; k < 6; ++k) { double t = M[6 * c + k]; M[6 * c + k] = M[6 * piv + k]; M[6 * piv + k] = t; }
+      double t = b[c]; b[c] = b[piv]; b[piv] = t;
+    }
+    for (int r = c + 1; r < 6; ++r) {
+      double f = M[6 * r + c] / M[6 * c + c];
+      for (int k = c; k < 6; ++k) M[6 * r + k] -= f * M[6 * c + k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int r = 5; r >= 0; --r) {
+    double s = b[r];
+    for (int k = r + 1; k < 6; ++k) s -= M[6 * r + k] * a[k];
+    a[r] = s / M[6 * r + r];
+  }
+  return ORC_OK;
+}
+
+typedef struct {
+  double y[3];        /* projected point cp_h(x) */
+  double kappa;       /* max |principal curvature| of the fitted patch at the foot */
+  double h_mean;      /* mean distance from x to the k neighbours */
+} orc_pc_result;
+
+/* Local reconstruction and projection of x onto a point cloud. */
+int orc_pc_project(const orc_problem* P, const double* x, orc_pc_result* res) {
+  int k = P->k_nn;
+  int64_t idx[ORC_MAXK];
+  double d2[ORC_MAXK];
+  int st = orc_knn(P->points, P->n_points, x, k, idx, d2);
+  if (st) return st;
+  double hsum = 0.0;
+  for (int j = 0; j < k; ++j) hsum += sqrt(d2[j]);
+  res->h_mean = hsum / (double)k;
+  double cen[3] = {0, 0, 0};
+  for (int j = 0; j < k; ++j)
+    for (int c = 0; c < 3; ++c) cen[c] += P->points[3 * idx[j] + c];
+  for (int c = 0; c < 3; ++c) cen[c] /= (double)k;
+  double C[9] = {0};
+  for (int j = 0; j < k; ++j) {
+    double d[3];
+    for (int c = 0; c < 3; ++c) d[c] = P->points[3 * idx[j] + c] - cen[c];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) C[3 * r + c] += d[r] * d[c];
+  }
+  double w[3], V[9];
+  orc_jacobi3(C, w, V);
+  double e1[3] = {V[0 * 3 + 2], V[1 * 3 + 2], V[2 * 3 + 2]};
+  double e2[3] = {V[0 * 3 + 1], V[1 * 3 + 1], V[2 * 3 + 1]};
+  double nn[3] = {V[0 * 3 + 0], V[1 * 3 + 0], V[2 * 3 + 0]};
+  /* least-squares height field h = a0 + a1 a + a2 b + a3 a^2 + a4 a b + a5 b^2 */
+  double M[36] = {0}, rhs[6] = {0}, coef[6];
+  for (int j = 0; j < k; ++j) {
+    double d[3];
+    for (int c = 0; c < 3; ++c) d[c] = P->points[3 * idx[j] + c] - cen[c];
+    double a = orc_dot(d, e1, 3), b = orc_dot(d, e2, 3), h = orc_dot(d, nn, 3);
+    double phi[6] = {1.0, a, b, a * a, a * b, b * b};
+    for (int r = 0; r < 6; ++r) {
+      rhs[r] += phi[r] * h;
+      for (int c = 0; c < 6; ++c) M[6 * r + c] += phi[r] * phi[c];
+    }
+  }
+  st = orc_solve6(M, rhs, coef);
+  if (st) return st;
+  double dx[3];
+  for (int c = 0; c < 3; ++c) dx[c] = x[c] - cen[c];
+  double ax = orc_dot(dx, e1, 3), bx = orc_dot(dx, e2, 3), hx = orc_dot(dx, nn, 3);
+  /* Newton on E(a,b) = (a-ax)^2 + (b-bx)^2 + (h(a,b)-hx)^2 from (ax,bx) */
+  double a = ax, b = bx;
+  for (int it = 0; it < P->newton_iters; ++it) {
+    double h = coef[0] + coef[1] * a + coef[2] * b + coef[3] * a * a + coef[4] * a * b + coef[5] * b * b;
+    double ha = coef[1] + 2.0 * coef[3] * a + coef[4] * b;
+    double hb = coef[2] + coef[4] * a + 2.0 * coef[5] * b;
+    double haa = 2.0 * coef[3], hab = coef[4], hbb = 2.0 * coef[5];
+    double r = h - hx;
+    double ga = (a - ax) + r * ha;
+    double gb = (b - bx) + r * hb;
+    double Haa = 1.0 + ha * ha + r * haa;
+    double Hab = ha * hb + r * hab;
+    double Hbb = 1.0 + hb * hb + r * hbb;
+    double det = Haa * Hbb - Hab * Hab;
+    if (det == 0.0) break;
+    double da = (Hbb * ga - Hab * gb) / det;
+    double db = (Haa * gb - Hab * ga) / det;
+    a -= da; b -= db;
+  }
+  double h = coef[0] + coef[1] * a + coef[2] * b + coef[3] * a * a + coef[4] * a * b + coef[5] * b * b;
+  for (int c = 0; c < 3; ++c) res->y[c] = cen[c] + a * e1[c] + b * e2[c] + h * nn[c];
+  /* curvature indicator: largest |eigenvalue| of the shape operator of the
+   * graph at the foot, I^-1 II with I = [[1+ha^2, ha hb],[ha hb, 1+hb^2]],
+   * II = Hess(h)/sqrt(1+ha^2+hb^2). */
+  {
+    double ha = coef[1] + 2.0 * coef[3] * a + coef[4] * b;
+    double hb = coef[2] + coef[4] * a + 2.0 * coef[5] * b;
+    double gfac = sqrt(1.0 + ha * ha + hb * hb);
+    double I11 = 1.0 + ha * ha, I12 = ha * hb, I22 = 1.0 + hb * hb;
+    double II11 = 2.0 * coef[3] / gfac, II12 = coef[4] / gfac, II22 = 2.0 * coef[5] / gfac;
+    double detI = I11 * I22 - I12 * I12;
+    /* S = I^-1 II */
+    double S11 = (I22 * II11 - I12 * II12) / detI;
+    double S12 = (I22 * II12 - I12 * II22) / detI;
+    double S21 = (I11 * II12 - I12 * II11) / detI;
+    double S22 = (I11 * II22 - I12 * II12) / detI;
+    double tr = S11 + S22, det = S11 * S22 - S12 * S21;
+    double disc = tr * tr / 4.0 - det;
+    if (disc < 0.0) disc = 0.0;
+    double l1 = tr / 2.0 + sqrt(disc), l2 = tr / 2.0 - sqrt(disc);
+    res->kappa = fmax(fabs(l1), fabs(l2));
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Manifolds: closest-point map cp (eq. cp_map), curvature indicator kappa    */
+/* (eq. rho_geo_curvature), nearest boundary point cp_Gamma and the effective */
+/* boundary distance delta_Gamma (eq. delta_Gamma_general).                   */
+/* ------------------------------------------------------------------------- */
+
+/* Torus (R, a) around the x3 axis.  Closest point: the nearest point C of the
+ * core circle, then the point at distance a from C towards x. */
+static int orc_torus_cp(double R, double a, const double* x, double* y) {
+  double rho = sqrt(x[0] * x[0] + x[1] * x[1]);
+  if (rho == 0.0) return ORC_EINVAL;
+  double C[3] = {R * x[0] / rho, R * x[1] / rho, 0.0};
+  double d[3] = {x[0] - C[0], x[1] - C[1], x[2]};
+  double dn = orc_norm(d, 3);
+  if (dn == 0.0) return ORC_EINVAL;
+  for (int i = 0; i < 3; ++i) y[i] = C[i] + a * d[i] / dn;
+  return ORC_OK;
+}
+
+/* Toroidal angle phi, tube angle psi and distance to the core circle. */
+static void orc_torus_angles(double R, const double* x, double* phi, double* psi, double* dist) {
+  double rho = sqrt(x[0] * x[0] + x[1] * x[1]);
+  *phi = atan2(x[1], x[0]);
+  *psi = atan2(x[2], rho - R);
+  *dist = sqrt((rho - R) * (rho - R) + x[2] * x[2]);
+}
+
+int orc_cp(const orc_problem* P, const double* x, double* y) {
+  int n = P->n;
+  switch (P->manifold) {
+    case ORC_SPHERE:
+    case ORC_SPHERE_CAP: {
+      double nx = orc_norm(x, n);
+      if (nx == 0.0) return ORC_EINVAL;
+      for (int i = 0; i < n; ++i) y[i] = P->p[0] * x[i] / nx;
+      return ORC_OK;
+    }
+    case ORC_TORUS: return orc_torus_cp(P->p[0], P->p[1], x, y);
+    case ORC_POINT_CLOUD: {
+      orc_pc_result res;
+      int st = orc_pc_project(P, x, &res);
+      if (st) return st;
+      for (int i = 0; i < 3; ++i) y[i] = res.y[i];
+      return ORC_OK;
+    }
+  }
+  return ORC_EINVAL;
+}
+
+/* Curvature indicator kappa(y): largest |principal curvature|. */
+static double orc_kappa(const orc_problem* P, const double* y) {
+  switch (P->manifold) {
+    case ORC_SPHERE:
+    case ORC_SPHERE_CAP: return 1.0 / P->p[0];
+    case ORC_TORUS: {
+      double phi, psi, dist;
+      orc_torus_angles(P->p[0], y, &phi, &psi, &dist);
+      double k1 = 1.0 / P->p[1];
+      double k2 = fabs(cos(psi)) / (P->p[0] + P->p[1] * cos(psi));
+      return k1 > k2 ? k1 : k2;
+    }
+  }
+  return 0.0;
+}
+
+/* Nearest point of the cap boundary Gamma = S^{n-1}_R cap {x_n = h}. */
+static void orc_cap_cp_gamma(const orc_problem* P, const double* y, double* yg) {
+  int n = P->n;
+  double R = P->p[0], h = P->p[1];
+  double rg = sqrt(R * R - h * h);
+  double ny = 0.0;
+  for (int i = 0; i < n - 1; ++i) ny += y[i] * y[i];
+  ny = sqrt(ny);
+  for (int i = 0; i < n - 1; ++i) yg[i] = rg * y[i] / ny;
+  yg[n - 1] = h;
+}
+
+/* delta_Gamma(y) = dist(y, E_Gamma(y_Gamma)) with the normal disk of radius
+ * ell = rho_geo(y_Gamma) (eq. extended_boundary_disk, eq. delta_Gamma_general). */
+static double orc_cap_delta(const orc_problem* P, const double* y) {
+  int n = P->n;
+  double yg[ORC_MAXN], rG[ORC_MAXN], nrm[ORC_MAXN], rT[ORC_MAXN];
+  orc_cap_cp_gamma(P, y, yg);
+  double R = P->p[0];
+  for (int i = 0; i < n; ++i) { rG[i] = yg[i] - y[i]; nrm[i] = yg[i] / R; }
+  double rn = orc_dot(rG, nrm, n);
+  for (int i = 0; i < n; ++i) rT[i] = rG[i] - rn * nrm[i];
+  double ell = P->c_kappa / (1.0 + orc_kappa(P, yg));
+  double tN = fabs(rn) - ell;
+  if (tN < 0.0) tN = 0.0;
+  return sqrt(orc_dot(rT, rT, n) + tN * tN);
+}
+
+/* Membership of the boundary layer Gamma_eps (eq. boundary_layer).  A point
+ * at or below the cutting plane counts as inside the layer. */
+static int orc_in_layer(const orc_problem* P, const double* y) {
+  if (y[P->n - 1] <= P->p[1]) return 1;
+  return orc_cap_delta(P, y) < P->eps;
+}
+
+double orc_delta_gamma(const orc_problem* P, const double* y) {
+  if (P->manifold != ORC_SPHERE_CAP) return INFINITY;
+  return orc_cap_delta(P, y);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Sources: f(x) = f_Omega(cp(x)) (eq. cp_extension) and the exact            */
+/* compensation m(x) = -Lap(Eu)(x) + sigma Eu(x) - f(x) (eq.                  */
+/* mismatch_definition) for families whose solution u is known.               */
+/* ------------------------------------------------------------------------- */
+static double orc_legendre(int l, double t) {
+  double p0 = 1.0, p1 = t;
+  if (l == 0) return p0;
+  for (int k = 1; k < l; ++k) {
+    double p2 = ((2.0 * k + 1.0) * t * p1 - (double)k * p0) / (double)(k + 1);
+    p0 = p1; p1 = p2;
+  }
+  return p1;
+}
+
+/* -Lap_T of sin(phi) cos(2 psi) on the torus of tube radius `a` (or, with a
+ * replaced by the distance to the core circle, the ambient Laplacian of its
+ * closest-point extension). */
+static double orc_torus_neg_lap(double R, double a, double phi, double psi) {
+  double rt = R + a * cos(psi);
+  double u = sin(phi) * cos(2.0 * psi);
+  return 4.0 * u / (a * a) + u / (rt * rt) - 2.0 * sin(phi) * sin(psi) * sin(2.0 * psi) / (a * rt);
+}
+
+/* Linear interpolation of a periodic table over theta in [0, 2 pi). */
+static double orc_table_s1(const double* v, int64_t M, double theta) {
+  double t = theta / 6.283185307179586;
+  t -= floor(t);
+  double pos = t * (double)M;
+  int64_t i0 = (int64_t)floor(pos);
+  double fr = pos - (double)i0;
+  i0 %= M;
+  int64_t i1 = (i0 + 1) % M;
+  return (1.0 - fr) * v[i0] + fr * v[i1];
+}
+
+/* f_Omega at a point y of M. */
+static double orc_f_omega(const orc_problem* P, const double* y) {
+  int n = P->n;
+  const double* c = P->f_coef;
+  switch (P->f_kind) {
+    case ORC_FN_ZERO: return 0.0;
+    case ORC_FN_CONST: return c[0];
+    case ORC_FN_SPH_PAIR: {
+      double R = P->p[0];
+      return c[0] * (y[P->f_idx[0]] / R) * (y[P->f_idx[1]] / R);
+    }
+    case ORC_FN_CIRCLE_MODE: {
+      double th = atan2(y[1], y[0]);
+      int k = P->f_idx[0];
+      return c[0] * cos((double)k * th) + c[1] * sin((double)k * th);
+    }
+    case ORC_FN_LEGENDRE: {
+      double t = y[n - 1] / P->p[0];
+      double s = 0.0;
+      for (int l = 0; l < 8; ++l) s += c[l] * orc_legendre(l, t);
+      return s;
+    }
+    case ORC_FN_TORUS_MODE: {
+      double phi, psi, dist;
+      orc_torus_angles(P->p[0], y, &phi, &psi, &dist);
+      double u = c[0] * sin(phi) * cos(2.0 * psi);
+      return c[0] * orc_torus_neg_lap(P->p[0], P->p[1], phi, psi) + P->sigma * u;
+    }
+    case ORC_FN_TABLE_S1: {
+      double th = atan2(y[1], y[0]);
+      return orc_table_s1(P->f_values, P->f_nvalues / 2, th);
+    }
+  }
+  return NAN;
+}
+
+/* Exact compensation m(x), y = cp(x). */
+static double orc_m_exact(const orc_problem* P, const double* x, const double* y) {
+  int n = P->n;
+  const double* c = P->f_coef;
+  double sg = P->sigma;
+  switch (P->f_kind) {
+    case ORC_FN_ZERO:
+    case ORC_FN_CONST: return 0.0;
+    case ORC_FN_SPH_PAIR:
+    case ORC_FN_CIRCLE_MODE:
+    case ORC_FN_LEGENDRE:
+    case ORC_FN_TABLE_S1: {
+      /* on S^{n-1}_R the degree-0 extension has Lap(Eu)(x) = (R/|x|)^2 Lap_S u,
+       * so m(x) = (f - sigma u)(y) ((R/|x|)^2 - 1). */
+      double R = P->p[0];
+      double rr = orc_dot(x, x, n);
+      double fac = R * R / rr - 1.0;
+      double lap_part; /* (f - sigma u)(y) = -Lap_S u (y) */
+      if (P->f_kind == ORC_FN_SPH_PAIR) {
+        double lam = 2.0 * (double)n / (R * R);
+        double f = orc_f_omega(P, y);
+        lap_part = lam * f / (lam + sg);
+      } else if (P->f_kind == ORC_FN_CIRCLE_MODE) {
+        int k = P->f_idx[0];
+        double lam = (double)(k * k) / (R * R);
+        double f = orc_f_omega(P, y);
+        lap_part = lam * f / (lam + sg);
+      } else if (P->f_kind == ORC_FN_LEGENDRE) {
+        double t = y[n - 1] / R;
+        lap_part = 0.0;
+        for (int l = 0; l < 8; ++l) {
+          double lam = (double)(l * (l + 1)) / (R * R);
+          lap_part += lam * c[l] / (lam + sg) * orc_legendre(l, t);
+        }
+      } else {
+        double th = atan2(y[1], y[0]);
+        int64_t M = P->f_nvalues / 2;
+        double f = orc_table_s1(P->f_values, M, th);
+        double us = orc_table_s1(P->f_values + M, M, th);
+        lap_part = f - sg * us;
+      }
+      return lap_part * fac;
+    }
+    case ORC_FN_TORUS_MODE: {
+      double phi, psi, dist;
+      orc_torus_angles(P->p[0], x, &phi, &psi, &dist);
+      return c[0] * (orc_torus_neg_lap(P->p[0], dist, phi, psi) - orc_torus_neg_lap(P->p[0], P->p[1], phi, psi));
+    }
+  }
+  return NAN;
+}
+
+/* Dirichlet datum g_Omega at a boundary point. */
+static double orc_g_omega(const orc_problem* P, const double* y) {
+  const double* c = P->g_coef;
+  int n = P->n;
+  switch (P->g_kind) {
+    case ORC_FN_ZERO: return 0.0;
+    case ORC_FN_CONST: return c[0];
+    case ORC_FN_SPH_PAIR: {
+      double R = P->p[0];
+      return c[0] * (y[P->g_idx[0]] / R) * (y[P->g_idx[1]] / R);
+    }
+    case ORC_FN_LEGENDRE: {
+      double t = y[n - 1] / P->p[0];
+      double s = 0.0;
+      for (int l = 0; l < 8; ++l) s += c[l] * orc_legendre(l, t);
+      return s;
+    }
+  }
+  return NAN;
+}
+
+/* Source term of one Green sample at ambient point z: f(z) + m(z). */
+double orc_source(const orc_problem* P, const double* z) {
+  double y[ORC_MAXN];
+  if (orc_cp(P, z, y)) return NAN;
+  double v = orc_f_omega(P, y);
+  if (P->compensation == ORC_COMP_EXACT) v += orc_m_exact(P, z, y);
+  return v;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Radius rule r(y) = theta min{delta_Gamma(y), rho_geo(y)}                   */
+/* (eq. radius_rule_unified, eq. rho_geo_curvature, eq. rho_geo_spacing).     */
+/* For point clouds rho_geo comes from the reconstruction that produced y.    */
+/* ------------------------------------------------------------------------- */
+static double orc_rho_geo(const orc_problem* P, const double* y, const orc_pc_result* pc) {
+  if (P->manifold == ORC_POINT_CLOUD) {
+    if (P->radius_rule == ORC_RADIUS_SPACING) return P->c_h * pc->h_mean;
+    return P->c_kappa / (1.0 + pc->kappa);
+  }
+  return P->c_kappa / (1.0 + orc_kappa(P, y));
+}
+
+double orc_radius(const orc_problem* P, const double* y) {
+  orc_pc_result pc;
+  if (P->manifold == ORC_POINT_CLOUD) {
+    if (orc_pc_project(P, y, &pc)) return NAN;
+  }
+  double rg = orc_rho_geo(P, y, &pc);
+  double dg = (P->manifold == ORC_SPHERE_CAP) ? orc_cap_delta(P, y) : INFINITY;
+  return P->theta * (dg < rg ? dg : rg);
+}
+
+/* ------------------------------------------------------------------------- */
+/* One path of Algorithm 1 and its score S (eq. path_score_definition).       */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  const orc_problem* P;
+  orc_radial rad;
+  uint64_t seed;
+} orc_ctx;
+
+static void orc_sum_add(double* s, double* comp, double x) {
+  /* Neumaier compensated summation */
+  double t = *s + x;
+  if (fabs(*s) >= fabs(x)) *comp += (*s - t) + x;
+  else *comp += (x - t) + *s;
+  *s = t;
+}
+
+static int orc_walk(const orc_ctx* C, const double* y0, uint32_t q, uint32_t w, double* S_out,
+                    int32_t* K_out, int* truncated) {
+  const orc_problem* P = C->P;
+  int n = P->n;
+  int boundary = (P->manifold == ORC_SPHERE_CAP);
+  double* buf = (double*)malloc(sizeof(double) * 6 * (size_t)n);
+  if (!buf) return ORC_ENOMEM;
+  double *Y = buf, *Yn = buf + n, *Th = buf + 2 * n, *Z = buf + 3 * n, *g = buf + 4 * n, *yg = buf + 5 * n;
+  memcpy(Y, y0, sizeof(double) * (size_t)n);
+  double W = 1.0, S = 0.0, comp = 0.0;
+  uint32_t k = 0;
+  *truncated = 0;
+  orc_pc_result pc_cur, pc_next;
+  if (P->manifold == ORC_POINT_CLOUD) {
+    if (orc_pc_project(P, Y, &pc_cur)) { free(buf); return ORC_EINVAL; }
+  }
+  if (boundary && orc_in_layer(P, Y)) {
+    orc_cap_cp_gamma(P, Y, yg);
+    *S_out = W * orc_g_omega(P, yg);
+    *K_out = 0;
+    free(buf);
+    return ORC_OK;
+  }
+  for (;;) {
+    /* (i) radius */
+    double rg = orc_rho_geo(P, Y, &pc_cur);
+    double dg = boundary ? orc_cap_delta(P, Y) : INFINITY;
+    double r = P->theta * (dg < rg ? dg : rg);
+    double c = orc_c_sigma_r(n, P->sigma, r);
+    double om = orc_omega(n, P->sigma, r);
+    double X = sqrt(P->sigma) * r;
+    if (!(X <= orc_radial_xmax(n))) { free(buf); return ORC_EINVAL; }
+    /* (ii) projected state: Theta = Y + r zeta, zeta = g/|g| (eq. projected_chain_update) */
+    orc_normals(C->seed, q, w, k, 0, n, g);
+    double gn = orc_norm(g, n);
+    for (int i = 0; i < n; ++i) Th[i] = Y[i] + r * (g[i] / gn);
+    if (P->manifold == ORC_POINT_CLOUD) {
+      if (orc_pc_project(P, Th, &pc_next)) { free(buf); return ORC_EINVAL; }
+      for (int i = 0; i < 3; ++i) Yn[i] = pc_next.y[i];
+    } else if (orc_cp(P, Th, Yn)) {
+      free(buf);
+      return ORC_EINVAL;
+    }
+    /* Green samples Z ~ rho(Y, .) (eq. Z_sampling_density), averaged over N_V
+     * (eq. local_average_source) */
+    double F = 0.0;
+    for (int l = 1; l <= P->n_v; ++l) {
+      double u = orc_radius_uniform(C->seed, q, w, k, (uint32_t)l, n);
+      double s = orc_radial_inv_r(&C->rad, X, u);
+      orc_normals(C->seed, q, w, k, (uint32_t)l, n, g);
+      double gz = orc_norm(g, n);
+      for (int i = 0; i < n; ++i) Z[i] = Y[i] + (r * s) * (g[i] / gz);
+      F += orc_source(P, Z);
+    }
+    F = F / (double)P->n_v;
+    orc_sum_add(&S, &comp, (W * om) * F);
+    W = W * c;
+    memcpy(Y, Yn, sizeof(double) * (size_t)n);
+    if (P->manifold == ORC_POINT_CLOUD) pc_cur = pc_next;
+    k += 1;
+    if (boundary && orc_in_layer(P, Y)) {
+      orc_cap_cp_gamma(P, Y, yg);
+      orc_sum_add(&S, &comp, W * orc_g_omega(P, yg));
+      break;
+    }
+    if (!boundary && W < P->tau_w) break;
+    if ((int64_t)k >= P->max_steps) { *truncated = 1; break; }
+  }
+  *S_out = S + comp;
+  *K_out = (int32_t)k;
+  free(buf);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Solve: every walk of every query, then the Monte Carlo estimator           */
+/* u ~ N^-1 sum_i S^i (eq. mc_estimator) and its standard error.              */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  const orc_ctx* C;
+  const double* queries;
+  int64_t nq, nw;
+  double* walk_S;
+  int32_t* walk_K;
+  int64_t next;
+  pthread_mutex_t lock;
+  int status;
+  int64_t truncated;
+} orc_job;
+
+static void* orc_worker(void* arg) {
+  orc_job* J = (orc_job*)arg;
+  int n = J->C->P->n;
+  int64_t total = J->nq * J->nw;
+  for (;;) {
+    int64_t start = __atomic_fetch_add(&J->next, 64, __ATOMIC_RELAXED);
+    if (start >= total) break;
+    int64_t end = start + 64 < total ? start + 64 : total;
+    for (int64_t i = start; i < end; ++i) {
+      int64_t q = i / J->nw, w = i % J->nw;
+      int trunc = 0;
+      int st = orc_walk(J->C, J->queries + q * n, (uint32_t)q, (uint32_t)w, &J->walk_S[i], &J->walk_K[i], &trunc);
+      if (st || trunc) {
+        pthread_mutex_lock(&J->lock);
+        if (st) J->status = st;
+        if (trunc) J->truncated += 1;
+        pthread_mutex_unlock(&J->lock);
+      }
+    }
+  }
+  return NULL;
+}
+
+static int orc_check(const orc_problem* P) {
+  if (P->n < 2 || P->n > ORC_MAXN) return ORC_EINVAL;
+  if (!(P->sigma > 0.0) || !isfinite(P->sigma)) return ORC_EINVAL;
+  if (!(P->theta > 0.0 && P->theta < 1.0)) return ORC_EINVAL;
+  if (!(P->c_kappa > 0.0)) return ORC_EINVAL;
+  if (P->n_v < 1 || P->n_v > 255) return ORC_EINVAL;
+  if (P->max_steps < 1) return ORC_EINVAL;
+  if (P->manifold == ORC_SPHERE_CAP) {
+    if (!(P->eps > 0.0)) return ORC_EINVAL;
+    if (!(fabs(P->p[1]) < P->p[0])) return ORC_EINVAL;
+  } else {
+    if (!(P->tau_w > 0.0 && P->tau_w < 1.0)) return ORC_EINVAL;
+  }
+  if ((P->manifold == ORC_TORUS || P->manifold == ORC_POINT_CLOUD) && P->n != 3) return ORC_EINVAL;
+  if (P->manifold == ORC_POINT_CLOUD && (P->k_nn < 6 || P->k_nn > ORC_MAXK || P->n_points < P->k_nn))
+    return ORC_EINVAL;
+  return ORC_OK;
+}
+
+/* Largest X = sqrt(sigma) r the solve can reach (constant radius bound). */
+static double orc_max_radius(const orc_problem* P) {
+  if (P->manifold == ORC_POINT_CLOUD) {
+    if (P->radius_rule == ORC_RADIUS_SPACING) return INFINITY;
+    return P->theta * P->c_kappa;
+  }
+  double kmin = 1.0 / P->p[0];
+  if (P->manifold == ORC_TORUS) kmin = 1.0 / P->p[1];
+  return P->theta * P->c_kappa / (1.0 + kmin);
+}
+
+int orc_solve(const orc_problem* P, const double* queries, int64_t nq, int64_t nw, uint64_t seed,
+              int n_threads, double* walk_S, int32_t* walk_K, double* u_out, double* stderr_out,
+              int64_t* n_truncated) {
+  int st = orc_check(P);
+  if (st) return st;
+  if (nq < 1 || nw < 1 || nq > 0xFFFFFFFFll || nw > 0xFFFFFFFFll) return ORC_EINVAL;
+  {
+    double rmax = orc_max_radius(P);
+    if (isfinite(rmax) && sqrt(P->sigma) * rmax > orc_radial_xmax(P->n)) return ORC_EINVAL;
+  }
+  int n = P->n;
+  /* every query must lie on M */
+  double* tmp = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!tmp) return ORC_ENOMEM;
+  for (int64_t q = 0; q < nq; ++q) {
+    const double* y = queries + q * n;
+    if (orc_cp(P, y, tmp)) { free(tmp); return ORC_EOFFMANIFOLD; }
+    double d2 = 0.0, sc = 0.0;
+    for (int i = 0; i < n; ++i) { d2 += (tmp[i] - y[i]) * (tmp[i] - y[i]); sc += y[i] * y[i]; }
+    double tol = (P->manifold == ORC_POINT_CLOUD) ? 1e-6 : 1e-9;
+    if (sqrt(d2) > tol * (1.0 + sqrt(sc))) { free(tmp); return ORC_EOFFMANIFOLD; }
+  }
+  free(tmp);
+  orc_ctx C;
+  C.P = P;
+  C.seed = seed;
+  orc_radial_init(&C.rad, n);
+  orc_job J;
+  J.C = &C; J.queries = queries; J.nq = nq; J.nw = nw;
+  J.walk_S = walk_S; J.walk_K = walk_K; J.next = 0; J.status = ORC_OK; J.truncated = 0;
+  pthread_mutex_init(&J.lock, NULL);
+  if (n_threads < 1) n_threads = 1;
+  if (n_threads > 256) n_threads = 256;
+  pthread_t th[256];
+  for (int t = 0; t < n_threads; ++t) pthread_create(&th[t], NULL, orc_worker, &J);
+  for (int t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
+  pthread_mutex_destroy(&J.lock);
+  if (J.status) return J.status;
+  for (int64_t q = 0; q < nq; ++q) {
+    double s = 0.0, comp = 0.0;
+    for (int64_t w = 0; w < nw; ++w) orc_sum_add(&s, &comp, walk_S[q * nw + w]);
+    double mean = (s + comp) / (double)nw;
+    double v = 0.0;
+    for (int64_t w = 0; w < nw; ++w) { double d = walk_S[q * nw + w] - mean; v += d * d; }
+    if (u_out) u_out[q] = mean;
+    if (stderr_out) stderr_out[q] = nw > 1 ? sqrt(v / (double)(nw - 1) / (double)nw) : 0.0;
+  }
+  if (n_truncated) *n_truncated = J.truncated;
+  return J.truncated ? ORC_WTRUNC : ORC_OK;
+}
+
+/* One walk, for tests. */
+int orc_walk_one(const orc_problem* P, const double* y0, uint32_t q, uint32_t w, uint64_t seed,
+                 double* S_out, int32_t* K_out, int* truncated) {
+  int st = orc_check(P);
+  if (st) return st;
+  orc_ctx C;
+  C.P = P;
+  C.seed = seed;
+  orc_radial_init(&C.rad, P->n);
+  return orc_walk(&C, y0, q, w, S_out, K_out, truncated);
+}

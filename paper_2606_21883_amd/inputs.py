@@ -1,0 +1,221 @@
+"""Seeded synthetic inputs: query sets, point clouds and problem descriptions.
+
+This module holds none of the walk's arithmetic.  It draws query points and
+point clouds with numpy's PCG64 generator (independent of the walk's Philox
+stream), describes the benchmark problems as plain dicts, and evaluates the
+closed-form solutions u that the estimates are scored against.
+
+Problem shapes follow the paper's experiments (Sec. 4): unit circle and unit
+sphere problems with spherical-harmonic solutions, hyperspheres up to
+n = 1000, a torus (R = 1, a = 0.3) given implicitly and as a noisy point cloud.
+"""
+import math
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# query sets
+# ---------------------------------------------------------------------------
+
+
+def circle_queries(nq):
+    """nq points uniform in angle on the unit circle: theta_p = 2 pi p / nq."""
+    th = 2.0 * np.pi * np.arange(nq) / nq
+    return np.stack([np.cos(th), np.sin(th)], axis=1)
+
+
+def sphere_uniform(nq, n, seed=1, radius=1.0):
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((nq, n))
+    return radius * g / np.linalg.norm(g, axis=1, keepdims=True)
+
+
+def cap_uniform(nq, n=3, h=0.0, seed=1, radius=1.0, margin=0.0):
+    """Uniform (area measure) on the cap {x_n > h + margin} of S^{n-1}_R, by rejection."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while sum(len(o) for o in out) < nq:
+        g = rng.standard_normal((4 * nq + 16, n))
+        g = radius * g / np.linalg.norm(g, axis=1, keepdims=True)
+        out.append(g[g[:, -1] > h + margin])
+    return np.concatenate(out)[:nq]
+
+
+def hypersphere_queries(nq, n, seed=1):
+    """Half the queries on the (x1, x2) great circle, half uniform on S^{n-1}.
+
+    Uniform points in high dimension give |x1 x2| ~ 1/n; the great circle gives
+    values of order one (u = sin(2 alpha)/2 there)."""
+    nc = nq // 2
+    q = np.zeros((nq, n))
+    al = 2.0 * np.pi * (np.arange(nc) + 0.5) / max(nc, 1)
+    q[:nc, 0] = np.cos(al)
+    q[:nc, 1] = np.sin(al)
+    q[nc:] = sphere_uniform(nq - nc, n, seed)
+    return q
+
+
+def torus_point(R, a, phi, psi):
+    rt = R + a * np.cos(psi)
+    return np.stack([rt * np.cos(phi), rt * np.sin(phi), a * np.sin(psi)], axis=-1)
+
+
+def torus_area_uniform(nq, R=1.0, a=0.3, seed=1):
+    """Area-uniform points on the torus: phi uniform, psi with density ~ R + a cos psi."""
+    rng = np.random.default_rng(seed)
+    phis, psis = [], []
+    cnt = 0
+    while cnt < nq:
+        m = 2 * (nq - cnt) + 16
+        psi = rng.uniform(0.0, 2.0 * np.pi, m)
+        acc = rng.uniform(0.0, R + a, m) < R + a * np.cos(psi)
+        psi = psi[acc]
+        phi = rng.uniform(0.0, 2.0 * np.pi, psi.size)
+        phis.append(phi)
+        psis.append(psi)
+        cnt += psi.size
+    phi = np.concatenate(phis)[:nq]
+    psi = np.concatenate(psis)[:nq]
+    return torus_point(R, a, phi, psi)
+
+
+def torus_point_cloud(npts, R=1.0, a=0.3, noise=1e-4, seed=1):
+    """Area-uniform torus samples plus isotropic Gaussian noise N(0, noise^2 I)."""
+    pts = torus_area_uniform(npts, R, a, seed)
+    rng = np.random.default_rng(seed + 1000)
+    return pts + noise * rng.standard_normal(pts.shape)
+
+
+# ---------------------------------------------------------------------------
+# problem descriptions (plain dicts understood by the solver binding)
+# ---------------------------------------------------------------------------
+
+DEFAULTS = dict(theta=0.95, c_kappa=1.2, tau_w=1e-8, n_v=1, compensation="exact",
+                max_steps=10_000_000)
+
+
+def problem(**kw):
+    d = dict(DEFAULTS)
+    d.update(kw)
+    return d
+
+
+def circle_problem():
+    """u = cos(3 theta) on S^1, sigma = 1, f = 10 cos(3 theta)."""
+    return problem(manifold="sphere", n=2, p=[1.0], sigma=1.0,
+                   f=dict(kind="circle_mode", idx=[3], coef=[10.0, 0.0]))
+
+
+def sphere_problem():
+    """u = x1 x2 on S^2, sigma = 2, f = 8 x1 x2."""
+    return problem(manifold="sphere", n=3, p=[1.0], sigma=2.0,
+                   f=dict(kind="sph_pair", idx=[0, 1], coef=[8.0]))
+
+
+def cap_problem(eps=1e-3):
+    """Cap x3 > 0 of S^2, u = x1 x2, sigma = 0.5, f = 6.5 x1 x2, g = u."""
+    return problem(manifold="sphere_cap", n=3, p=[1.0, 0.0], sigma=0.5, eps=eps,
+                   f=dict(kind="sph_pair", idx=[0, 1], coef=[6.5]),
+                   g=dict(kind="sph_pair", idx=[0, 1], coef=[1.0]))
+
+
+def hypersphere_problem(n):
+    """u = x1 x2 on S^{n-1}, sigma = 1, f = (2n + 1) x1 x2."""
+    return problem(manifold="sphere", n=n, p=[1.0], sigma=1.0,
+                   f=dict(kind="sph_pair", idx=[0, 1], coef=[2.0 * n + 1.0]))
+
+
+def torus_problem(R=1.0, a=0.3):
+    """u = sin(phi) cos(2 psi) on the implicit torus, sigma = 1."""
+    return problem(manifold="torus", n=3, p=[R, a], sigma=1.0,
+                   f=dict(kind="torus_mode", coef=[1.0]))
+
+
+def point_cloud_problem(points, k_nn=16, radius_rule="curvature_fit", R=1.0, a=0.3):
+    return problem(manifold="point_cloud", n=3, p=[R, a], sigma=1.0, points=points, k_nn=k_nn,
+                   radius_rule=radius_rule, c_h=2.4, newton_iters=6,
+                   f=dict(kind="torus_mode", coef=[1.0]))
+
+
+# ---------------------------------------------------------------------------
+# closed-form solutions u (what the estimates are scored against)
+# ---------------------------------------------------------------------------
+
+
+def _legendre(l, t):
+    p0, p1 = np.ones_like(t), t
+    if l == 0:
+        return p0
+    for k in range(1, l):
+        p0, p1 = p1, ((2 * k + 1) * t * p1 - k * p0) / (k + 1)
+    return p1
+
+
+def exact_u(prob, y):
+    """u(y) for the problem's manufactured solution at points y on M."""
+    y = np.asarray(y, dtype=np.float64)
+    f = prob["f"]
+    kind = f["kind"]
+    sg = prob["sigma"]
+    n = prob["n"]
+    R = prob.get("p", [1.0])[0]
+    if kind == "zero":
+        return np.zeros(len(y))
+    if kind == "const":
+        return np.full(len(y), f["coef"][0] / sg)
+    if kind == "sph_pair":
+        i, j = f["idx"][:2]
+        lam = 2.0 * n / R ** 2
+        return f["coef"][0] / (lam + sg) * (y[:, i] / R) * (y[:, j] / R)
+    if kind == "circle_mode":
+        k = f["idx"][0]
+        lam = k * k / R ** 2
+        th = np.arctan2(y[:, 1], y[:, 0])
+        c = list(f["coef"]) + [0.0]
+        return (c[0] * np.cos(k * th) + c[1] * np.sin(k * th)) / (lam + sg)
+    if kind == "legendre":
+        t = y[:, -1] / R
+        out = np.zeros(len(y))
+        for l, c in enumerate(f["coef"]):
+            out += c / (l * (l + 1) / R ** 2 + sg) * _legendre(l, t)
+        return out
+    if kind == "torus_mode":
+        Rt = prob["p"][0]
+        phi = np.arctan2(y[:, 1], y[:, 0])
+        rho = np.hypot(y[:, 0], y[:, 1])
+        psi = np.arctan2(y[:, 2], rho - Rt)
+        return f["coef"][0] * np.sin(phi) * np.cos(2.0 * psi)
+    raise ValueError(kind)
+
+
+# ---------------------------------------------------------------------------
+# the benchmark configurations
+# ---------------------------------------------------------------------------
+
+
+def config(name, scale=1.0, seed=1):
+    """Return (problem, queries, n_walks) for a named configuration.
+
+    scale < 1 shrinks queries and walks (for tests); 1 is the full size."""
+    def sz(v, lo=1):
+        return max(lo, int(round(v * scale)))
+
+    if name == "circle":
+        return circle_problem(), circle_queries(sz(64)), sz(1000)
+    if name == "sphere":
+        return sphere_problem(), sphere_uniform(sz(4096), 3, seed), sz(4096)
+    if name == "cap":
+        return cap_problem(), cap_uniform(sz(4096), 3, 0.0, seed), sz(4096)
+    if name == "hyper100":
+        return hypersphere_problem(100), hypersphere_queries(sz(1024, 2), 100, seed), sz(2048)
+    if name == "hyper1000":
+        return hypersphere_problem(1000), hypersphere_queries(sz(1024, 2), 1000, seed), sz(2048)
+    if name == "torus":
+        return torus_problem(), torus_area_uniform(sz(8192), 1.0, 0.3, seed), sz(1024)
+    raise ValueError(name)
+
+
+def rmse(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(math.sqrt(np.mean((a - b) ** 2)))

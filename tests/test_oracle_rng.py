@@ -1,0 +1,124 @@
+"""Pins of the oracle's random stream: Philox4x32-10 words, uniforms, Box-Muller
+normals and uniform sphere directions (Sec. 2.3.2, eq. projected_chain_update:
+zeta is a normalised standard Gaussian vector).
+
+Known-answer vectors of Philox are not available here, so the generator is
+pinned by the properties its published construction guarantees (bijectivity in
+the counter, avalanche, equidistribution), and by a GPU-box test against the
+ROCm library's own Philox4x32-10 (tests/test_gpu_rocrand_philox.py).
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+
+def _words(orc, n_blocks, key=(0, 0), field=0):
+    out = np.zeros((n_blocks, 4), dtype=np.uint32)
+    for i in range(n_blocks):
+        ctr = [0, 0, 0, 0]
+        ctr[field] = i
+        out[i] = orc.philox(ctr, key)
+    return out
+
+
+def test_philox_deterministic_and_counter_sensitive(orc):
+    a = orc.philox([1, 2, 3, 4], [5, 6])
+    b = orc.philox([1, 2, 3, 4], [5, 6])
+    assert np.array_equal(a, b)
+    for f in range(4):
+        c = [1, 2, 3, 4]
+        c[f] += 1
+        assert not np.array_equal(orc.philox(c, [5, 6]), a)
+    assert not np.array_equal(orc.philox([1, 2, 3, 4], [5, 7]), a)
+    assert not np.array_equal(orc.philox([1, 2, 3, 4], [6, 6]), a)
+
+
+def test_philox_injective_over_counters(orc):
+    # Philox is a bijection of the 128-bit counter for a fixed key.
+    w = _words(orc, 20000, key=(123, 456))
+    packed = {tuple(r) for r in w}
+    assert len(packed) == 20000
+
+
+def test_philox_word_equidistribution(orc):
+    w = _words(orc, 16384).ravel()
+    # top byte histogram: chi^2 with 255 dof
+    hist = np.bincount(w >> 24, minlength=256)
+    chi2 = ((hist - w.size / 256) ** 2 / (w.size / 256)).sum()
+    assert stats.chi2.sf(chi2, 255) > 1e-4
+    # every bit is set about half the time
+    bits = ((w[:, None] >> np.arange(32)) & 1).mean(axis=0)
+    assert np.all(np.abs(bits - 0.5) < 0.02)
+
+
+def test_philox_avalanche(orc):
+    rng = np.random.default_rng(7)
+    flips = []
+    for _ in range(200):
+        ctr = rng.integers(0, 2 ** 32, 4, dtype=np.uint64).astype(np.uint32)
+        key = rng.integers(0, 2 ** 32, 2, dtype=np.uint64).astype(np.uint32)
+        base = orc.philox(ctr, key)
+        bit = rng.integers(0, 128)
+        c2 = ctr.copy()
+        c2[bit // 32] ^= np.uint32(1 << (bit % 32))
+        out = orc.philox(c2, key)
+        flips.append(sum(bin(int(x) ^ int(y)).count("1") for x, y in zip(base, out)))
+    m = np.mean(flips)
+    assert 60.0 < m < 68.0, m
+
+
+def test_uniform_open_interval(orc):
+    assert orc.uniform(0) == 0.5 * 2.0 ** -32
+    assert orc.uniform(2 ** 32 - 1) == 1.0 - 0.5 * 2.0 ** -32
+    assert 0.0 < orc.uniform(0) and orc.uniform(2 ** 32 - 1) < 1.0
+
+
+def test_box_muller_pair(orc):
+    # u0 = u1 = 1/2 -> radius sqrt(2 ln 2), angle pi
+    x = 2 ** 31
+    u = orc.uniform(x)
+    g = orc.box_muller(x, x)
+    rad = np.sqrt(-2.0 * np.log(u))
+    assert g[0] == pytest.approx(rad * np.cos(2 * np.pi * u), rel=1e-15)
+    assert g[1] == pytest.approx(rad * np.sin(2 * np.pi * u), abs=1e-15)
+
+
+def test_normals_are_standard_gaussian(orc):
+    g = np.concatenate([orc.normals(3, q, 0, k, 0, 8) for q in range(50) for k in range(200)])
+    assert abs(g.mean()) < 0.015
+    assert abs(g.var() - 1.0) < 0.02
+    assert stats.kstest(g, "norm").pvalue > 1e-4
+    # pairs are uncorrelated
+    assert abs(np.corrcoef(g[0::2], g[1::2])[0, 1]) < 0.02
+
+
+def test_substreams_are_independent(orc):
+    a = np.concatenate([orc.normals(0, 1, w, 5, 0, 4) for w in range(4000)])
+    b = np.concatenate([orc.normals(0, 1, w, 5, 1, 4) for w in range(4000)])
+    assert abs(np.corrcoef(a, b)[0, 1]) < 0.03
+
+
+@pytest.mark.parametrize("n", [2, 3, 10])
+def test_sphere_direction_uniform(orc, n):
+    z = []
+    for w in range(6000):
+        g = orc.normals(11, 0, w, 0, 0, n)
+        z.append(g / np.linalg.norm(g))
+    z = np.array(z)
+    if n == 2:
+        ang = np.arctan2(z[:, 1], z[:, 0])
+        assert stats.kstest(ang, stats.uniform(loc=-np.pi, scale=2 * np.pi).cdf).pvalue > 1e-4
+    elif n == 3:
+        # Archimedes: one coordinate of a uniform point on S^2 is uniform on [-1, 1]
+        assert stats.kstest(z[:, 2], stats.uniform(loc=-1, scale=2).cdf).pvalue > 1e-4
+    else:
+        # x1^2 ~ Beta(1/2, (n-1)/2) on S^{n-1}
+        assert stats.kstest(z[:, 0] ** 2, stats.beta(0.5, (n - 1) / 2).cdf).pvalue > 1e-4
+
+
+def test_radius_uniform_word_position(orc):
+    # The Green-sample radius uses word 2*ceil(n/2) of its sub-stream.
+    for n, blk, word in [(2, 0, 2), (3, 1, 0), (4, 1, 0), (5, 1, 2), (100, 25, 0)]:
+        u = orc.radius_uniform(9, 3, 4, 5, 1, n)
+        x = orc.philox([3, 4, 5, (1 << 24) | blk], [9, 0])
+        assert u == orc.uniform(x[word])
