@@ -1,0 +1,253 @@
+/*
+ * mpwos.h -- C ABI of the MI355X (gfx950) MPWoS solver.
+ *
+ * MPWoS (modified projected Walk on Spheres) estimates the solution of the
+ * screened Poisson equation
+ *      -Lap_Omega u + sigma u = f  on Omega, a patch of an embedded manifold
+ *                                  M of R^n                 (Sec. 2.1, eq. surface_pde)
+ *      u = g on Gamma = dOmega when Omega has a boundary     (eq. surface_bc)
+ * at query points of Omega, from independent random walks in the ambient
+ * R^n (Algorithm 1): each step picks the radius r(Y) = theta min(delta_Gamma,
+ * rho_geo) (eq. radius_rule_unified), samples a point Theta uniformly on the
+ * sphere of radius r around Y and projects it back, Y' = cp(Theta)
+ * (eq. projected_chain_update), draws N_V points Z from the normalised Green
+ * density of the ball (eq. Z_sampling_density), accumulates
+ * W omega(Y) (f + m)(Z) (eq. path_score_definition, eq. local_average_source)
+ * and multiplies the screening weight W by c_{sigma,r} (eq. def_c_sigma_r).
+ * A walk stops in the eps-shell of the boundary (eq. boundary_layer) or,
+ * on a closed manifold, once W < tau_W.  The estimate is the mean score
+ * (eq. mc_estimator).
+ *
+ * Conventions for every entry point:
+ *   - Every call returns an mpwos_status; no exception crosses the ABI.
+ *   - On failure nothing is written to the outputs, and mpwos_last_error()
+ *     returns a message for the calling thread.
+ *   - Arrays are row-major.  Pointers named "queries", "u_out" and
+ *     "stderr_out" are host pointers unless opt->device_io is 1, in which
+ *     case all three (and walk_S / walk_K) are device pointers.
+ *   - The library never frees caller memory; caller buffers must stay valid
+ *     until the call (or, for a served request, the request) completes.
+ *   - Calls are synchronous on opt->stream (a hipStream_t, NULL = the
+ *     library's own stream) unless stated otherwise.
+ */
+#ifndef MPWOS_H
+#define MPWOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MPWOS_OK = 0,
+  MPWOS_EINVAL = -1,        /* an argument is outside the documented domain */
+  MPWOS_EOFFMANIFOLD = -2,  /* a query is not on M (|cp(y) - y| > 1e-9 (1 + |y|)) */
+  MPWOS_ENOMEM = -3,        /* device or host allocation, or the HBM budget, failed */
+  MPWOS_EDEVICE = -4,       /* a HIP runtime error; the message names the call */
+  MPWOS_EBUSY = -5,         /* a resource is still referenced (manifold in use, server full) */
+  MPWOS_WTRUNC = 1          /* warning: some walks reached max_steps and were cut there */
+} mpwos_status;
+
+/* Manifold kinds (Sec. 2.1: parameterised, implicit and point-cloud forms). */
+typedef enum {
+  MPWOS_SPHERE = 0,          /* S^{n-1}_R, closed; cp(x) = R x/|x| (explicit projection) */
+  MPWOS_SPHERE_CAP = 1,      /* Omega = S^{n-1}_R cap {x_n > h}, Gamma = {x_n = h} (boundary case) */
+  MPWOS_TORUS_IMPLICIT = 2,  /* {((|x|^2 + R^2 - a^2)^2 - 4R^2(x1^2 + x2^2)) = 0} in R^3; cp by a
+                                local Newton solve on the level set (Sec. 2.3.2) */
+  MPWOS_POINT_CLOUD = 3      /* points p_i in R^3; cp by k-nearest-neighbour search and a local
+                                quadratic reconstruction (Sec. 2.3.2) */
+} mpwos_kind;
+
+/* Source and boundary-data families.  For f the family describes f_Omega;
+ * for g it describes g_Omega on Gamma.  Families whose solution u is known
+ * in closed form also give the exact compensation m (eq. mismatch_definition). */
+typedef enum {
+  MPWOS_FN_ZERO = 0,         /* 0 */
+  MPWOS_FN_CONST = 1,        /* coef[0] */
+  MPWOS_FN_SPH_PAIR = 2,     /* S^{n-1}_R: coef[0] (y_i/R)(y_j/R), i = idx[0] != j = idx[1];
+                                eigenvalue 2n/R^2, so u = f/(2n/R^2 + sigma) */
+  MPWOS_FN_CIRCLE_MODE = 3,  /* S^1_R: coef[0] cos(k th) + coef[1] sin(k th), k = idx[0] */
+  MPWOS_FN_LEGENDRE = 4,     /* S^2_R: sum_{l<8} coef[l] P_l(y_3/R) */
+  MPWOS_FN_TORUS_MODE = 5,   /* torus / point-cloud torus (R = p[0], a = p[1]):
+                                u = coef[0] sin(phi) cos(2 psi), f = -Lap_T u + sigma u;
+                                as g: g = u */
+  MPWOS_FN_TABLE_S1 = 6      /* S^1_R, f: values[0..M) = f at th_i = 2 pi i/M (linear
+                                interpolation), values[M..2M) = predictor u_* used by
+                                the compensation; n_values = 2M (host memory) */
+} mpwos_fn_kind;
+
+typedef enum { MPWOS_FP64_PLAIN = 0, MPWOS_FP32_MIXED = 1 } mpwos_precision;
+typedef enum { MPWOS_COMP_NONE = 0, MPWOS_COMP_EXACT = 1 } mpwos_compensation;
+typedef enum {
+  MPWOS_RADIUS_CURVATURE = 0,     /* rho_geo = c_kappa/(1 + kappa(y)) (eq. rho_geo_curvature) */
+  MPWOS_RADIUS_SPACING = 1,       /* rho_geo = c_h h(y), h = mean kNN distance (eq. rho_geo_spacing) */
+  MPWOS_RADIUS_CURVATURE_FIT = 2  /* point cloud: kappa from the fitted patch, then eq. rho_geo_curvature */
+} mpwos_radius_rule;
+
+typedef struct mpwos_manifold mpwos_manifold;
+
+typedef struct {
+  int32_t kind;             /* mpwos_kind */
+  int32_t n;                /* ambient dimension: >= 2; 3 for torus and point cloud; <= 4096 */
+  double p[4];              /* SPHERE: R; SPHERE_CAP: R, h (|h| < R); TORUS / POINT_CLOUD: R, a
+                               (the torus the source families refer to) */
+  const float* points;      /* POINT_CLOUD: n_points x 3 FP32 */
+  int64_t n_points;         /* POINT_CLOUD: >= k_nn */
+  int32_t k_nn;             /* POINT_CLOUD: neighbours of the local fit, 6..32 (default 16) */
+  int32_t points_on_device; /* 1: `points` is a device pointer */
+} mpwos_manifold_desc;
+
+typedef struct {
+  int32_t kind;             /* mpwos_fn_kind */
+  int32_t idx[3];
+  double coef[8];
+  const double* values;     /* TABLE_S1 only, host memory, copied at solve time */
+  int64_t n_values;
+} mpwos_fn;
+
+typedef struct {
+  double theta;             /* safety factor, 0 < theta < 1 (default 0.95) */
+  double c_kappa;           /* > 0 (default 1.2) */
+  double c_h;               /* > 0 (default 2.4) */
+  double tau_w;             /* closed manifolds: stop when W < tau_w, 0 < tau_w < 1 (default 1e-8) */
+  int32_t n_v;              /* Green samples per step, 1..255 (default 1) */
+  int32_t precision;        /* mpwos_precision (default FP64_PLAIN) */
+  int32_t compensation;     /* mpwos_compensation (default EXACT) */
+  int32_t radius_rule;      /* mpwos_radius_rule (default CURVATURE) */
+  int64_t max_steps;        /* per-walk step cap, >= 1 (default 1e7); hitting it -> MPWOS_WTRUNC */
+  void* stream;             /* hipStream_t or NULL */
+  int32_t device_io;        /* 1: queries / outputs / walk_S / walk_K are device pointers */
+  int32_t block_size;       /* threads per workgroup, 0 = default (256); else 64, 128, 192 or 256 */
+  int32_t lanes_per_walk;   /* 0 = default; 1 for n <= 3; else 8, 16, 32 or 64 */
+  int32_t persistent;       /* 1: persistent kernel refilling lanes from a global queue;
+                               0: plain launch, one walk per lane (or per lane group) */
+  int32_t newton_iters;     /* point-cloud foot-point Newton iterations (default 6) */
+  int32_t k_spacing;        /* reserved (spacing rule uses k_nn neighbours) */
+  double* walk_S;           /* optional, n_queries x n_walks: per-walk score S^i */
+  int32_t* walk_K;          /* optional, n_queries x n_walks: per-walk stopping index K^i */
+} mpwos_options;
+
+typedef struct {
+  int64_t walk_steps;       /* total walk-steps (sum of K^i) */
+  int64_t truncated;        /* walks cut at max_steps */
+  int32_t k_max;            /* largest K^i */
+  double k_mean;            /* mean K^i */
+  double seconds;           /* wall time of the call */
+  double kernel_ms;         /* device time of the walk kernel(s), HIP events on the solve stream */
+  double reduce_ms;         /* device time of the per-query reduction */
+} mpwos_stats;
+
+/* Fills `opt` with the defaults listed above. */
+void mpwos_options_default(mpwos_options* opt);
+
+/* Creates an immutable manifold (Sec. 2.1).  For POINT_CLOUD the points are
+ * copied to the device, and a uniform grid over them is built and kept
+ * resident until mpwos_manifold_destroy.  EINVAL for a bad descriptor. */
+mpwos_status mpwos_manifold_create(const mpwos_manifold_desc* desc, mpwos_manifold** out);
+
+/* Releases a manifold.  EBUSY while a served request still references it. */
+mpwos_status mpwos_manifold_destroy(mpwos_manifold* m);
+
+/* Solves at n_queries points of M (Algorithm 1, eq. mc_estimator).
+ *   f, g: source and boundary data; g must be NULL exactly when M is closed.
+ *   c: the screening constant sigma > 0 of eq. surface_pde.
+ *   queries: n_queries x n doubles, each on M.
+ *   n_walks: paths per query, >= 1.
+ *   eps: boundary-layer width (eq. boundary_layer), > 0 on SPHERE_CAP, ignored when closed.
+ *   seed: key of the Philox4x32-10 stream; walk w of query q at step k draws
+ *         counter (q, w, k, sub << 24 | block), sub 0 = sphere direction,
+ *         sub l = Green sample l.
+ *   opt: NULL = defaults.
+ *   u_out: n_queries estimates; stderr_out (nullable): their standard errors.
+ *   stats (nullable).
+ * The result depends only on the arguments (not on the stream, timing or
+ * other work on the device), for a fixed precision and lanes_per_walk. */
+mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_fn* f, const mpwos_fn* g,
+                         double c, const double* queries, int64_t n_queries, int64_t n_walks,
+                         double eps, uint64_t seed, const mpwos_options* opt, double* u_out,
+                         double* stderr_out, mpwos_stats* stats);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* mpwos_last_error(void);
+
+/* ---- serving: continuous batching of solves (one device) ----------------
+ * Requests are admitted against an HBM budget; admitted requests share the
+ * device: each scheduling round launches one batch that holds walks of every
+ * admitted request, so a request that arrives while others run joins at the
+ * next round.  A request's result is identical to the same solve run alone. */
+typedef struct mpwos_server mpwos_server;
+
+typedef struct {
+  const mpwos_manifold* manifold;
+  mpwos_fn f, g;
+  int32_t has_g;              /* 1 when the manifold has a boundary */
+  double c;
+  const double* queries;      /* host, n_queries x n; must stay valid until done */
+  int64_t n_queries, n_walks;
+  double eps;
+  uint64_t seed;
+  mpwos_options opt;          /* precision, theta, ... (stream, device_io and walk_* ignored) */
+  double* u_out;              /* host, n_queries */
+  double* stderr_out;         /* host, nullable */
+} mpwos_request;
+
+typedef struct {
+  int64_t admitted, completed, rejected;
+  int64_t walk_steps;
+  double busy_seconds;        /* time with at least one request on the device */
+  int64_t in_flight_bytes;    /* HBM held by admitted requests */
+  int32_t rounds;             /* scheduling rounds launched */
+} mpwos_server_stats;
+
+/* hbm_budget_bytes: device memory the server may hold for admitted requests
+ * (queries, per-walk scores, outputs).  slice_walk_steps: work per
+ * scheduling round (0 = default 2^26 walk-steps). */
+mpwos_status mpwos_server_create(size_t hbm_budget_bytes, int64_t slice_walk_steps, mpwos_server** out);
+
+/* Queues a request (non-blocking); returns its ticket.  EINVAL for bad
+ * arguments; ENOMEM when the request alone exceeds the HBM budget. */
+mpwos_status mpwos_submit(mpwos_server* s, const mpwos_request* req, uint64_t* ticket);
+
+/* done = 1 once the request finished; `result` then holds its status. */
+mpwos_status mpwos_poll(mpwos_server* s, uint64_t ticket, int32_t* done, int32_t* result);
+
+/* Blocks until the request finished (timeout_ms < 0: no limit); EBUSY on timeout. */
+mpwos_status mpwos_wait(mpwos_server* s, uint64_t ticket, int64_t timeout_ms, int32_t* result);
+
+mpwos_status mpwos_server_stats_get(mpwos_server* s, mpwos_server_stats* out);
+
+/* Drains outstanding work and frees the server. */
+mpwos_status mpwos_server_destroy(mpwos_server* s);
+
+/* ---- inspection entry points (device implementations of single steps) -- */
+
+/* cp (eq. cp_map) of n_points ambient points x (n_points x n doubles, host)
+ * into y (host), computed by the device code of the given precision. */
+mpwos_status mpwos_debug_cp(const mpwos_manifold* m, const double* x, int64_t n_points,
+                            int32_t precision, double* y);
+
+/* Radius fraction s = t/r of a Green sample for uniforms u (host arrays of
+ * `count`), dimension n and X = sqrt(sigma) r: the device inverse of the
+ * radial law of eq. Z_sampling_density, in the given precision. */
+mpwos_status mpwos_debug_radial_inv(int32_t n, double X, const double* u, int64_t count,
+                                    int32_t precision, double* s);
+
+/* `count` Philox4x32-10 blocks for counters (c0 + i, c1, c2, c3), key
+ * (seed_lo, seed_hi), written as 4 x count words (host). */
+mpwos_status mpwos_debug_philox(const uint32_t ctr[4], uint64_t seed, int64_t count, uint32_t* out);
+
+/* Times a plain device-to-device copy of `bytes` (device memory owned by the
+ * library) repeated `reps` times; average ms per copy in *ms.  Used to
+ * calibrate HBM traffic counters. */
+mpwos_status mpwos_copy_probe(int64_t bytes, int32_t reps, double* ms);
+
+/* Library version string. */
+const char* mpwos_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPWOS_H */

@@ -1,0 +1,48 @@
+// Internal interfaces between the host translation units of the solver.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "kernel_args.h"
+#include "mpwos.h"
+
+namespace mpwos {
+
+struct CloudState;
+
+mpwos_status fail(mpwos_status st, const std::string& msg);
+mpwos_status hip_fail(hipError_t e, const char* what);
+int device_cu_count();
+void manifold_ref(const mpwos_manifold* m, int d);
+
+mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const mpwos_fn* g, double sigma,
+                           int64_t nq, int64_t nw, double eps, uint64_t seed, const mpwos_options& o,
+                           WalkArgs& a);
+mpwos_status launch_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue);
+
+// walk_lane.hip
+hipError_t launch_walk_lane(const WalkArgs& a, int grid, int block, hipStream_t s);
+int lane_occupancy(int kind, int n, bool fp64, int block);
+hipError_t launch_reduce(const double* walk_S, const int32_t* walk_K, int64_t nq, int64_t nw, int64_t max_steps,
+                         double* u, double* se, unsigned long long* ksum, int32_t* kmax,
+                         unsigned long long* ntrunc, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+hipError_t launch_cp_points(const WalkArgs& a, const double* x, double* y, int64_t m, hipStream_t s);
+hipError_t launch_radial_inv(const WalkArgs& a, const double* u, double* s_out, int64_t m, int fp64,
+                             hipStream_t s);
+hipError_t launch_philox(const uint32_t* c, uint64_t seed, uint32_t* out, int64_t m, hipStream_t s);
+hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
+
+// walk_group.hip
+mpwos_status launch_group_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue);
+
+// cloud.hip
+mpwos_status cloud_create(const mpwos_manifold_desc& d, hipStream_t s, CloudState** out);
+void cloud_destroy(CloudState* c);
+double cloud_spacing_rmax(const CloudState* c, const mpwos_options& o);
+void cloud_fill_args(const CloudState* c, const mpwos_options& o, WalkArgs& a);
+mpwos_status launch_cloud_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue);
+hipError_t launch_cloud_cp(const WalkArgs& a, const double* x, double* y, int64_t m, hipStream_t s);
+
+}  // namespace mpwos

@@ -1,0 +1,107 @@
+// Plain-old-data arguments shared by the host orchestration and the gfx950
+// walk kernels.  Passed by value as kernel arguments.
+#pragma once
+#include <stdint.h>
+
+namespace mpwos {
+
+constexpr int kMaxJ = 32;       // series terms kept for the radial law
+constexpr int kMaxK = 32;       // point-cloud neighbours
+
+enum Kind : int32_t { kSphere = 0, kCap = 1, kTorus = 2, kCloud = 3 };
+enum FnKind : int32_t {
+  kFnZero = 0, kFnConst = 1, kFnSphPair = 2, kFnCircle = 3, kFnLegendre = 4, kFnTorus = 5, kFnTableS1 = 6
+};
+
+// A source / boundary family as the device sees it.
+struct FnDev {
+  int32_t kind;
+  int32_t idx[3];
+  double coef[8];
+  const double* values;   // device copy of a TABLE_S1 table (2M doubles)
+  int64_t m;              // M (table length of one half)
+  double lam;             // eigenvalue of the family (sphere families), 0 otherwise
+  double u_scale;         // u = u_scale * f for eigen families
+};
+
+// Coefficients of the radial law of the normalised Green density for one
+// dimension n (independent of the radius).
+//   S_nu(x)      = sum_j alpha[j]  z^j, z = x^2
+//   S_{nu+1}(x)  = sum_j alpha1[j] z^j
+//   D(s)         = sum_{j != nu} bd[j] X^{2j} (s^{2j} - s^{2 nu}) - beta_nu X^{2 nu} s^{2 nu} ln s
+struct RadialLaw {
+  int32_t n;
+  int32_t nu_int;         // nu when n is even (log term index), else -1
+  int32_t js;             // terms used for S_nu and S_{nu+1}
+  int32_t jd;             // terms used for D
+  double nu;
+  double inv_2nu1;        // 1 / (2 (nu + 1))
+  double alpha[kMaxJ];
+  double alpha1[kMaxJ];
+  double bd[kMaxJ];       // beta_j / (2 (nu - j)); at j == nu_int: beta_nu
+};
+
+// The same law with a fixed X = sqrt(sigma) r folded in.
+struct RadialFixed {
+  double X2;
+  double A[kMaxJ];        // alpha[j] X^{2j} (A[0] unused)
+  double A1[kMaxJ];       // alpha1[j] X^{2j}
+  double B[kMaxJ];        // bd[j] X^{2j} (0 at the log index)
+  double Q1;              // sum_j B[j]
+  double L;               // beta_nu X^{2nu} (log term), 0 when n is odd
+  double norm;            // 1 / (1 - c)
+};
+
+// Inverse-CDF guess table: s at u = i/(mu-1), for mx radius slices.
+struct InvTable {
+  const double* s64;      // mx * mu doubles (FP64 guesses / brackets)
+  const float* s32;       // mx * mu floats
+  int32_t mu;             // points per slice (power of two + 1)
+  int32_t mx;             // slices in X^2 (1 when X is fixed)
+  double x2max;           // X^2 of the last slice
+};
+
+struct CloudDev {
+  const float* pts;       // n_points x 3, sorted by grid cell
+  const int32_t* cell_start;  // ncell + 1
+  const int32_t* orig_idx;    // sorted position -> input index (tie-breaks)
+  int64_t n_points;
+  int32_t dims[3];
+  float lo[3];
+  float inv_h;            // 1 / cell size
+  float h;
+  int32_t k;              // neighbours
+  int32_t newton_iters;
+  int32_t radius_rule;
+};
+
+struct WalkArgs {
+  // problem
+  int32_t kind, n;
+  double p[4];
+  double sigma, lam_sqrt, eps, theta, c_kappa, c_h, tau_w;
+  int32_t n_v, comp, precision, persistent;
+  int64_t max_steps;
+  FnDev f, g;
+  // constant-radius data (closed analytic manifolds)
+  int32_t const_r;
+  double r0, c0, om0, X0;
+  RadialLaw law;
+  RadialFixed fixed;
+  InvTable tab;
+  CloudDev cloud;
+  // work
+  const double* queries;       // this launch's queries (q_offset .. q_offset + nq)
+  int64_t nq, nw;
+  int64_t q_offset;            // global index of queries[0] in the solve (Philox counter word 0)
+  uint64_t seed;
+  double* walk_S;
+  int32_t* walk_K;
+  unsigned long long* queue;   // persistent work counter
+  int32_t chunk;               // walks taken per queue grab
+  int32_t lanes;               // lanes per walk (group kernels)
+  int32_t nblk;                // Philox blocks per Green sub-stream (group kernels)
+  int32_t rblk, rword;         // block / word of the Green radius uniform
+};
+
+}  // namespace mpwos

@@ -1,0 +1,817 @@
+// Host side of the C ABI (include/mpwos.h): argument validation, the
+// per-dimension coefficients of the radial Green law and its inverse tables,
+// device workspaces, and the launch sequence of a solve:
+//   queries -> walk kernel (per-walk S^i, K^i) -> per-query reduction -> u, stderr.
+#include "mpwos.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "host_internal.h"
+#include "kernel_args.h"
+
+namespace mpwos {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+mpwos_status fail(mpwos_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+mpwos_status hip_fail(hipError_t e, const char* what) {
+  return fail(MPWOS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                   \
+  do {                                                  \
+    hipError_t _e = (call);                             \
+    if (_e != hipSuccess) return hip_fail(_e, #call);   \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device context: stream, events, grow-only workspace
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+struct Context {
+  std::mutex lock;
+  int device = 0;
+  int n_cu = 256;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev[4] = {};
+  DevBuf queries, walkS, walkK, u, se, stats, tmp;
+  bool ready = false;
+};
+
+static Context g_ctx;
+
+static mpwos_status ensure(DevBuf& b, size_t bytes) {
+  if (b.cap >= bytes) return MPWOS_OK;
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+  const size_t want = std::max<size_t>(bytes, 256);
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    hipGetLastError();
+    return fail(MPWOS_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+  }
+  b.cap = want;
+  return MPWOS_OK;
+}
+
+static mpwos_status context_init(Context& c) {
+  if (c.ready) return MPWOS_OK;
+  HIP_TRY(hipGetDevice(&c.device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, c.device));
+  c.n_cu = prop.multiProcessorCount;
+  HIP_TRY(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+  for (auto& e : c.ev) HIP_TRY(hipEventCreate(&e));
+  c.ready = true;
+  return MPWOS_OK;
+}
+
+int device_cu_count() { return g_ctx.ready ? g_ctx.n_cu : 256; }
+
+// ---------------------------------------------------------------------------
+// radial law of the Green density: coefficients for dimension n
+//   S_nu(x) = sum_j (x^2/4)^j / (j! (nu+1)_j),  sum_j beta_j y^{2j} = S_nu(y)^{-2}
+// ---------------------------------------------------------------------------
+static constexpr int kHostJ = 96;
+
+struct HostLaw {
+  int n = 0;
+  double nu = 0;
+  int nu_int = -1;
+  double alpha[kHostJ], alpha1[kHostJ], beta[kHostJ];
+};
+
+static void host_law(int n, HostLaw& h) {
+  h.n = n;
+  h.nu = 0.5 * (n - 2);
+  h.nu_int = (n % 2 == 0) ? (n - 2) / 2 : -1;
+  h.alpha[0] = h.alpha1[0] = 1.0;
+  for (int j = 1; j < kHostJ; ++j) {
+    h.alpha[j] = h.alpha[j - 1] / (4.0 * j * (h.nu + j));
+    h.alpha1[j] = h.alpha1[j - 1] / (4.0 * j * (h.nu + 1.0 + j));
+  }
+  // power-series reciprocal of S_nu^2
+  double sq[kHostJ];
+  for (int j = 0; j < kHostJ; ++j) {
+    double acc = 0.0;
+    for (int i = 0; i <= j; ++i) acc += h.alpha[i] * h.alpha[j - i];
+    sq[j] = acc;
+  }
+  h.beta[0] = 1.0;
+  for (int j = 1; j < kHostJ; ++j) {
+    double acc = 0.0;
+    for (int i = 1; i <= j; ++i) acc += sq[i] * h.beta[j - i];
+    h.beta[j] = -acc;
+  }
+}
+
+static double bd_of(const HostLaw& h, int j) {
+  if (j == h.nu_int) return h.beta[j];
+  return h.beta[j] / (2.0 * (h.nu - j));
+}
+
+// Series lengths for X^2 <= x2max: S_nu / S_{nu+1} keep terms until they drop
+// below 1e-18; D keeps every beta term above 1e-20 (the log term at j = nu is
+// dropped when it is below that too).  False when more than kMaxJ are needed.
+static bool law_terms(const HostLaw& h, double x2max, int& js, int& jd) {
+  js = kMaxJ + 1;
+  for (int j = 1; j <= kMaxJ; ++j) {
+    if (h.alpha[j] * std::pow(x2max, j) < 1e-18) { js = j; break; }
+  }
+  jd = 1;
+  for (int j = kHostJ - 1; j >= 1; --j) {
+    if (std::fabs(h.beta[j]) * std::pow(x2max, j) >= 1e-20) { jd = j + 1; break; }
+  }
+  return js <= kMaxJ && jd <= kMaxJ;
+}
+
+static void fill_law(const HostLaw& h, int js, int jd, RadialLaw& L) {
+  memset(&L, 0, sizeof(L));
+  L.n = h.n;
+  L.nu = h.nu;
+  L.nu_int = (h.nu_int >= 0 && h.nu_int < jd) ? h.nu_int : -1;
+  L.js = js;
+  L.jd = jd;
+  L.inv_2nu1 = 1.0 / (2.0 * (h.nu + 1.0));
+  for (int j = 0; j < kMaxJ; ++j) {
+    L.alpha[j] = h.alpha[j];
+    L.alpha1[j] = h.alpha1[j];
+    L.bd[j] = bd_of(h, j);
+  }
+}
+
+static void fill_fixed(const HostLaw& h, const RadialLaw& L, double X, RadialFixed& R) {
+  memset(&R, 0, sizeof(R));
+  const double X2 = X * X;
+  R.X2 = X2;
+  double xp = 1.0, q1 = 0.0, s1 = 0.0;
+  for (int j = 0; j < kMaxJ; ++j) {
+    if (j > 0) xp *= X2;
+    R.A[j] = h.alpha[j] * xp;
+    R.A1[j] = h.alpha1[j] * xp;
+    if (j == L.nu_int) {
+      R.L = h.beta[j] * xp;
+      R.B[j] = 0.0;
+    } else if (j < L.jd) {
+      R.B[j] = bd_of(h, j) * xp;
+      q1 += R.B[j];
+    }
+  }
+  R.Q1 = q1;
+  xp = 1.0;
+  for (int j = 1; j < kHostJ; ++j) {
+    xp *= X2;
+    s1 += h.alpha[j] * xp;
+  }
+  R.norm = (1.0 + s1) / s1;
+}
+
+// exact F(s) and F'(s) on the host (full-length series)
+static void host_F(const HostLaw& h, double X2, double s, double& F, double& pdf) {
+  if (s <= 0.0) { F = 0.0; pdf = 0.0; return; }
+  if (s >= 1.0) { F = 1.0; pdf = 0.0; return; }
+  const double z = s * s;
+  double t1 = 0, S1 = 0, Dz = 0, Q1 = 0, Lg = 0, s1X = 0;
+  double xp = 1.0, zp = 1.0;
+  for (int j = 0; j < kHostJ; ++j) {
+    if (j > 0) { xp *= X2; zp *= z; }
+    if (j > 0) { t1 += h.alpha[j] * xp * zp; s1X += h.alpha[j] * xp; }
+    S1 += h.alpha1[j] * xp * zp;
+    const double b = bd_of(h, j) * xp;
+    if (j == h.nu_int) Lg = b;
+    else { Dz += b * zp; Q1 += b; }
+  }
+  const double s2nu = std::pow(s, (double)(h.n - 2));
+  double D = Dz - s2nu * Q1;
+  if (h.nu_int >= 0) D -= Lg * s2nu * std::log(s);
+  const double norm = (1.0 + s1X) / s1X;
+  F = norm * (t1 / (1.0 + t1) + X2 * z * S1 / (2.0 * (h.nu + 1.0)) * D);
+  pdf = norm * X2 * s * (1.0 + t1) * D;
+}
+
+static double host_inv(const HostLaw& h, double X2, double u, double lo, double hi) {
+  double s = 0.5 * (lo + hi);
+  for (int it = 0; it < 200; ++it) {
+    double F, p;
+    host_F(h, X2, s, F, p);
+    if (F < u) lo = s; else hi = s;
+    double sn = s - (F - u) / p;
+    if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
+    if (std::fabs(sn - s) <= 1e-17 || hi - lo <= 1e-17) { s = sn; break; }
+    s = sn;
+  }
+  return s;
+}
+
+// Inverse tables, cached per (n, slices, X^2 range).
+struct TableKey {
+  int n, mx;
+  double x2max;
+  bool operator<(const TableKey& o) const { return std::tie(n, mx, x2max) < std::tie(o.n, o.mx, o.x2max); }
+};
+struct TableVal {
+  double* d64 = nullptr;
+  float* d32 = nullptr;
+  int mu = 0;
+};
+static std::mutex g_tab_lock;
+static std::map<TableKey, TableVal> g_tables;
+
+static mpwos_status get_table(const HostLaw& h, int mx, double x2max, InvTable& t) {
+  const int mu = 1025;
+  TableKey key{h.n, mx, x2max};
+  std::lock_guard<std::mutex> g(g_tab_lock);
+  auto it = g_tables.find(key);
+  if (it == g_tables.end()) {
+    std::vector<double> s64((size_t)mx * mu);
+    std::vector<float> s32((size_t)mx * mu);
+    for (int k = 0; k < mx; ++k) {
+      const double X2 = (mx == 1) ? x2max : (k == 0 ? x2max * 1e-6 : x2max * k / (mx - 1));
+      double prev = 0.0;
+      for (int i = 0; i < mu; ++i) {
+        double s;
+        if (i == 0) s = 0.0;
+        else if (i == mu - 1) s = 1.0;
+        else s = host_inv(h, X2, (double)i / (mu - 1), prev, 1.0);
+        s64[(size_t)k * mu + i] = s;
+        s32[(size_t)k * mu + i] = (float)s;
+        prev = s;
+      }
+    }
+    TableVal v;
+    v.mu = mu;
+    hipError_t e = hipMalloc(&v.d64, s64.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&v.d32, s32.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(v.d64, s64.data(), s64.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(v.d32, s32.data(), s32.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "inverse table upload");
+    it = g_tables.emplace(key, v).first;
+  }
+  t.s64 = it->second.d64;
+  t.s32 = it->second.d32;
+  t.mu = it->second.mu;
+  t.mx = mx;
+  t.x2max = x2max;
+  return MPWOS_OK;
+}
+
+// screening factor c and omega (Lemma 3.1 series)
+static void host_weights(int n, double sigma, double r, double& c, double& om) {
+  const double nu = 0.5 * (n - 2);
+  const double q = 0.25 * sigma * r * r;
+  double term = 1.0, s1 = 0.0;
+  for (int j = 1; j < 100000; ++j) {
+    term = term * q / ((double)j * (nu + (double)j));
+    s1 += term;
+    if (term <= 1e-18 * s1) break;
+  }
+  c = 1.0 / (1.0 + s1);
+  om = s1 / (sigma * (1.0 + s1));
+}
+
+// ---------------------------------------------------------------------------
+// manifolds
+// ---------------------------------------------------------------------------
+}  // namespace mpwos
+
+struct mpwos_manifold {
+  mpwos_manifold_desc desc;
+  mpwos::CloudState* cloud = nullptr;
+  std::atomic<int> refs{0};
+};
+
+namespace mpwos {
+
+static mpwos_status check_manifold_desc(const mpwos_manifold_desc* d) {
+  if (!d) return fail(MPWOS_EINVAL, "manifold descriptor is NULL");
+  switch (d->kind) {
+    case MPWOS_SPHERE:
+      if (d->n < 2 || d->n > 4096) return fail(MPWOS_EINVAL, "sphere: n must be in [2, 4096]");
+      if (!(d->p[0] > 0) || !std::isfinite(d->p[0])) return fail(MPWOS_EINVAL, "sphere: radius p[0] must be > 0");
+      return MPWOS_OK;
+    case MPWOS_SPHERE_CAP:
+      if (d->n < 2 || d->n > 3) return fail(MPWOS_EINVAL, "sphere cap: n must be 2 or 3");
+      if (!(d->p[0] > 0)) return fail(MPWOS_EINVAL, "sphere cap: radius p[0] must be > 0");
+      if (!(std::fabs(d->p[1]) < d->p[0])) return fail(MPWOS_EINVAL, "sphere cap: |h| must be < R");
+      return MPWOS_OK;
+    case MPWOS_TORUS_IMPLICIT:
+      if (d->n != 3) return fail(MPWOS_EINVAL, "torus: n must be 3");
+      if (!(d->p[1] > 0 && d->p[1] <= 0.5 * d->p[0]))
+        return fail(MPWOS_EINVAL, "torus: need 0 < a <= R/2 (constant curvature indicator 1/a)");
+      return MPWOS_OK;
+    case MPWOS_POINT_CLOUD:
+      if (d->n != 3) return fail(MPWOS_EINVAL, "point cloud: n must be 3");
+      if (!d->points) return fail(MPWOS_EINVAL, "point cloud: points is NULL");
+      if (d->k_nn < 6 || d->k_nn > kMaxK) return fail(MPWOS_EINVAL, "point cloud: k_nn must be in [6, 32]");
+      if (d->n_points < d->k_nn || d->n_points > (int64_t)1 << 30)
+        return fail(MPWOS_EINVAL, "point cloud: n_points must be in [k_nn, 2^30]");
+      return MPWOS_OK;
+  }
+  return fail(MPWOS_EINVAL, "unknown manifold kind");
+}
+
+// curvature indicator kappa (largest |principal curvature|) when constant
+static double const_kappa(const mpwos_manifold_desc& d) {
+  switch (d.kind) {
+    case MPWOS_SPHERE:
+    case MPWOS_SPHERE_CAP: return 1.0 / d.p[0];
+    case MPWOS_TORUS_IMPLICIT: return 1.0 / d.p[1];
+  }
+  return 0.0;
+}
+
+static mpwos_status check_fn(const mpwos_fn* f, const mpwos_manifold_desc& d, bool is_g) {
+  if (!f) return MPWOS_OK;
+  const char* which = is_g ? "g" : "f";
+  auto bad = [&](const char* m) { return fail(MPWOS_EINVAL, std::string(which) + ": " + m); };
+  const bool sph = d.kind == MPWOS_SPHERE || d.kind == MPWOS_SPHERE_CAP;
+  switch (f->kind) {
+    case MPWOS_FN_ZERO:
+    case MPWOS_FN_CONST: return MPWOS_OK;
+    case MPWOS_FN_SPH_PAIR:
+      if (!sph) return bad("SPH_PAIR needs a sphere");
+      if (f->idx[0] < 0 || f->idx[1] < 0 || f->idx[0] >= d.n || f->idx[1] >= d.n || f->idx[0] == f->idx[1])
+        return bad("SPH_PAIR needs distinct indices in [0, n)");
+      return MPWOS_OK;
+    case MPWOS_FN_CIRCLE_MODE:
+      if (!sph || d.n != 2 || is_g) return bad("CIRCLE_MODE is a source on S^1");
+      if (f->idx[0] < 0 || f->idx[0] > 64) return bad("CIRCLE_MODE: k must be in [0, 64]");
+      return MPWOS_OK;
+    case MPWOS_FN_LEGENDRE:
+      if (!sph || d.n != 3) return bad("LEGENDRE needs S^2");
+      return MPWOS_OK;
+    case MPWOS_FN_TORUS_MODE:
+      if (is_g || (d.kind != MPWOS_TORUS_IMPLICIT && d.kind != MPWOS_POINT_CLOUD))
+        return bad("TORUS_MODE is a source on a torus");
+      return MPWOS_OK;
+    case MPWOS_FN_TABLE_S1:
+      if (!sph || d.n != 2 || is_g) return bad("TABLE_S1 is a source on S^1");
+      if (!f->values || f->n_values < 4 || (f->n_values % 2)) return bad("TABLE_S1 needs 2M >= 4 values");
+      return MPWOS_OK;
+  }
+  return bad("unknown function kind");
+}
+
+static void fill_fn(const mpwos_fn* f, const mpwos_manifold_desc& d, double sigma, FnDev& o) {
+  memset(&o, 0, sizeof(o));
+  if (!f) return;
+  o.kind = f->kind;
+  for (int i = 0; i < 3; ++i) o.idx[i] = f->idx[i];
+  for (int i = 0; i < 8; ++i) o.coef[i] = f->coef[i];
+  const double R = d.p[0];
+  if (f->kind == MPWOS_FN_SPH_PAIR) o.lam = 2.0 * d.n / (R * R);
+  if (f->kind == MPWOS_FN_CIRCLE_MODE) o.lam = (double)f->idx[0] * f->idx[0] / (R * R);
+  o.u_scale = 1.0 / (o.lam + sigma);
+  if (f->kind == MPWOS_FN_TABLE_S1) o.m = f->n_values / 2;
+}
+
+// on-manifold test of a query (host side, analytic manifolds)
+static bool query_on_manifold(const mpwos_manifold_desc& d, const double* y) {
+  const int n = d.n;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += y[i] * y[i];
+  const double tol = 1e-9 * (1.0 + std::sqrt(s));
+  switch (d.kind) {
+    case MPWOS_SPHERE: return std::fabs(std::sqrt(s) - d.p[0]) <= tol;
+    case MPWOS_SPHERE_CAP: return std::fabs(std::sqrt(s) - d.p[0]) <= tol && y[n - 1] > d.p[1];
+    case MPWOS_TORUS_IMPLICIT: {
+      const double rho = std::hypot(y[0], y[1]);
+      const double dc = std::hypot(rho - d.p[0], y[2]);
+      return std::fabs(dc - d.p[1]) <= tol;
+    }
+  }
+  return true;
+}
+
+}  // namespace mpwos
+
+using namespace mpwos;
+
+extern "C" {
+
+const char* mpwos_last_error(void) { return g_last_error.c_str(); }
+
+const char* mpwos_version(void) { return "mpwos-gfx950 0.1"; }
+
+void mpwos_options_default(mpwos_options* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->theta = 0.95;
+  o->c_kappa = 1.2;
+  o->c_h = 2.4;
+  o->tau_w = 1e-8;
+  o->n_v = 1;
+  o->precision = MPWOS_FP64_PLAIN;
+  o->compensation = MPWOS_COMP_EXACT;
+  o->radius_rule = MPWOS_RADIUS_CURVATURE;
+  o->max_steps = 10000000;
+  o->persistent = 0;
+  o->newton_iters = 6;
+}
+
+mpwos_status mpwos_manifold_create(const mpwos_manifold_desc* desc, mpwos_manifold** out) {
+  g_last_error.clear();
+  if (!out) return fail(MPWOS_EINVAL, "out is NULL");
+  mpwos_status st = check_manifold_desc(desc);
+  if (st) return st;
+  {
+    std::lock_guard<std::mutex> g(g_ctx.lock);
+    st = context_init(g_ctx);
+    if (st) return st;
+  }
+  auto* m = new (std::nothrow) mpwos_manifold;
+  if (!m) return fail(MPWOS_ENOMEM, "host allocation");
+  m->desc = *desc;
+  if (desc->kind == MPWOS_POINT_CLOUD) {
+    st = cloud_create(*desc, g_ctx.stream, &m->cloud);
+    if (st) {
+      delete m;
+      return st;
+    }
+  }
+  m->desc.points = nullptr;
+  *out = m;
+  return MPWOS_OK;
+}
+
+mpwos_status mpwos_manifold_destroy(mpwos_manifold* m) {
+  g_last_error.clear();
+  if (!m) return fail(MPWOS_EINVAL, "manifold is NULL");
+  if (m->refs.load() > 0) return fail(MPWOS_EBUSY, "manifold is referenced by a queued request");
+  if (m->cloud) cloud_destroy(m->cloud);
+  delete m;
+  return MPWOS_OK;
+}
+
+}  // extern "C"
+
+namespace mpwos {
+
+void manifold_ref(const mpwos_manifold* m, int d) { const_cast<mpwos_manifold*>(m)->refs += d; }
+
+// Validates a solve and fills the kernel arguments (except buffers).
+mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const mpwos_fn* g, double sigma,
+                           int64_t nq, int64_t nw, double eps, uint64_t seed, const mpwos_options& o,
+                           WalkArgs& a) {
+  if (!man) return fail(MPWOS_EINVAL, "manifold is NULL");
+  const mpwos_manifold_desc& d = man->desc;
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(MPWOS_EINVAL, "c (sigma) must be finite and > 0");
+  if (nq < 1 || nq > 0xFFFFFFFFll) return fail(MPWOS_EINVAL, "n_queries must be in [1, 2^32)");
+  if (nw < 1 || nw > 0xFFFFFFFFll) return fail(MPWOS_EINVAL, "n_walks must be in [1, 2^32)");
+  const bool boundary = d.kind == MPWOS_SPHERE_CAP;
+  if (boundary && !g) return fail(MPWOS_EINVAL, "g is required on a manifold with boundary");
+  if (!boundary && g) return fail(MPWOS_EINVAL, "g must be NULL on a closed manifold");
+  if (boundary && !(eps > 0.0 && std::isfinite(eps))) return fail(MPWOS_EINVAL, "eps must be > 0");
+  if (!f) return fail(MPWOS_EINVAL, "f is NULL");
+  if (!(o.theta > 0.0 && o.theta < 1.0)) return fail(MPWOS_EINVAL, "theta must be in (0, 1)");
+  if (!(o.c_kappa > 0.0)) return fail(MPWOS_EINVAL, "c_kappa must be > 0");
+  if (!(o.c_h > 0.0)) return fail(MPWOS_EINVAL, "c_h must be > 0");
+  if (!boundary && !(o.tau_w > 0.0 && o.tau_w < 1.0)) return fail(MPWOS_EINVAL, "tau_w must be in (0, 1)");
+  if (o.n_v < 1 || o.n_v > 255) return fail(MPWOS_EINVAL, "n_v must be in [1, 255]");
+  if (o.max_steps < 1) return fail(MPWOS_EINVAL, "max_steps must be >= 1");
+  if (o.precision != MPWOS_FP64_PLAIN && o.precision != MPWOS_FP32_MIXED)
+    return fail(MPWOS_EINVAL, "unknown precision");
+  if (o.compensation != MPWOS_COMP_NONE && o.compensation != MPWOS_COMP_EXACT)
+    return fail(MPWOS_EINVAL, "unknown compensation");
+  if (o.block_size != 0 && (o.block_size < 64 || o.block_size > 256 || o.block_size % 64))
+    return fail(MPWOS_EINVAL, "block_size must be 0 or a multiple of 64 in [64, 256]");
+  {
+    const int l = o.lanes_per_walk;
+    if (!(l == 0 || l == 1 || l == 4 || l == 8 || l == 16 || l == 32 || l == 64))
+      return fail(MPWOS_EINVAL, "lanes_per_walk must be 0, 1, 4, 8, 16, 32 or 64");
+  }
+  mpwos_status st = check_fn(f, d, false);
+  if (st) return st;
+  st = check_fn(g, d, true);
+  if (st) return st;
+  if (o.compensation == MPWOS_COMP_EXACT && f->kind == MPWOS_FN_TABLE_S1 && !f->values)
+    return fail(MPWOS_EINVAL, "TABLE_S1 needs values");
+
+  memset(&a, 0, sizeof(a));
+  a.kind = d.kind;
+  a.n = d.n;
+  for (int i = 0; i < 4; ++i) a.p[i] = d.p[i];
+  a.sigma = sigma;
+  a.lam_sqrt = std::sqrt(sigma);
+  a.eps = eps;
+  a.theta = o.theta;
+  a.c_kappa = o.c_kappa;
+  a.c_h = o.c_h;
+  a.tau_w = o.tau_w;
+  a.n_v = o.n_v;
+  a.comp = o.compensation;
+  a.precision = o.precision;
+  a.persistent = o.persistent;
+  a.max_steps = o.max_steps;
+  a.seed = seed;
+  fill_fn(f, d, sigma, a.f);
+  fill_fn(g, d, sigma, a.g);
+
+  HostLaw h;
+  host_law(d.n, h);
+  // largest X^2 = sigma r^2 the walk can reach
+  double rmax;
+  if (d.kind == MPWOS_POINT_CLOUD) {
+    rmax = o.radius_rule == MPWOS_RADIUS_SPACING ? 0.0 : o.theta * o.c_kappa;
+    if (o.radius_rule == MPWOS_RADIUS_SPACING) rmax = cloud_spacing_rmax(man->cloud, o);
+  } else {
+    rmax = o.theta * o.c_kappa / (1.0 + const_kappa(d));
+  }
+  const double x2max = sigma * rmax * rmax;
+  int js, jd;
+  if (!law_terms(h, x2max, js, jd))
+    return fail(MPWOS_EINVAL, "sqrt(sigma) r_max = " + std::to_string(std::sqrt(x2max)) +
+                                  " is beyond the range of the series radial law for this n");
+  fill_law(h, js, jd, a.law);
+  a.const_r = (d.kind == MPWOS_SPHERE || d.kind == MPWOS_TORUS_IMPLICIT) ? 1 : 0;
+  if (a.const_r) {
+    a.r0 = rmax;
+    host_weights(d.n, sigma, a.r0, a.c0, a.om0);
+    a.X0 = std::sqrt(sigma) * a.r0;
+    fill_fixed(h, a.law, a.X0, a.fixed);
+    st = get_table(h, 1, a.X0 * a.X0, a.tab);
+  } else {
+    st = get_table(h, 17, x2max, a.tab);
+  }
+  if (st) return st;
+  if (d.kind == MPWOS_POINT_CLOUD) cloud_fill_args(man->cloud, o, a);
+  return MPWOS_OK;
+}
+
+// Walk kernel launch for a batch (queries/outputs already on the device).
+mpwos_status launch_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue) {
+  const int64_t total = a.nq * a.nw;
+  const int n_cu = device_cu_count();
+  if (a.n <= 3 && a.kind != MPWOS_POINT_CLOUD) {
+    const int block = o.block_size ? o.block_size : 256;
+    hipError_t e;
+    if (a.persistent) {
+      const int occ = lane_occupancy(a.kind, a.n, a.precision == 0, block);
+      const int64_t grid_max = (int64_t)occ * n_cu;
+      const int64_t need = (total + block - 1) / block;
+      const int64_t grid = std::max<int64_t>(1, std::min(grid_max, need));
+      const int64_t waves = grid * (block / 64);
+      int64_t chunk = total / (waves * 8);
+      chunk = std::max<int64_t>(64, std::min<int64_t>(4096, (chunk / 64) * 64));
+      a.chunk = (int32_t)chunk;
+      a.queue = queue;
+      e = launch_zero_u64(queue, 1, s);
+      if (e == hipSuccess) e = launch_walk_lane(a, (int)grid, block, s);
+    } else {
+      const int64_t grid = (total + block - 1) / block;
+      if (grid > 0x7FFFFFFF) return fail(MPWOS_EINVAL, "too many walks for one launch");
+      e = launch_walk_lane(a, (int)grid, block, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "walk kernel launch");
+    return MPWOS_OK;
+  }
+  if (a.kind == MPWOS_POINT_CLOUD) return launch_cloud_walks(a, o, s, queue);
+  return launch_group_walks(a, o, s, queue);
+}
+
+}  // namespace mpwos
+
+extern "C" mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_fn* f, const mpwos_fn* g, double c,
+                                    const double* queries, int64_t n_queries, int64_t n_walks, double eps,
+                                    uint64_t seed, const mpwos_options* opt, double* u_out, double* stderr_out,
+                                    mpwos_stats* stats) {
+  g_last_error.clear();
+  const auto t0 = std::chrono::steady_clock::now();
+  mpwos_options o;
+  if (opt) o = *opt;
+  else mpwos_options_default(&o);
+  if (!queries || !u_out) return fail(MPWOS_EINVAL, "queries and u_out must not be NULL");
+  std::lock_guard<std::mutex> guard(g_ctx.lock);
+  mpwos_status st = context_init(g_ctx);
+  if (st) return st;
+  WalkArgs a;
+  st = prepare_solve(manifold, f, g, c, n_queries, n_walks, eps, seed, o, a);
+  if (st) return st;
+  const mpwos_manifold_desc& d = manifold->desc;
+  const int n = d.n;
+  hipStream_t s = o.stream ? (hipStream_t)o.stream : g_ctx.stream;
+
+  // host view of the queries for validation
+  std::vector<double> hq;
+  const double* qhost = queries;
+  if (o.device_io) {
+    hq.resize((size_t)n_queries * n);
+    HIP_TRY(hipMemcpyAsync(hq.data(), queries, hq.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    qhost = hq.data();
+  }
+  if (d.kind != MPWOS_POINT_CLOUD) {
+    for (int64_t q = 0; q < n_queries; ++q)
+      if (!query_on_manifold(d, qhost + q * n))
+        return fail(MPWOS_EOFFMANIFOLD, "query " + std::to_string(q) + " is not on the manifold");
+  }
+
+  // TABLE_S1 values to the device
+  DevBuf& tmp = g_ctx.tmp;
+  if (f->kind == MPWOS_FN_TABLE_S1) {
+    st = ensure(tmp, (size_t)f->n_values * sizeof(double));
+    if (st) return st;
+    HIP_TRY(hipMemcpyAsync(tmp.p, f->values, (size_t)f->n_values * sizeof(double), hipMemcpyHostToDevice, s));
+    a.f.values = (const double*)tmp.p;
+  }
+
+  // batches of queries, bounded by the per-walk buffer size
+  const int64_t walk_budget = (int64_t)1 << 27;
+  int64_t qb = std::max<int64_t>(1, walk_budget / n_walks);
+  qb = std::min(qb, n_queries);
+  const bool user_walk_dev = o.device_io && o.walk_S && o.walk_K;
+  if (user_walk_dev) qb = n_queries;
+
+  st = ensure(g_ctx.queries, (size_t)n_queries * n * sizeof(double));
+  if (!st) st = ensure(g_ctx.u, (size_t)n_queries * sizeof(double));
+  if (!st) st = ensure(g_ctx.se, (size_t)n_queries * sizeof(double));
+  if (!st) st = ensure(g_ctx.stats, 8 * sizeof(unsigned long long));
+  if (!st && !user_walk_dev) st = ensure(g_ctx.walkS, (size_t)qb * n_walks * sizeof(double));
+  if (!st && !user_walk_dev) st = ensure(g_ctx.walkK, (size_t)qb * n_walks * sizeof(int32_t));
+  if (st) return st;
+  double* dq = (double*)g_ctx.queries.p;
+  if (o.device_io) HIP_TRY(hipMemcpyAsync(dq, queries, (size_t)n_queries * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else HIP_TRY(hipMemcpyAsync(dq, queries, (size_t)n_queries * n * sizeof(double), hipMemcpyHostToDevice, s));
+  unsigned long long* dstat = (unsigned long long*)g_ctx.stats.p;
+  HIP_TRY(launch_zero_u64(dstat, 8, s));
+  double* du = (double*)g_ctx.u.p;
+  double* dse = (double*)g_ctx.se.p;
+  float kernel_ms = 0.f, reduce_ms = 0.f;
+  for (int64_t q0 = 0; q0 < n_queries; q0 += qb) {
+    const int64_t nb = std::min(qb, n_queries - q0);
+    double* wS = user_walk_dev ? o.walk_S : (double*)g_ctx.walkS.p;
+    int32_t* wK = user_walk_dev ? o.walk_K : (int32_t*)g_ctx.walkK.p;
+    a.queries = dq + q0 * n;
+    a.nq = nb;
+    a.nw = n_walks;
+    a.q_offset = q0;
+    a.walk_S = wS;
+    a.walk_K = wK;
+    HIP_TRY(hipEventRecord(g_ctx.ev[0], s));
+    st = launch_walks(a, o, s, dstat + 4);
+    if (st) return st;
+    HIP_TRY(hipEventRecord(g_ctx.ev[1], s));
+    HIP_TRY(launch_reduce(wS, wK, nb, n_walks, o.max_steps, du + q0, dse + q0, dstat + 0, (int32_t*)(dstat + 1),
+                          dstat + 2, s));
+    HIP_TRY(hipEventRecord(g_ctx.ev[2], s));
+    if (!o.device_io && o.walk_S)
+      HIP_TRY(hipMemcpyAsync(o.walk_S + q0 * n_walks, wS, (size_t)nb * n_walks * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (!o.device_io && o.walk_K)
+      HIP_TRY(hipMemcpyAsync(o.walk_K + q0 * n_walks, wK, (size_t)nb * n_walks * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventSynchronize(g_ctx.ev[2]));
+    float ms1 = 0.f, ms2 = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms1, g_ctx.ev[0], g_ctx.ev[1]));
+    HIP_TRY(hipEventElapsedTime(&ms2, g_ctx.ev[1], g_ctx.ev[2]));
+    kernel_ms += ms1;
+    reduce_ms += ms2;
+  }
+  const hipMemcpyKind dk = o.device_io ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  HIP_TRY(hipMemcpyAsync(u_out, du, (size_t)n_queries * sizeof(double), dk, s));
+  if (stderr_out) HIP_TRY(hipMemcpyAsync(stderr_out, dse, (size_t)n_queries * sizeof(double), dk, s));
+  unsigned long long hs[8];
+  HIP_TRY(hipMemcpyAsync(hs, dstat, sizeof(hs), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t ksum = (int64_t)hs[0];
+  const int32_t kmax = (int32_t)(uint32_t)hs[1];
+  const int64_t ntr = (int64_t)hs[2];
+  if (stats) {
+    stats->walk_steps = ksum;
+    stats->truncated = ntr;
+    stats->k_max = kmax;
+    stats->k_mean = (double)ksum / ((double)n_queries * (double)n_walks);
+    stats->kernel_ms = kernel_ms;
+    stats->reduce_ms = reduce_ms;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return ntr ? MPWOS_WTRUNC : MPWOS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// inspection entry points
+// ---------------------------------------------------------------------------
+extern "C" mpwos_status mpwos_debug_cp(const mpwos_manifold* m, const double* x, int64_t n_points, int32_t precision,
+                                       double* y) {
+  g_last_error.clear();
+  if (!m || !x || !y || n_points < 1) return fail(MPWOS_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> guard(g_ctx.lock);
+  mpwos_status st = context_init(g_ctx);
+  if (st) return st;
+  WalkArgs a;
+  memset(&a, 0, sizeof(a));
+  a.kind = m->desc.kind;
+  a.n = m->desc.n;
+  for (int i = 0; i < 4; ++i) a.p[i] = m->desc.p[i];
+  a.precision = precision ? 1 : 0;
+  mpwos_options o;
+  mpwos_options_default(&o);
+  o.precision = a.precision;
+  if (m->cloud) cloud_fill_args(m->cloud, o, a);
+  const size_t bytes = (size_t)n_points * a.n * sizeof(double);
+  st = ensure(g_ctx.tmp, 2 * bytes);
+  if (st) return st;
+  hipStream_t s = g_ctx.stream;
+  double* dx = (double*)g_ctx.tmp.p;
+  double* dy = dx + (size_t)n_points * a.n;
+  HIP_TRY(hipMemcpyAsync(dx, x, bytes, hipMemcpyHostToDevice, s));
+  hipError_t e = (a.kind == MPWOS_POINT_CLOUD) ? launch_cloud_cp(a, dx, dy, n_points, s)
+                                               : launch_cp_points(a, dx, dy, n_points, s);
+  if (e != hipSuccess) return hip_fail(e, "cp kernel");
+  HIP_TRY(hipMemcpyAsync(y, dy, bytes, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MPWOS_OK;
+}
+
+extern "C" mpwos_status mpwos_debug_radial_inv(int32_t n, double X, const double* u, int64_t count, int32_t precision,
+                                               double* s_out) {
+  g_last_error.clear();
+  if (n < 2 || n > 4096 || !(X > 0) || !u || !s_out || count < 1) return fail(MPWOS_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> guard(g_ctx.lock);
+  mpwos_status st = context_init(g_ctx);
+  if (st) return st;
+  WalkArgs a;
+  memset(&a, 0, sizeof(a));
+  HostLaw h;
+  host_law(n, h);
+  int js, jd;
+  if (!law_terms(h, X * X, js, jd)) return fail(MPWOS_EINVAL, "X beyond the series radial law");
+  fill_law(h, js, jd, a.law);
+  a.const_r = 1;
+  a.X0 = X;
+  fill_fixed(h, a.law, X, a.fixed);
+  st = get_table(h, 1, X * X, a.tab);
+  if (st) return st;
+  st = ensure(g_ctx.tmp, 2 * (size_t)count * sizeof(double));
+  if (st) return st;
+  hipStream_t s = g_ctx.stream;
+  double* du = (double*)g_ctx.tmp.p;
+  double* ds = du + count;
+  HIP_TRY(hipMemcpyAsync(du, u, (size_t)count * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_radial_inv(a, du, ds, count, precision ? 0 : 1, s));
+  HIP_TRY(hipMemcpyAsync(s_out, ds, (size_t)count * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MPWOS_OK;
+}
+
+extern "C" mpwos_status mpwos_debug_philox(const uint32_t ctr[4], uint64_t seed, int64_t count, uint32_t* out) {
+  g_last_error.clear();
+  if (!ctr || !out || count < 1) return fail(MPWOS_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> guard(g_ctx.lock);
+  mpwos_status st = context_init(g_ctx);
+  if (st) return st;
+  st = ensure(g_ctx.tmp, (size_t)count * 16);
+  if (st) return st;
+  hipStream_t s = g_ctx.stream;
+  HIP_TRY(launch_philox(ctr, seed, (uint32_t*)g_ctx.tmp.p, count, s));
+  HIP_TRY(hipMemcpyAsync(out, g_ctx.tmp.p, (size_t)count * 16, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MPWOS_OK;
+}
+
+extern "C" mpwos_status mpwos_copy_probe(int64_t bytes, int32_t reps, double* ms) {
+  g_last_error.clear();
+  if (bytes < 16 || reps < 1 || !ms) return fail(MPWOS_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> guard(g_ctx.lock);
+  mpwos_status st = context_init(g_ctx);
+  if (st) return st;
+  void *src = nullptr, *dst = nullptr;
+  HIP_TRY(hipMalloc(&src, (size_t)bytes));
+  HIP_TRY(hipMalloc(&dst, (size_t)bytes));
+  hipStream_t s = g_ctx.stream;
+  HIP_TRY(hipMemsetAsync(src, 1, (size_t)bytes, s));
+  HIP_TRY(launch_copy(src, dst, bytes, s));
+  HIP_TRY(hipEventRecord(g_ctx.ev[0], s));
+  for (int r = 0; r < reps; ++r) HIP_TRY(launch_copy(src, dst, bytes, s));
+  HIP_TRY(hipEventRecord(g_ctx.ev[1], s));
+  HIP_TRY(hipEventSynchronize(g_ctx.ev[1]));
+  float t = 0.f;
+  HIP_TRY(hipEventElapsedTime(&t, g_ctx.ev[0], g_ctx.ev[1]));
+  *ms = t / reps;
+  (void)hipFree(src);
+  (void)hipFree(dst);
+  return MPWOS_OK;
+}

@@ -1,0 +1,458 @@
+// One lane per walk (n <= 3): the whole walk state (Y, W, S, k) lives in
+// registers; each iteration of the loop is one step of Algorithm 1.
+//
+// Two launch forms share the step code:
+//   plain      - one walk per lane, grid covers every walk, one launch per solve;
+//   persistent - a grid sized to the device; a lane whose walk stops takes the
+//                next walk index from a per-wave chunk of a global queue, so
+//                uneven walk lengths (boundary problems) keep lanes busy.
+#include <hip/hip_runtime.h>
+
+#include "kernel_args.h"
+#include "mpwos_dev.h"
+
+namespace mpwos {
+
+template <class T, int N>
+struct LaneState {
+  T Y[N];
+  double W, S, C;
+  uint32_t k, q, w;
+  int64_t idx;
+};
+
+// ---- geometry of the sphere cap (n <= 3) ----------------------------------
+// Gamma = S_R cap {x_n = h}; y_Gamma is the nearest point of Gamma; the
+// effective distance is the distance to the normal disk of radius ell at
+// y_Gamma (eq. extended_boundary_disk, eq. delta_Gamma_general).
+template <class T, int N>
+__device__ __forceinline__ void cap_gamma_point(const WalkArgs& a, const T* y, T* yg) {
+  const T R = (T)a.p[0], h = (T)a.p[1];
+  const T rg = sqrt_(R * R - h * h);
+  T s = (T)0;
+  for (int i = 0; i < N - 1; ++i) s += y[i] * y[i];
+  const T is = (T)1 / sqrt_(s);
+  for (int i = 0; i < N - 1; ++i) yg[i] = rg * y[i] * is;
+  yg[N - 1] = h;
+}
+
+template <class T, int N>
+__device__ __forceinline__ T cap_delta(const WalkArgs& a, const T* y) {
+  T yg[N], rG[N], nr[N];
+  cap_gamma_point<T, N>(a, y, yg);
+  const T R = (T)a.p[0];
+  T rn = (T)0;
+  for (int i = 0; i < N; ++i) {
+    rG[i] = yg[i] - y[i];
+    nr[i] = yg[i] / R;
+    rn += rG[i] * nr[i];
+  }
+  T rt2 = (T)0;
+  for (int i = 0; i < N; ++i) {
+    const T v = rG[i] - rn * nr[i];
+    rt2 += v * v;
+  }
+  const T ell = (T)(a.c_kappa / (1.0 + 1.0 / a.p[0]));
+  T tn = abs_(rn) - ell;
+  tn = tn > (T)0 ? tn : (T)0;
+  return sqrt_(rt2 + tn * tn);
+}
+
+template <class T, int N>
+__device__ __forceinline__ bool cap_in_layer(const WalkArgs& a, const T* y) {
+  if ((double)y[N - 1] <= a.p[1]) return true;
+  return (double)cap_delta<T, N>(a, y) < a.eps;
+}
+
+// ---- closest point ----------------------------------------------------------
+template <class T, int N, int KIND>
+__device__ __forceinline__ void closest_point(const WalkArgs& a, const T* x, T* y) {
+  if constexpr (KIND == kTorus) {
+    torus_cp_newton<T>((T)a.p[0], (T)a.p[1], x, y, sizeof(T) == 8 ? 6 : 3);
+  } else {
+    T s = (T)0;
+    for (int i = 0; i < N; ++i) s += x[i] * x[i];
+    const T f = (T)a.p[0] * rsqrt_(s);
+    for (int i = 0; i < N; ++i) y[i] = x[i] * f;
+  }
+}
+
+// ---- one walk ---------------------------------------------------------------
+template <class T, int N, int KIND>
+__device__ __forceinline__ bool walk_init(const WalkArgs& a, int64_t idx, LaneState<T, N>& st) {
+  st.idx = idx;
+  const int64_t ql = idx / a.nw;
+  st.q = (uint32_t)(ql + a.q_offset);
+  st.w = (uint32_t)(idx - ql * a.nw);
+  const double* y0 = a.queries + ql * N;
+  for (int i = 0; i < N; ++i) st.Y[i] = (T)y0[i];
+  st.W = 1.0;
+  st.S = 0.0;
+  st.C = 0.0;
+  st.k = 0;
+  if constexpr (KIND == kCap) {
+    if (cap_in_layer<T, N>(a, st.Y)) {
+      T yg[N];
+      cap_gamma_point<T, N>(a, st.Y, yg);
+      st.S = boundary_value<T>(a, yg, N);
+      return true;
+    }
+  }
+  return false;
+}
+
+template <class T, int N>
+__device__ __forceinline__ void walk_store(const WalkArgs& a, const LaneState<T, N>& st) {
+  a.walk_S[st.idx] = st.S + st.C;
+  a.walk_K[st.idx] = (int32_t)st.k;
+}
+
+template <class T, int N, int KIND>
+__device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st) {
+  const Stream rs{st.q, st.w, (uint32_t)a.seed, (uint32_t)(a.seed >> 32)};
+  // (i) radius r(Y) = theta min(delta_Gamma, rho_geo) and the weights
+  double r, c, om, X2, norm = 0.0;
+  if constexpr (KIND == kCap) {
+    const double dg = (double)cap_delta<T, N>(a, st.Y);
+    const double rg = a.c_kappa / (1.0 + 1.0 / a.p[0]);
+    r = a.theta * (dg < rg ? dg : rg);
+    weights(a, r, c, om);
+    X2 = a.sigma * r * r;
+    if constexpr (sizeof(T) == 8) norm = radial_norm(a.law, X2);
+  } else {
+    r = a.r0;
+    c = a.c0;
+    om = a.om0;
+    X2 = a.X0 * a.X0;
+  }
+  const T rT = (T)r;
+  // (ii) Theta = Y + r g/|g| and Y' = cp(Theta)
+  T Yn[N];
+  {
+    const uint4 b = rs.block(st.k, 0, 0);
+    T g[4];
+    box_muller(b.x, b.y, g[0], g[1]);
+    if (N > 2) box_muller(b.z, b.w, g[2], g[3]);
+    T gg = (T)0;
+    for (int i = 0; i < N; ++i) gg += g[i] * g[i];
+    const T ig = rsqrt_(gg);
+    T Th[N];
+    for (int i = 0; i < N; ++i) Th[i] = st.Y[i] + rT * (g[i] * ig);
+    closest_point<T, N, KIND>(a, Th, Yn);
+  }
+  // Green samples Z ~ rho(Y, .): radius from the radial law, direction uniform
+  T Fsum = (T)0;
+  for (int l = 1; l <= a.n_v; ++l) {
+    const uint4 b = rs.block(st.k, (uint32_t)l, 0);
+    T g[4];
+    uint32_t ux;
+    box_muller(b.x, b.y, g[0], g[1]);
+    if (N > 2) {
+      box_muller(b.z, b.w, g[2], g[3]);
+      ux = rs.block(st.k, (uint32_t)l, 1).x;
+    } else {
+      ux = b.z;
+    }
+    T s;
+    if constexpr (sizeof(T) == 8) s = radial_inv64(a, u01_64(ux), X2, norm);
+    else s = radial_inv32(a, u01_32(ux), (float)X2);
+    T gg = (T)0;
+    for (int i = 0; i < N; ++i) gg += g[i] * g[i];
+    const T ig = rsqrt_(gg);
+    const T t = rT * s;
+    T Z[N], Zc[N];
+    for (int i = 0; i < N; ++i) Z[i] = st.Y[i] + t * (g[i] * ig);
+    closest_point<T, N, KIND>(a, Z, Zc);
+    Fsum += source<T>(a, Z, Zc, N);
+  }
+  const double F = (double)Fsum / (double)a.n_v;
+  kahan_add(st.S, st.C, (st.W * om) * F);
+  st.W = st.W * c;
+  for (int i = 0; i < N; ++i) st.Y[i] = Yn[i];
+  st.k += 1;
+  if constexpr (KIND == kCap) {
+    if (cap_in_layer<T, N>(a, st.Y)) {
+      T yg[N];
+      cap_gamma_point<T, N>(a, st.Y, yg);
+      kahan_add(st.S, st.C, st.W * boundary_value<T>(a, yg, N));
+      return true;
+    }
+  } else {
+    if (st.W < a.tau_w) return true;
+  }
+  return (int64_t)st.k >= a.max_steps;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+template <class T, int N, int KIND>
+__global__ __launch_bounds__(256) void walk_lane_kernel(WalkArgs a) {
+  const int64_t total = a.nq * a.nw;
+  LaneState<T, N> st;
+  if (!a.persistent) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    if (walk_init<T, N, KIND>(a, idx, st)) {
+      walk_store(a, st);
+      return;
+    }
+    while (!walk_step<T, N, KIND>(a, st)) {
+    }
+    walk_store(a, st);
+    return;
+  }
+  // persistent form: per-wave chunks of the global queue
+  const uint32_t lane = lane_id();
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  bool active = false;
+  bool exhausted = false;
+  int64_t next = 0, end = 0;
+  for (;;) {
+    for (;;) {
+      const uint64_t want = __ballot(!active);
+      if (want == 0 || exhausted) break;
+      if (next >= end) {
+        const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)want) - 1);
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)a.chunk);
+        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
+        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
+        const int64_t b = (int64_t)(((uint64_t)hi << 32) | lo);
+        if (b >= total) {
+          exhausted = true;
+          break;
+        }
+        next = b;
+        end = b + a.chunk < total ? b + a.chunk : total;
+      }
+      const int rank = __popcll(want & lt_mask);
+      const int64_t avail = end - next;
+      const int64_t cnt = (int64_t)__popcll(want) < avail ? (int64_t)__popcll(want) : avail;
+      if (!active && rank < cnt) {
+        if (walk_init<T, N, KIND>(a, next + rank, st)) walk_store(a, st);
+        else active = true;
+      }
+      next += cnt;
+    }
+    if (__ballot(active) == 0) break;
+    if (active) {
+      if (walk_step<T, N, KIND>(a, st)) {
+        walk_store(a, st);
+        active = false;
+      }
+    }
+  }
+}
+
+// ---- per-query estimator (eq. mc_estimator) --------------------------------
+// One 256-thread block per query: compensated sums per thread over a fixed
+// stride, then a fixed-order tree, so the result does not depend on timing.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+__global__ __launch_bounds__(256) void reduce_queries_kernel(const double* __restrict__ walk_S,
+                                                             const int32_t* __restrict__ walk_K, int64_t nq,
+                                                             int64_t nw, int64_t max_steps, double* u_out,
+                                                             double* se_out, unsigned long long* ksum,
+                                                             int32_t* kmax, unsigned long long* ntrunc) {
+  __shared__ double sh_s[256], sh_c[256];
+  __shared__ long long sh_k[256];
+  __shared__ int sh_m[256], sh_t[256];
+  const int t = threadIdx.x;
+  for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
+    const double* S = walk_S + q * nw;
+    const int32_t* K = walk_K + q * nw;
+    double s = 0.0, c = 0.0;
+    long long ks = 0;
+    int km = 0, tr = 0;
+    for (int64_t w = t; w < nw; w += 256) {
+      kahan_add(s, c, S[w]);
+      const int kk = K[w];
+      ks += kk;
+      km = kk > km ? kk : km;
+      tr += (kk >= max_steps) ? 1 : 0;
+    }
+    sh_s[t] = s;
+    sh_c[t] = c;
+    sh_k[t] = ks;
+    sh_m[t] = km;
+    sh_t[t] = tr;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o) {
+        double ss, ee;
+        two_sum(sh_s[t], sh_s[t + o], ss, ee);
+        sh_s[t] = ss;
+        sh_c[t] = sh_c[t] + sh_c[t + o] + ee;
+        sh_k[t] += sh_k[t + o];
+        sh_m[t] = sh_m[t] > sh_m[t + o] ? sh_m[t] : sh_m[t + o];
+        sh_t[t] += sh_t[t + o];
+      }
+      __syncthreads();
+    }
+    const double mean = (sh_s[0] + sh_c[0]) / (double)nw;
+    if (t == 0) {
+      atomicAdd(ksum, (unsigned long long)sh_k[0]);
+      atomicMax(kmax, sh_m[0]);
+      if (sh_t[0]) atomicAdd(ntrunc, (unsigned long long)sh_t[0]);
+    }
+    __syncthreads();
+    double v = 0.0, vc = 0.0;
+    for (int64_t w = t; w < nw; w += 256) {
+      const double d = S[w] - mean;
+      kahan_add(v, vc, d * d);
+    }
+    sh_s[t] = v + vc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o) sh_s[t] += sh_s[t + o];
+      __syncthreads();
+    }
+    if (t == 0) {
+      u_out[q] = mean;
+      if (se_out) se_out[q] = nw > 1 ? sqrt(sh_s[0] / (double)(nw - 1) / (double)nw) : 0.0;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// ---- inspection kernels -------------------------------------------------------
+template <class T, int N, int KIND>
+__global__ void cp_points_kernel(WalkArgs a, const double* x, double* y, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  T xi[N], yi[N];
+  for (int d = 0; d < N; ++d) xi[d] = (T)x[i * N + d];
+  closest_point<T, N, KIND>(a, xi, yi);
+  for (int d = 0; d < N; ++d) y[i * N + d] = (double)yi[d];
+}
+
+__global__ void radial_inv_kernel(WalkArgs a, const double* u, double* s, int64_t m, int fp64) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double X2 = a.X0 * a.X0;
+  if (fp64) s[i] = radial_inv64(a, u[i], X2, a.fixed.norm);
+  else s[i] = (double)radial_inv32(a, (float)u[i], (float)X2);
+}
+
+__global__ void philox_kernel(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                              uint32_t* out, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint4 v = philox(c0 + (uint32_t)i, c1, c2, c3, k0, k1);
+  out[4 * i + 0] = v.x;
+  out[4 * i + 1] = v.y;
+  out[4 * i + 2] = v.z;
+  out[4 * i + 3] = v.w;
+}
+
+// Plain streaming copy, 16 B per lane per iteration: the reference kernel for
+// calibrating HBM byte counters.
+__global__ __launch_bounds__(256) void copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t m) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+#define MPWOS_LANE_DISPATCH(FN, ...)                                                   \
+  do {                                                                               \
+    if (fp64) {                                                                      \
+      if (kind == kSphere && n == 2) return FN<double, 2, kSphere>(__VA_ARGS__);     \
+      if (kind == kSphere && n == 3) return FN<double, 3, kSphere>(__VA_ARGS__);     \
+      if (kind == kCap && n == 3) return FN<double, 3, kCap>(__VA_ARGS__);           \
+      if (kind == kCap && n == 2) return FN<double, 2, kCap>(__VA_ARGS__);           \
+      if (kind == kTorus && n == 3) return FN<double, 3, kTorus>(__VA_ARGS__);       \
+    } else {                                                                         \
+      if (kind == kSphere && n == 2) return FN<float, 2, kSphere>(__VA_ARGS__);      \
+      if (kind == kSphere && n == 3) return FN<float, 3, kSphere>(__VA_ARGS__);      \
+      if (kind == kCap && n == 3) return FN<float, 3, kCap>(__VA_ARGS__);            \
+      if (kind == kCap && n == 2) return FN<float, 2, kCap>(__VA_ARGS__);            \
+      if (kind == kTorus && n == 3) return FN<float, 3, kTorus>(__VA_ARGS__);        \
+    }                                                                                \
+  } while (0)
+
+// ---- host launchers -----------------------------------------------------------
+template <class T, int N, int KIND>
+static hipError_t launch_cp_t(const WalkArgs& a, const double* x, double* y, int64_t m, hipStream_t s) {
+  hipLaunchKernelGGL((cp_points_kernel<T, N, KIND>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a, x, y, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_cp_points(const WalkArgs& a, const double* x, double* y, int64_t m, hipStream_t s) {
+  const bool fp64 = a.precision == 0;
+  const int kind = a.kind, n = a.n;
+  MPWOS_LANE_DISPATCH(launch_cp_t, a, x, y, m, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_radial_inv(const WalkArgs& a, const double* u, double* s_out, int64_t m, int fp64,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(radial_inv_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a, u, s_out, m, fp64);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox(const uint32_t* c, uint64_t seed, uint32_t* out, int64_t m, hipStream_t s) {
+  hipLaunchKernelGGL(philox_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, c[0], c[1], c[2], c[3],
+                     (uint32_t)seed, (uint32_t)(seed >> 32), out, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s) {
+  const int64_t m = bytes / 16;
+  hipLaunchKernelGGL(copy_kernel, dim3(2048), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, m);
+  return hipGetLastError();
+}
+
+template <class T, int N, int KIND>
+static hipError_t launch_lane_t(const WalkArgs& a, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL((walk_lane_kernel<T, N, KIND>), dim3(grid), dim3(block), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class T, int N, int KIND>
+static int occupancy_t(int block) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_lane_kernel<T, N, KIND>, block, 0) != hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+
+hipError_t launch_walk_lane(const WalkArgs& a, int grid, int block, hipStream_t s) {
+  const bool fp64 = a.precision == 0;
+  const int kind = a.kind, n = a.n;
+  MPWOS_LANE_DISPATCH(launch_lane_t, a, grid, block, s);
+  return hipErrorInvalidValue;
+}
+
+int lane_occupancy(int kind, int n, bool fp64, int block) {
+  MPWOS_LANE_DISPATCH(occupancy_t, block);
+  return 1;
+}
+
+bool lane_supported(int kind, int n) {
+  return (n == 2 || n == 3) && (kind == kSphere || kind == kCap || (kind == kTorus && n == 3));
+}
+
+hipError_t launch_reduce(const double* walk_S, const int32_t* walk_K, int64_t nq, int64_t nw, int64_t max_steps,
+                         double* u, double* se, unsigned long long* ksum, int32_t* kmax,
+                         unsigned long long* ntrunc, hipStream_t s) {
+  const int64_t g = nq < 65536 ? nq : 65536;
+  hipLaunchKernelGGL(reduce_queries_kernel, dim3((unsigned)g), dim3(256), 0, s, walk_S, walk_K, nq, nw, max_steps,
+                     u, se, ksum, kmax, ntrunc);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace mpwos

@@ -1,0 +1,223 @@
+"""GPU parity: the gfx950 FP64 walk against the FP64 oracle, walk by walk, on
+the same Philox stream; the FP32 mixed mode against the closed form; launch
+forms, edge cases and errors of mpwos_solve.  Every call goes through the C ABI.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_21883_amd import inputs, mpwos
+from tests.gpu_util import announce, compare_walks
+
+pytestmark = pytest.mark.gpu
+
+
+def run_both(prob, Q, nw, seed, **opt):
+    announce(f"{prob['manifold']} n={prob['n']} nq={len(Q)} nw={nw} opt={opt}")
+    g = mpwos.solve(prob, Q, nw, seed, walk_outputs=True, **opt)
+    o = oracle.solve(prob, Q, nw, seed)
+    return g, o
+
+
+CASES = {
+    "circle": (inputs.circle_problem(), inputs.circle_queries(64), 61),
+    "sphere": (inputs.sphere_problem(), inputs.sphere_uniform(37, 3, seed=1), 53),
+    "cap": (inputs.cap_problem(), inputs.cap_uniform(48, 3, 0.0, seed=1), 77),
+    "torus": (inputs.torus_problem(), inputs.torus_area_uniform(16, seed=1), 24),
+    "hyper10": (inputs.hypersphere_problem(10), inputs.hypersphere_queries(16, 10, seed=1), 33),
+    "legendre": (inputs.problem(manifold="sphere", n=3, p=[1.0], sigma=1.0,
+                                f=dict(kind="legendre", coef=[0.0, 3.0, 0.0, 2.6, 0.0, 3.1])),
+                 inputs.sphere_uniform(20, 3, seed=4), 40),
+    "circle_R": (inputs.problem(manifold="sphere", n=2, p=[1.7], sigma=1.3,
+                                f=dict(kind="circle_mode", idx=[2], coef=[0.4, -1.1])),
+                 1.7 * inputs.circle_queries(24), 45),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_walks_match_oracle(name):
+    prob, Q, nw = CASES[name]
+    g, o = run_both(prob, Q, nw, seed=7)
+    compare_walks(g, o, prob)
+    np.testing.assert_allclose(g["u"], o["u"], rtol=1e-10, atol=1e-12)
+    assert g["stats"]["walk_steps"] == int(o["walk_K"].sum())
+
+
+def test_fp64_hypersphere_n100_matches_oracle():
+    prob = dict(inputs.hypersphere_problem(100), tau_w=1e-3)
+    Q = inputs.hypersphere_queries(6, 100, seed=2)
+    g, o = run_both(prob, Q, 8, seed=3)
+    compare_walks(g, o, prob)
+
+
+def test_fp64_hypersphere_n1000_matches_oracle():
+    prob = dict(inputs.hypersphere_problem(1000), tau_w=0.5)
+    Q = inputs.hypersphere_queries(4, 1000, seed=2)
+    g, o = run_both(prob, Q, 4, seed=3)
+    compare_walks(g, o, prob)
+
+
+def test_fp64_odd_dimension_and_lane_groups():
+    prob = dict(inputs.hypersphere_problem(7), tau_w=1e-4)
+    Q = inputs.sphere_uniform(9, 7, seed=5)
+    for lanes in (4, 8):
+        g, o = run_both(prob, Q, 19, seed=11, lanes_per_walk=lanes)
+        compare_walks(g, o, prob)
+
+
+def test_fp64_multiple_green_samples():
+    prob = dict(inputs.sphere_problem(), n_v=3)
+    Q = inputs.sphere_uniform(8, 3, seed=6)
+    g, o = run_both(prob, Q, 17, seed=2)
+    compare_walks(g, o, prob)
+    prob = dict(inputs.cap_problem(), n_v=2)
+    Q = inputs.cap_uniform(8, 3, 0.0, seed=6)
+    g, o = run_both(prob, Q, 17, seed=2)
+    compare_walks(g, o, prob)
+
+
+def test_fp64_without_compensation():
+    prob = dict(inputs.sphere_problem(), compensation="none")
+    Q = inputs.sphere_uniform(8, 3, seed=6)
+    g, o = run_both(prob, Q, 31, seed=4)
+    compare_walks(g, o, prob)
+
+
+def test_fp64_table_source_circle():
+    M = 256
+    th = 2 * np.pi * np.arange(M) / M
+    f = np.exp(np.cos(th))
+    us = f / 2.0
+    prob = inputs.problem(manifold="sphere", n=2, p=[1.0], sigma=1.0,
+                          f=dict(kind="table_s1", values=np.concatenate([f, us])))
+    Q = inputs.circle_queries(12)
+    g, o = run_both(prob, Q, 21, seed=9)
+    compare_walks(g, o, prob)
+
+
+def test_persistent_and_block_size_do_not_change_results():
+    for name in ("sphere", "cap", "torus"):
+        prob, Q, nw = CASES[name]
+        for prec in ("fp64", "fp32"):
+            announce(f"invariance {name} {prec}")
+            base = mpwos.solve(prob, Q, nw, 5, walk_outputs=True, precision=prec)
+            for kw in (dict(persistent=1), dict(block_size=64), dict(block_size=128, persistent=1)):
+                other = mpwos.solve(prob, Q, nw, 5, walk_outputs=True, precision=prec, **kw)
+                assert np.array_equal(base["walk_S"], other["walk_S"]), (name, prec, kw)
+                assert np.array_equal(base["walk_K"], other["walk_K"])
+                assert np.array_equal(base["u"], other["u"])
+
+
+def test_group_kernel_persistent_matches_plain():
+    prob = dict(inputs.hypersphere_problem(100), tau_w=1e-3)
+    Q = inputs.hypersphere_queries(5, 100, seed=2)
+    for prec in ("fp64", "fp32"):
+        announce(f"group invariance {prec}")
+        a = mpwos.solve(prob, Q, 13, 5, walk_outputs=True, precision=prec)
+        b = mpwos.solve(prob, Q, 13, 5, walk_outputs=True, precision=prec, persistent=1, block_size=128)
+        assert np.array_equal(a["walk_S"], b["walk_S"])
+
+
+def test_fp32_walks_track_fp64_walks():
+    # the mixed mode draws the same Philox words (23-bit uniforms), so walk by
+    # walk it stays close to the FP64 walk
+    for name in ("sphere", "torus", "hyper10"):
+        prob, Q, nw = CASES[name]
+        announce(f"fp32 tracking {name}")
+        a = mpwos.solve(prob, Q, nw, 7, walk_outputs=True, precision="fp64")
+        b = mpwos.solve(prob, Q, nw, 7, walk_outputs=True, precision="fp32")
+        assert np.array_equal(a["walk_K"], b["walk_K"])
+        assert np.max(np.abs(a["walk_S"] - b["walk_S"])) < 1e-3 * (1 + np.abs(a["walk_S"]).max())
+
+
+@pytest.mark.parametrize("name", ["sphere", "cap"])
+def test_fp32_rmse_within_5_percent_of_fp64_full_size(name):
+    prob, Q, nw = inputs.config(name)
+    exact = inputs.exact_u(prob, Q)
+    announce(f"full-size rmse {name} fp64")
+    a = mpwos.solve(prob, Q, nw, 0, precision="fp64")
+    announce(f"full-size rmse {name} fp32 persistent")
+    b = mpwos.solve(prob, Q, nw, 0, precision="fp32", persistent=1)
+    ra, rb = inputs.rmse(a["u"], exact), inputs.rmse(b["u"], exact)
+    assert rb <= 1.05 * ra, (ra, rb)
+    # both are unbiased to the Monte Carlo error
+    assert ra < 4 * np.sqrt(np.mean(a["stderr"] ** 2))
+
+
+def test_full_size_sampled_walks_match_oracle():
+    # the launch configuration the benchmark times (FP64 plain, full config),
+    # checked on sampled walks that the oracle recomputes one by one
+    for name in ("sphere", "cap"):
+        prob, Q, nw = inputs.config(name)
+        announce(f"full-size sampled parity {name}")
+        g = mpwos.solve(prob, Q, nw, 0, walk_outputs=True, precision="fp64")
+        rng = np.random.default_rng(0)
+        P = oracle.Problem(prob)
+        picks = [(int(rng.integers(len(Q))), int(rng.integers(nw))) for _ in range(48)]
+        picks += [(len(Q) - 1, nw - 1), (0, 0)]
+        bad = 0
+        for q, w in picks:
+            S, K, _ = oracle.walk(P, Q[q], q, w, 0)
+            if not (K == g["walk_K"][q, w] and abs(S - g["walk_S"][q, w]) <= 1e-12 * 10):
+                bad += 1
+        assert bad == 0
+
+
+def test_edge_sizes():
+    prob = inputs.sphere_problem()
+    Q = inputs.sphere_uniform(1, 3, seed=1)
+    g, o = run_both(prob, Q, 1, seed=1)
+    compare_walks(g, o, prob)
+    assert g["stderr"][0] == 0.0
+
+
+def test_query_in_boundary_layer_and_truncation():
+    prob = inputs.cap_problem(eps=1e-3)
+    y = np.array([[math.cos(1e-4) * 0.6, math.cos(1e-4) * 0.8, math.sin(1e-4)]])
+    g = mpwos.solve(prob, y, 8, 1, walk_outputs=True)
+    assert np.all(g["walk_K"] == 0)
+    np.testing.assert_allclose(g["walk_S"], 0.48 * math.cos(1e-4) ** 2 / math.cos(1e-4) ** 2, rtol=1e-12)
+    prob = dict(inputs.sphere_problem(), max_steps=10)
+    Q = inputs.sphere_uniform(3, 3, seed=1)
+    g, o = run_both(prob, Q, 5, seed=2)
+    assert g["status"] == "WTRUNC" and g["stats"]["truncated"] == 15
+    compare_walks(g, o, prob)
+
+
+def test_invalid_arguments():
+    Q = inputs.sphere_uniform(2, 3, seed=1)
+    prob = inputs.sphere_problem()
+    for bad in (dict(sigma=0.0), dict(sigma=float("nan")), dict(theta=1.0), dict(n_v=0), dict(tau_w=0.0)):
+        with pytest.raises(mpwos.MpwosError) as e:
+            mpwos.solve(dict(prob, **bad), Q, 4, 1)
+        assert e.value.status == mpwos.EINVAL
+    with pytest.raises(mpwos.MpwosError) as e:
+        mpwos.solve(prob, Q * 1.001, 4, 1)
+    assert e.value.status == mpwos.EOFFMANIFOLD
+    with pytest.raises(mpwos.MpwosError) as e:
+        mpwos.solve(prob, Q, 0, 1)
+    assert e.value.status == mpwos.EINVAL
+    with pytest.raises(mpwos.MpwosError) as e:
+        mpwos.solve(dict(prob, f=dict(kind="sph_pair", idx=[0, 0], coef=[1.0])), Q, 4, 1)
+    assert e.value.status == mpwos.EINVAL
+    cap = inputs.cap_problem()
+    Qc = inputs.cap_uniform(2, 3, 0.0, seed=1)
+    Qc[0, 2] = -Qc[0, 2]
+    with pytest.raises(mpwos.MpwosError) as e:
+        mpwos.solve(cap, Qc, 4, 1)
+    assert e.value.status == mpwos.EOFFMANIFOLD
+    with pytest.raises(mpwos.MpwosError):
+        mpwos.Manifold(dict(manifold="torus", n=3, p=[1.0, 0.7]))
+    with pytest.raises(mpwos.MpwosError):
+        mpwos.Manifold(dict(manifold="sphere", n=1, p=[1.0]))
+
+
+def test_seed_changes_the_stream_and_is_reproducible():
+    prob, Q, nw = CASES["sphere"]
+    a = mpwos.solve(prob, Q, nw, 1, walk_outputs=True)
+    b = mpwos.solve(prob, Q, nw, 1, walk_outputs=True)
+    c = mpwos.solve(prob, Q, nw, 2, walk_outputs=True)
+    assert np.array_equal(a["walk_S"], b["walk_S"])
+    assert not np.array_equal(a["walk_S"], c["walk_S"])
