@@ -219,11 +219,13 @@ static double host_inv(const HostLaw& h, double X2, double u, double lo, double 
   for (int it = 0; it < 200; ++it) {
     double F, p;
     host_F(h, X2, s, F, p);
+    if (F == u) break;
     if (F < u) lo = s; else hi = s;
     double sn = s - (F - u) / p;
-    if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
-    if (std::fabs(sn - s) <= 1e-17 || hi - lo <= 1e-17) { s = sn; break; }
+    if (!(sn >= lo && sn <= hi)) sn = 0.5 * (lo + hi);
+    const double ds = std::fabs(sn - s);
     s = sn;
+    if (ds <= 0x1p-51 * s || hi - lo <= 0x1p-52 * hi) break;
   }
   return s;
 }

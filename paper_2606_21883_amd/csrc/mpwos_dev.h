@@ -235,12 +235,14 @@ __device__ __forceinline__ double radial_inv64(const WalkArgs& a, double u, doub
   for (int it = 0; it < 40; ++it) {
     if (!(s > 0.0)) s = 0.5 * (lo + hi);
     const RadialEval<double> e = fixed ? radial_eval_fixed<double>(a.law, a.fixed, s) : radial_eval_var(a.law, X2, norm, s);
-    if (e.F < u) lo = s; else hi = s;
-    double sn = s - (e.F - u) / e.pdf;
-    if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
+    const double df = e.F - u;
+    if (df == 0.0) break;
+    if (df < 0.0) lo = s; else hi = s;
+    double sn = s - df / e.pdf;
+    if (!(sn >= lo && sn <= hi)) sn = 0.5 * (lo + hi);
     const double ds = fabs(sn - s);
     s = sn;
-    if (ds <= 0x1p-52 * s || hi - lo <= 0x1p-53 * hi) break;
+    if (ds <= 0x1p-51 * s || hi - lo <= 0x1p-52 * hi) break;
   }
   return s;
 }
@@ -282,68 +284,198 @@ __device__ __forceinline__ T torus_phi(T R2, T a2, const T* x, T* g, T* H) {
   return phi;
 }
 
-// Local Newton solve for the closest point on the implicit torus.  Stage 1:
-// safeguarded Newton along the gradient line through x to reach the level set
-// (bracketed, so it cannot jump across the core circle).  Stage 2: Newton on
-// the Lagrange system y - x + mu grad phi(y) = 0, phi(y) = 0.
+// Projection onto the level set from a point near it: Newton along the
+// gradient, z <- z - phi grad phi / |grad phi|^2, until the first-order
+// distance |phi|/|grad phi| is below tol.  Returns false if it does not get
+// there within `iters` steps.
+template <class T>
+__device__ __forceinline__ bool torus_retract(T R2, T a2, T* z, int iters, T tol) {
+  for (int it = 0; it < iters; ++it) {
+    T g[3];
+    const T ph = torus_phi(R2, a2, z, g, (T*)nullptr);
+    const T gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    const T f = ph / gg;
+    z[0] -= f * g[0];
+    z[1] -= f * g[1];
+    z[2] -= f * g[2];
+    if (abs_(f) * sqrt_(gg) <= tol) {
+      // one more step polishes to the rounding level of phi
+      const T p2 = torus_phi(R2, a2, z, g, (T*)nullptr);
+      const T f2 = p2 / (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+      z[0] -= f2 * g[0];
+      z[1] -= f2 * g[1];
+      z[2] -= f2 * g[2];
+      return true;
+    }
+  }
+  return false;
+}
+
+// Newton on the manifold from a point p of the level set: the tangential
+// gradient P_T (y - x) and tangential Hessian P_T (I + mu Hess phi) P_T (mu the
+// Lagrange multiplier) give a step in the tangent plane, which is retracted
+// onto the level set.  Early steps must shorten |y - x|; once steps are below
+// 1e-6 a the tangential gradient norm is the acceptance test (the distance
+// itself no longer resolves them).
+template <class T>
+struct RefineResult {
+  T dist2;   // |y - x|^2 at the end
+  T gt2;     // squared tangential gradient at the last Newton iterate
+  bool pd;   // tangential Hessian positive definite there (a local minimum)
+};
+
+template <class T>
+__device__ __forceinline__ RefineResult<T> torus_refine(T R2, T a2, T a, const T* x, T* y, int iters) {
+  bool pd = false;
+  constexpr bool dbl = sizeof(T) == 8;
+  const T tol = (T)(dbl ? 1e-15 : 2e-7) * a;
+  T g[3], H[9];
+  T gt2 = (T)0;
+  for (int it = 0; it < iters; ++it) {
+    torus_phi(R2, a2, y, g, H);
+    const T ig = rsqrt_(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    const T n[3] = {g[0] * ig, g[1] * ig, g[2] * ig};
+    const T r[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+    const T rn = r[0] * n[0] + r[1] * n[1] + r[2] * n[2];
+    const T gt[3] = {r[0] - rn * n[0], r[1] - rn * n[1], r[2] - rn * n[2]};
+    gt2 = gt[0] * gt[0] + gt[1] * gt[1] + gt[2] * gt[2];
+    const T mu = -rn * ig;
+    T e1[3];
+    if (abs_(n[0]) <= abs_(n[1]) && abs_(n[0]) <= abs_(n[2])) { e1[0] = (T)0; e1[1] = -n[2]; e1[2] = n[1]; }
+    else if (abs_(n[1]) <= abs_(n[2])) { e1[0] = n[2]; e1[1] = (T)0; e1[2] = -n[0]; }
+    else { e1[0] = -n[1]; e1[1] = n[0]; e1[2] = (T)0; }
+    const T ie = rsqrt_(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    e1[0] *= ie; e1[1] *= ie; e1[2] *= ie;
+    const T e2[3] = {n[1] * e1[2] - n[2] * e1[1], n[2] * e1[0] - n[0] * e1[2], n[0] * e1[1] - n[1] * e1[0]};
+    T He1[3], He2[3];
+    for (int i = 0; i < 3; ++i) {
+      He1[i] = H[3 * i] * e1[0] + H[3 * i + 1] * e1[1] + H[3 * i + 2] * e1[2];
+      He2[i] = H[3 * i] * e2[0] + H[3 * i + 1] * e2[1] + H[3 * i + 2] * e2[2];
+    }
+    const T a11 = (T)1 + mu * (e1[0] * He1[0] + e1[1] * He1[1] + e1[2] * He1[2]);
+    const T a12 = mu * (e1[0] * He2[0] + e1[1] * He2[1] + e1[2] * He2[2]);
+    const T a22 = (T)1 + mu * (e2[0] * He2[0] + e2[1] * He2[1] + e2[2] * He2[2]);
+    const T b1 = -(e1[0] * gt[0] + e1[1] * gt[1] + e1[2] * gt[2]);
+    const T b2 = -(e2[0] * gt[0] + e2[1] * gt[1] + e2[2] * gt[2]);
+    const T det = a11 * a22 - a12 * a12;
+    pd = a11 > (T)0 && det > (T)0;
+    if (gt2 <= tol * tol) break;
+    T c1 = b1, c2 = b2;  // steepest descent where the model is not convex
+    if (pd) {
+      c1 = (a22 * b1 - a12 * b2) / det;
+      c2 = (a11 * b2 - a12 * b1) / det;
+    }
+    T v[3] = {c1 * e1[0] + c2 * e2[0], c1 * e1[1] + c2 * e2[1], c1 * e1[2] + c2 * e2[2]};
+    T vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    if (vv > (T)0.25 * a2) {  // trust region of radius a/2
+      const T sc = (T)0.5 * a * rsqrt_(vv);
+      v[0] *= sc; v[1] *= sc; v[2] *= sc;
+      vv = (T)0.25 * a2;
+    }
+    const bool fine = vv <= (T)1e-12 * a2;
+    const T f0 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    T lam = (T)1;
+    T yt[3];
+    for (int bt = 0; bt < 40; ++bt) {
+      yt[0] = y[0] + lam * v[0];
+      yt[1] = y[1] + lam * v[1];
+      yt[2] = y[2] + lam * v[2];
+      const bool on = torus_retract<T>(R2, a2, yt, 16, (T)(dbl ? 1e-12 : 1e-5) * a);
+      const T q[3] = {yt[0] - x[0], yt[1] - x[1], yt[2] - x[2]};
+      if (!on) {
+        // not back on the level set: shorter step
+      } else if (fine) {
+        T gq[3];
+        torus_phi(R2, a2, yt, gq, (T*)nullptr);
+        const T iq = rsqrt_(gq[0] * gq[0] + gq[1] * gq[1] + gq[2] * gq[2]);
+        const T qn = (q[0] * gq[0] + q[1] * gq[1] + q[2] * gq[2]) * iq;
+        const T t0 = q[0] - qn * gq[0] * iq, t1 = q[1] - qn * gq[1] * iq, t2 = q[2] - qn * gq[2] * iq;
+        if (t0 * t0 + t1 * t1 + t2 * t2 < gt2) break;
+      } else if (q[0] * q[0] + q[1] * q[1] + q[2] * q[2] < f0) {
+        break;
+      }
+      lam *= (T)0.5;
+      if (bt == 39) { yt[0] = y[0]; yt[1] = y[1]; yt[2] = y[2]; }
+    }
+    if (yt[0] == y[0] && yt[1] == y[1] && yt[2] == y[2]) break;
+    y[0] = yt[0];
+    y[1] = yt[1];
+    y[2] = yt[2];
+  }
+  const T r0 = y[0] - x[0], r1 = y[1] - x[1], r2 = y[2] - x[2];
+  RefineResult<T> res;
+  res.dist2 = r0 * r0 + r1 * r1 + r2 * r2;
+  res.gt2 = gt2;
+  res.pd = pd;
+  return res;
+}
+
+// Local Newton solve for the closest point on the implicit torus
+// (minimise |y - x|^2 subject to phi(y) = 0).  The line through x along
+// grad phi(x) meets the level set on both sides when x lies inside the tube;
+// near the core circle the gradient of this quartic leans away from the
+// normal, so the nearer wall is not always the one the gradient points to.
+// The crossing the descent direction of |phi| points to is refined first; it
+// is the nearest point exactly when the refined point is a converged local
+// minimum of the distance (positive tangential Hessian: for a point within the
+// reach, the far wall has 1 - t kappa < 0 across the tube).  Otherwise the
+// other crossing is refined too and the nearer (on a tie, the better
+// converged) result is kept.
 template <class T>
 __device__ __forceinline__ void torus_cp_newton(T R, T a, const T* x, T* y, int iters) {
   const T R2 = R * R, a2 = a * a;
-  T g[3], H[9];
+  constexpr bool dbl = sizeof(T) == 8;
+  T g[3];
   const T phi0 = torus_phi(R2, a2, x, g, (T*)nullptr);
-  T gn = sqrt_(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-  T d[3] = {g[0] / gn, g[1] / gn, g[2] / gn};
-  // move against the sign of phi along d: y(t) = x - sgn(phi0) t d, t in [0, tmax]
-  const T sg = phi0 > (T)0 ? (T)1 : (T)-1;
-  T lo = (T)0, hi = (T)2 * a, t = (T)0;
-  for (int it = 0; it < 40; ++it) {
-    T p[3] = {x[0] - sg * t * d[0], x[1] - sg * t * d[1], x[2] - sg * t * d[2]};
-    T gp[3];
-    const T ph = torus_phi(R2, a2, p, gp, (T*)nullptr);
-    if (ph * sg > (T)0) lo = t; else hi = t;
-    const T dph = -sg * (gp[0] * d[0] + gp[1] * d[1] + gp[2] * d[2]);
-    T tn = t - ph / dph;
-    if (!(tn > lo && tn < hi)) tn = (T)0.5 * (lo + hi);
-    const T dt = abs_(tn - t);
-    t = tn;
-    if (dt <= (T)(sizeof(T) == 8 ? 1e-13 : 1e-6) * a) break;
+  if (phi0 == (T)0) {
+    y[0] = x[0]; y[1] = x[1]; y[2] = x[2];
+    return;
   }
-  for (int i = 0; i < 3; ++i) y[i] = x[i] - sg * t * d[i];
-  // stage 2: Lagrange-Newton with Schur complement of the 4x4 system
-  torus_phi(R2, a2, y, g, (T*)nullptr);
-  const T gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
-  T mu = ((x[0] - y[0]) * g[0] + (x[1] - y[1]) * g[1] + (x[2] - y[2]) * g[2]) / gg;
-  for (int it = 0; it < iters; ++it) {
-    const T ph = torus_phi(R2, a2, y, g, H);
-    T F1[3];
-    for (int i = 0; i < 3; ++i) F1[i] = y[i] - x[i] + mu * g[i];
-    // A = I + mu H
-    T A[9];
-    for (int i = 0; i < 9; ++i) A[i] = mu * H[i];
-    A[0] += (T)1; A[4] += (T)1; A[8] += (T)1;
-    // adjugate inverse
-    T C0 = A[4] * A[8] - A[5] * A[7], C1 = A[5] * A[6] - A[3] * A[8], C2 = A[3] * A[7] - A[4] * A[6];
-    T det = A[0] * C0 + A[1] * C1 + A[2] * C2;
-    T inv[9] = {C0, A[2] * A[7] - A[1] * A[8], A[1] * A[5] - A[2] * A[4],
-                C1, A[0] * A[8] - A[2] * A[6], A[2] * A[3] - A[0] * A[5],
-                C2, A[1] * A[6] - A[0] * A[7], A[0] * A[4] - A[1] * A[3]};
-    const T id = (T)1 / det;
-    T Ag[3], AF[3];
-    for (int i = 0; i < 3; ++i) {
-      Ag[i] = id * (inv[3 * i] * g[0] + inv[3 * i + 1] * g[1] + inv[3 * i + 2] * g[2]);
-      AF[i] = id * (inv[3 * i] * F1[0] + inv[3 * i + 1] * F1[1] + inv[3 * i + 2] * F1[2]);
+  const T ign = rsqrt_(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  const T d[3] = {g[0] * ign, g[1] * ign, g[2] * ign};
+  T best = (T)-1, best_gt = (T)0;
+  const T tol = (T)(dbl ? 1e-15 : 2e-7) * a;
+  for (int side = 0; side < 2; ++side) {
+    const T dir = side == 0 ? (phi0 > (T)0 ? (T)-1 : (T)1) : (phi0 > (T)0 ? (T)1 : (T)-1);
+    // scan t in (0, 3a] for a sign change of phi along x + dir t d
+    const T h = (T)0.125 * a;
+    T lo = (T)0, hi = (T)-1;
+    for (int k = 1; k <= 24; ++k) {
+      const T t = h * (T)k;
+      const T p[3] = {x[0] + dir * t * d[0], x[1] + dir * t * d[1], x[2] + dir * t * d[2]};
+      T gp[3];
+      const T ph = torus_phi(R2, a2, p, gp, (T*)nullptr);
+      if ((ph > (T)0) != (phi0 > (T)0) || ph == (T)0) { hi = t; break; }
+      lo = t;
     }
-    const T gAg = g[0] * Ag[0] + g[1] * Ag[1] + g[2] * Ag[2];
-    const T gAF = g[0] * AF[0] + g[1] * AF[1] + g[2] * AF[2];
-    const T dmu = (ph - gAF) / gAg;
-    T dy2 = (T)0;
-    for (int i = 0; i < 3; ++i) {
-      const T dy = -AF[i] - dmu * Ag[i];
-      y[i] += dy;
-      dy2 += dy * dy;
+    if (hi < (T)0) continue;
+    T t = (T)0.5 * (lo + hi);
+    for (int it = 0; it < 60; ++it) {
+      const T p[3] = {x[0] + dir * t * d[0], x[1] + dir * t * d[1], x[2] + dir * t * d[2]};
+      T gp[3];
+      const T ph = torus_phi(R2, a2, p, gp, (T*)nullptr);
+      if (ph == (T)0) break;
+      if ((ph > (T)0) == (phi0 > (T)0)) lo = t; else hi = t;
+      const T dph = dir * (gp[0] * d[0] + gp[1] * d[1] + gp[2] * d[2]);
+      T tn = t - ph / dph;
+      if (!(tn >= lo && tn <= hi)) tn = (T)0.5 * (lo + hi);
+      const T dt = abs_(tn - t);
+      t = tn;
+      if (dt <= (T)(dbl ? 1e-15 : 1e-7) * a || hi - lo <= (T)(dbl ? 1e-15 : 1e-7) * a) break;
     }
-    mu += dmu;
-    if (dy2 <= (T)(sizeof(T) == 8 ? 1e-32 : 1e-14) * a2) break;
+    T yc[3] = {x[0] + dir * t * d[0], x[1] + dir * t * d[1], x[2] + dir * t * d[2]};
+    const RefineResult<T> rr = torus_refine<T>(R2, a2, a, x, yc, iters);
+    const bool tie = best >= (T)0 && abs_(rr.dist2 - best) <= (T)(dbl ? 1e-10 : 1e-4) * best;
+    if (best < (T)0 || (tie ? rr.gt2 < best_gt : rr.dist2 < best)) {
+      best = rr.dist2;
+      best_gt = rr.gt2;
+      y[0] = yc[0]; y[1] = yc[1]; y[2] = yc[2];
+    }
+    if (side == 0 && rr.pd && rr.gt2 <= (T)100 * tol * tol) break;
+  }
+  if (best < (T)0) {
+    y[0] = x[0]; y[1] = x[1]; y[2] = x[2];
+    torus_retract<T>(R2, a2, y, 16, (T)(dbl ? 1e-12 : 1e-5) * a);
   }
 }
 

@@ -68,7 +68,11 @@ __device__ __forceinline__ bool cap_in_layer(const WalkArgs& a, const T* y) {
 template <class T, int N, int KIND>
 __device__ __forceinline__ void closest_point(const WalkArgs& a, const T* x, T* y) {
   if constexpr (KIND == kTorus) {
-    torus_cp_newton<T>((T)a.p[0], (T)a.p[1], x, y, sizeof(T) == 8 ? 6 : 3);
+    // FP64 in both modes: the quartic cancels to a few bits in FP32 near the
+    // surface, which the Newton solve cannot recover
+    double xd[3] = {(double)x[0], (double)x[1], (double)x[2]}, yd[3];
+    torus_cp_newton<double>(a.p[0], a.p[1], xd, yd, 16);
+    for (int i = 0; i < 3; ++i) y[i] = (T)yd[i];
   } else {
     T s = (T)0;
     for (int i = 0; i < N; ++i) s += x[i] * x[i];

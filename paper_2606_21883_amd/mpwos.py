@@ -81,6 +81,13 @@ def lib():
     """Loads libmpwos.so; raises if it has not been built (no fallback)."""
     global _lib
     if _lib is None:
+        # Load torch's HIP runtime first when torch is installed: the library
+        # then binds to that same runtime (one HIP runtime per process, so
+        # torch device pointers and streams are valid in both).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIBPATH):
             raise RuntimeError(f"{LIBPATH} is missing: build it with paper_2606_21883_amd/build.py")
         L = ctypes.CDLL(LIBPATH)

@@ -67,16 +67,19 @@ def test_torus_newton_cp_matches_closed_form():
     prob = inputs.torus_problem()
     m = mpwos.Manifold(prob)
     rng = np.random.default_rng(1)
-    base = inputs.torus_area_uniform(4000, seed=3)
-    # points within the ball radius of the surface, including near the core circle
+    base = inputs.torus_area_uniform(6000, seed=3)
+    # points of the walk: on spheres of the walk radius around torus points
+    # (half), and inside those balls (half) -- down to 0.037 from the core circle
     d = rng.standard_normal(base.shape)
     d /= np.linalg.norm(d, axis=1, keepdims=True)
-    x = base + 0.2631 * rng.uniform(0, 1, (len(base), 1)) ** 0.5 * d
+    rad = 0.95 * 1.2 / (1 + 1 / 0.3) * np.where(np.arange(len(base)) % 2 == 0, 1.0,
+                                                 rng.uniform(0, 1, len(base)) ** (1 / 3))
+    x = base + rad[:, None] * d
     ref = np.array([oracle.cp(prob, v) for v in x])
     y64 = mpwos.debug_cp(m, x, "fp64")
     y32 = mpwos.debug_cp(m, x, "fp32")
-    np.testing.assert_allclose(y64, ref, rtol=0, atol=1e-13)
-    np.testing.assert_allclose(y32, ref, rtol=0, atol=5e-6)
+    np.testing.assert_allclose(y64, ref, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(y32, ref, rtol=0, atol=5e-7)
     m.close()
 
 
