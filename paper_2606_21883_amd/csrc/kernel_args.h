@@ -52,11 +52,14 @@ struct RadialFixed {
   double norm;            // 1 / (1 - c)
 };
 
-// Inverse-CDF guess table: s at u = i/(mu-1), for mx radius slices.
+// Inverse-CDF guess table.  For each of mx radius slices, two halves of mu
+// points each: the lower half holds s at u = w^2, the upper half s at
+// u = 1 - w^2, with w = sqrt(1/2) i/(mu-1); s is close to linear in w at both
+// ends of the law (s ~ sqrt(u) near 0, 1 - s ~ sqrt(1 - u) near 1).
 struct InvTable {
-  const double* s64;      // mx * mu doubles (FP64 guesses / brackets)
-  const float* s32;       // mx * mu floats
-  int32_t mu;             // points per slice (power of two + 1)
+  const double* s64;      // mx * 2 * mu doubles (FP64 guesses / brackets)
+  const float* s32;       // mx * 2 * mu floats
+  int32_t mu;             // points per half
   int32_t mx;             // slices in X^2 (1 when X is fixed)
   double x2max;           // X^2 of the last slice
 };

@@ -245,24 +245,28 @@ static std::mutex g_tab_lock;
 static std::map<TableKey, TableVal> g_tables;
 
 static mpwos_status get_table(const HostLaw& h, int mx, double x2max, InvTable& t) {
-  const int mu = 1025;
+  const int mu = 513;
   TableKey key{h.n, mx, x2max};
   std::lock_guard<std::mutex> g(g_tab_lock);
   auto it = g_tables.find(key);
   if (it == g_tables.end()) {
-    std::vector<double> s64((size_t)mx * mu);
-    std::vector<float> s32((size_t)mx * mu);
+    std::vector<double> s64((size_t)mx * 2 * mu);
+    std::vector<float> s32((size_t)mx * 2 * mu);
+    const double wmax = std::sqrt(0.5);
     for (int k = 0; k < mx; ++k) {
       const double X2 = (mx == 1) ? x2max : (k == 0 ? x2max * 1e-6 : x2max * k / (mx - 1));
-      double prev = 0.0;
-      for (int i = 0; i < mu; ++i) {
-        double s;
-        if (i == 0) s = 0.0;
-        else if (i == mu - 1) s = 1.0;
-        else s = host_inv(h, X2, (double)i / (mu - 1), prev, 1.0);
-        s64[(size_t)k * mu + i] = s;
-        s32[(size_t)k * mu + i] = (float)s;
-        prev = s;
+      for (int half = 0; half < 2; ++half) {
+        double* row = s64.data() + ((size_t)k * 2 + half) * mu;
+        for (int i = 0; i < mu; ++i) {
+          const double w = wmax * (double)i / (mu - 1);
+          const double u = half == 0 ? w * w : 1.0 - w * w;
+          double sv;
+          if (half == 0 && i == 0) sv = 0.0;
+          else if (half == 1 && i == 0) sv = 1.0;
+          else sv = host_inv(h, X2, u, 0.0, 1.0);
+          row[i] = sv;
+        }
+        for (int i = 0; i < mu; ++i) s32[((size_t)k * 2 + half) * mu + i] = (float)row[i];
       }
     }
     TableVal v;

@@ -179,45 +179,55 @@ __device__ __forceinline__ double radial_norm(const RadialLaw& L, double X2) {
   return (1.0 + t) / t;
 }
 
-// Table guess for s(u): slice of X^2 (nearest below, linear blend) and linear
-// interpolation in u; also returns the u-cell bracket of the fixed-X table.
+// Table guess for s(u): the half and cell from w = sqrt(min(u, 1-u)), linear
+// in w, blended linearly between X^2 slices when the radius varies; for a
+// fixed radius it also returns the cell's bracket of the root.
 __device__ __forceinline__ double table_guess64(const InvTable& t, double u, double X2, double& lo, double& hi) {
-  const double pos = u * (double)(t.mu - 1);
+  const bool up = u > 0.5;
+  const double w = sqrt(up ? 1.0 - u : u);
+  const double pos = w * ((double)(t.mu - 1) * 1.4142135623730951);
   int i = (int)pos;
   i = i < 0 ? 0 : (i > t.mu - 2 ? t.mu - 2 : i);
   const double fr = pos - (double)i;
   if (t.mx == 1) {
-    lo = t.s64[i];
-    hi = t.s64[i + 1];
-    return lo + fr * (hi - lo);
+    const double* r = t.s64 + (up ? t.mu : 0);
+    const double a = r[i], b = r[i + 1];
+    lo = a < b ? a : b;
+    hi = a < b ? b : a;
+    return a + fr * (b - a);
   }
   const double xpos = X2 / t.x2max * (double)(t.mx - 1);
   int k = (int)xpos;
   k = k < 0 ? 0 : (k > t.mx - 2 ? t.mx - 2 : k);
   const double fx = xpos - (double)k;
-  const double* a = t.s64 + (size_t)k * t.mu;
-  const double* b = a + t.mu;
-  const double ga = a[i] + fr * (a[i + 1] - a[i]);
-  const double gb = b[i] + fr * (b[i + 1] - b[i]);
+  const double* ra = t.s64 + ((size_t)k * 2 + (up ? 1 : 0)) * t.mu;
+  const double* rb = ra + 2 * (size_t)t.mu;
+  const double ga = ra[i] + fr * (ra[i + 1] - ra[i]);
+  const double gb = rb[i] + fr * (rb[i + 1] - rb[i]);
   lo = 0.0;
   hi = 1.0;
   return ga + fx * (gb - ga);
 }
 
 __device__ __forceinline__ float table_guess32(const InvTable& t, float u, float X2) {
-  const float pos = u * (float)(t.mu - 1);
+  const bool up = u > 0.5f;
+  const float w = __builtin_amdgcn_sqrtf(up ? 1.0f - u : u);
+  const float pos = w * ((float)(t.mu - 1) * 1.41421356f);
   int i = (int)pos;
   i = i < 0 ? 0 : (i > t.mu - 2 ? t.mu - 2 : i);
   const float fr = pos - (float)i;
-  if (t.mx == 1) return t.s32[i] + fr * (t.s32[i + 1] - t.s32[i]);
+  if (t.mx == 1) {
+    const float* r = t.s32 + (up ? t.mu : 0);
+    return r[i] + fr * (r[i + 1] - r[i]);
+  }
   const float xpos = X2 / (float)t.x2max * (float)(t.mx - 1);
   int k = (int)xpos;
   k = k < 0 ? 0 : (k > t.mx - 2 ? t.mx - 2 : k);
   const float fx = xpos - (float)k;
-  const float* a = t.s32 + (size_t)k * t.mu;
-  const float* b = a + t.mu;
-  const float ga = a[i] + fr * (a[i + 1] - a[i]);
-  const float gb = b[i] + fr * (b[i + 1] - b[i]);
+  const float* ra = t.s32 + ((size_t)k * 2 + (up ? 1 : 0)) * t.mu;
+  const float* rb = ra + 2 * (size_t)t.mu;
+  const float ga = ra[i] + fr * (ra[i + 1] - ra[i]);
+  const float gb = rb[i] + fr * (rb[i + 1] - rb[i]);
   return ga + fx * (gb - ga);
 }
 
@@ -229,7 +239,7 @@ __device__ __forceinline__ double radial_inv64(const WalkArgs& a, double u, doub
   const bool fixed = a.const_r != 0;
   if (fixed) {
     lo = lo * (1.0 - 1e-12);
-    hi = fmin(1.0, hi * (1.0 + 1e-12));
+    hi = fmin(1.0, hi * (1.0 + 1e-12) + 1e-300);
   }
   s = fmin(fmax(s, lo), hi);
   for (int it = 0; it < 40; ++it) {

@@ -12,7 +12,12 @@ def announce(msg):
 
 def score_scale(prob):
     """Bound of sum_k W_k omega_k |F_k| (<= max|f + m| / sigma) plus the boundary term."""
-    s = 1.0 + sum(abs(c) for c in prob.get("f", {}).get("coef", [0.0])) / prob["sigma"]
+    f = prob.get("f", {})
+    s = 1.0 + sum(abs(c) for c in f.get("coef", [0.0])) / prob["sigma"]
+    if f.get("kind") == "torus_mode":
+        R, a = prob["p"][:2]
+        fmax = 4 / a ** 2 + 1 / (R - a) ** 2 + 2 / (a * (R - a)) + prob["sigma"]
+        s = 1.0 + abs(f["coef"][0]) * 2 * fmax / prob["sigma"]
     if "values" in prob.get("f", {}):
         s += float(np.max(np.abs(prob["f"]["values"]))) * 2 / prob["sigma"]
     if prob["manifold"] == "sphere_cap":

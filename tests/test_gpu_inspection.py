@@ -58,8 +58,17 @@ def test_device_radial_inverse_matches_oracle(n):
     s64 = mpwos.debug_radial_inv(n, X, u, "fp64")
     s32 = mpwos.debug_radial_inv(n, X, u, "fp32")
     ref = np.array([oracle.radial_inv(n, X, v) for v in u])
-    np.testing.assert_allclose(s64, ref, rtol=5e-14, atol=1e-15)
-    np.testing.assert_allclose(s32, ref, rtol=0, atol=2e-5)
+    # where F' is not small the roots agree closely; everywhere, the device
+    # root solves F(s) = u to the rounding of F (the root itself is
+    # ill-conditioned as u -> 1, where F' -> 0)
+    ok = u < 0.99
+    np.testing.assert_allclose(s64[ok], ref[ok], rtol=2e-14, atol=1e-15)
+    res = np.array([oracle.radial_cdf(n, X, s) for s in s64]) - u
+    assert np.max(np.abs(res)) <= 2e-15
+    # the FP32 path takes u in binary32 (the walk's 23-bit uniforms are exact there)
+    u32 = u.astype(np.float32).astype(np.float64)
+    ref32 = np.array([oracle.radial_inv(n, X, v) if v < 1.0 else 1.0 for v in u32])
+    np.testing.assert_allclose(s32, ref32, rtol=0, atol=1e-5)
 
 
 def test_torus_newton_cp_matches_closed_form():
