@@ -132,7 +132,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None, help="time only one form (profiling)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="time the library's plain copy kernel on BYTES (HBM calibration) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        from paper_2606_21883_amd import mpwos
+        ms = mpwos.copy_probe(args.copy_probe, 5)
+        print(json.dumps({"copy_bytes": args.copy_probe, "ms": ms,
+                          "GB_per_s": 2 * args.copy_probe / (ms * 1e-3) / 1e9}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
         sys.exit(2)

@@ -97,6 +97,8 @@ struct WalkArgs {
   const double* queries;       // this launch's queries (q_offset .. q_offset + nq)
   int64_t nq, nw;
   int64_t q_offset;            // global index of queries[0] in the solve (Philox counter word 0)
+  int64_t idx_base;            // first walk (linear index q_local * nw + w) of this launch
+  int64_t count;               // walks in this launch
   uint64_t seed;
   double* walk_S;
   int32_t* walk_K;

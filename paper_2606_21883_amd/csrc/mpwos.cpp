@@ -571,7 +571,7 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
 
 // Walk kernel launch for a batch (queries/outputs already on the device).
 mpwos_status launch_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue) {
-  const int64_t total = a.nq * a.nw;
+  const int64_t total = a.count;
   const int n_cu = device_cu_count();
   if (a.n <= 3 && a.kind != MPWOS_POINT_CLOUD) {
     const int block = o.block_size ? o.block_size : 256;
@@ -676,6 +676,8 @@ extern "C" mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_
     a.nq = nb;
     a.nw = n_walks;
     a.q_offset = q0;
+    a.idx_base = 0;
+    a.count = nb * n_walks;
     a.walk_S = wS;
     a.walk_K = wK;
     HIP_TRY(hipEventRecord(g_ctx.ev[0], s));

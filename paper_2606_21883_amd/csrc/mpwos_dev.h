@@ -257,11 +257,12 @@ __device__ __forceinline__ double radial_inv64(const WalkArgs& a, double u, doub
   return s;
 }
 
-// FP32: table guess and one Newton step with the FP32 law (fixed X), or the
-// blended 2-D table alone (varying X).
+// FP32: table guess, then (lower half, fixed X) one Newton step with the FP32
+// law.  In the upper half F is near 1 and known only to FP32 absolute
+// precision while F' -> 0, so the sqrt(1-u) table alone is the better value.
 __device__ __forceinline__ float radial_inv32(const WalkArgs& a, float u, float X2) {
   float s = table_guess32(a.tab, u, X2);
-  if (a.const_r) {
+  if (a.const_r && u <= 0.5f) {
     s = fminf(fmaxf(s, 1e-20f), 1.0f);
     const RadialEval<float> e = radial_eval_fixed<float>(a.law, a.fixed, s);
     if (e.pdf > 0.0f) {

@@ -183,13 +183,13 @@ __device__ __forceinline__ void group_init(const WalkArgs& a, int64_t idx, Group
 // spheres have one deterministic walk length, so a static split is balanced).
 template <class T, int L, int MB>
 __global__ __launch_bounds__(256) void walk_group_kernel(WalkArgs a) {
-  const int64_t total = a.nq * a.nw;
+  const int64_t total = a.count;
   const int gl = threadIdx.x % L;
   const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / L;
   const int64_t ngroups = (int64_t)gridDim.x * blockDim.x / L;
   GroupWalk<T, L, MB> st;
   for (int64_t idx = gid; idx < total; idx += (a.persistent ? ngroups : total)) {
-    group_init<T, L, MB>(a, idx, st, gl);
+    group_init<T, L, MB>(a, a.idx_base + idx, st, gl);
     while (!group_step<T, L, MB>(a, st, gl)) {
     }
     if (gl == 0) {
@@ -283,7 +283,7 @@ mpwos_status launch_group_walks(WalkArgs& a, const mpwos_options& o, hipStream_t
   a.rword = rword;
   const int block = o.block_size ? o.block_size : 256;
   const bool fp64 = a.precision == 0;
-  const int64_t total = a.nq * a.nw;
+  const int64_t total = a.count;
   const int64_t need = (total * L + block - 1) / block;
   int64_t grid = need;
   if (a.persistent) {

@@ -191,12 +191,12 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 template <class T, int N, int KIND>
 __global__ __launch_bounds__(256) void walk_lane_kernel(WalkArgs a) {
-  const int64_t total = a.nq * a.nw;
+  const int64_t total = a.count;
   LaneState<T, N> st;
   if (!a.persistent) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    if (walk_init<T, N, KIND>(a, idx, st)) {
+    if (walk_init<T, N, KIND>(a, a.idx_base + idx, st)) {
       walk_store(a, st);
       return;
     }
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void walk_lane_kernel(WalkArgs a) {
       const int64_t avail = end - next;
       const int64_t cnt = (int64_t)__popcll(want) < avail ? (int64_t)__popcll(want) : avail;
       if (!active && rank < cnt) {
-        if (walk_init<T, N, KIND>(a, next + rank, st)) walk_store(a, st);
+        if (walk_init<T, N, KIND>(a, a.idx_base + next + rank, st)) walk_store(a, st);
         else active = true;
       }
       next += cnt;

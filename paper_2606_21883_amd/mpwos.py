@@ -295,3 +295,67 @@ def copy_probe(nbytes, reps):
 
 def version():
     return lib().mpwos_version().decode()
+
+
+class Server:
+    """mpwos_server_*: continuous batching of solves on one device.
+
+    Arrays handed to submit() are kept alive here until the request is
+    collected with wait()."""
+
+    def __init__(self, hbm_budget_bytes, slice_walk_steps=0):
+        self.handle = ctypes.c_void_p()
+        _check(lib().mpwos_server_create(int(hbm_budget_bytes), int(slice_walk_steps), ctypes.byref(self.handle)))
+        self._live = {}
+
+    def submit(self, manifold, prob, queries, n_walks, seed, **optkw):
+        keep = []
+        Q = np.ascontiguousarray(queries, dtype=np.float64)
+        req = Request()
+        req.manifold = manifold.handle
+        req.f = make_fn(prob.get("f", {"kind": "zero"}), keep)
+        if prob["manifold"] == "sphere_cap":
+            req.g = make_fn(prob["g"], keep)
+            req.has_g = 1
+        req.c = float(prob["sigma"])
+        req.queries = Q.ctypes.data
+        req.n_queries = Q.shape[0]
+        req.n_walks = int(n_walks)
+        req.eps = float(prob.get("eps", 1e-3))
+        req.seed = int(seed)
+        req.opt = make_options(prob, **optkw)
+        u = np.zeros(Q.shape[0])
+        se = np.zeros(Q.shape[0])
+        req.u_out = u.ctypes.data
+        req.stderr_out = se.ctypes.data
+        t = ctypes.c_uint64()
+        _check(lib().mpwos_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
+        self._live[t.value] = (Q, u, se, keep, req)
+        return t.value
+
+    def poll(self, ticket):
+        done = ctypes.c_int32()
+        res = ctypes.c_int32()
+        _check(lib().mpwos_poll(self.handle, int(ticket), ctypes.byref(done), ctypes.byref(res)))
+        return bool(done.value), res.value
+
+    def wait(self, ticket, timeout_ms=-1):
+        res = ctypes.c_int32()
+        _check(lib().mpwos_wait(self.handle, int(ticket), int(timeout_ms), ctypes.byref(res)))
+        Q, u, se, keep, req = self._live.pop(ticket)
+        _check(res.value)
+        return {"u": u, "stderr": se, "status": STATUS_NAMES[res.value]}
+
+    def stats(self):
+        st = ServerStats()
+        _check(lib().mpwos_server_stats_get(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(lib().mpwos_server_destroy(self.handle))
+            self.handle = ctypes.c_void_p()
+
+
+def server_create(hbm_budget_bytes, slice_walk_steps=0):
+    return Server(hbm_budget_bytes, slice_walk_steps)

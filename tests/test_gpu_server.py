@@ -1,0 +1,122 @@
+"""GPU tests of the continuous-batching server (mpwos_server_*): each request's
+result in a mix equals the same solve run alone, bit for bit; admission by HBM
+budget; requests that arrive while others run join them."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2606_21883_amd import inputs, mpwos
+from tests.gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+
+
+def mix():
+    out = []
+    p, Q, _ = inputs.config("sphere", scale=0.05)
+    out.append((p, Q, 257, 11, dict(precision="fp32", persistent=1)))
+    p, Q, _ = inputs.config("cap", scale=0.05)
+    out.append((p, Q, 300, 12, dict(precision="fp32", persistent=1)))
+    p, Q, _ = inputs.config("torus", scale=0.01)
+    out.append((p, Q, 64, 13, dict(precision="fp64")))
+    p = inputs.hypersphere_problem(10)
+    out.append((p, inputs.hypersphere_queries(40, 10, seed=3), 100, 14, dict(precision="fp32")))
+    p, Q, _ = inputs.config("circle", scale=0.5)
+    out.append((p, Q, 333, 15, dict(precision="fp64", persistent=1)))
+    p = dict(inputs.hypersphere_problem(100), tau_w=1e-3)
+    out.append((p, inputs.hypersphere_queries(6, 100, seed=3), 16, 16, dict(precision="fp32")))
+    return out
+
+
+def test_served_results_equal_solo_results():
+    reqs = mix()
+    announce("server mix solo")
+    solo = [mpwos.solve(p, Q, nw, seed, **kw) for p, Q, nw, seed, kw in reqs]
+    announce("server mix served")
+    mans = [mpwos.Manifold(p) for p, *_ in reqs]
+    srv = mpwos.Server(8 << 30)
+    tickets = [srv.submit(m, p, Q, nw, seed, **kw) for m, (p, Q, nw, seed, kw) in zip(mans, reqs)]
+    outs = [srv.wait(t, 120_000) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    for s, o, (p, *_ ) in zip(solo, outs, reqs):
+        assert np.array_equal(s["u"], o["u"]), p["manifold"]
+        assert np.array_equal(s["stderr"], o["stderr"])
+    assert st["completed"] == len(reqs) and st["admitted"] == len(reqs)
+    assert st["walk_steps"] > 0 and st["rounds"] >= 1
+    for m in mans:
+        m.close()
+
+
+def test_budget_rejects_and_queues():
+    p, Q, _ = inputs.config("sphere", scale=0.02)
+    m = mpwos.Manifold(p)
+    need = len(Q) * 3 * 8 + len(Q) * 2048 * 12 + 4096
+    assert need > 1 << 20
+    srv = mpwos.Server(int(need * 1.5))
+    with pytest.raises(mpwos.MpwosError) as e:
+        srv.submit(m, p, np.repeat(Q, 40, axis=0), 2048, 1, precision="fp32")
+    assert e.value.status == mpwos.ENOMEM
+    # three requests that fit only one at a time all complete, in order
+    announce("server budget queue")
+    ts = [srv.submit(m, p, Q, 2048, s, precision="fp32") for s in (1, 2, 3)]
+    outs = [srv.wait(t, 120_000) for t in ts]
+    st = srv.stats()
+    srv.close()
+    assert st["rejected"] == 1 and st["completed"] == 3
+    alone = mpwos.solve(p, Q, 2048, 2, precision="fp32")
+    assert np.array_equal(alone["u"], outs[1]["u"])
+    m.close()
+
+
+def test_late_arrival_joins_running_work():
+    big, Qb, _ = inputs.config("sphere", scale=0.25)
+    small, Qs, _ = inputs.config("cap", scale=0.02)
+    mb, ms = mpwos.Manifold(big), mpwos.Manifold(small)
+    announce("server late arrival")
+    srv = mpwos.Server(16 << 30, slice_walk_steps=1 << 24)
+    tb = srv.submit(mb, big, Qb, 1024, 5, precision="fp64")
+    time.sleep(0.05)
+    ts = srv.submit(ms, small, Qs, 256, 6, precision="fp32", persistent=1)
+    t0 = time.perf_counter()
+    os_ = srv.wait(ts, 120_000)
+    t_small = time.perf_counter() - t0
+    done_big, _ = srv.poll(tb)
+    ob = srv.wait(tb, 120_000)
+    st = srv.stats()
+    srv.close()
+    assert st["rounds"] >= 2
+    # the small request did not wait for the big one to finish
+    assert not done_big or t_small < 1.0
+    assert np.array_equal(os_["u"], mpwos.solve(small, Qs, 256, 6, precision="fp32", persistent=1)["u"])
+    assert np.array_equal(ob["u"], mpwos.solve(big, Qb, 1024, 5, precision="fp64")["u"])
+    mb.close()
+    ms.close()
+
+
+def test_manifold_busy_while_referenced():
+    p, Q, _ = inputs.config("sphere", scale=0.02)
+    m = mpwos.Manifold(p)
+    srv = mpwos.Server(4 << 30)
+    t = srv.submit(m, p, Q, 4096, 1, precision="fp64")
+    with pytest.raises(mpwos.MpwosError) as e:
+        m.close()
+    assert e.value.status == mpwos.EBUSY
+    srv.wait(t, 120_000)
+    srv.close()
+    m.close()
+
+
+def test_invalid_requests_are_rejected_at_submit():
+    p, Q, _ = inputs.config("sphere", scale=0.01)
+    m = mpwos.Manifold(p)
+    srv = mpwos.Server(1 << 30)
+    with pytest.raises(mpwos.MpwosError) as e:
+        srv.submit(m, dict(p, sigma=-1.0), Q, 16, 1)
+    assert e.value.status == mpwos.EINVAL
+    with pytest.raises(mpwos.MpwosError):
+        srv.submit(m, p, Q, 0, 1)
+    assert srv.stats()["rejected"] == 2
+    srv.close()
+    m.close()
