@@ -407,19 +407,28 @@ static int orc_solve6(double M[36], double b[6], double a[6]) {
 typedef struct {
   double y[3];        /* projected point cp_h(x) */
   double kappa;       /* max |principal curvature| of the fitted patch at the foot */
-  double h_mean;      /* mean distance from x to the k neighbours */
+  double h_mean;      /* mean distance from the nearest cloud point to its k-1 neighbours */
 } orc_pc_result;
 
-/* Local reconstruction and projection of x onto a point cloud. */
+/* Local reconstruction and projection of x onto a point cloud: the nearest
+ * cloud point p of x, the k nearest cloud points of p (p included), their
+ * centroid and PCA frame, the least-squares quadratic height field over the
+ * tangent plane, and the foot point of x on that patch by Newton. */
 int orc_pc_project(const orc_problem* P, const double* x, orc_pc_result* res) {
   int k = P->k_nn;
+  int64_t inn;
+  double nn_d2;
+  int st = orc_knn(P->points, P->n_points, x, 1, &inn, &nn_d2);
+  if (st) return st;
+  const double* pn = P->points + 3 * inn;
   int64_t idx[ORC_MAXK];
   double d2[ORC_MAXK];
-  int st = orc_knn(P->points, P->n_points, x, k, idx, d2);
+  st = orc_knn(P->points, P->n_points, pn, k, idx, d2);
   if (st) return st;
+  /* local spacing: mean distance from p to its k-1 other neighbours */
   double hsum = 0.0;
-  for (int j = 0; j < k; ++j) hsum += sqrt(d2[j]);
-  res->h_mean = hsum / (double)k;
+  for (int j = 1; j < k; ++j) hsum += sqrt(d2[j]);
+  res->h_mean = hsum / (double)(k - 1);
   double cen[3] = {0, 0, 0};
   for (int j = 0; j < k; ++j)
     for (int c = 0; c < 3; ++c) cen[c] += P->points[3 * idx[j] + c];

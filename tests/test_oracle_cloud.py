@@ -1,0 +1,119 @@
+"""Pins of the oracle's point-cloud projection (nearest-neighbour search with
+local reconstruction, Sec. 2.3.2): brute-force kNN against scipy's KD-tree;
+exact recovery of a plane; reconstruction error against the analytic sphere
+and torus projections; the curvature indicator of the fitted patch; the
+foot-point optimality of the Newton projection."""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+from paper_2606_21883_amd import inputs
+
+
+def cloud_problem(points, **kw):
+    d = inputs.problem(manifold="point_cloud", n=3, p=[1.0, 0.3], sigma=1.0, points=points, k_nn=16,
+                       radius_rule="curvature_fit", newton_iters=6, f=dict(kind="torus_mode", coef=[1.0]))
+    d.update(kw)
+    return d
+
+
+def test_knn_matches_kdtree(orc):
+    rng = np.random.default_rng(0)
+    pts = rng.uniform(-1, 1, (3000, 3))
+    tree = cKDTree(pts)
+    for _ in range(30):
+        x = rng.uniform(-1.2, 1.2, 3)
+        idx, d2 = orc.knn(pts, x, 16)
+        dd, ii = tree.query(x, 16)
+        assert np.array_equal(idx, ii)
+        np.testing.assert_allclose(np.sqrt(d2), dd, rtol=1e-14)
+
+
+def test_knn_ties_broken_by_index(orc):
+    pts = np.array([[1.0, 0, 0], [0, 1.0, 0], [-1.0, 0, 0], [0, -1.0, 0], [2.0, 0, 0]])
+    idx, d2 = orc.knn(pts, np.zeros(3), 4)
+    assert list(idx) == [0, 1, 2, 3]
+
+
+def test_plane_is_recovered_exactly(orc):
+    rng = np.random.default_rng(1)
+    g = np.stack(np.meshgrid(np.linspace(-1, 1, 61), np.linspace(-1, 1, 61)), -1).reshape(-1, 2)
+    g = g + rng.uniform(-0.004, 0.004, g.shape)
+    pts = np.concatenate([g, np.zeros((len(g), 1))], 1)
+    P = orc.Problem(cloud_problem(pts))
+    for _ in range(20):
+        x = np.array([rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5), rng.uniform(-0.2, 0.2)])
+        y = orc.cp(P, x)
+        np.testing.assert_allclose(y, [x[0], x[1], 0.0], atol=1e-12)
+
+
+def test_sphere_cloud_reconstruction_error(orc):
+    pts = inputs.sphere_uniform(20000, 3, seed=5)
+    P = orc.Problem(cloud_problem(pts))
+    rng = np.random.default_rng(2)
+    errs = []
+    for _ in range(40):
+        y0 = inputs.sphere_uniform(1, 3, seed=int(rng.integers(1 << 30)))[0]
+        x = y0 * (1.0 + rng.uniform(-0.25, 0.25))
+        errs.append(np.linalg.norm(orc.cp(P, x) - x / np.linalg.norm(x)))
+    # quadratic fit over k = 16 neighbours at spacing ~0.025: error O(h^3)
+    assert max(errs) < 2e-4, max(errs)
+
+
+def test_torus_cloud_reconstruction_and_curvature(orc):
+    pts = inputs.torus_area_uniform(40000, seed=6)
+    prob = cloud_problem(pts)
+    P = orc.Problem(prob)
+    T = orc.Problem(inputs.torus_problem())
+    rng = np.random.default_rng(3)
+    base = inputs.torus_area_uniform(40, seed=9)
+    errs, radii = [], []
+    for b in base:
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        x = b + 0.2 * d
+        errs.append(np.linalg.norm(orc.cp(P, x) - orc.cp(T, x)))
+        radii.append(orc.radius(P, b))
+    assert max(errs) < 1e-3, max(errs)
+    # curvature-fit radius: theta c_kappa / (1 + kappa) with kappa ~ 1/a
+    r_exact = 0.95 * 1.2 / (1 + 1 / 0.3)
+    assert np.all(np.abs(np.array(radii) / r_exact - 1) < 0.05), radii
+
+
+def test_spacing_radius_rule(orc):
+    pts = inputs.sphere_uniform(8000, 3, seed=7)
+    P = orc.Problem(cloud_problem(pts, radius_rule="spacing", c_h=2.4, k_nn=6))
+    y = pts[123]
+    idx, d2 = orc.knn(pts, y, 6)
+    h = np.mean(np.sqrt(d2[1:]))
+    assert orc.radius(P, y) == pytest.approx(0.95 * 2.4 * h, rel=1e-12)
+
+
+def test_newton_foot_point_is_stationary(orc):
+    pts = inputs.torus_area_uniform(20000, seed=8)
+    P = orc.Problem(cloud_problem(pts, newton_iters=8))
+    rng = np.random.default_rng(4)
+    for b in inputs.torus_area_uniform(20, seed=10):
+        d = rng.standard_normal(3)
+        x = b + 0.15 * d / np.linalg.norm(d)
+        y = orc.cp(P, x)
+        # moving y along the reconstructed surface cannot shorten |x - y| to first order:
+        # compare with nearby projected points
+        for e in np.eye(3):
+            y2 = orc.cp(P, y + 1e-4 * e)
+            assert np.linalg.norm(x - y) <= np.linalg.norm(x - y2) + 1e-10
+
+
+def test_point_cloud_estimator_unbiased_within_reconstruction(orc):
+    pts = inputs.torus_area_uniform(12000, seed=11)
+    prob = cloud_problem(pts, tau_w=1e-3)
+    Q = inputs.torus_area_uniform(2, seed=12)
+    # queries must lie on the reconstructed surface
+    P = orc.Problem(prob)
+    Q = np.array([orc.cp(P, q) for q in Q])
+    res = orc.solve(prob, Q, 96, seed=1)
+    exact = inputs.exact_u(inputs.torus_problem(), Q)
+    # Monte Carlo error plus truncation (tau_W) and reconstruction bias
+    assert np.all(np.abs(res["u"] - exact) < 5 * res["stderr"] + 0.05), (res["u"], exact, res["stderr"])
