@@ -142,9 +142,14 @@ typedef struct {
 /* Fills `opt` with the defaults listed above. */
 void mpwos_options_default(mpwos_options* opt);
 
-/* Creates an immutable manifold (Sec. 2.1).  For POINT_CLOUD the points are
- * copied to the device, and a uniform grid over them is built and kept
- * resident until mpwos_manifold_destroy.  EINVAL for a bad descriptor. */
+/* Creates an immutable manifold (Sec. 2.1).  For POINT_CLOUD (Sec. 2.3.2) the
+ * points are copied to the device once and the reconstruction is built there
+ * and kept resident until mpwos_manifold_destroy: the k nearest cloud points
+ * of every cloud point (grid tiles with BF16 MFMA distance estimates and an
+ * exact FP64 re-rank; a KD-tree search where the tile result cannot be shown
+ * exact), each point's local quadratic patch, and a KD-tree for the
+ * nearest-point queries of the walk.  EINVAL for a bad descriptor or a
+ * non-finite coordinate. */
 mpwos_status mpwos_manifold_create(const mpwos_manifold_desc* desc, mpwos_manifold** out);
 
 /* Releases a manifold.  EBUSY while a served request still references it. */
@@ -153,7 +158,10 @@ mpwos_status mpwos_manifold_destroy(mpwos_manifold* m);
 /* Solves at n_queries points of M (Algorithm 1, eq. mc_estimator).
  *   f, g: source and boundary data; g must be NULL exactly when M is closed.
  *   c: the screening constant sigma > 0 of eq. surface_pde.
- *   queries: n_queries x n doubles, each on M.
+ *   queries: n_queries x n doubles, each on M (within 1e-9 (1 + |q|)); on a
+ *            POINT_CLOUD each within two local spacings of the reconstructed
+ *            surface, and the walk starts from its projection cp_h(q), the
+ *            point the estimate refers to.  EOFFMANIFOLD otherwise.
  *   n_walks: paths per query, >= 1.
  *   eps: boundary-layer width (eq. boundary_layer), > 0 on SPHERE_CAP, ignored when closed.
  *   seed: key of the Philox4x32-10 stream; walk w of query q at step k draws
@@ -227,6 +235,12 @@ mpwos_status mpwos_server_destroy(mpwos_server* s);
  * into y (host), computed by the device code of the given precision. */
 mpwos_status mpwos_debug_cp(const mpwos_manifold* m, const double* x, int64_t n_points,
                             int32_t precision, double* y);
+
+/* Build facts of a POINT_CLOUD manifold (Sec. 2.3.2): how many cloud points
+ * took the KD-tree search because the grid-tile kNN result could not be shown
+ * exact, and the largest local spacing h (mean distance from a point to its
+ * k-1 other neighbours).  EINVAL for another kind. */
+mpwos_status mpwos_debug_cloud_info(const mpwos_manifold* m, int64_t* knn_fallback_points, double* max_spacing);
 
 /* Radius fraction s = t/r of a Green sample for uniforms u (host arrays of
  * `count`), dimension n and X = sqrt(sigma) r: the device inverse of the

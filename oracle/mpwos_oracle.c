@@ -820,7 +820,10 @@ static int orc_walk(const orc_ctx* C, const double* y0, uint32_t q, uint32_t w, 
   *truncated = 0;
   orc_pc_result pc_cur, pc_next;
   if (P->manifold == ORC_POINT_CLOUD) {
+    /* a point-cloud query is an ambient point near the cloud: the walk
+     * starts from its projection onto the reconstructed surface */
     if (orc_pc_project(P, Y, &pc_cur)) { free(buf); return ORC_EINVAL; }
+    memcpy(Y, pc_cur.y, sizeof(double) * 3);
   }
   if (boundary && orc_in_layer(P, Y)) {
     orc_cap_cp_gamma(P, Y, yg);
@@ -965,11 +968,22 @@ int orc_solve(const orc_problem* P, const double* queries, int64_t nq, int64_t n
   if (!tmp) return ORC_ENOMEM;
   for (int64_t q = 0; q < nq; ++q) {
     const double* y = queries + q * n;
-    if (orc_cp(P, y, tmp)) { free(tmp); return ORC_EOFFMANIFOLD; }
-    double d2 = 0.0, sc = 0.0;
-    for (int i = 0; i < n; ++i) { d2 += (tmp[i] - y[i]) * (tmp[i] - y[i]); sc += y[i] * y[i]; }
-    double tol = (P->manifold == ORC_POINT_CLOUD) ? 1e-6 : 1e-9;
-    if (sqrt(d2) > tol * (1.0 + sqrt(sc))) { free(tmp); return ORC_EOFFMANIFOLD; }
+    double tol;
+    if (P->manifold == ORC_POINT_CLOUD) {
+      /* within two local spacings of the reconstructed surface */
+      orc_pc_result pc;
+      if (orc_pc_project(P, y, &pc)) { free(tmp); return ORC_EOFFMANIFOLD; }
+      for (int i = 0; i < 3; ++i) tmp[i] = pc.y[i];
+      tol = 2.0 * pc.h_mean;
+    } else {
+      if (orc_cp(P, y, tmp)) { free(tmp); return ORC_EOFFMANIFOLD; }
+      double sc = 0.0;
+      for (int i = 0; i < n; ++i) sc += y[i] * y[i];
+      tol = 1e-9 * (1.0 + sqrt(sc));
+    }
+    double d2 = 0.0;
+    for (int i = 0; i < n; ++i) d2 += (tmp[i] - y[i]) * (tmp[i] - y[i]);
+    if (!(sqrt(d2) <= tol)) { free(tmp); return ORC_EOFFMANIFOLD; }
   }
   free(tmp);
   orc_ctx C;

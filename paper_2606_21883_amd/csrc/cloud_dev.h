@@ -1,0 +1,154 @@
+// Device side of the point-cloud closest-point map (Sec. 2.3.2: nearest-
+// neighbour search with local reconstruction).  cp_h(x): the nearest cloud
+// point p of x (KD-tree search, ties to the lower original index), then the
+// Newton foot point of x on p's local quadratic patch (built once per
+// manifold from p's k nearest cloud points).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernel_args.h"
+#include "mpwos_dev.h"
+
+namespace mpwos {
+
+// |x - p|^2 evaluated as ((dx dx + dy dy) + dz dz) without contraction in FP64,
+// so that equal inputs give equal bits on every path that compares distances.
+__device__ __forceinline__ double dist2_exact(const double* x, float px, float py, float pz) {
+  const double dx = (double)px - x[0], dy = (double)py - x[1], dz = (double)pz - x[2];
+  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+__device__ __forceinline__ float dist2_exact(const float* x, float px, float py, float pz) {
+  const float dx = px - x[0], dy = py - x[1], dz = pz - x[2];
+  return dx * dx + dy * dy + dz * dz;
+}
+
+template <class T>
+__device__ __forceinline__ T box_dist2(const KdNode& nd, const T* x) {
+  T s = (T)0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    T e = (T)0;
+    if (x[d] < (T)nd.lo[d]) e = (T)nd.lo[d] - x[d];
+    else if (x[d] > (T)nd.hi[d]) e = x[d] - (T)nd.hi[d];
+    s += e * e;
+  }
+  return s;
+}
+
+// Nearest cloud point of x: depth-first search, nearer child first, pruning
+// boxes farther than the best distance (a box at exactly the best distance is
+// still visited so that the index tie-break is exact).  Returns the original
+// index.
+template <class T>
+__device__ __forceinline__ int32_t kd_nearest(const CloudDev& c, const T* x) {
+  int32_t stack[64];
+  int sp = 0;
+  stack[sp++] = 0;
+  T best = (T)3.0e38;
+  int32_t bidx = 0x7fffffff;
+  while (sp > 0) {
+    const KdNode nd = c.nodes[stack[--sp]];
+    if (box_dist2(nd, x) > best) continue;
+    if (nd.left < 0) {
+      for (int32_t i = nd.start; i < nd.start + nd.count; ++i) {
+        const float4 p = c.kd_pts[i];
+        const T d2 = dist2_exact(x, p.x, p.y, p.z);
+        const int32_t id = __float_as_int(p.w);
+        if (d2 < best || (d2 == best && id < bidx)) {
+          best = d2;
+          bidx = id;
+        }
+      }
+    } else {
+      const T dl = box_dist2(c.nodes[nd.left], x);
+      const T dr = box_dist2(c.nodes[nd.right], x);
+      // the nearer child is pushed last, so it is searched first
+      if (dl <= dr) {
+        if (dr <= best && sp < 64) stack[sp++] = nd.right;
+        if (dl <= best && sp < 64) stack[sp++] = nd.left;
+      } else {
+        if (dl <= best && sp < 64) stack[sp++] = nd.left;
+        if (dr <= best && sp < 64) stack[sp++] = nd.right;
+      }
+    }
+  }
+  return bidx;
+}
+
+template <class T>
+struct CloudProj {
+  T y[3];
+  T kappa;   // largest |principal curvature| of the patch at the foot point
+  T hmean;   // local spacing of the nearest cloud point
+};
+
+// Newton foot point of x on patch P: minimise (a - ax)^2 + (b - bx)^2 +
+// (h(a,b) - hx)^2 from (ax, bx), then the curvature of the patch there
+// (eigenvalues of the shape operator I^-1 II of the graph).
+template <class T>
+__device__ __forceinline__ CloudProj<T> patch_project(const Patch<T>& P, const T* x, int iters) {
+  const T d0 = x[0] - P.cen[0], d1 = x[1] - P.cen[1], d2 = x[2] - P.cen[2];
+  const T ax = d0 * P.e1[0] + d1 * P.e1[1] + d2 * P.e1[2];
+  const T bx = d0 * P.e2[0] + d1 * P.e2[1] + d2 * P.e2[2];
+  const T hx = d0 * P.n[0] + d1 * P.n[1] + d2 * P.n[2];
+  const T* c = P.c;
+  T a = ax, b = bx;
+  for (int it = 0; it < iters; ++it) {
+    const T h = c[0] + c[1] * a + c[2] * b + c[3] * a * a + c[4] * a * b + c[5] * b * b;
+    const T ha = c[1] + (T)2 * c[3] * a + c[4] * b;
+    const T hb = c[2] + c[4] * a + (T)2 * c[5] * b;
+    const T res = h - hx;
+    const T ga = (a - ax) + res * ha;
+    const T gb = (b - bx) + res * hb;
+    const T Haa = (T)1 + ha * ha + res * (T)2 * c[3];
+    const T Hab = ha * hb + res * c[4];
+    const T Hbb = (T)1 + hb * hb + res * (T)2 * c[5];
+    const T det = Haa * Hbb - Hab * Hab;
+    if (det == (T)0) break;
+    a -= (Hbb * ga - Hab * gb) / det;
+    b -= (Haa * gb - Hab * ga) / det;
+  }
+  CloudProj<T> out;
+  const T h = c[0] + c[1] * a + c[2] * b + c[3] * a * a + c[4] * a * b + c[5] * b * b;
+  for (int i = 0; i < 3; ++i) out.y[i] = P.cen[i] + a * P.e1[i] + b * P.e2[i] + h * P.n[i];
+  const T ha = c[1] + (T)2 * c[3] * a + c[4] * b;
+  const T hb = c[2] + c[4] * a + (T)2 * c[5] * b;
+  const T gf = sqrt_((T)1 + ha * ha + hb * hb);
+  const T I11 = (T)1 + ha * ha, I12 = ha * hb, I22 = (T)1 + hb * hb;
+  const T L11 = (T)2 * c[3] / gf, L12 = c[4] / gf, L22 = (T)2 * c[5] / gf;
+  const T dI = I11 * I22 - I12 * I12;
+  const T S11 = (I22 * L11 - I12 * L12) / dI, S12 = (I22 * L12 - I12 * L22) / dI;
+  const T S21 = (I11 * L12 - I12 * L11) / dI, S22 = (I11 * L22 - I12 * L12) / dI;
+  const T tr = S11 + S22, dt = S11 * S22 - S12 * S21;
+  T disc = tr * tr / (T)4 - dt;
+  disc = disc > (T)0 ? disc : (T)0;
+  const T sq = sqrt_(disc);
+  const T k1 = abs_(tr / (T)2 + sq), k2 = abs_(tr / (T)2 - sq);
+  out.kappa = k1 > k2 ? k1 : k2;
+  out.hmean = P.hmean;
+  return out;
+}
+
+template <class T>
+__device__ __forceinline__ const Patch<T>& patch_of(const CloudDev& c, int32_t i);
+template <>
+__device__ __forceinline__ const Patch<double>& patch_of<double>(const CloudDev& c, int32_t i) { return c.patch64[i]; }
+template <>
+__device__ __forceinline__ const Patch<float>& patch_of<float>(const CloudDev& c, int32_t i) { return c.patch32[i]; }
+
+template <class T>
+__device__ __forceinline__ CloudProj<T> cloud_cp(const CloudDev& c, const T* x) {
+  const int32_t nn = kd_nearest<T>(c, x);
+  const Patch<T> P = patch_of<T>(c, nn);
+  return patch_project<T>(P, x, c.newton_iters);
+}
+
+// rho_geo of a projected point: curvature rule on the fitted patch, or c_h h.
+template <class T>
+__device__ __forceinline__ double cloud_rho_geo(const WalkArgs& a, const CloudProj<T>& p) {
+  if (a.cloud.radius_rule == 1) return a.c_h * (double)p.hmean;
+  return a.c_kappa / (1.0 + (double)p.kappa);
+}
+
+}  // namespace mpwos

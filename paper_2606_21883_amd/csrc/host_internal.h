@@ -20,6 +20,8 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
                            int64_t nq, int64_t nw, double eps, uint64_t seed, const mpwos_options& o,
                            WalkArgs& a);
 mpwos_status launch_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue);
+mpwos_status cloud_check_queries(const WalkArgs& a, const double* dq, int64_t nq, hipStream_t s);
+mpwos_status check_queries_host(const mpwos_manifold* man, const WalkArgs& a, const double* q, int64_t nq);
 
 // walk_lane.hip
 hipError_t launch_walk_lane(const WalkArgs& a, int grid, int block, hipStream_t s);
@@ -42,7 +44,7 @@ mpwos_status cloud_create(const mpwos_manifold_desc& d, hipStream_t s, CloudStat
 void cloud_destroy(CloudState* c);
 double cloud_spacing_rmax(const CloudState* c, const mpwos_options& o);
 void cloud_fill_args(const CloudState* c, const mpwos_options& o, WalkArgs& a);
-mpwos_status launch_cloud_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue);
-hipError_t launch_cloud_cp(const WalkArgs& a, const double* x, double* y, int64_t m, hipStream_t s);
+int64_t cloud_fallback_points(const CloudState* c);
+double cloud_max_spacing(const CloudState* c);
 
 }  // namespace mpwos

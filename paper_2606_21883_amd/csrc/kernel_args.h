@@ -64,18 +64,33 @@ struct InvTable {
   double x2max;           // X^2 of the last slice
 };
 
+// KD-tree node over the cloud: bounding box of its points, children (internal
+// node) or a range of the KD-ordered point array (leaf: left < 0).
+struct KdNode {
+  float lo[3], hi[3];
+  int32_t left, right;   // children; left = -1 marks a leaf
+  int32_t start, count;  // leaf points: kd_pts[start .. start + count)
+};
+
+// Local quadratic patch of one cloud point: centroid, tangent frame e1, e2,
+// unit normal n, height field h(a,b) = c0 + c1 a + c2 b + c3 a^2 + c4 a b + c5 b^2
+// over (a, b) = ((x - cen).e1, (x - cen).e2), and the mean distance from the
+// point to its other k-1 neighbours.
+template <class T>
+struct Patch {
+  T cen[3], e1[3], e2[3], n[3], c[6], hmean;
+};
+
 struct CloudDev {
-  const float* pts;       // n_points x 3, sorted by grid cell
-  const int32_t* cell_start;  // ncell + 1
-  const int32_t* orig_idx;    // sorted position -> input index (tie-breaks)
+  const KdNode* nodes;
+  const float4* kd_pts;        // x, y, z, original index (bit pattern of an int32)
+  const Patch<double>* patch64; // indexed by original point index
+  const Patch<float>* patch32;
   int64_t n_points;
-  int32_t dims[3];
-  float lo[3];
-  float inv_h;            // 1 / cell size
-  float h;
-  int32_t k;              // neighbours
+  int32_t n_nodes;
+  int32_t k;                   // neighbours of the reconstruction
   int32_t newton_iters;
-  int32_t radius_rule;
+  int32_t radius_rule;         // 1 = spacing, otherwise curvature of the fitted patch
 };
 
 struct WalkArgs {

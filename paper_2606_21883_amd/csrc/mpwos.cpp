@@ -569,11 +569,33 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
   return MPWOS_OK;
 }
 
+// Every query on the manifold, for a host array of queries.
+mpwos_status check_queries_host(const mpwos_manifold* man, const WalkArgs& a, const double* q, int64_t nq) {
+  const mpwos_manifold_desc& d = man->desc;
+  if (d.kind != MPWOS_POINT_CLOUD) {
+    for (int64_t i = 0; i < nq; ++i)
+      if (!query_on_manifold(d, q + i * d.n))
+        return fail(MPWOS_EOFFMANIFOLD, "query " + std::to_string(i) + " is not on the manifold");
+    return MPWOS_OK;
+  }
+  hipStream_t s = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "query check stream");
+  double* dq = nullptr;
+  const size_t bytes = (size_t)nq * 3 * sizeof(double);
+  e = hipMalloc((void**)&dq, bytes);
+  if (e == hipSuccess) e = hipMemcpyAsync(dq, q, bytes, hipMemcpyHostToDevice, s);
+  mpwos_status st = e == hipSuccess ? cloud_check_queries(a, dq, nq, s) : hip_fail(e, "query check upload");
+  if (dq) (void)hipFree(dq);
+  (void)hipStreamDestroy(s);
+  return st;
+}
+
 // Walk kernel launch for a batch (queries/outputs already on the device).
 mpwos_status launch_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue) {
   const int64_t total = a.count;
   const int n_cu = device_cu_count();
-  if (a.n <= 3 && a.kind != MPWOS_POINT_CLOUD) {
+  if (a.n <= 3) {
     const int block = o.block_size ? o.block_size : 256;
     hipError_t e;
     if (a.persistent) {
@@ -596,7 +618,6 @@ mpwos_status launch_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, un
     if (e != hipSuccess) return hip_fail(e, "walk kernel launch");
     return MPWOS_OK;
   }
-  if (a.kind == MPWOS_POINT_CLOUD) return launch_cloud_walks(a, o, s, queue);
   return launch_group_walks(a, o, s, queue);
 }
 
@@ -663,6 +684,10 @@ extern "C" mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_
   double* dq = (double*)g_ctx.queries.p;
   if (o.device_io) HIP_TRY(hipMemcpyAsync(dq, queries, (size_t)n_queries * n * sizeof(double), hipMemcpyDeviceToDevice, s));
   else HIP_TRY(hipMemcpyAsync(dq, queries, (size_t)n_queries * n * sizeof(double), hipMemcpyHostToDevice, s));
+  if (d.kind == MPWOS_POINT_CLOUD) {
+    st = cloud_check_queries(a, dq, n_queries, s);
+    if (st) return st;
+  }
   unsigned long long* dstat = (unsigned long long*)g_ctx.stats.p;
   HIP_TRY(launch_zero_u64(dstat, 8, s));
   double* du = (double*)g_ctx.u.p;
@@ -746,11 +771,19 @@ extern "C" mpwos_status mpwos_debug_cp(const mpwos_manifold* m, const double* x,
   double* dx = (double*)g_ctx.tmp.p;
   double* dy = dx + (size_t)n_points * a.n;
   HIP_TRY(hipMemcpyAsync(dx, x, bytes, hipMemcpyHostToDevice, s));
-  hipError_t e = (a.kind == MPWOS_POINT_CLOUD) ? launch_cloud_cp(a, dx, dy, n_points, s)
-                                               : launch_cp_points(a, dx, dy, n_points, s);
+  hipError_t e = launch_cp_points(a, dx, dy, n_points, s);
   if (e != hipSuccess) return hip_fail(e, "cp kernel");
   HIP_TRY(hipMemcpyAsync(y, dy, bytes, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  return MPWOS_OK;
+}
+
+extern "C" mpwos_status mpwos_debug_cloud_info(const mpwos_manifold* m, int64_t* knn_fallback_points,
+                                               double* max_spacing) {
+  g_last_error.clear();
+  if (!m || !m->cloud) return fail(MPWOS_EINVAL, "not a point-cloud manifold");
+  if (knn_fallback_points) *knn_fallback_points = cloud_fallback_points(m->cloud);
+  if (max_spacing) *max_spacing = cloud_max_spacing(m->cloud);
   return MPWOS_OK;
 }
 

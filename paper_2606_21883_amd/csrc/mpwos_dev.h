@@ -592,7 +592,14 @@ __device__ __forceinline__ T source(const WalkArgs& a, const T* z, const T* y, i
       if (comp) {
         const T rz = sqrt_(z[0] * z[0] + z[1] * z[1]);
         const T dz = sqrt_((rz - R) * (rz - R) + z[2] * z[2]);
-        v += c0 * (torus_neg_lap<T>(R, dz, sphi, cpsi, spsi) - nl);
+        if (a.kind == kCloud) {
+          // a reconstructed surface moves the foot point off z's normal line:
+          // the correction takes z's own angles in both terms
+          const T zs = z[1] / rz, zc = (rz - R) / dz, zp = z[2] / dz;
+          v += c0 * (torus_neg_lap<T>(R, dz, zs, zc, zp) - torus_neg_lap<T>(R, tube, zs, zc, zp));
+        } else {
+          v += c0 * (torus_neg_lap<T>(R, dz, sphi, cpsi, spsi) - nl);
+        }
       }
       return v;
     }

@@ -279,6 +279,7 @@ mpwos_status mpwos_submit(mpwos_server* s, const mpwos_request* req, uint64_t* t
     R->table.assign(req->f.values, req->f.values + req->f.n_values);
   mpwos_status st = prepare_solve(req->manifold, &R->r.f, g, req->c, req->n_queries, req->n_walks, req->eps,
                                   req->seed, R->opt, R->args);
+  if (!st) st = check_queries_host(req->manifold, R->args, req->queries, req->n_queries);
   if (st) {
     delete R;
     std::lock_guard<std::mutex> lk(s->mu);

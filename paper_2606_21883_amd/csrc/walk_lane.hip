@@ -8,6 +8,7 @@
 //                uneven walk lengths (boundary problems) keep lanes busy.
 #include <hip/hip_runtime.h>
 
+#include "cloud_dev.h"
 #include "kernel_args.h"
 #include "mpwos_dev.h"
 
@@ -17,6 +18,7 @@ template <class T, int N>
 struct LaneState {
   T Y[N];
   double W, S, C;
+  double rg;           // point cloud: rho_geo from the reconstruction that produced Y
   uint32_t k, q, w;
   int64_t idx;
 };
@@ -73,6 +75,9 @@ __device__ __forceinline__ void closest_point(const WalkArgs& a, const T* x, T* 
     double xd[3] = {(double)x[0], (double)x[1], (double)x[2]}, yd[3];
     torus_cp_newton<double>(a.p[0], a.p[1], xd, yd, 16);
     for (int i = 0; i < 3; ++i) y[i] = (T)yd[i];
+  } else if constexpr (KIND == kCloud) {
+    const CloudProj<T> p = cloud_cp<T>(a.cloud, x);
+    for (int i = 0; i < 3; ++i) y[i] = p.y[i];
   } else {
     T s = (T)0;
     for (int i = 0; i < N; ++i) s += x[i] * x[i];
@@ -94,6 +99,13 @@ __device__ __forceinline__ bool walk_init(const WalkArgs& a, int64_t idx, LaneSt
   st.S = 0.0;
   st.C = 0.0;
   st.k = 0;
+  st.rg = 0.0;
+  if constexpr (KIND == kCloud) {
+    // the walk starts from the query's projection onto the reconstruction
+    const CloudProj<T> p = cloud_cp<T>(a.cloud, st.Y);
+    for (int i = 0; i < N; ++i) st.Y[i] = p.y[i];
+    st.rg = cloud_rho_geo(a, p);
+  }
   if constexpr (KIND == kCap) {
     if (cap_in_layer<T, N>(a, st.Y)) {
       T yg[N];
@@ -123,6 +135,11 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
     weights(a, r, c, om);
     X2 = a.sigma * r * r;
     if constexpr (sizeof(T) == 8) norm = radial_norm(a.law, X2);
+  } else if constexpr (KIND == kCloud) {
+    r = a.theta * st.rg;
+    weights(a, r, c, om);
+    X2 = a.sigma * r * r;
+    if constexpr (sizeof(T) == 8) norm = radial_norm(a.law, X2);
   } else {
     r = a.r0;
     c = a.c0;
@@ -132,6 +149,7 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
   const T rT = (T)r;
   // (ii) Theta = Y + r g/|g| and Y' = cp(Theta)
   T Yn[N];
+  double rg_next = 0.0;
   {
     const uint4 b = rs.block(st.k, 0, 0);
     T g[4];
@@ -142,7 +160,13 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
     const T ig = rsqrt_(gg);
     T Th[N];
     for (int i = 0; i < N; ++i) Th[i] = st.Y[i] + rT * (g[i] * ig);
-    closest_point<T, N, KIND>(a, Th, Yn);
+    if constexpr (KIND == kCloud) {
+      const CloudProj<T> p = cloud_cp<T>(a.cloud, Th);
+      for (int i = 0; i < N; ++i) Yn[i] = p.y[i];
+      rg_next = cloud_rho_geo(a, p);
+    } else {
+      closest_point<T, N, KIND>(a, Th, Yn);
+    }
   }
   // Green samples Z ~ rho(Y, .): radius from the radial law, direction uniform
   T Fsum = (T)0;
@@ -173,6 +197,7 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
   kahan_add(st.S, st.C, (st.W * om) * F);
   st.W = st.W * c;
   for (int i = 0; i < N; ++i) st.Y[i] = Yn[i];
+  if constexpr (KIND == kCloud) st.rg = rg_next;
   st.k += 1;
   if constexpr (KIND == kCap) {
     if (cap_in_layer<T, N>(a, st.Y)) {
@@ -373,12 +398,14 @@ __global__ __launch_bounds__(256) void copy_kernel(const uint4* __restrict__ src
       if (kind == kCap && n == 3) return FN<double, 3, kCap>(__VA_ARGS__);           \
       if (kind == kCap && n == 2) return FN<double, 2, kCap>(__VA_ARGS__);           \
       if (kind == kTorus && n == 3) return FN<double, 3, kTorus>(__VA_ARGS__);       \
+      if (kind == kCloud && n == 3) return FN<double, 3, kCloud>(__VA_ARGS__);       \
     } else {                                                                         \
       if (kind == kSphere && n == 2) return FN<float, 2, kSphere>(__VA_ARGS__);      \
       if (kind == kSphere && n == 3) return FN<float, 3, kSphere>(__VA_ARGS__);      \
       if (kind == kCap && n == 3) return FN<float, 3, kCap>(__VA_ARGS__);            \
       if (kind == kCap && n == 2) return FN<float, 2, kCap>(__VA_ARGS__);            \
       if (kind == kTorus && n == 3) return FN<float, 3, kTorus>(__VA_ARGS__);        \
+      if (kind == kCloud && n == 3) return FN<float, 3, kCloud>(__VA_ARGS__);        \
     }                                                                                \
   } while (0)
 
@@ -442,7 +469,7 @@ int lane_occupancy(int kind, int n, bool fp64, int block) {
 }
 
 bool lane_supported(int kind, int n) {
-  return (n == 2 || n == 3) && (kind == kSphere || kind == kCap || (kind == kTorus && n == 3));
+  return (n == 2 || n == 3) && (kind == kSphere || kind == kCap || ((kind == kTorus || kind == kCloud) && n == 3));
 }
 
 hipError_t launch_reduce(const double* walk_S, const int32_t* walk_K, int64_t nq, int64_t nw, int64_t max_steps,

@@ -80,10 +80,21 @@ def torus_area_uniform(nq, R=1.0, a=0.3, seed=1):
 
 
 def torus_point_cloud(npts, R=1.0, a=0.3, noise=1e-4, seed=1):
-    """Area-uniform torus samples plus isotropic Gaussian noise N(0, noise^2 I)."""
+    """Area-uniform torus samples plus isotropic Gaussian noise N(0, noise^2 I),
+    rounded to FP32 (the precision a cloud is stored in), returned as float64."""
     pts = torus_area_uniform(npts, R, a, seed)
     rng = np.random.default_rng(seed + 1000)
-    return pts + noise * rng.standard_normal(pts.shape)
+    pts = pts + noise * rng.standard_normal(pts.shape)
+    return pts.astype(np.float32).astype(np.float64)
+
+
+def torus_near_points(m, offset, R=1.0, a=0.3, seed=1):
+    """Points at distance up to `offset` from the torus along random directions."""
+    base = torus_area_uniform(m, R, a, seed)
+    rng = np.random.default_rng(seed + 2000)
+    d = rng.standard_normal(base.shape)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return base + offset * rng.uniform(-1.0, 1.0, (m, 1)) * d
 
 
 # ---------------------------------------------------------------------------
@@ -212,6 +223,11 @@ def config(name, scale=1.0, seed=1):
         return hypersphere_problem(1000), hypersphere_queries(sz(1024, 2), 1000, seed), sz(2048)
     if name == "torus":
         return torus_problem(), torus_area_uniform(sz(8192), 1.0, 0.3, seed), sz(1024)
+    if name == "cloud":
+        # 1e6 noisy torus samples (queries: analytic torus points, within the
+        # noise and the fit error of the reconstruction)
+        pts = torus_point_cloud(sz(1_000_000, 2000), 1.0, 0.3, 1e-4, seed)
+        return point_cloud_problem(pts), torus_area_uniform(sz(8192), 1.0, 0.3, seed + 7), sz(1024)
     raise ValueError(name)
 
 

@@ -71,7 +71,8 @@ class ServerStats(ctypes.Structure):
 
 EXPORTS = ["mpwos_options_default", "mpwos_manifold_create", "mpwos_manifold_destroy", "mpwos_solve",
            "mpwos_last_error", "mpwos_server_create", "mpwos_submit", "mpwos_poll", "mpwos_wait",
-           "mpwos_server_stats_get", "mpwos_server_destroy", "mpwos_debug_cp", "mpwos_debug_radial_inv",
+           "mpwos_server_stats_get", "mpwos_server_destroy", "mpwos_debug_cp", "mpwos_debug_cloud_info",
+           "mpwos_debug_radial_inv",
            "mpwos_debug_philox", "mpwos_copy_probe", "mpwos_version"]
 
 _lib = None
@@ -106,6 +107,7 @@ def lib():
         L.mpwos_server_stats_get.argtypes = [vp, vp]
         L.mpwos_server_destroy.argtypes = [vp]
         L.mpwos_debug_cp.argtypes = [vp, vp, i64, i32, vp]
+        L.mpwos_debug_cloud_info.argtypes = [vp, vp, vp]
         L.mpwos_debug_radial_inv.argtypes = [i32, d, vp, i64, i32, vp]
         L.mpwos_debug_philox.argtypes = [vp, ctypes.c_uint64, i64, vp]
         L.mpwos_copy_probe.argtypes = [i64, i32, vp]
@@ -271,6 +273,13 @@ def debug_cp(manifold, x, precision="fp64"):
     Y = np.zeros_like(X)
     _check(lib().mpwos_debug_cp(manifold.handle, _ptr(X), X.shape[0], PRECISION[precision], _ptr(Y)))
     return Y
+
+
+def debug_cloud_info(manifold):
+    fb = ctypes.c_int64()
+    h = ctypes.c_double()
+    _check(lib().mpwos_debug_cloud_info(manifold.handle, ctypes.byref(fb), ctypes.byref(h)))
+    return {"knn_fallback_points": fb.value, "max_spacing": h.value}
 
 
 def debug_radial_inv(n, X, u, precision="fp64"):

@@ -1,0 +1,139 @@
+"""GPU parity of the point-cloud path (Sec. 2.3.2: nearest-neighbour search with
+local reconstruction) against the oracle: the FP64 projection cp_h at cloud
+points (which checks every patch, hence the device kNN build, through both the
+MFMA grid-tile path and the KD-tree path) and at points off the surface; the
+FP32 projection; whole FP64 walks on a small cloud, walk by walk; truncated
+walks on the full 1e6-point cloud in the launch form the benchmark times; FP32
+statistics; query validation."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_21883_amd import inputs, mpwos
+from tests.gpu_util import announce, compare_walks
+
+pytestmark = pytest.mark.gpu
+
+
+def cloud(npts, seed, k=16, **kw):
+    p = inputs.point_cloud_problem(inputs.torus_point_cloud(npts, seed=seed), k_nn=k)
+    p.update(kw)
+    return p
+
+
+@pytest.mark.parametrize("k", [16, 28])
+def test_cp_at_cloud_points_matches_oracle(k):
+    """cp_h of a cloud point is the Newton foot point on its own patch: every
+    sampled point checks its k nearest neighbours and its fit."""
+    prob = cloud(20000, seed=31, k=k)
+    announce(f"cloud cp at cloud points k={k}")
+    m = mpwos.Manifold(prob)
+    info = mpwos.debug_cloud_info(m)
+    if k <= 24:
+        # the grid tiles settle almost every point
+        assert info["knn_fallback_points"] < 0.05 * 20000, info
+    else:
+        assert info["knn_fallback_points"] == 20000, info
+    P = oracle.Problem(prob)
+    pts = prob["points"][np.random.default_rng(1).choice(20000, 600, replace=False)]
+    y_gpu = mpwos.debug_cp(m, pts, "fp64")
+    y_orc = np.array([oracle.cp(P, x) for x in pts])
+    np.testing.assert_allclose(y_gpu, y_orc, rtol=0, atol=1e-11)
+    m.close()
+
+
+def test_cp_off_surface_matches_oracle():
+    prob = cloud(20000, seed=32)
+    announce("cloud cp off surface")
+    m = mpwos.Manifold(prob)
+    P = oracle.Problem(prob)
+    x = np.concatenate([inputs.torus_near_points(400, 0.02, seed=3), inputs.torus_near_points(200, 0.25, seed=4)])
+    y_gpu = mpwos.debug_cp(m, x, "fp64")
+    y_orc = np.array([oracle.cp(P, xi) for xi in x])
+    err = np.linalg.norm(y_gpu - y_orc, axis=1)
+    # far from the surface the foot point extrapolates the patch: Newton amplifies rounding there
+    assert np.max(err[:400]) < 1e-10, np.max(err[:400])
+    assert np.mean(err[400:] < 1e-8) >= 0.99, np.sort(err)[-5:]
+    # FP32: the same reconstruction, single-precision search and Newton
+    y32 = mpwos.debug_cp(m, x[:400], "fp32")
+    assert np.max(np.linalg.norm(y32 - y_orc[:400], axis=1)) < 2e-5
+    m.close()
+
+
+def test_walks_fp64_match_oracle_walk_by_walk():
+    prob = cloud(12000, seed=33, tau_w=1e-3)
+    P = oracle.Problem(prob)
+    Q = inputs.torus_area_uniform(6, seed=34)
+    announce("cloud walks fp64 plain 6x48")
+    gpu = mpwos.solve(prob, Q, 48, 9, walk_outputs=True, precision="fp64")
+    orc = oracle.solve(P, Q, 48, 9)
+    frac = compare_walks(gpu, orc, prob, tol=1e-9, min_frac=0.999)
+    assert frac == 1.0
+    np.testing.assert_allclose(gpu["u"], orc["u"], rtol=1e-10, atol=1e-12)
+    announce("cloud walks fp64 persistent 6x48")
+    per = mpwos.solve(prob, Q, 48, 9, walk_outputs=True, precision="fp64", persistent=1)
+    assert np.array_equal(per["walk_S"], gpu["walk_S"])
+
+
+def test_full_cloud_truncated_walks_sampled():
+    """1e6-point cloud at the benchmark's launch form (persistent lanes): a
+    sample of walks truncated after 30 steps against the oracle."""
+    prob, Q, _ = inputs.config("cloud")
+    prob = dict(prob, max_steps=30)
+    announce("cloud 1e6 build")
+    m = mpwos.Manifold(prob)
+    info = mpwos.debug_cloud_info(m)
+    assert info["knn_fallback_points"] < 0.05 * len(prob["points"]), info
+    Qs = Q[:4]
+    announce("cloud 1e6 truncated walks fp64 persistent 4x4")
+    gpu = mpwos.solve(prob, Qs, 4, 3, manifold=m, walk_outputs=True, precision="fp64", persistent=1)
+    assert gpu["stats"]["truncated"] == 16
+    P = oracle.Problem(prob)
+    orc = oracle.solve(P, Qs, 4, 3)
+    compare_walks(gpu, orc, prob, tol=1e-9, min_frac=0.999)
+    announce("cloud 1e6 truncated walks fp32 persistent")
+    g32 = mpwos.solve(prob, Qs, 4, 3, manifold=m, walk_outputs=True, precision="fp32", persistent=1)
+    assert np.all(g32["walk_K"] == 30)
+    assert np.max(np.abs(g32["walk_S"] - orc["walk_S"])) < 1e-3 * (1 + np.max(np.abs(orc["walk_S"])))
+    m.close()
+
+
+def test_fp32_statistics_and_closed_form():
+    prob = cloud(12000, seed=35, tau_w=1e-3)
+    Q = inputs.torus_area_uniform(16, seed=36)
+    m = mpwos.Manifold(prob)
+    announce("cloud fp64 vs fp32 16x2048")
+    r64 = mpwos.solve(prob, Q, 2048, 5, manifold=m, precision="fp64")
+    r32 = mpwos.solve(prob, Q, 2048, 5, manifold=m, precision="fp32", persistent=1)
+    se = np.sqrt(r64["stderr"] ** 2 + r32["stderr"] ** 2)
+    assert np.all(np.abs(r64["u"] - r32["u"]) < 5 * se + 1e-6), (r64["u"] - r32["u"], se)
+    # against u at the projected queries: Monte Carlo, tau_W truncation and reconstruction
+    y = mpwos.debug_cp(m, Q, "fp64")
+    exact = inputs.exact_u(prob, y)
+    assert np.all(np.abs(r64["u"] - exact) < 5 * r64["stderr"] + 0.02), (r64["u"] - exact, r64["stderr"])
+    m.close()
+
+
+def test_query_far_from_cloud_is_rejected():
+    prob = cloud(8000, seed=37)
+    m = mpwos.Manifold(prob)
+    Q = inputs.torus_area_uniform(3, seed=38)
+    Q[1] *= 1.3
+    with pytest.raises(mpwos.MpwosError) as e:
+        mpwos.solve(prob, Q, 4, 1, manifold=m)
+    assert e.value.status == mpwos.EOFFMANIFOLD
+    m.close()
+
+
+def test_server_serves_cloud_requests():
+    prob = cloud(12000, seed=39, tau_w=1e-3)
+    Q = inputs.torus_area_uniform(8, seed=40)
+    m = mpwos.Manifold(prob)
+    announce("cloud served vs solo")
+    solo = mpwos.solve(prob, Q, 256, 2, manifold=m, precision="fp32", persistent=1)
+    srv = mpwos.Server(4 << 30)
+    t = srv.submit(m, prob, Q, 256, 2, precision="fp32", persistent=1)
+    out = srv.wait(t, 120_000)
+    srv.close()
+    assert np.array_equal(out["u"], solo["u"])
+    m.close()

@@ -117,3 +117,25 @@ def test_point_cloud_estimator_unbiased_within_reconstruction(orc):
     exact = inputs.exact_u(inputs.torus_problem(), Q)
     # Monte Carlo error plus truncation (tau_W) and reconstruction bias
     assert np.all(np.abs(res["u"] - exact) < 5 * res["stderr"] + 0.05), (res["u"], exact, res["stderr"])
+
+
+def test_cloud_query_starts_from_its_projection(orc):
+    """A point-cloud query near the surface is evaluated at its projection: on a
+    planar cloud (reconstructed exactly, so cp_h(cp_h(q)) = cp_h(q)) the walks
+    from q and from cp_h(q) coincide, and a query beyond two local spacings is
+    rejected."""
+    rng = np.random.default_rng(5)
+    g = np.stack(np.meshgrid(np.linspace(-1, 1, 61), np.linspace(-1, 1, 61)), -1).reshape(-1, 2)
+    g = g + rng.uniform(-0.004, 0.004, g.shape)
+    pts = np.concatenate([g, np.zeros((len(g), 1))], 1)
+    prob = cloud_problem(pts, tau_w=1e-2)
+    P = orc.Problem(prob)
+    h = np.mean(np.sqrt(orc.knn(pts, pts[1900], 16)[1][1:]))
+    y = np.array([[0.1, -0.2, 0.0], [0.3, 0.25, 0.0]])
+    q = y + np.array([0.0, 0.0, 0.5 * h])
+    rq = orc.solve(P, q, 8, seed=4)
+    ry = orc.solve(P, y, 8, seed=4)
+    np.testing.assert_allclose(rq["walk_S"], ry["walk_S"], rtol=1e-9, atol=1e-12)
+    assert np.array_equal(rq["walk_K"], ry["walk_K"])
+    with pytest.raises(ValueError):
+        orc.solve(P, y + np.array([0.0, 0.0, 4.0 * h]), 2, seed=4)
