@@ -252,7 +252,7 @@ def solve(problem, queries, n_walks, seed, threads=None):
     nq = Q.shape[0]
     nw = int(n_walks)
     if threads is None:
-        threads = os.cpu_count() or 1
+        threads = min(16, os.cpu_count() or 1)
     wS = np.zeros((nq, nw), dtype=np.float64)
     wK = np.zeros((nq, nw), dtype=np.int32)
     u = np.zeros(nq, dtype=np.float64)

@@ -874,7 +874,7 @@ static int orc_walk(const orc_ctx* C, const double* y0, uint32_t q, uint32_t w, 
       orc_sum_add(&S, &comp, W * orc_g_omega(P, yg));
       break;
     }
-    if (!boundary && W < P->tau_w) break;
+    if (!boundary && !(W >= P->tau_w)) break;
     if ((int64_t)k >= P->max_steps) { *truncated = 1; break; }
   }
   *S_out = S + comp;

@@ -73,7 +73,9 @@ __device__ __forceinline__ int32_t kd_nearest(const CloudDev& c, const T* x) {
       }
     }
   }
-  return bidx;
+  // a non-finite x matches no point: fall back to point 0 so the caller's
+  // patch read stays in bounds (the walk then ends on its non-finite state)
+  return (uint32_t)bidx < (uint32_t)c.n_points ? bidx : 0;
 }
 
 template <class T>

@@ -153,7 +153,7 @@ __device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB
 #pragma unroll
   for (int i = 0; i < 4 * MB; ++i) st.Y[i] = Yn[i];
   st.k += 1;
-  if (st.W < a.tau_w) return true;
+  if (!(st.W >= a.tau_w)) return true;  // NaN ends the walk too
   return (int64_t)st.k >= a.max_steps;
 }
 

@@ -207,8 +207,11 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
       return true;
     }
   } else {
-    if (st.W < a.tau_w) return true;
+    // a non-finite weight (NaN from a degenerate projection) also ends the walk
+    if (!(st.W >= a.tau_w)) return true;
   }
+  // a non-finite state ends the walk instead of running it to max_steps
+  if (!(st.Y[0] == st.Y[0])) return true;
   return (int64_t)st.k >= a.max_steps;
 }
 
