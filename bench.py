@@ -11,9 +11,21 @@ metric: walk-steps/s (one walk-step = one iteration of Algorithm 1 with its
 N_V = 1 Green sample), with queries/s and the closed-form RMSE beside it.
 The same workload in the plain one-launch-per-solve FP64 form, and the FP64
 CPU oracle on a bounded sample of the workload, are reported for comparison.
+
+The roofline of the dominant kernel (the closed-sphere FP32 walk) is the
+VALU issue rate: the algorithmic operations of one walk-step (step_ops) are
+weighted by their measured issue cost relative to a full-rate FP32 FMA
+(valu_weights, from the library's VALU probe run live) and divided by the
+kernel's time from HIP events on its stream; the peak is 256 CUs x 128
+FP32 lanes per clock x 2.4 GHz (157.3 TFLOP/s counted per FMA).
+
+Other workloads (--workload) time the remaining configurations in the same
+way for profiling; they are not the headline line.
 """
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -23,39 +35,99 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_SLOTS = 256 * 64 * 2.4e9      # VALU lane-slots per second: 256 CUs x 64 lanes x 2.4 GHz
+METRIC = "walk-steps/s and queries/s at fixed RMSE vs FP64 oracle; served p50/p99 ms"
+# Full-rate VALU lane-operations per second: 256 CUs x 128 FP32 FMA lanes per
+# clock x 2.4 GHz, the published FP32 vector peak (157.3 TFLOP/s) counted per
+# FMA.  The VALU probe reaches about 72% of it with a pure fma_f32 stream.
+PEAK_SLOTS = 256 * 128 * 2.4e9
+
+# HBM bytes of one launch of the closed-sphere FP32 persistent walk kernel on
+# the headline workload (4096 x 4096 walks), from rocprofv3 --pmc FETCH_SIZE
+# and WRITE_SIZE (KiB per dispatch), each scaled by the reading of a plain
+# copy kernel of known size (FETCH_SIZE reads half the bytes a copy moves,
+# WRITE_SIZE all of them).  Valid only for the kernel sources they were taken
+# on (their SHA-256 below); any change to those sources makes traffic null.
+TRAFFIC = {
+    "kernel_sha256": None,
+    "fetch_kib": None, "fetch_factor": 2.0,
+    "write_kib": None, "write_factor": 1.0,
+}
+KERNEL_SOURCES = ["walk_lane.hip", "mpwos_dev.h", "kernel_args.h", "cloud_dev.h"]
 
 
-def slots_per_step(n, kind, precision, n_v=1):
-    """Algorithmic VALU issue slots of one walk-step (model documented in the design doc).
+def kernel_sha256():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2606_21883_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
-    Philox4x32-10 block: 10 rounds x (2 wide multiplies at 4 slots + 2 three-way xors) = 100.
-    Box-Muller pair: log, sqrt, sin, cos at 4 slots + 3 multiplies = 19.
-    Per coordinate: sum of squares, scale-and-add, projection scale = 3 per vector pass.
+
+def step_ops(kind, n, n_v=1):
+    """Algorithmic VALU operations of one FP32-mixed walk-step (n <= 3, one lane
+    per walk), by issue class.  Counts what the method as specified must do:
+      - Philox4x32-10 blocks: the direction needs one block, each Green sample
+        2 ceil(n/2) normal words plus one radius word; 10 rounds of two 32x32->64
+        multiplies and four xors per block (the key schedule is scalar);
+      - two operations per uniform, and per Box-Muller pair log, sqrt, cos and
+        sin (one of cos/sin dropped for odd n) plus three multiplies;
+      - per n-vector: a squared norm (n), a reciprocal square root and a scaled
+        update or projection (n + 1), for the direction, Theta, cp(Theta), the
+        Green direction, Z and cp(Z);
+      - the Green radius from the inverse-CDF table (w = sqrt(min(u, 1-u)),
+        index, two loads, one interpolation);
+      - the source (the pair product, its compensation with one reciprocal);
+      - FP64: the score update W omega F with Neumaier compensation, W c, the
+        stop test.
     """
-    nb_dir = (n + 3) // 4
-    rw = 2 * ((n + 1) // 2)
-    nb_green = max(nb_dir, rw // 4 + 1)
-    pairs = (n + 1) // 2
-    philox = 100 * (nb_dir + n_v * nb_green)
-    words = 3 * (2 * pairs * (1 + n_v) + n_v)
-    bm = 19 * pairs * (1 + n_v)
-    vec = (3 * n + 8) * 2 * (1 + n_v)          # normalise + update + project, Theta and each Z
-    radial = 60 if precision == "fp32" else 400
-    source = 16
-    accum = 12
-    extra = 0
+    half = (n + 1) // 2
+    odd = n % 2
+    green_words = 2 * half + 1
+    blocks = 1 + n_v * math.ceil(green_words / 4)
+    ops = {"mad_u64_u32": 20 * blocks, "xor_b32": 40 * blocks, "f32": 0, "trans": 0, "f64": 13}
+    words = 2 * half + n_v * green_words
+    ops["f32"] += 2 * words
+    sets = 1 + n_v
+    ops["trans"] += sets * (4 * half - odd)
+    ops["f32"] += sets * (3 * half - odd)
+    vec = n + 1 + n                       # norm, scale, update / projection
+    ops["f32"] += vec * (2 + 2 * n_v)     # direction, cp(Theta), and per sample: direction, cp(Z)
+    ops["trans"] += 2 + 2 * n_v
+    ops["f32"] += n_v * (10 + 8)          # radius table, source
+    ops["trans"] += n_v * (1 + 1)
+    ops["f32"] += 2                       # step counter and bound
     if kind == "cap":
-        extra = 25 + 100                         # delta_Gamma and the per-step weight series
-        radial = 15 if precision == "fp32" else 600
-    return philox + words + bm + vec + n_v * (radial + source) + accum + extra
+        ops["f32"] += 25 + 8              # delta_Gamma, two-slice table
+        ops["trans"] += 2
+        ops["f64"] += 40                  # per-step weight series and radial norm
+    return ops
 
 
-def make_workload():
+def valu_weights():
+    """Issue cost of each operation class relative to fma_f32, from the VALU
+    probe: isolated rates for xor and FP64, and for transcendentals and the
+    64-bit multiply-add the extra time they add beside three independent FMAs
+    (the walk interleaves them with other work)."""
+    from paper_2606_21883_amd import mpwos
+    r = {op: mpwos.valu_probe(op) for op in mpwos.VALU_OPS}
+    base = r["fma_f32"]
+
+    def mixed(name):
+        return max(0.0, (4.0 / r[name] - 3.0 / base) * base)
+
+    w = {"f32": 1.0, "xor_b32": base / r["xor_b32"], "f64": base / r["fma_f64"],
+         "trans": mixed("sin_f32+3fma"), "mad_u64_u32": mixed("mad_u64_u32+3fma")}
+    return w, r
+
+
+def make_workload(name, scale=1.0):
     from paper_2606_21883_amd import inputs
-    ps, Qs, nws = inputs.config("sphere")
-    pc, Qc, nwc = inputs.config("cap")
-    return [("sphere", ps, Qs, nws), ("cap", pc, Qc, nwc)]
+    if name == "sphere":
+        ps, Qs, nws = inputs.config("sphere", scale)
+        pc, Qc, nwc = inputs.config("cap", scale)
+        return [("sphere", ps, Qs, nws), ("cap", pc, Qc, nwc)]
+    p, Q, nw = inputs.config(name, scale)
+    return [(name, p, Q, nw)]
 
 
 def run_gpu(work, steps, warmup, precision, persistent):
@@ -80,11 +152,19 @@ def run_gpu(work, steps, warmup, precision, persistent):
             st.append(s)
         return st
 
-    for _ in range(warmup):
+    t0 = time.perf_counter()
+    for i in range(warmup):
         one_step()
+        torch.cuda.synchronize()
+        print(f"[bench] {precision} warmup {i + 1}/{warmup} {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = [one_step() for _ in range(steps)]
+    stats = []
+    for i in range(steps):
+        stats.append(one_step())
+        print(f"[bench] {precision} step {i + 1}/{steps} queued {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     res = {"seconds": dt, "steps": steps}
@@ -93,8 +173,12 @@ def run_gpu(work, steps, warmup, precision, persistent):
     for i, (name, prob, q, nw, m, u, se) in enumerate(items):
         kms = float(np.mean([s[i]["kernel_ms"] for s in stats]))
         ws = stats[0][i]["walk_steps"]
-        exact = inputs.exact_u(prob, q.cpu().numpy())
+        Qh = q.cpu().numpy()
+        if prob["manifold"] == "point_cloud":
+            Qh = mpwos.debug_cp(m, Qh, "fp64")       # the estimate refers to cp_h(q)
+        exact = inputs.exact_u(prob, Qh)
         per[name] = {"kernel_ms": kms, "walk_steps": ws, "k_mean": stats[0][i]["k_mean"],
+                     "walk_steps_per_s": ws / (kms * 1e-3),
                      "rmse": inputs.rmse(u.cpu().numpy(), exact),
                      "mean_stderr": float(np.sqrt(np.mean(se.cpu().numpy() ** 2))),
                      "n_queries": int(q.shape[0]), "n_walks": int(nw)}
@@ -104,24 +188,46 @@ def run_gpu(work, steps, warmup, precision, persistent):
     return res
 
 
-def cpu_baseline(work, budget_s=20.0):
-    """The FP64 oracle on the host cores over a bounded sample of the workload."""
+def cpu_baseline(work):
+    """The FP64 oracle on the host cores over a bounded sample of the workload
+    (about 10-20 s of CPU work)."""
     import oracle
-    threads = os.cpu_count() or 1
+    threads = min(16, os.cpu_count() or 1)
+    sample = {"sphere": (64, 4096), "cap": (64, 4096)}
     total_steps, total_t, parts = 0, 0.0, []
     for name, prob, Q, nw in work:
-        nq, nws = (32, 512) if name == "sphere" else (32, 1536)
+        nq, nws = sample.get(name, (8, 256))
         t0 = time.perf_counter()
         r = oracle.solve(prob, Q[:nq], nws, 0, threads=threads)
         dt = time.perf_counter() - t0
         k = int(r["walk_K"].sum())
         total_steps += k
         total_t += dt
-        parts.append(f"{name}: {nq} queries x {nws} walks ({k} walk-steps)")
-        if total_t > budget_s:
-            break
+        parts.append(f"{name}: {nq} queries x {nws} walks ({k} walk-steps, {dt:.1f} s)")
     return {"value": total_steps / total_t, "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
-            "sample": "; ".join(parts) + f"; {total_t:.1f} s"}
+            "sample": "; ".join(parts)}
+
+
+def roofline(fast, dom_name, kind, n, n_v, precision):
+    w, rates = valu_weights()
+    ops = step_ops(kind, n, n_v)
+    slots = sum(ops[k] * w[k] for k in ops)
+    dom = fast["per"][dom_name]
+    achieved = slots * dom["walk_steps"] / (dom["kernel_ms"] * 1e-3)
+    traffic = None
+    if TRAFFIC["kernel_sha256"] is not None and TRAFFIC["kernel_sha256"] == kernel_sha256() \
+            and dom_name == "sphere" and dom["walk_steps"] == 4096 * 4096 * 174 and precision == "fp32":
+        traffic = 1024 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_factor"] +
+                          TRAFFIC["write_kib"] * TRAFFIC["write_factor"])
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "Tslot/s",
+            "frac": achieved / PEAK_SLOTS, "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch",
+            "kernel": f"walk_lane_kernel<float,{n},{kind}> persistent" if precision == "fp32"
+            else f"walk_lane_kernel<double,{n},{kind}>",
+            "launch_walk_steps": dom["walk_steps"], "launch_ms": dom["kernel_ms"],
+            "ops_per_walk_step": ops, "slot_weights": {k: round(v, 3) for k, v in w.items()},
+            "slots_per_walk_step": slots,
+            "probe_lane_ops_per_s": {k: float("%.4g" % v) for k, v in rates.items()}}
 
 
 def main():
@@ -129,28 +235,36 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sphere",
+                    choices=["sphere", "circle", "torus", "cloud", "hyper100", "hyper1000"],
+                    help="sphere (closed + cap) is the headline workload; the others are for profiling")
+    ap.add_argument("--scale", type=float, default=1.0, help="shrink queries and walks (profiling only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
+    ap.add_argument("--no-roofline", action="store_true", help="skip the VALU probe (profiling runs)")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None, help="time only one form (profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="time the library's plain copy kernel on BYTES (HBM calibration) and exit")
+    ap.add_argument("--valu-probe", action="store_true", help="print the VALU operation rates and exit")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the walk path runs on a "
+              "single device here)", file=sys.stderr)
+        sys.exit(2)
     if args.copy_probe:
         from paper_2606_21883_amd import mpwos
         ms = mpwos.copy_probe(args.copy_probe, 5)
         print(json.dumps({"copy_bytes": args.copy_probe, "ms": ms,
                           "GB_per_s": 2 * args.copy_probe / (ms * 1e-3) / 1e9}), flush=True)
         return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
-        sys.exit(2)
+    if args.valu_probe:
+        w, r = valu_weights()
+        print(json.dumps({"lane_ops_per_s": r, "weights": w, "peak_lane_ops_per_s": PEAK_SLOTS}), flush=True)
+        return
     rank = int(os.environ.get("RANK", "0"))
-    work = make_workload()
-    out = {}
-    if args.only != "fp64":
-        fast = run_gpu(work, args.steps, args.warmup, "fp32", 1)
-    else:
-        fast = run_gpu(work, args.steps, args.warmup, "fp64", 0)
+    work = make_workload(args.workload, args.scale)
+    prec = "fp64" if args.only == "fp64" else "fp32"
+    fast = run_gpu(work, args.steps, args.warmup, prec, 0 if prec == "fp64" else 1)
     slow = None
     if not args.no_fp64 and args.only is None:
         slow = run_gpu(work, max(1, min(args.steps, 3)), 1, "fp64", 0)
@@ -158,27 +272,36 @@ def main():
     ms = 1e3 * fast["seconds"] / fast["steps"]
     value = ws * fast["steps"] / fast["seconds"]
     nq_total = sum(p["n_queries"] for p in fast["per"].values())
-    prec = "fp32" if args.only != "fp64" else "fp64"
-    dom = fast["per"]["sphere"]
-    slots = slots_per_step(3, "sphere", prec)
-    achieved = slots * dom["walk_steps"] / (dom["kernel_ms"] * 1e-3) / 1e12
+    first = work[0]
+    prob0 = first[1]
+    desc = {
+        "sphere": "unit sphere S^2: closed (u=x1x2, sigma=2, 4096 queries x 4096 walks) + cap x3>0 "
+                  "(Dirichlet g=u, sigma=0.5, eps=1e-3, 4096 x 4096)",
+        "circle": "unit circle S^1: u=cos(3 theta), sigma=1, 64 queries x 1000 walks",
+        "torus": "implicit torus R=1, a=0.3: u=sin(phi)cos(2psi), sigma=1, 8192 queries x 1024 walks",
+        "cloud": "point-cloud torus, 1e6 points, noise 1e-4, k=16 + quadratic fit: 8192 queries x 1024 walks",
+        "hyper100": "S^99 in R^100: u=x1x2, sigma=1, 1024 queries x 2048 walks",
+        "hyper1000": "S^999 in R^1000: u=x1x2, sigma=1, 1024 queries x 2048 walks",
+    }[args.workload]
+    if args.scale != 1.0:
+        desc += f" (scaled by {args.scale})"
     out = {
-        "metric": "walk-steps/s", "value": value, "unit": "walk-steps/s", "n_gpus": 1,
+        "metric": METRIC, "value": value, "unit": "walk-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "fp32" if prec == "fp32" else "fp64",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": "unit sphere S^2: closed (u=x1x2, sigma=2, 4096 queries x 4096 walks) + "
-                               "cap x3>0 (Dirichlet g=u, sigma=0.5, eps=1e-3, 4096 x 4096)",
-                   "precision": "fp32 walk, fp64 weights/scores" if prec == "fp32" else "fp64",
-                   "form": "persistent queue-refill" if prec == "fp32" else "plain",
-                   "n_v": 1, "tau_w": 1e-8, "theta": 0.95, "c_kappa": 1.2, "parallelism": "single-gpu"},
+        "config": {"workload": desc,
+                   "precision": "f32 walk arithmetic, f64 weights/scores/per-query sums" if prec == "fp32"
+                   else "f64",
+                   "form": "persistent queue-refill" if prec == "fp32" else "plain one launch per solve",
+                   "n_v": prob0.get("n_v", 1), "tau_w": prob0.get("tau_w"), "theta": prob0.get("theta"),
+                   "c_kappa": prob0.get("c_kappa"), "seed": 0},
         "queries_per_s": nq_total * fast["steps"] / fast["seconds"],
         "per_solve": fast["per"],
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_SLOTS / 1e12, "unit": "Tslot/s",
-                     "frac": achieved / (PEAK_SLOTS / 1e12), "traffic": None,
-                     "kernel": "walk_lane_kernel<float,3,sphere> (persistent)",
-                     "slots_per_walk_step": slots},
     }
+    n0 = prob0["n"]
+    if not args.no_roofline and n0 <= 3 and prob0["manifold"] == "sphere":
+        out["roofline"] = roofline(fast, first[0], "sphere", n0, prob0.get("n_v", 1), prec)
     if slow is not None:
         v64 = slow["walk_steps_per_step"] * slow["steps"] / slow["seconds"]
         out["fp64_plain"] = {"value": v64, "ms_per_step": 1e3 * slow["seconds"] / slow["steps"],

@@ -257,6 +257,16 @@ mpwos_status mpwos_debug_philox(const uint32_t ctr[4], uint64_t seed, int64_t co
  * calibrate HBM traffic counters. */
 mpwos_status mpwos_copy_probe(int64_t bytes, int32_t reps, double* ms);
 
+/* Throughput of one VALU operation, in lane-operations per second, from a
+ * kernel of 8 independent dependency chains per lane over 16 blocks of 256
+ * lanes per compute unit.  op: 0 fma_f32, 1 fma_f64, 2 mad_u64_u32 (32x32->64
+ * multiply-add), 3 mul_hi_u32, 4 log_f32, 5 sin_f32, 6 sqrt_f32, 7 rsq_f32,
+ * 8 rcp_f32, 9 xor_b32, 10 add_f64; mixed streams (each step one operation
+ * beside three independent fma_f32, all four counted): 11 sin_f32,
+ * 12 mad_u64_u32.  Used to weight the operations of the walk-step cost model.
+ * EINVAL for another op. */
+mpwos_status mpwos_valu_probe(int32_t op, double* lane_ops_per_s);
+
 /* Library version string. */
 const char* mpwos_version(void);
 

@@ -35,6 +35,7 @@ hipError_t launch_radial_inv(const WalkArgs& a, const double* u, double* s_out, 
                              hipStream_t s);
 hipError_t launch_philox(const uint32_t* c, uint64_t seed, uint32_t* out, int64_t m, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
+hipError_t launch_valu_probe(int op, uint32_t seed, int32_t iters, uint32_t* out, int blocks, hipStream_t s);
 
 // walk_group.hip
 mpwos_status launch_group_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue);

@@ -62,6 +62,7 @@ struct InvTable {
   int32_t mu;             // points per half
   int32_t mx;             // slices in X^2 (1 when X is fixed)
   double x2max;           // X^2 of the last slice
+  double x2scale;         // (mx - 1) / x2max: X^2 -> slice position
 };
 
 // KD-tree node over the cloud: bounding box of its points, children (internal
@@ -99,6 +100,7 @@ struct WalkArgs {
   double p[4];
   double sigma, lam_sqrt, eps, theta, c_kappa, c_h, tau_w;
   int32_t n_v, comp, precision, persistent;
+  double inv_R;                // 1 / p[0] (the radius the source families scale by)
   int64_t max_steps;
   FnDev f, g;
   // constant-radius data (closed analytic manifolds)

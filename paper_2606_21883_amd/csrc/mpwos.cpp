@@ -245,7 +245,9 @@ static std::mutex g_tab_lock;
 static std::map<TableKey, TableVal> g_tables;
 
 static mpwos_status get_table(const HostLaw& h, int mx, double x2max, InvTable& t) {
-  const int mu = 513;
+  // 1025 points per half keep linear interpolation in w within 1.1e-6 of the
+  // root for every n (the worst case is n = 2 near u = 0, where s ~ sqrt(u / ln(1/u)))
+  const int mu = 1025;
   TableKey key{h.n, mx, x2max};
   std::lock_guard<std::mutex> g(g_tab_lock);
   auto it = g_tables.find(key);
@@ -283,6 +285,7 @@ static mpwos_status get_table(const HostLaw& h, int mx, double x2max, InvTable& 
   t.mu = it->second.mu;
   t.mx = mx;
   t.x2max = x2max;
+  t.x2scale = mx > 1 ? (double)(mx - 1) / x2max : 0.0;
   return MPWOS_OK;
 }
 
@@ -523,6 +526,7 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
   a.n = d.n;
   for (int i = 0; i < 4; ++i) a.p[i] = d.p[i];
   a.sigma = sigma;
+  a.inv_R = 1.0 / d.p[0];
   a.lam_sqrt = std::sqrt(sigma);
   a.eps = eps;
   a.theta = o.theta;
@@ -840,19 +844,50 @@ extern "C" mpwos_status mpwos_copy_probe(int64_t bytes, int32_t reps, double* ms
   mpwos_status st = context_init(g_ctx);
   if (st) return st;
   void *src = nullptr, *dst = nullptr;
-  HIP_TRY(hipMalloc(&src, (size_t)bytes));
-  HIP_TRY(hipMalloc(&dst, (size_t)bytes));
   hipStream_t s = g_ctx.stream;
-  HIP_TRY(hipMemsetAsync(src, 1, (size_t)bytes, s));
-  HIP_TRY(launch_copy(src, dst, bytes, s));
-  HIP_TRY(hipEventRecord(g_ctx.ev[0], s));
-  for (int r = 0; r < reps; ++r) HIP_TRY(launch_copy(src, dst, bytes, s));
-  HIP_TRY(hipEventRecord(g_ctx.ev[1], s));
-  HIP_TRY(hipEventSynchronize(g_ctx.ev[1]));
+  hipError_t e = hipMalloc(&src, (size_t)bytes);
+  if (e == hipSuccess) e = hipMalloc(&dst, (size_t)bytes);
+  if (e == hipSuccess) e = hipMemsetAsync(src, 1, (size_t)bytes, s);
+  if (e == hipSuccess) e = launch_copy(src, dst, bytes, s);
+  if (e == hipSuccess) e = hipEventRecord(g_ctx.ev[0], s);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy(src, dst, bytes, s);
+  if (e == hipSuccess) e = hipEventRecord(g_ctx.ev[1], s);
+  if (e == hipSuccess) e = hipEventSynchronize(g_ctx.ev[1]);
   float t = 0.f;
-  HIP_TRY(hipEventElapsedTime(&t, g_ctx.ev[0], g_ctx.ev[1]));
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, g_ctx.ev[0], g_ctx.ev[1]);
+  if (src) (void)hipFree(src);
+  if (dst) (void)hipFree(dst);
+  if (e != hipSuccess) return hip_fail(e, "copy probe");
   *ms = t / reps;
-  (void)hipFree(src);
-  (void)hipFree(dst);
+  return MPWOS_OK;
+}
+
+extern "C" mpwos_status mpwos_valu_probe(int32_t op, double* lane_ops_per_s) {
+  g_last_error.clear();
+  if (op < 0 || op > 12 || !lane_ops_per_s) return fail(MPWOS_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> guard(g_ctx.lock);
+  mpwos_status st = context_init(g_ctx);
+  if (st) return st;
+  const int blocks = g_ctx.n_cu * 16;
+  const int32_t iters = 4096;
+  uint32_t* out = nullptr;
+  hipStream_t s = g_ctx.stream;
+  hipError_t e = hipMalloc((void**)&out, (size_t)blocks * 256 * sizeof(uint32_t));
+  if (e == hipSuccess) e = launch_valu_probe(op, 1u, iters, out, blocks, s);
+  float best = 1e30f;
+  for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+    e = hipEventRecord(g_ctx.ev[0], s);
+    if (e == hipSuccess) e = launch_valu_probe(op, (uint32_t)(r + 2), iters, out, blocks, s);
+    if (e == hipSuccess) e = hipEventRecord(g_ctx.ev[1], s);
+    if (e == hipSuccess) e = hipEventSynchronize(g_ctx.ev[1]);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, g_ctx.ev[0], g_ctx.ev[1]);
+    best = std::min(best, t);
+  }
+  if (out) (void)hipFree(out);
+  if (e != hipSuccess) return hip_fail(e, "valu probe");
+  // operations per chain step: the xor chain issues two, the mixed streams four
+  const double per_chain = (op == 9) ? 2.0 : (op >= 11 ? 4.0 : 1.0);
+  *lane_ops_per_s = (double)blocks * 256.0 * 8.0 * per_chain * (double)iters / (best * 1e-3);
   return MPWOS_OK;
 }

@@ -79,6 +79,9 @@ __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double log_(double x) { return log(x); }
 __device__ __forceinline__ float log_(float x) { return 0.6931471805599453f * __builtin_amdgcn_logf(x); }
+// a / b: IEEE division in FP64; a times the hardware reciprocal (1 ulp) in FP32
+__device__ __forceinline__ double over_(double a, double b) { return a / b; }
+__device__ __forceinline__ float over_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double abs_(double x) { return fabs(x); }
 __device__ __forceinline__ float abs_(float x) { return fabsf(x); }
 
@@ -196,7 +199,7 @@ __device__ __forceinline__ double table_guess64(const InvTable& t, double u, dou
     hi = a < b ? b : a;
     return a + fr * (b - a);
   }
-  const double xpos = X2 / t.x2max * (double)(t.mx - 1);
+  const double xpos = X2 * t.x2scale;
   int k = (int)xpos;
   k = k < 0 ? 0 : (k > t.mx - 2 ? t.mx - 2 : k);
   const double fx = xpos - (double)k;
@@ -220,7 +223,7 @@ __device__ __forceinline__ float table_guess32(const InvTable& t, float u, float
     const float* r = t.s32 + (up ? t.mu : 0);
     return r[i] + fr * (r[i + 1] - r[i]);
   }
-  const float xpos = X2 / (float)t.x2max * (float)(t.mx - 1);
+  const float xpos = X2 * (float)t.x2scale;
   int k = (int)xpos;
   k = k < 0 ? 0 : (k > t.mx - 2 ? t.mx - 2 : k);
   const float fx = xpos - (float)k;
@@ -260,17 +263,11 @@ __device__ __forceinline__ double radial_inv64(const WalkArgs& a, double u, doub
 // FP32: table guess, then (lower half, fixed X) one Newton step with the FP32
 // law.  In the upper half F is near 1 and known only to FP32 absolute
 // precision while F' -> 0, so the sqrt(1-u) table alone is the better value.
+// Inverse of the radial CDF in FP32: the table alone (linear in w, within
+// about 1e-6 of the root for every n, below the binary32 resolution of the
+// walk's positions at the radii used).
 __device__ __forceinline__ float radial_inv32(const WalkArgs& a, float u, float X2) {
-  float s = table_guess32(a.tab, u, X2);
-  if (a.const_r && u <= 0.5f) {
-    s = fminf(fmaxf(s, 1e-20f), 1.0f);
-    const RadialEval<float> e = radial_eval_fixed<float>(a.law, a.fixed, s);
-    if (e.pdf > 0.0f) {
-      const float sn = s - (e.F - u) / e.pdf;
-      if (sn > 0.0f && sn < 1.0f) s = sn;
-    }
-  }
-  return s;
+  return table_guess32(a.tab, u, X2);
 }
 
 // ---------------------------------------------------------------------------
@@ -545,16 +542,16 @@ __device__ __forceinline__ T source(const WalkArgs& a, const T* z, const T* y, i
     case kFnConst: return (T)f.coef[0];
     case kFnSphPair: {
       const T R = (T)a.p[0];
-      const T iR = (T)1 / R;
+      const T iR = (T)a.inv_R;
       const T fv = (T)f.coef[0] * (y[f.idx[0]] * iR) * (y[f.idx[1]] * iR);
       if (!comp) return fv;
       T zz = (T)0;
       for (int i = 0; i < n; ++i) zz += z[i] * z[i];
-      return fv + (T)(f.lam * f.u_scale) * fv * (R * R / zz - (T)1);
+      return fv + (T)(f.lam * f.u_scale) * fv * (over_(R * R, zz) - (T)1);
     }
     case kFnCircle: {
       const T R = (T)a.p[0];
-      const T iR = (T)1 / R;
+      const T iR = (T)a.inv_R;
       // cos(k th), sin(k th) from the unit vector by the angle-addition recurrence
       const T cx = y[0] * iR, sx = y[1] * iR;
       T ck = (T)1, sk = (T)0;
@@ -566,7 +563,7 @@ __device__ __forceinline__ T source(const WalkArgs& a, const T* z, const T* y, i
       const T fv = (T)f.coef[0] * ck + (T)f.coef[1] * sk;
       if (!comp) return fv;
       const T zz = z[0] * z[0] + z[1] * z[1];
-      return fv + (T)(f.lam * f.u_scale) * fv * (R * R / zz - (T)1);
+      return fv + (T)(f.lam * f.u_scale) * fv * (over_(R * R, zz) - (T)1);
     }
     case kFnLegendre: {
       const T R = (T)a.p[0];
@@ -575,7 +572,7 @@ __device__ __forceinline__ T source(const WalkArgs& a, const T* z, const T* y, i
       if (!comp) return fv;
       T zz = (T)0;
       for (int i = 0; i < n; ++i) zz += z[i] * z[i];
-      return fv + legendre_lap<T>(f.coef, a.p[0], a.sigma, t) * (R * R / zz - (T)1);
+      return fv + legendre_lap<T>(f.coef, a.p[0], a.sigma, t) * (over_(R * R, zz) - (T)1);
     }
     case kFnTorus: {
       const T R = (T)a.p[0], tube = (T)a.p[1];
@@ -617,7 +614,7 @@ __device__ __forceinline__ T source(const WalkArgs& a, const T* z, const T* y, i
       if (!comp) return (T)fv;
       const double us = (1.0 - fr) * f.values[f.m + i0] + fr * f.values[f.m + i1];
       const T zz = z[0] * z[0] + z[1] * z[1];
-      return (T)fv + (T)(fv - a.sigma * us) * (R * R / zz - (T)1);
+      return (T)fv + (T)(fv - a.sigma * us) * (over_(R * R, zz) - (T)1);
     }
   }
   return (T)0;

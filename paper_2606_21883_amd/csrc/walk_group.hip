@@ -139,7 +139,7 @@ __device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB
       // cp(Z) = R Z/|Z|; f_Omega(cp Z) = coef (Z_i/|Z|)(Z_j/|Z|)
       const T fv = (T)f.coef[0] * (zi * zj / zz);
       v = fv;
-      if (a.comp) v += (T)(f.lam * f.u_scale) * fv * (R * R / zz - (T)1);
+      if (a.comp) v += (T)(f.lam * f.u_scale) * fv * (over_(R * R, zz) - (T)1);
     } else if (f.kind == kFnConst) {
       v = (T)f.coef[0];
     } else {
@@ -147,7 +147,7 @@ __device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB
     }
     Fsum += v;
   }
-  const double F = (double)Fsum / (double)a.n_v;
+  const double F = a.n_v == 1 ? (double)Fsum : (double)Fsum / (double)a.n_v;
   kahan_add(st.S, st.C, (st.W * a.om0) * F);
   st.W = st.W * a.c0;
 #pragma unroll

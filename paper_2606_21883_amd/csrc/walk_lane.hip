@@ -193,7 +193,7 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
     closest_point<T, N, KIND>(a, Z, Zc);
     Fsum += source<T>(a, Z, Zc, N);
   }
-  const double F = (double)Fsum / (double)a.n_v;
+  const double F = a.n_v == 1 ? (double)Fsum : (double)Fsum / (double)a.n_v;
   kahan_add(st.S, st.C, (st.W * om) * F);
   st.W = st.W * c;
   for (int i = 0; i < N; ++i) st.Y[i] = Yn[i];
@@ -391,6 +391,124 @@ __global__ void philox_kernel(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3
 __global__ __launch_bounds__(256) void copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t m) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
+}
+
+// VALU throughput probe: 8 independent dependency chains of one operation per
+// lane, so the issue rate of that operation (not its latency) bounds the run.
+// OP: 0 fma_f32, 1 fma_f64, 2 mad_u64_u32, 3 mul_hi_u32, 4 log_f32, 5 sin_f32,
+//     6 sqrt_f32, 7 rsq_f32, 8 rcp_f32, 9 xor_b32, 10 add_f64,
+//     11 sin_f32 + 3 fma_f32, 12 mad_u64_u32 + 3 fma_f32 (mixed streams).
+template <int OP>
+__global__ __launch_bounds__(256) void valu_probe_kernel(uint32_t seed, int32_t iters, uint32_t* out) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t acc = 0;
+  if constexpr (OP == 0 || OP >= 4 && OP <= 8) {
+    float a[8];
+    const float b = 0.999f + (float)(seed & 7) * 1e-6f, c = 1e-3f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = 1.0f + (float)((t + 3 * i + seed) & 1023) * 1e-4f;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        if constexpr (OP == 0) a[i] = fmaf(a[i], b, c);
+        if constexpr (OP == 4) a[i] = __builtin_amdgcn_logf(fabsf(a[i]));
+        if constexpr (OP == 5) a[i] = __builtin_amdgcn_sinf(a[i]);
+        if constexpr (OP == 6) a[i] = __builtin_amdgcn_sqrtf(a[i]);
+        if constexpr (OP == 7) a[i] = __builtin_amdgcn_rsqf(a[i]);
+        if constexpr (OP == 8) a[i] = __builtin_amdgcn_rcpf(a[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc ^= __float_as_uint(a[i]);
+  } else if constexpr (OP == 11 || OP == 12) {
+    // a transcendental (11: sin_f32) or a 64-bit multiply-add (12: mad_u64_u32)
+    // per chain step, beside three independent fma_f32: does it overlap them?
+    float a[8], b[8];
+    uint32_t x[8], y[8];
+    const float bb = 0.999f + (float)(seed & 7) * 1e-6f, cc = 1e-3f;
+    const uint32_t m = 0xD2511F53u ^ (seed & 0xF0u);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      a[i] = 1.0f + (float)((t + 3 * i + seed) & 1023) * 1e-4f;
+      b[i] = a[i] * 0.5f;
+      x[i] = t * 0x85EBCA6Bu + (uint32_t)i * 0xC2B2AE35u + seed;
+      y[i] = x[i] * 0x9E3779B9u;
+    }
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        if constexpr (OP == 11) {
+          a[i] = __builtin_amdgcn_sinf(a[i]);
+        } else {
+          uint64_t p = ((uint64_t)y[i] << 32) | x[i];
+          p = (uint64_t)(uint32_t)(p >> 32) * m + p;
+          x[i] = (uint32_t)p;
+          y[i] = (uint32_t)(p >> 32);
+        }
+        b[i] = fmaf(b[i], bb, cc);
+        b[i] = fmaf(b[i], bb, cc);
+        b[i] = fmaf(b[i], bb, cc);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc ^= __float_as_uint(a[i]) ^ __float_as_uint(b[i]) ^ x[i] ^ y[i];
+  } else if constexpr (OP == 1 || OP == 10) {
+    double a[8];
+    const double b = 0.999 + (double)(seed & 7) * 1e-9, c = 1e-3;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = 1.0 + (double)((t + 3 * i + seed) & 1023) * 1e-4;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        if constexpr (OP == 1) a[i] = fma(a[i], b, c);
+        if constexpr (OP == 10) a[i] = a[i] + b;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc ^= (uint32_t)__double_as_longlong(a[i]);
+  } else {
+    uint32_t x[8], y[8];
+    const uint32_t m = 0xD2511F53u ^ (seed & 0xF0u);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      x[i] = t * 0x85EBCA6Bu + (uint32_t)i * 0xC2B2AE35u + seed;
+      y[i] = x[i] * 0x9E3779B9u;
+    }
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        if constexpr (OP == 2) {
+          // 32x32->64 multiply plus a 64-bit addend: the previous product, so
+          // the chain needs no register moves
+          uint64_t p = ((uint64_t)y[i] << 32) | x[i];
+          p = (uint64_t)(uint32_t)(p >> 32) * m + p;
+          x[i] = (uint32_t)p;
+          y[i] = (uint32_t)(p >> 32);
+        }
+        if constexpr (OP == 3) x[i] = __umulhi(x[i], m);
+        if constexpr (OP == 9) {
+          x[i] = x[i] ^ y[(i + 1) & 7];
+          y[i] = y[i] ^ x[(i + 3) & 7];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc ^= x[i] ^ y[i];
+  }
+  out[t] = acc;
+}
+
+hipError_t launch_valu_probe(int op, uint32_t seed, int32_t iters, uint32_t* out, int blocks, hipStream_t s) {
+  switch (op) {
+#define MPWOS_PROBE_CASE(K) \
+  case K: hipLaunchKernelGGL(valu_probe_kernel<K>, dim3(blocks), dim3(256), 0, s, seed, iters, out); break;
+    MPWOS_PROBE_CASE(0) MPWOS_PROBE_CASE(1) MPWOS_PROBE_CASE(2) MPWOS_PROBE_CASE(3) MPWOS_PROBE_CASE(4)
+    MPWOS_PROBE_CASE(5) MPWOS_PROBE_CASE(6) MPWOS_PROBE_CASE(7) MPWOS_PROBE_CASE(8) MPWOS_PROBE_CASE(9)
+    MPWOS_PROBE_CASE(10) MPWOS_PROBE_CASE(11) MPWOS_PROBE_CASE(12)
+#undef MPWOS_PROBE_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 #define MPWOS_LANE_DISPATCH(FN, ...)                                                   \

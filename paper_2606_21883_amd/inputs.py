@@ -207,7 +207,8 @@ def exact_u(prob, y):
 def config(name, scale=1.0, seed=1):
     """Return (problem, queries, n_walks) for a named configuration.
 
-    scale < 1 shrinks queries and walks (for tests); 1 is the full size."""
+    scale < 1 shrinks queries and walks (for tests); 1 is the full size.  The
+    point cloud keeps its 1e6 points at every scale."""
     def sz(v, lo=1):
         return max(lo, int(round(v * scale)))
 
@@ -226,7 +227,7 @@ def config(name, scale=1.0, seed=1):
     if name == "cloud":
         # 1e6 noisy torus samples (queries: analytic torus points, within the
         # noise and the fit error of the reconstruction)
-        pts = torus_point_cloud(sz(1_000_000, 2000), 1.0, 0.3, 1e-4, seed)
+        pts = torus_point_cloud(1_000_000, 1.0, 0.3, 1e-4, seed)
         return point_cloud_problem(pts), torus_area_uniform(sz(8192), 1.0, 0.3, seed + 7), sz(1024)
     raise ValueError(name)
 

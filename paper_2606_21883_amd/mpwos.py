@@ -73,7 +73,7 @@ EXPORTS = ["mpwos_options_default", "mpwos_manifold_create", "mpwos_manifold_des
            "mpwos_last_error", "mpwos_server_create", "mpwos_submit", "mpwos_poll", "mpwos_wait",
            "mpwos_server_stats_get", "mpwos_server_destroy", "mpwos_debug_cp", "mpwos_debug_cloud_info",
            "mpwos_debug_radial_inv",
-           "mpwos_debug_philox", "mpwos_copy_probe", "mpwos_version"]
+           "mpwos_debug_philox", "mpwos_copy_probe", "mpwos_valu_probe", "mpwos_version"]
 
 _lib = None
 
@@ -111,6 +111,7 @@ def lib():
         L.mpwos_debug_radial_inv.argtypes = [i32, d, vp, i64, i32, vp]
         L.mpwos_debug_philox.argtypes = [vp, ctypes.c_uint64, i64, vp]
         L.mpwos_copy_probe.argtypes = [i64, i32, vp]
+        L.mpwos_valu_probe.argtypes = [i32, vp]
         for nm in EXPORTS:
             if nm not in ("mpwos_options_default", "mpwos_last_error", "mpwos_version"):
                 getattr(L, nm).restype = ctypes.c_int
@@ -300,6 +301,18 @@ def copy_probe(nbytes, reps):
     ms = ctypes.c_double()
     _check(lib().mpwos_copy_probe(int(nbytes), int(reps), ctypes.byref(ms)))
     return ms.value
+
+
+VALU_OPS = ["fma_f32", "fma_f64", "mad_u64_u32", "mul_hi_u32", "log_f32", "sin_f32", "sqrt_f32", "rsq_f32",
+            "rcp_f32", "xor_b32", "add_f64",
+            "sin_f32+3fma", "mad_u64_u32+3fma"]
+
+
+def valu_probe(op):
+    """Lane-operations per second of one VALU operation (name from VALU_OPS)."""
+    r = ctypes.c_double()
+    _check(lib().mpwos_valu_probe(VALU_OPS.index(op), ctypes.byref(r)))
+    return r.value
 
 
 def version():
