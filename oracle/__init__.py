@@ -13,7 +13,8 @@ Problems are plain dicts (the same dict a test also hands to the GPU binding):
      "g": {...} (boundary only), "eps": float, "theta": 0.95, "c_kappa": 1.2,
      "tau_w": 1e-8, "n_v": 1, "compensation": "exact" | "none",
      "max_steps": int, "points": ndarray (point cloud), "k_nn": 16,
-     "radius_rule": "curvature" | "spacing" | "curvature_fit", "c_h": 2.4}
+     "radius_rule": "curvature" | "spacing" | "curvature_fit" | "curvature_bound", "c_h": 2.4,
+     "kappa_bound": float (curvature_bound only)}
 """
 import ctypes
 import os
@@ -27,7 +28,7 @@ MANIFOLDS = {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3}
 FN_KINDS = {"zero": 0, "const": 1, "sph_pair": 2, "circle_mode": 3, "legendre": 4,
             "torus_mode": 5, "table_s1": 6}
 COMP = {"none": 0, "exact": 1}
-RADIUS_RULES = {"curvature": 0, "spacing": 1, "curvature_fit": 2}
+RADIUS_RULES = {"curvature": 0, "spacing": 1, "curvature_fit": 2, "curvature_bound": 3}
 STATUS = {0: "OK", -1: "EINVAL", -2: "EOFFMANIFOLD", -3: "ENOMEM", 1: "WTRUNC"}
 
 
@@ -43,6 +44,7 @@ class _Problem(ctypes.Structure):
         ("c_kappa", ctypes.c_double), ("c_h", ctypes.c_double), ("tau_w", ctypes.c_double),
         ("n_v", ctypes.c_int32), ("compensation", ctypes.c_int32), ("max_steps", ctypes.c_int64),
         ("k_spacing", ctypes.c_int32), ("newton_iters", ctypes.c_int32),
+        ("kappa_bound", ctypes.c_double),
     ]
 
 
@@ -134,6 +136,7 @@ class Problem:
         s.max_steps = int(d.get("max_steps", 10_000_000))
         s.k_spacing = int(d.get("k_spacing", d.get("k_nn", 16)))
         s.newton_iters = int(d.get("newton_iters", 6))
+        s.kappa_bound = float(d.get("kappa_bound", 0.0))
         self.s = s
 
     @property

@@ -35,7 +35,8 @@ enum {
   ORC_FN_LEGENDRE = 4, ORC_FN_TORUS_MODE = 5, ORC_FN_TABLE_S1 = 6
 };
 enum { ORC_COMP_NONE = 0, ORC_COMP_EXACT = 1 };
-enum { ORC_RADIUS_CURVATURE = 0, ORC_RADIUS_SPACING = 1, ORC_RADIUS_CURVATURE_FIT = 2 };
+enum { ORC_RADIUS_CURVATURE = 0, ORC_RADIUS_SPACING = 1, ORC_RADIUS_CURVATURE_FIT = 2,
+       ORC_RADIUS_CURVATURE_BOUND = 3 };
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_EOFFMANIFOLD = -2, ORC_ENOMEM = -3, ORC_WTRUNC = 1 };
 
 #define ORC_MAXN 4096
@@ -58,6 +59,7 @@ typedef struct {
   int64_t max_steps;
   int32_t k_spacing;     /* neighbours for the spacing rule h(y) */
   int32_t newton_iters;  /* foot-point Newton iterations on the fitted patch */
+  double kappa_bound;    /* point cloud, CURVATURE_BOUND rule: a bound of kappa over M */
 } orc_problem;
 
 /* ------------------------------------------------------------------------- */
@@ -447,10 +449,12 @@ int orc_pc_project(const orc_problem* P, const double* x, orc_pc_result* res) {
   double nn[3] = {V[0 * 3 + 0], V[1 * 3 + 0], V[2 * 3 + 0]};
   /* least-squares height field h = a0 + a1 a + a2 b + a3 a^2 + a4 a b + a5 b^2 */
   double M[36] = {0}, rhs[6] = {0}, coef[6];
+  double ext = 0.0; /* support of the patch: largest |a| or |b| of its points */
   for (int j = 0; j < k; ++j) {
     double d[3];
     for (int c = 0; c < 3; ++c) d[c] = P->points[3 * idx[j] + c] - cen[c];
     double a = orc_dot(d, e1, 3), b = orc_dot(d, e2, 3), h = orc_dot(d, nn, 3);
+    ext = fmax(ext, fmax(fabs(a), fabs(b)));
     double phi[6] = {1.0, a, b, a * a, a * b, b * b};
     for (int r = 0; r < 6; ++r) {
       rhs[r] += phi[r] * h;
@@ -462,8 +466,12 @@ int orc_pc_project(const orc_problem* P, const double* x, orc_pc_result* res) {
   double dx[3];
   for (int c = 0; c < 3; ++c) dx[c] = x[c] - cen[c];
   double ax = orc_dot(dx, e1, 3), bx = orc_dot(dx, e2, 3), hx = orc_dot(dx, nn, 3);
-  /* Newton on E(a,b) = (a-ax)^2 + (b-bx)^2 + (h(a,b)-hx)^2 from (ax,bx) */
-  double a = ax, b = bx;
+  /* Foot point: minimise E(a,b) = (a-ax)^2 + (b-bx)^2 + (h(a,b)-hx)^2 over
+   * the patch's support square |a|, |b| <= ext, from (ax,bx) clamped to it.
+   * Newton steps; where the Newton Hessian is not positive definite (x beyond
+   * the focal distance of the fitted quadratic) the Gauss-Newton matrix
+   * I + J^T J replaces it; every iterate is clamped to the square. */
+  double a = fmin(fmax(ax, -ext), ext), b = fmin(fmax(bx, -ext), ext);
   for (int it = 0; it < P->newton_iters; ++it) {
     double h = coef[0] + coef[1] * a + coef[2] * b + coef[3] * a * a + coef[4] * a * b + coef[5] * b * b;
     double ha = coef[1] + 2.0 * coef[3] * a + coef[4] * b;
@@ -476,10 +484,16 @@ int orc_pc_project(const orc_problem* P, const double* x, orc_pc_result* res) {
     double Hab = ha * hb + r * hab;
     double Hbb = 1.0 + hb * hb + r * hbb;
     double det = Haa * Hbb - Hab * Hab;
-    if (det == 0.0) break;
+    if (!(Haa > 0.0 && det > 0.0)) {
+      Haa = 1.0 + ha * ha;
+      Hab = ha * hb;
+      Hbb = 1.0 + hb * hb;
+      det = Haa * Hbb - Hab * Hab;
+    }
     double da = (Hbb * ga - Hab * gb) / det;
     double db = (Haa * gb - Hab * ga) / det;
-    a -= da; b -= db;
+    a = fmin(fmax(a - da, -ext), ext);
+    b = fmin(fmax(b - db, -ext), ext);
   }
   double h = coef[0] + coef[1] * a + coef[2] * b + coef[3] * a * a + coef[4] * a * b + coef[5] * b * b;
   for (int c = 0; c < 3; ++c) res->y[c] = cen[c] + a * e1[c] + b * e2[c] + h * nn[c];
@@ -774,6 +788,9 @@ double orc_source(const orc_problem* P, const double* z) {
 static double orc_rho_geo(const orc_problem* P, const double* y, const orc_pc_result* pc) {
   if (P->manifold == ORC_POINT_CLOUD) {
     if (P->radius_rule == ORC_RADIUS_SPACING) return P->c_h * pc->h_mean;
+    /* a bound of kappa over M in eq. rho_geo_curvature: a radius no larger
+     * than the local rule gives anywhere */
+    if (P->radius_rule == ORC_RADIUS_CURVATURE_BOUND) return P->c_kappa / (1.0 + P->kappa_bound);
     return P->c_kappa / (1.0 + pc->kappa);
   }
   return P->c_kappa / (1.0 + orc_kappa(P, y));
@@ -938,6 +955,9 @@ static int orc_check(const orc_problem* P) {
   if ((P->manifold == ORC_TORUS || P->manifold == ORC_POINT_CLOUD) && P->n != 3) return ORC_EINVAL;
   if (P->manifold == ORC_POINT_CLOUD && (P->k_nn < 6 || P->k_nn > ORC_MAXK || P->n_points < P->k_nn))
     return ORC_EINVAL;
+  if (P->radius_rule == ORC_RADIUS_CURVATURE_BOUND &&
+      (P->manifold != ORC_POINT_CLOUD || !(P->kappa_bound >= 0.0) || !isfinite(P->kappa_bound)))
+    return ORC_EINVAL;
   return ORC_OK;
 }
 
@@ -945,6 +965,7 @@ static int orc_check(const orc_problem* P) {
 static double orc_max_radius(const orc_problem* P) {
   if (P->manifold == ORC_POINT_CLOUD) {
     if (P->radius_rule == ORC_RADIUS_SPACING) return INFINITY;
+    if (P->radius_rule == ORC_RADIUS_CURVATURE_BOUND) return P->theta * P->c_kappa / (1.0 + P->kappa_bound);
     return P->theta * P->c_kappa;
   }
   double kmin = 1.0 / P->p[0];

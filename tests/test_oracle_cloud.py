@@ -139,3 +139,32 @@ def test_cloud_query_starts_from_its_projection(orc):
     assert np.array_equal(rq["walk_K"], ry["walk_K"])
     with pytest.raises(ValueError):
         orc.solve(P, y + np.array([0.0, 0.0, 4.0 * h]), 2, seed=4)
+
+
+def test_curvature_bound_radius_rule(orc):
+    """CURVATURE_BOUND: rho_geo = c_kappa / (1 + kappa_bound) everywhere on the
+    cloud, whatever the fitted patch says; rejected for analytic manifolds."""
+    pts = inputs.torus_point_cloud(8000, seed=15)
+    P = orc.Problem(cloud_problem(pts, radius_rule="curvature_bound", kappa_bound=1 / 0.3))
+    for y in pts[:5]:
+        assert orc.radius(P, y) == 0.95 * 1.2 / (1 + 1 / 0.3)
+    Pf = orc.Problem(cloud_problem(pts, radius_rule="curvature_fit"))
+    assert orc.radius(Pf, pts[0]) != orc.radius(P, pts[0])
+    bad = dict(inputs.torus_problem(), radius_rule="curvature_bound", kappa_bound=1.0)
+    with pytest.raises(ValueError):
+        orc.solve(bad, inputs.torus_area_uniform(1), 1, seed=1)
+
+
+def test_foot_point_stays_on_its_patch_for_far_points(orc):
+    """Walk positions reach about r = 0.26 from the surface, beyond the focal
+    distance of noisy 16-point fits: the foot point is kept on the patch's
+    support (Newton with a Gauss-Newton fallback, clamped), so on a noisy
+    3e5-point torus the projection stays within 0.03 of the exact one (an
+    unguarded Newton step leaves the support and errs by up to 0.1)."""
+    pts = inputs.torus_point_cloud(300000, seed=3)
+    P = orc.Problem(cloud_problem(pts))
+    T = orc.Problem(inputs.torus_problem())
+    x = inputs.torus_near_points(600, 0.27, seed=5)
+    err = np.array([np.linalg.norm(orc.cp(P, xi) - orc.cp(T, xi)) for xi in x])
+    assert np.all(np.isfinite(err))
+    assert err.max() < 0.03, err.max()
