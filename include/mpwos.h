@@ -83,7 +83,9 @@ typedef enum { MPWOS_COMP_NONE = 0, MPWOS_COMP_EXACT = 1 } mpwos_compensation;
 typedef enum {
   MPWOS_RADIUS_CURVATURE = 0,     /* rho_geo = c_kappa/(1 + kappa(y)) (eq. rho_geo_curvature) */
   MPWOS_RADIUS_SPACING = 1,       /* rho_geo = c_h h(y), h = mean kNN distance (eq. rho_geo_spacing) */
-  MPWOS_RADIUS_CURVATURE_FIT = 2  /* point cloud: kappa from the fitted patch, then eq. rho_geo_curvature */
+  MPWOS_RADIUS_CURVATURE_FIT = 2, /* point cloud: kappa from the fitted patch, then eq. rho_geo_curvature */
+  MPWOS_RADIUS_CURVATURE_BOUND = 3 /* point cloud: eq. rho_geo_curvature with a bound kappa_bound of kappa
+                                      over M (a constant radius no larger than the local rule's) */
 } mpwos_radius_rule;
 
 typedef struct mpwos_manifold mpwos_manifold;
@@ -115,7 +117,9 @@ typedef struct {
   int32_t n_v;              /* Green samples per step, 1..255 (default 1) */
   int32_t precision;        /* mpwos_precision (default FP64_PLAIN) */
   int32_t compensation;     /* mpwos_compensation (default EXACT) */
-  int32_t radius_rule;      /* mpwos_radius_rule (default CURVATURE) */
+  int32_t radius_rule;      /* mpwos_radius_rule (default CURVATURE); SPACING, CURVATURE_FIT and
+                               CURVATURE_BOUND apply to POINT_CLOUD only, where CURVATURE means
+                               CURVATURE_FIT */
   int64_t max_steps;        /* per-walk step cap, >= 1 (default 1e7); hitting it -> MPWOS_WTRUNC */
   void* stream;             /* hipStream_t or NULL */
   int32_t device_io;        /* 1: queries / outputs / walk_S / walk_K are device pointers */
@@ -127,6 +131,7 @@ typedef struct {
   int32_t k_spacing;        /* reserved (spacing rule uses k_nn neighbours) */
   double* walk_S;           /* optional, n_queries x n_walks: per-walk score S^i */
   int32_t* walk_K;          /* optional, n_queries x n_walks: per-walk stopping index K^i */
+  double kappa_bound;       /* CURVATURE_BOUND: finite, >= 0 (default 0) */
 } mpwos_options;
 
 typedef struct {

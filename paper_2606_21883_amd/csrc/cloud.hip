@@ -330,6 +330,7 @@ __global__ void fit_kernel(GridArgs g, Patch<double>* P64, Patch<float>* P32) {
     sc = fmax(sc, fabs(d[0] * e1[0] + d[1] * e1[1] + d[2] * e1[2]));
     sc = fmax(sc, fabs(d[0] * e2[0] + d[1] * e2[1] + d[2] * e2[2]));
   }
+  const double ext = sc;
   sc = sc > 0.0 ? sc : 1.0;
   double M[6][6], rhs[6];
   for (int r = 0; r < 6; ++r) {
@@ -374,6 +375,7 @@ __global__ void fit_kernel(GridArgs g, Patch<double>* P64, Patch<float>* P32) {
     P.cen[d] = cen[d]; P.e1[d] = e1[d]; P.e2[d] = e2[d]; P.n[d] = nn[d];
   }
   for (int t = 0; t < 6; ++t) P.c[t] = cf[t];
+  P.ext = ext;
   P.hmean = hs / (double)(k - 1);
   P64[i] = P;
   Patch<float> Q;
@@ -381,6 +383,7 @@ __global__ void fit_kernel(GridArgs g, Patch<double>* P64, Patch<float>* P32) {
     Q.cen[d] = (float)cen[d]; Q.e1[d] = (float)e1[d]; Q.e2[d] = (float)e2[d]; Q.n[d] = (float)nn[d];
   }
   for (int t = 0; t < 6; ++t) Q.c[t] = (float)cf[t];
+  Q.ext = (float)ext;
   Q.hmean = (float)P.hmean;
   P32[i] = Q;
 }
@@ -417,7 +420,7 @@ int kd_build(HostKd& t, const std::vector<float>& P, int lo, int hi, int depth) 
     }
   const int id = (int)t.nodes.size();
   t.nodes.push_back(nd);
-  if (hi - lo <= 8 || depth >= 48) {
+  if (hi - lo <= 8 || depth >= kKdDepth) {
     t.nodes[id].left = -1;
     t.nodes[id].right = -1;
     t.nodes[id].start = lo;

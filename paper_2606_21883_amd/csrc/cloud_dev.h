@@ -36,19 +36,29 @@ __device__ __forceinline__ T box_dist2(const KdNode& nd, const T* x) {
   return s;
 }
 
+// The KD-tree is at most kKdDepth levels deep (leaves below that depth hold
+// more points), so a depth-first search holds at most kKdDepth + 1 deferred
+// nodes: one per level above the current node plus its two children.
+constexpr int kKdDepth = 30;
+constexpr int kKdStack = 32;
+
 // Nearest cloud point of x: depth-first search, nearer child first, pruning
 // boxes farther than the best distance (a box at exactly the best distance is
 // still visited so that the index tie-break is exact).  Returns the original
-// index.
+// index.  The per-lane stack lives in LDS (column threadIdx.x of a
+// kKdStack x 256 array: 32 KB per workgroup of at most 256 lanes).
 template <class T>
 __device__ __forceinline__ int32_t kd_nearest(const CloudDev& c, const T* x) {
-  int32_t stack[64];
+  __shared__ int32_t stack[kKdStack][256];
+  const int lane = threadIdx.x;
+  // a non-finite x matches no point: skip the search (it would visit every node)
+  if (!(abs_(x[0]) + abs_(x[1]) + abs_(x[2]) < (T)3.0e38)) return 0;
   int sp = 0;
-  stack[sp++] = 0;
+  stack[sp++][lane] = 0;
   T best = (T)3.0e38;
   int32_t bidx = 0x7fffffff;
   while (sp > 0) {
-    const KdNode nd = c.nodes[stack[--sp]];
+    const KdNode nd = c.nodes[stack[--sp][lane]];
     if (box_dist2(nd, x) > best) continue;
     if (nd.left < 0) {
       for (int32_t i = nd.start; i < nd.start + nd.count; ++i) {
@@ -65,11 +75,11 @@ __device__ __forceinline__ int32_t kd_nearest(const CloudDev& c, const T* x) {
       const T dr = box_dist2(c.nodes[nd.right], x);
       // the nearer child is pushed last, so it is searched first
       if (dl <= dr) {
-        if (dr <= best && sp < 64) stack[sp++] = nd.right;
-        if (dl <= best && sp < 64) stack[sp++] = nd.left;
+        if (dr <= best && sp < kKdStack) stack[sp++][lane] = nd.right;
+        if (dl <= best && sp < kKdStack) stack[sp++][lane] = nd.left;
       } else {
-        if (dl <= best && sp < 64) stack[sp++] = nd.left;
-        if (dr <= best && sp < 64) stack[sp++] = nd.right;
+        if (dl <= best && sp < kKdStack) stack[sp++][lane] = nd.left;
+        if (dr <= best && sp < kKdStack) stack[sp++][lane] = nd.right;
       }
     }
   }
@@ -85,9 +95,12 @@ struct CloudProj {
   T hmean;   // local spacing of the nearest cloud point
 };
 
-// Newton foot point of x on patch P: minimise (a - ax)^2 + (b - bx)^2 +
-// (h(a,b) - hx)^2 from (ax, bx), then the curvature of the patch there
-// (eigenvalues of the shape operator I^-1 II of the graph).
+// Foot point of x on patch P: minimise E = (a - ax)^2 + (b - bx)^2 +
+// (h(a,b) - hx)^2 over the support square |a|, |b| <= ext from (ax, bx)
+// clamped to it, by Newton steps that fall back to the Gauss-Newton matrix
+// I + J^T J where the Newton Hessian is not positive definite (x beyond the
+// focal distance of the fitted quadratic), each iterate clamped; then the
+// curvature of the patch there (eigenvalues of the shape operator I^-1 II).
 template <class T>
 __device__ __forceinline__ CloudProj<T> patch_project(const Patch<T>& P, const T* x, int iters) {
   const T d0 = x[0] - P.cen[0], d1 = x[1] - P.cen[1], d2 = x[2] - P.cen[2];
@@ -95,7 +108,8 @@ __device__ __forceinline__ CloudProj<T> patch_project(const Patch<T>& P, const T
   const T bx = d0 * P.e2[0] + d1 * P.e2[1] + d2 * P.e2[2];
   const T hx = d0 * P.n[0] + d1 * P.n[1] + d2 * P.n[2];
   const T* c = P.c;
-  T a = ax, b = bx;
+  const T ext = P.ext;
+  T a = fmin(fmax(ax, -ext), ext), b = fmin(fmax(bx, -ext), ext);
   for (int it = 0; it < iters; ++it) {
     const T h = c[0] + c[1] * a + c[2] * b + c[3] * a * a + c[4] * a * b + c[5] * b * b;
     const T ha = c[1] + (T)2 * c[3] * a + c[4] * b;
@@ -103,13 +117,18 @@ __device__ __forceinline__ CloudProj<T> patch_project(const Patch<T>& P, const T
     const T res = h - hx;
     const T ga = (a - ax) + res * ha;
     const T gb = (b - bx) + res * hb;
-    const T Haa = (T)1 + ha * ha + res * (T)2 * c[3];
-    const T Hab = ha * hb + res * c[4];
-    const T Hbb = (T)1 + hb * hb + res * (T)2 * c[5];
-    const T det = Haa * Hbb - Hab * Hab;
-    if (det == (T)0) break;
-    a -= (Hbb * ga - Hab * gb) / det;
-    b -= (Haa * gb - Hab * ga) / det;
+    T Haa = (T)1 + ha * ha + res * (T)2 * c[3];
+    T Hab = ha * hb + res * c[4];
+    T Hbb = (T)1 + hb * hb + res * (T)2 * c[5];
+    T det = Haa * Hbb - Hab * Hab;
+    if (!(Haa > (T)0 && det > (T)0)) {
+      Haa = (T)1 + ha * ha;
+      Hab = ha * hb;
+      Hbb = (T)1 + hb * hb;
+      det = Haa * Hbb - Hab * Hab;
+    }
+    a = fmin(fmax(a - (Hbb * ga - Hab * gb) / det, -ext), ext);
+    b = fmin(fmax(b - (Haa * gb - Hab * ga) / det, -ext), ext);
   }
   CloudProj<T> out;
   const T h = c[0] + c[1] * a + c[2] * b + c[3] * a * a + c[4] * a * b + c[5] * b * b;

@@ -75,11 +75,12 @@ struct KdNode {
 
 // Local quadratic patch of one cloud point: centroid, tangent frame e1, e2,
 // unit normal n, height field h(a,b) = c0 + c1 a + c2 b + c3 a^2 + c4 a b + c5 b^2
-// over (a, b) = ((x - cen).e1, (x - cen).e2), and the mean distance from the
-// point to its other k-1 neighbours.
+// over (a, b) = ((x - cen).e1, (x - cen).e2), the support half-width ext (the
+// largest |a| or |b| of the k points) and the mean distance from the point to
+// its other k-1 neighbours.
 template <class T>
 struct Patch {
-  T cen[3], e1[3], e2[3], n[3], c[6], hmean;
+  T cen[3], e1[3], e2[3], n[3], c[6], ext, hmean;
 };
 
 struct CloudDev {

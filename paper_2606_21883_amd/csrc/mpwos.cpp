@@ -507,6 +507,12 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
     return fail(MPWOS_EINVAL, "unknown precision");
   if (o.compensation != MPWOS_COMP_NONE && o.compensation != MPWOS_COMP_EXACT)
     return fail(MPWOS_EINVAL, "unknown compensation");
+  if (o.radius_rule < MPWOS_RADIUS_CURVATURE || o.radius_rule > MPWOS_RADIUS_CURVATURE_BOUND)
+    return fail(MPWOS_EINVAL, "unknown radius_rule");
+  if (d.kind != MPWOS_POINT_CLOUD && o.radius_rule != MPWOS_RADIUS_CURVATURE)
+    return fail(MPWOS_EINVAL, "radius rules other than CURVATURE apply to point clouds only");
+  if (o.radius_rule == MPWOS_RADIUS_CURVATURE_BOUND && !(o.kappa_bound >= 0.0 && std::isfinite(o.kappa_bound)))
+    return fail(MPWOS_EINVAL, "kappa_bound must be finite and >= 0");
   if (o.block_size != 0 && (o.block_size < 64 || o.block_size > 256 || o.block_size % 64))
     return fail(MPWOS_EINVAL, "block_size must be 0 or a multiple of 64 in [64, 256]");
   {
@@ -546,9 +552,11 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
   host_law(d.n, h);
   // largest X^2 = sigma r^2 the walk can reach
   double rmax;
-  if (d.kind == MPWOS_POINT_CLOUD) {
-    rmax = o.radius_rule == MPWOS_RADIUS_SPACING ? 0.0 : o.theta * o.c_kappa;
-    if (o.radius_rule == MPWOS_RADIUS_SPACING) rmax = cloud_spacing_rmax(man->cloud, o);
+  const bool cloud_bound = d.kind == MPWOS_POINT_CLOUD && o.radius_rule == MPWOS_RADIUS_CURVATURE_BOUND;
+  if (cloud_bound) {
+    rmax = o.theta * o.c_kappa / (1.0 + o.kappa_bound);
+  } else if (d.kind == MPWOS_POINT_CLOUD) {
+    rmax = o.radius_rule == MPWOS_RADIUS_SPACING ? cloud_spacing_rmax(man->cloud, o) : o.theta * o.c_kappa;
   } else {
     rmax = o.theta * o.c_kappa / (1.0 + const_kappa(d));
   }
@@ -558,7 +566,7 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
     return fail(MPWOS_EINVAL, "sqrt(sigma) r_max = " + std::to_string(std::sqrt(x2max)) +
                                   " is beyond the range of the series radial law for this n");
   fill_law(h, js, jd, a.law);
-  a.const_r = (d.kind == MPWOS_SPHERE || d.kind == MPWOS_TORUS_IMPLICIT) ? 1 : 0;
+  a.const_r = (d.kind == MPWOS_SPHERE || d.kind == MPWOS_TORUS_IMPLICIT || cloud_bound) ? 1 : 0;
   if (a.const_r) {
     a.r0 = rmax;
     host_weights(d.n, sigma, a.r0, a.c0, a.om0);

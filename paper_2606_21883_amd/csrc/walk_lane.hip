@@ -104,7 +104,7 @@ __device__ __forceinline__ bool walk_init(const WalkArgs& a, int64_t idx, LaneSt
     // the walk starts from the query's projection onto the reconstruction
     const CloudProj<T> p = cloud_cp<T>(a.cloud, st.Y);
     for (int i = 0; i < N; ++i) st.Y[i] = p.y[i];
-    st.rg = cloud_rho_geo(a, p);
+    if (!a.const_r) st.rg = cloud_rho_geo(a, p);
   }
   if constexpr (KIND == kCap) {
     if (cap_in_layer<T, N>(a, st.Y)) {
@@ -135,7 +135,7 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
     weights(a, r, c, om);
     X2 = a.sigma * r * r;
     if constexpr (sizeof(T) == 8) norm = radial_norm(a.law, X2);
-  } else if constexpr (KIND == kCloud) {
+  } else if (KIND == kCloud && !a.const_r) {
     r = a.theta * st.rg;
     weights(a, r, c, om);
     X2 = a.sigma * r * r;
@@ -163,7 +163,7 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
     if constexpr (KIND == kCloud) {
       const CloudProj<T> p = cloud_cp<T>(a.cloud, Th);
       for (int i = 0; i < N; ++i) Yn[i] = p.y[i];
-      rg_next = cloud_rho_geo(a, p);
+      if (!a.const_r) rg_next = cloud_rho_geo(a, p);
     } else {
       closest_point<T, N, KIND>(a, Th, Yn);
     }

@@ -142,10 +142,13 @@ def torus_problem(R=1.0, a=0.3):
                    f=dict(kind="torus_mode", coef=[1.0]))
 
 
-def point_cloud_problem(points, k_nn=16, radius_rule="curvature_fit", R=1.0, a=0.3):
-    return problem(manifold="point_cloud", n=3, p=[R, a], sigma=1.0, points=points, k_nn=k_nn,
-                   radius_rule=radius_rule, c_h=2.4, newton_iters=6,
-                   f=dict(kind="torus_mode", coef=[1.0]))
+def point_cloud_problem(points, k_nn=16, radius_rule="curvature_fit", R=1.0, a=0.3, kappa_bound=None):
+    d = problem(manifold="point_cloud", n=3, p=[R, a], sigma=1.0, points=points, k_nn=k_nn,
+                radius_rule=radius_rule, c_h=2.4, newton_iters=6,
+                f=dict(kind="torus_mode", coef=[1.0]))
+    if kappa_bound is not None:
+        d["kappa_bound"] = kappa_bound
+    return d
 
 
 # ---------------------------------------------------------------------------
@@ -227,8 +230,12 @@ def config(name, scale=1.0, seed=1):
     if name == "cloud":
         # 1e6 noisy torus samples (queries: analytic torus points, within the
         # noise and the fit error of the reconstruction)
+        # At this density a 16-point patch spans about 0.008, where the quadratic
+        # term (about 1e-4) is at the noise level: the per-point fitted curvature
+        # is noise, so the radius takes the curvature bound of the torus, 1/a.
         pts = torus_point_cloud(1_000_000, 1.0, 0.3, 1e-4, seed)
-        return point_cloud_problem(pts), torus_area_uniform(sz(8192), 1.0, 0.3, seed + 7), sz(1024)
+        prob = point_cloud_problem(pts, radius_rule="curvature_bound", kappa_bound=1.0 / 0.3)
+        return prob, torus_area_uniform(sz(8192), 1.0, 0.3, seed + 7), sz(1024)
     raise ValueError(name)
 
 

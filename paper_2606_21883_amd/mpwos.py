@@ -20,7 +20,7 @@ FN_KINDS = {"zero": 0, "const": 1, "sph_pair": 2, "circle_mode": 3, "legendre": 
             "table_s1": 6}
 PRECISION = {"fp64": 0, "fp32": 1}
 COMP = {"none": 0, "exact": 1}
-RADIUS_RULES = {"curvature": 0, "spacing": 1, "curvature_fit": 2}
+RADIUS_RULES = {"curvature": 0, "spacing": 1, "curvature_fit": 2, "curvature_bound": 3}
 
 
 class MpwosError(RuntimeError):
@@ -47,7 +47,8 @@ class Options(ctypes.Structure):
                 ("max_steps", ctypes.c_int64), ("stream", ctypes.c_void_p), ("device_io", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("lanes_per_walk", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("newton_iters", ctypes.c_int32),
-                ("k_spacing", ctypes.c_int32), ("walk_S", ctypes.c_void_p), ("walk_K", ctypes.c_void_p)]
+                ("k_spacing", ctypes.c_int32), ("walk_S", ctypes.c_void_p), ("walk_K", ctypes.c_void_p),
+                ("kappa_bound", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -144,7 +145,7 @@ def make_options(prob=None, **kw):
     o = options_default()
     src = dict(prob or {})
     src.update(kw)
-    for k in ("theta", "c_kappa", "c_h", "tau_w"):
+    for k in ("theta", "c_kappa", "c_h", "tau_w", "kappa_bound"):
         if k in src:
             setattr(o, k, float(src[k]))
     if "n_v" in src:
