@@ -25,7 +25,7 @@ mpwos_status check_queries_host(const mpwos_manifold* man, const WalkArgs& a, co
 
 // walk_lane.hip
 hipError_t launch_walk_lane(const WalkArgs& a, int grid, int block, hipStream_t s);
-int lane_occupancy(int kind, int n, bool fp64, int block);
+int lane_occupancy(const WalkArgs& a, int block);
 hipError_t launch_reduce(const double* walk_S, const int32_t* walk_K, int64_t nq, int64_t nw, int64_t max_steps,
                          double* u, double* se, unsigned long long* ksum, int32_t* kmax,
                          unsigned long long* ntrunc, hipStream_t s);

@@ -611,7 +611,7 @@ mpwos_status launch_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, un
     const int block = o.block_size ? o.block_size : 256;
     hipError_t e;
     if (a.persistent) {
-      const int occ = lane_occupancy(a.kind, a.n, a.precision == 0, block);
+      const int occ = lane_occupancy(a, block);
       const int64_t grid_max = (int64_t)occ * n_cu;
       const int64_t need = (total + block - 1) / block;
       const int64_t grid = std::max<int64_t>(1, std::min(grid_max, need));

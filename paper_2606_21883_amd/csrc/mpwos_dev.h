@@ -45,7 +45,11 @@ struct Stream {
 // 32-bit word -> uniform in (0,1).  FP64: (x + 1/2) 2^-32.  FP32: the top 23
 // bits, (x>>9 + 1/2) 2^-23, exact in binary32.
 __device__ __forceinline__ double u01_64(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
-__device__ __forceinline__ float u01_32(uint32_t x) { return ((float)(x >> 9) + 0.5f) * 0x1p-23f; }
+// FP32 form built from the bits: 1 + m 2^-23 (m = x >> 9) minus (1 - 2^-24)
+// is (m + 1/2) 2^-23 exactly, in two operations.
+__device__ __forceinline__ float u01_32(uint32_t x) {
+  return __uint_as_float((x >> 9) | 0x3F800000u) - 0x1.fffffep-1f;
+}
 
 template <class T> __device__ __forceinline__ T u01(uint32_t x);
 template <> __device__ __forceinline__ double u01<double>(uint32_t x) { return u01_64(x); }
@@ -260,9 +264,6 @@ __device__ __forceinline__ double radial_inv64(const WalkArgs& a, double u, doub
   return s;
 }
 
-// FP32: table guess, then (lower half, fixed X) one Newton step with the FP32
-// law.  In the upper half F is near 1 and known only to FP32 absolute
-// precision while F' -> 0, so the sqrt(1-u) table alone is the better value.
 // Inverse of the radial CDF in FP32: the table alone (linear in w, within
 // about 1e-6 of the root for every n, below the binary32 resolution of the
 // walk's positions at the radii used).
@@ -532,23 +533,13 @@ __device__ __forceinline__ T torus_neg_lap(T R, T tube, T sphi, T cpsi, T spsi) 
   return (T)4 * u / (tube * tube) + u / (rt * rt) - (T)2 * sphi * spsi * s2 / (tube * rt);
 }
 
-// f_Omega(y) + m(z) for a point z of the ball and y = cp(z).
+// f_Omega(y) + m(z) for a point z of the ball and y = cp(z): the families
+// with more state (circle modes, Legendre sums, tabulated S^1 data).
 template <class T>
-__device__ __forceinline__ T source(const WalkArgs& a, const T* z, const T* y, int n) {
+__device__ T source_rich(const WalkArgs& a, const T* z, const T* y, int n) {
   const FnDev& f = a.f;
   const int comp = a.comp;
   switch (f.kind) {
-    case kFnZero: return (T)0;
-    case kFnConst: return (T)f.coef[0];
-    case kFnSphPair: {
-      const T R = (T)a.p[0];
-      const T iR = (T)a.inv_R;
-      const T fv = (T)f.coef[0] * (y[f.idx[0]] * iR) * (y[f.idx[1]] * iR);
-      if (!comp) return fv;
-      T zz = (T)0;
-      for (int i = 0; i < n; ++i) zz += z[i] * z[i];
-      return fv + (T)(f.lam * f.u_scale) * fv * (over_(R * R, zz) - (T)1);
-    }
     case kFnCircle: {
       const T R = (T)a.p[0];
       const T iR = (T)a.inv_R;
@@ -574,32 +565,6 @@ __device__ __forceinline__ T source(const WalkArgs& a, const T* z, const T* y, i
       for (int i = 0; i < n; ++i) zz += z[i] * z[i];
       return fv + legendre_lap<T>(f.coef, a.p[0], a.sigma, t) * (over_(R * R, zz) - (T)1);
     }
-    case kFnTorus: {
-      const T R = (T)a.p[0], tube = (T)a.p[1];
-      // angles of y on the torus (those of z are the same: cp keeps phi and psi)
-      const T rho = sqrt_(y[0] * y[0] + y[1] * y[1]);
-      const T sphi = y[1] / rho;
-      const T dr = rho - R;
-      const T dy = sqrt_(dr * dr + y[2] * y[2]);
-      const T cpsi = dr / dy, spsi = y[2] / dy;
-      const T u = sphi * (cpsi * cpsi - spsi * spsi);
-      const T c0 = (T)f.coef[0];
-      const T nl = torus_neg_lap<T>(R, tube, sphi, cpsi, spsi);
-      T v = c0 * nl + (T)a.sigma * c0 * u;
-      if (comp) {
-        const T rz = sqrt_(z[0] * z[0] + z[1] * z[1]);
-        const T dz = sqrt_((rz - R) * (rz - R) + z[2] * z[2]);
-        if (a.kind == kCloud) {
-          // a reconstructed surface moves the foot point off z's normal line:
-          // the correction takes z's own angles in both terms
-          const T zs = z[1] / rz, zc = (rz - R) / dz, zp = z[2] / dz;
-          v += c0 * (torus_neg_lap<T>(R, dz, zs, zc, zp) - torus_neg_lap<T>(R, tube, zs, zc, zp));
-        } else {
-          v += c0 * (torus_neg_lap<T>(R, dz, sphi, cpsi, spsi) - nl);
-        }
-      }
-      return v;
-    }
     case kFnTableS1: {
       const T R = (T)a.p[0];
       // theta in turns from the unit vector, then linear interpolation
@@ -618,6 +583,58 @@ __device__ __forceinline__ T source(const WalkArgs& a, const T* z, const T* y, i
     }
   }
   return (T)0;
+}
+
+// f_Omega(y) + m(z) for a point z of the ball and y = cp(z).  RICH = false
+// compiles only the ZERO, CONST, SPH_PAIR and TORUS_MODE families (the walk
+// kernels are instantiated for both sets, so the common families do not carry
+// the registers of the others).
+template <class T, bool RICH = true>
+__device__ __forceinline__ T source(const WalkArgs& a, const T* z, const T* y, int n) {
+  const FnDev& f = a.f;
+  const int comp = a.comp;
+  switch (f.kind) {
+    case kFnZero: return (T)0;
+    case kFnConst: return (T)f.coef[0];
+    case kFnSphPair: {
+      const T R = (T)a.p[0];
+      const T iR = (T)a.inv_R;
+      const T fv = (T)f.coef[0] * (y[f.idx[0]] * iR) * (y[f.idx[1]] * iR);
+      if (!comp) return fv;
+      T zz = (T)0;
+      for (int i = 0; i < n; ++i) zz += z[i] * z[i];
+      return fv + (T)(f.lam * f.u_scale) * fv * (over_(R * R, zz) - (T)1);
+    }
+    case kFnTorus: {
+      const T R = (T)a.p[0], tube = (T)a.p[1];
+      // angles of y on the torus (those of z are the same: cp keeps phi and psi)
+      const T rho = sqrt_(y[0] * y[0] + y[1] * y[1]);
+      const T sphi = over_(y[1], rho);
+      const T dr = rho - R;
+      const T dy = sqrt_(dr * dr + y[2] * y[2]);
+      const T cpsi = over_(dr, dy), spsi = over_(y[2], dy);
+      const T u = sphi * (cpsi * cpsi - spsi * spsi);
+      const T c0 = (T)f.coef[0];
+      const T nl = torus_neg_lap<T>(R, tube, sphi, cpsi, spsi);
+      T v = c0 * nl + (T)a.sigma * c0 * u;
+      if (comp) {
+        const T rz = sqrt_(z[0] * z[0] + z[1] * z[1]);
+        const T dz = sqrt_((rz - R) * (rz - R) + z[2] * z[2]);
+        if (a.kind == kCloud) {
+          // a reconstructed surface moves the foot point off z's normal line:
+          // the correction takes z's own angles in both terms
+          const T zs = over_(z[1], rz), zc = over_(rz - R, dz), zp = over_(z[2], dz);
+          v += c0 * (torus_neg_lap<T>(R, dz, zs, zc, zp) - torus_neg_lap<T>(R, tube, zs, zc, zp));
+        } else {
+          v += c0 * (torus_neg_lap<T>(R, dz, sphi, cpsi, spsi) - nl);
+        }
+      }
+      return v;
+    }
+    default:
+      if constexpr (RICH) return source_rich<T>(a, z, y, n);
+      return (T)0;
+  }
 }
 
 // g_Omega at a boundary point y.

@@ -123,7 +123,28 @@ __device__ __forceinline__ void walk_store(const WalkArgs& a, const LaneState<T,
   a.walk_K[st.idx] = (int32_t)st.k;
 }
 
-template <class T, int N, int KIND>
+// One Green sample Z = Y + t zeta' (t = r s, s from the radial law for the
+// uniform word ux, zeta' from the normals of block b) and (f + m)(Z).
+template <class T, int N, int KIND, bool RICH>
+__device__ __forceinline__ T green_sample(const WalkArgs& a, const T* Y, uint4 b, uint32_t ux, T rT, double X2,
+                                          double norm) {
+  T g[4];
+  box_muller(b.x, b.y, g[0], g[1]);
+  if (N > 2) box_muller(b.z, b.w, g[2], g[3]);
+  T s;
+  if constexpr (sizeof(T) == 8) s = radial_inv64(a, u01_64(ux), X2, norm);
+  else s = radial_inv32(a, u01_32(ux), (float)X2);
+  T gg = (T)0;
+  for (int i = 0; i < N; ++i) gg += g[i] * g[i];
+  const T ig = rsqrt_(gg);
+  const T t = rT * s;
+  T Z[N], Zc[N];
+  for (int i = 0; i < N; ++i) Z[i] = Y[i] + t * (g[i] * ig);
+  closest_point<T, N, KIND>(a, Z, Zc);
+  return source<T, RICH>(a, Z, Zc, N);
+}
+
+template <class T, int N, int KIND, bool RICH>
 __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st) {
   const Stream rs{st.q, st.w, (uint32_t)a.seed, (uint32_t)(a.seed >> 32)};
   // (i) radius r(Y) = theta min(delta_Gamma, rho_geo) and the weights
@@ -147,14 +168,19 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
     X2 = a.X0 * a.X0;
   }
   const T rT = (T)r;
+  // Each Philox block is drawn where it is used.  (Drawing the first Green
+  // sample's blocks together with the direction block, to interleave their
+  // rounds, changed FP64 cap results with this toolchain although the values
+  // are the same by construction; the multiple-Green-sample parity test
+  // guards the form kept here.)
+  const uint4 bd = rs.block(st.k, 0, 0);
   // (ii) Theta = Y + r g/|g| and Y' = cp(Theta)
   T Yn[N];
   double rg_next = 0.0;
   {
-    const uint4 b = rs.block(st.k, 0, 0);
     T g[4];
-    box_muller(b.x, b.y, g[0], g[1]);
-    if (N > 2) box_muller(b.z, b.w, g[2], g[3]);
+    box_muller(bd.x, bd.y, g[0], g[1]);
+    if (N > 2) box_muller(bd.z, bd.w, g[2], g[3]);
     T gg = (T)0;
     for (int i = 0; i < N; ++i) gg += g[i] * g[i];
     const T ig = rsqrt_(gg);
@@ -172,26 +198,8 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
   T Fsum = (T)0;
   for (int l = 1; l <= a.n_v; ++l) {
     const uint4 b = rs.block(st.k, (uint32_t)l, 0);
-    T g[4];
-    uint32_t ux;
-    box_muller(b.x, b.y, g[0], g[1]);
-    if (N > 2) {
-      box_muller(b.z, b.w, g[2], g[3]);
-      ux = rs.block(st.k, (uint32_t)l, 1).x;
-    } else {
-      ux = b.z;
-    }
-    T s;
-    if constexpr (sizeof(T) == 8) s = radial_inv64(a, u01_64(ux), X2, norm);
-    else s = radial_inv32(a, u01_32(ux), (float)X2);
-    T gg = (T)0;
-    for (int i = 0; i < N; ++i) gg += g[i] * g[i];
-    const T ig = rsqrt_(gg);
-    const T t = rT * s;
-    T Z[N], Zc[N];
-    for (int i = 0; i < N; ++i) Z[i] = st.Y[i] + t * (g[i] * ig);
-    closest_point<T, N, KIND>(a, Z, Zc);
-    Fsum += source<T>(a, Z, Zc, N);
+    const uint32_t ux = (N > 2) ? rs.block(st.k, (uint32_t)l, 1).x : b.z;
+    Fsum += green_sample<T, N, KIND, RICH>(a, st.Y, b, ux, rT, X2, norm);
   }
   const double F = a.n_v == 1 ? (double)Fsum : (double)Fsum / (double)a.n_v;
   kahan_add(st.S, st.C, (st.W * om) * F);
@@ -217,60 +225,61 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-template <class T, int N, int KIND>
+template <class T, int N, int KIND, bool PERSIST, bool RICH>
 __global__ __launch_bounds__(256) void walk_lane_kernel(WalkArgs a) {
   const int64_t total = a.count;
   LaneState<T, N> st;
-  if (!a.persistent) {
+  if constexpr (!PERSIST) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
     if (walk_init<T, N, KIND>(a, a.idx_base + idx, st)) {
       walk_store(a, st);
       return;
     }
-    while (!walk_step<T, N, KIND>(a, st)) {
+    while (!walk_step<T, N, KIND, RICH>(a, st)) {
     }
     walk_store(a, st);
     return;
-  }
-  // persistent form: per-wave chunks of the global queue
-  const uint32_t lane = lane_id();
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  bool active = false;
-  bool exhausted = false;
-  int64_t next = 0, end = 0;
-  for (;;) {
+  } else {
+    // persistent form: per-wave chunks of the global queue
+    const uint32_t lane = lane_id();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    bool active = false;
+    bool exhausted = false;
+    int64_t next = 0, end = 0;
     for (;;) {
-      const uint64_t want = __ballot(!active);
-      if (want == 0 || exhausted) break;
-      if (next >= end) {
-        const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)want) - 1);
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)a.chunk);
-        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
-        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
-        const int64_t b = (int64_t)(((uint64_t)hi << 32) | lo);
-        if (b >= total) {
-          exhausted = true;
-          break;
+      for (;;) {
+        const uint64_t want = __ballot(!active);
+        if (want == 0 || exhausted) break;
+        if (next >= end) {
+          const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)want) - 1);
+          unsigned long long base = 0;
+          if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)a.chunk);
+          const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
+          const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
+          const int64_t b = (int64_t)(((uint64_t)hi << 32) | lo);
+          if (b >= total) {
+            exhausted = true;
+            break;
+          }
+          next = b;
+          end = b + a.chunk < total ? b + a.chunk : total;
         }
-        next = b;
-        end = b + a.chunk < total ? b + a.chunk : total;
+        const int rank = __popcll(want & lt_mask);
+        const int64_t avail = end - next;
+        const int64_t cnt = (int64_t)__popcll(want) < avail ? (int64_t)__popcll(want) : avail;
+        if (!active && rank < cnt) {
+          if (walk_init<T, N, KIND>(a, a.idx_base + next + rank, st)) walk_store(a, st);
+          else active = true;
+        }
+        next += cnt;
       }
-      const int rank = __popcll(want & lt_mask);
-      const int64_t avail = end - next;
-      const int64_t cnt = (int64_t)__popcll(want) < avail ? (int64_t)__popcll(want) : avail;
-      if (!active && rank < cnt) {
-        if (walk_init<T, N, KIND>(a, a.idx_base + next + rank, st)) walk_store(a, st);
-        else active = true;
-      }
-      next += cnt;
-    }
-    if (__ballot(active) == 0) break;
-    if (active) {
-      if (walk_step<T, N, KIND>(a, st)) {
-        walk_store(a, st);
-        active = false;
+      if (__ballot(active) == 0) break;
+      if (active) {
+        if (walk_step<T, N, KIND, RICH>(a, st)) {
+          walk_store(a, st);
+          active = false;
+        }
       }
     }
   }
@@ -562,17 +571,34 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s)
   return hipGetLastError();
 }
 
+// Sources outside ZERO, CONST, SPH_PAIR and TORUS_MODE take the kernels that
+// carry every family.
+static bool rich_source(const WalkArgs& a) {
+  const int k = a.f.kind;
+  return !(k == kFnZero || k == kFnConst || k == kFnSphPair || k == kFnTorus);
+}
+
 template <class T, int N, int KIND>
 static hipError_t launch_lane_t(const WalkArgs& a, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL((walk_lane_kernel<T, N, KIND>), dim3(grid), dim3(block), 0, s, a);
+  const dim3 g(grid), b(block);
+  if (rich_source(a)) {
+    if (a.persistent) hipLaunchKernelGGL((walk_lane_kernel<T, N, KIND, true, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((walk_lane_kernel<T, N, KIND, false, true>), g, b, 0, s, a);
+  } else {
+    if (a.persistent) hipLaunchKernelGGL((walk_lane_kernel<T, N, KIND, true, false>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((walk_lane_kernel<T, N, KIND, false, false>), g, b, 0, s, a);
+  }
   return hipGetLastError();
 }
 
 template <class T, int N, int KIND>
-static int occupancy_t(int block) {
+static int occupancy_t(int block, bool rich) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_lane_kernel<T, N, KIND>, block, 0) != hipSuccess)
-    return 1;
+  const hipError_t e = rich ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                  &nb, walk_lane_kernel<T, N, KIND, true, true>, block, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                  &nb, walk_lane_kernel<T, N, KIND, true, false>, block, 0);
+  if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
 
@@ -584,8 +610,10 @@ hipError_t launch_walk_lane(const WalkArgs& a, int grid, int block, hipStream_t 
   return hipErrorInvalidValue;
 }
 
-int lane_occupancy(int kind, int n, bool fp64, int block) {
-  MPWOS_LANE_DISPATCH(occupancy_t, block);
+int lane_occupancy(const WalkArgs& a, int block) {
+  const bool fp64 = a.precision == 0, rich = rich_source(a);
+  const int kind = a.kind, n = a.n;
+  MPWOS_LANE_DISPATCH(occupancy_t, block, rich);
   return 1;
 }
 

@@ -24,6 +24,15 @@ def test_device_philox_matches_oracle_bitwise():
             assert np.array_equal(dev[i], ref), (ctr, seed, i)
 
 
+def test_device_philox_known_answer_vectors():
+    """The published Philox4x32-10 known-answer vectors (tests/golden) on the device."""
+    from tests.test_oracle_rng import _kat_vectors
+    announce("philox kat")
+    for ctr, key, out in _kat_vectors():
+        dev = mpwos.debug_philox(ctr, key[0] | (key[1] << 32), 1)
+        assert [int(x) for x in dev[0]] == out
+
+
 def test_oracle_philox_matches_rocrand():
     """rocRAND's PHILOX4_32_10 generator with seed s emits, in order, the words
     of Philox4x32-10 blocks with key (s_lo, s_hi) and counters 0, 1, 2, ..."""
