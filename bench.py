@@ -208,6 +208,109 @@ def cpu_baseline(work):
             "sample": "; ".join(parts)}
 
 
+# Served mix: manifolds of the S^1, S^2 (closed and cap), S^99, S^999 and
+# implicit-torus configurations with their walk lengths K at tau_W = 1e-8.
+SERVED_KINDS = {"circle": 232, "sphere": 174, "cap": 29, "torus": 1601, "hyper100": 11340, "hyper1000": 113393}
+
+
+def served_mix(rate=200.0, window=3.0, seed=2, work_range=(1e4, 1e7), q_range=(1, 16), min_walks=8):
+    """Poisson arrivals at `rate` per second for `window` seconds, served by the
+    continuous-batching server (FP32 persistent kernels).  Each request draws a
+    manifold uniformly, a query count log-uniform in q_range and a total work
+    log-uniform in work_range walk-steps (walks per query = work / (queries K),
+    at least min_walks).  Latency = completion - arrival.  The same requests run alone
+    and first-in first-out through mpwos_solve give the per-solve comparison
+    (its latencies from the measured service times) and the bitwise check."""
+    import torch  # noqa: F401  (one HIP runtime with torch)
+
+    from paper_2606_21883_amd import inputs, mpwos
+    rng = np.random.default_rng(seed)
+    probs, mans = {}, {}
+    for name in SERVED_KINDS:
+        p, _, _ = inputs.config(name, 1.0 / 1024)
+        probs[name] = p
+        mans[name] = mpwos.Manifold(p)
+    t, reqs = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > window:
+            break
+        name = list(SERVED_KINDS)[rng.integers(len(SERVED_KINDS))]
+        nq = int(round(math.exp(rng.uniform(math.log(q_range[0]), math.log(q_range[1])))))
+        work = math.exp(rng.uniform(math.log(work_range[0]), math.log(work_range[1])))
+        nw = max(min_walks, int(work / (nq * SERVED_KINDS[name])))
+        qs = int(rng.integers(1 << 30))
+        if name == "circle":
+            th = np.random.default_rng(qs).uniform(0, 2 * np.pi, nq)
+            Q = np.stack([np.cos(th), np.sin(th)], 1)
+        elif name == "sphere":
+            Q = inputs.sphere_uniform(nq, 3, qs)
+        elif name == "cap":
+            Q = inputs.cap_uniform(nq, 3, 0.0, qs)
+        elif name == "torus":
+            Q = inputs.torus_area_uniform(nq, seed=qs)
+        else:
+            Q = inputs.hypersphere_queries(max(nq, 2), probs[name]["n"], qs)
+        reqs.append((t, name, Q, nw, int(rng.integers(1 << 62))))
+    opt = dict(precision="fp32", persistent=1)
+    srv = mpwos.Server(64 << 30)
+    t0 = time.perf_counter()
+    tickets, pending, done_at = [], {}, {}
+
+    def poll_all():
+        for tk in list(pending):
+            if srv.poll(tk)[0]:
+                done_at[tk] = time.perf_counter() - t0
+                del pending[tk]
+
+    for (ta, name, Q, nw, sd) in reqs:
+        while time.perf_counter() - t0 < ta:
+            poll_all()
+            time.sleep(0.0005)
+        tk = srv.submit(mans[name], probs[name], Q, nw, sd, **opt)
+        tickets.append(tk)
+        pending[tk] = ta
+    last_print = time.perf_counter()
+    while pending:
+        poll_all()
+        time.sleep(0.0005)
+        if time.perf_counter() - last_print > 20:
+            print(f"[bench] served: {len(pending)} requests outstanding", file=sys.stderr, flush=True)
+            last_print = time.perf_counter()
+    wall = time.perf_counter() - t0
+    outs = [srv.wait(tk) for tk in tickets]
+    st = srv.stats()
+    srv.close()
+    lat = np.array([done_at[tk] - r[0] for tk, r in zip(tickets, reqs)])
+    print(f"[bench] served: {len(reqs)} requests done in {wall:.1f} s; solving them alone", file=sys.stderr,
+          flush=True)
+    # the same requests alone, first in first out, with the per-solve entry point
+    service, same = [], 0
+    for (ta, name, Q, nw, sd), o in zip(reqs, outs):
+        ts = time.perf_counter()
+        r = mpwos.solve(probs[name], Q, nw, sd, manifold=mans[name], **opt)
+        service.append(time.perf_counter() - ts)
+        same += int(np.array_equal(r["u"], o["u"]))
+    finish, fifo = 0.0, []
+    for (ta, *_), sv in zip(reqs, service):
+        finish = max(finish, ta) + sv
+        fifo.append(finish - ta)
+    fifo = np.array(fifo)
+    for m in mans.values():
+        m.close()
+    return {"rate_req_per_s": rate, "window_s": window, "requests": len(reqs),
+            "request_mix": "manifold uniform over S^1, S^2, S^2 cap, implicit torus, S^99, S^999; queries "
+                           f"log-uniform in [{q_range[0]}, {q_range[1]}]; work log-uniform in "
+                           f"[{work_range[0]:.0e}, {work_range[1]:.0e}] walk-steps per request, at least "
+                           f"{min_walks} walks per query",
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "walk_steps": int(st["walk_steps"]), "walk_steps_per_s": st["walk_steps"] / wall,
+            "rounds": st["rounds"], "results_equal_alone": f"{same}/{len(reqs)}",
+            "per_solve_fifo": {"p50_ms": float(np.percentile(fifo, 50) * 1e3),
+                               "p99_ms": float(np.percentile(fifo, 99) * 1e3),
+                               "busy_s": float(sum(service))}}
+
+
 def roofline(fast, dom_name, kind, n, n_v, precision):
     w, rates = valu_weights()
     ops = step_ops(kind, n, n_v)
@@ -246,6 +349,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="time the library's plain copy kernel on BYTES (HBM calibration) and exit")
     ap.add_argument("--valu-probe", action="store_true", help="print the VALU operation rates and exit")
+    ap.add_argument("--no-served", action="store_true", help="skip the served-mix leg")
+    ap.add_argument("--served-only", action="store_true", help="run only the served-mix leg and print it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the walk path runs on a "
@@ -260,6 +365,9 @@ def main():
     if args.valu_probe:
         w, r = valu_weights()
         print(json.dumps({"lane_ops_per_s": r, "weights": w, "peak_lane_ops_per_s": PEAK_SLOTS}), flush=True)
+        return
+    if args.served_only:
+        print(json.dumps(served_mix()), flush=True)
         return
     rank = int(os.environ.get("RANK", "0"))
     work = make_workload(args.workload, args.scale)
@@ -309,6 +417,8 @@ def main():
         out["speedup_vs_fp64_plain"] = value / v64
         out["rmse_ratio_fp32_over_fp64"] = {k: fast["per"][k]["rmse"] / slow["per"][k]["rmse"]
                                             for k in fast["per"]}
+    if not args.no_served and args.workload == "sphere" and args.only is None:
+        out["served"] = served_mix()
     if not args.no_cpu and rank == 0:
         out["cpu_baseline"] = cpu_baseline(work)
     if rank == 0:

@@ -186,10 +186,12 @@ mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_fn* f, cons
 const char* mpwos_last_error(void);
 
 /* ---- serving: continuous batching of solves (one device) ----------------
- * Requests are admitted against an HBM budget; admitted requests share the
- * device: each scheduling round launches one batch that holds walks of every
- * admitted request, so a request that arrives while others run joins at the
- * next round.  A request's result is identical to the same solve run alone. */
+ * Requests are admitted in arrival order against an HBM budget.  Admitted
+ * requests share the device through a fixed number of in-flight slices of
+ * walks (two per stream on four streams); whenever a slice completes its slot
+ * takes the next slice, round-robin over the admitted requests, so a request
+ * that arrives while others run starts as soon as a slot frees.  A request's
+ * result is identical to the same solve run alone. */
 typedef struct mpwos_server mpwos_server;
 
 typedef struct {
@@ -211,12 +213,13 @@ typedef struct {
   int64_t walk_steps;
   double busy_seconds;        /* time with at least one request on the device */
   int64_t in_flight_bytes;    /* HBM held by admitted requests */
-  int32_t rounds;             /* scheduling rounds launched */
+  int32_t rounds;             /* slices of walks launched */
 } mpwos_server_stats;
 
 /* hbm_budget_bytes: device memory the server may hold for admitted requests
- * (queries, per-walk scores, outputs).  slice_walk_steps: work per
- * scheduling round (0 = default 2^26 walk-steps). */
+ * (queries, per-walk scores, outputs).  slice_walk_steps: work of one slice,
+ * shared by the admitted requests, in three-dimensional walk-steps (0 = about
+ * 9e7); a slice holds at least an eighth of the walks that fill the device. */
 mpwos_status mpwos_server_create(size_t hbm_budget_bytes, int64_t slice_walk_steps, mpwos_server** out);
 
 /* Queues a request (non-blocking); returns its ticket.  EINVAL for bad

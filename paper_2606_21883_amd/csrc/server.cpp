@@ -1,13 +1,15 @@
 // Continuous-batching server (include/mpwos.h, "serving").
 //
 // Requests are validated and costed at submit time and queued.  A worker
-// thread runs scheduling rounds: it admits queued requests in arrival order
-// while their device footprint fits the HBM budget, then launches one slice
-// of walks of every admitted request -- each request on one of a few streams
-// of default priority, so slices of different requests overlap on the
-// device -- and waits for the round.  A request whose walks are all done is
-// reduced per query, copied out, released and signalled.  A request that
-// arrives while others run is admitted at the next round.
+// thread admits queued requests in arrival order while their device
+// footprint fits the HBM budget and keeps a fixed number of walk slices in
+// flight: two per stream on a few streams of default priority.  Whenever a
+// slice completes (its event, polled by the host) the stream's slot takes the
+// next slice, chosen round-robin over the admitted requests, so slices of
+// different requests overlap on the device and a request that arrives while
+// others run gets slots as soon as slices drain, without waiting for the
+// others.  A request whose walks have all completed is reduced per query on a
+// separate completion stream, copied out, released and signalled.
 //
 // A walk's score depends only on (request, query, walk) through the Philox
 // counter, and the per-query reduction runs in a fixed order, so a served
@@ -35,6 +37,8 @@ namespace mpwos {
 namespace {
 
 constexpr int kStreams = 4;
+constexpr int kDepth = 2;                  // slices in flight per stream
+constexpr int kSlots = kStreams * kDepth;
 
 struct SrvReq {
   uint64_t ticket = 0;
@@ -56,10 +60,19 @@ struct SrvReq {
   double* d_se = nullptr;
   unsigned long long* d_stats = nullptr;  // ksum, kmax, ntrunc, queue
   double* d_table = nullptr;
-  int stream = 0;
   int32_t status = MPWOS_OK;
   bool finished = false;
+  bool async_alloc = false;    // device memory from the stream-ordered allocator
+  int inflight = 0;            // slices launched and not yet completed
+  bool queue_busy[kDepth] = {};  // per-slice work counters of the persistent kernels
   int64_t walk_steps = 0;
+};
+
+// One slot of in-flight work: a slice of walks of a request on a stream.
+struct Slot {
+  SrvReq* R = nullptr;
+  hipEvent_t ev = nullptr;
+  int queue = 0;
 };
 
 }  // namespace
@@ -67,7 +80,7 @@ struct SrvReq {
 
 struct mpwos_server {
   size_t budget = 0;
-  int64_t slice = 0;           // Philox blocks of work per round
+  int64_t slice = 0;           // Philox blocks of work per slice (all admitted requests share it)
   int device = 0;
   int n_cu = 256;
   std::mutex mu;
@@ -80,6 +93,7 @@ struct mpwos_server {
   uint64_t next_ticket = 1;
   size_t in_flight = 0;
   hipStream_t streams[mpwos::kStreams] = {};
+  hipStream_t done_stream = nullptr;   // per-query reductions and copies out
   mpwos_server_stats st = {};
   std::chrono::steady_clock::time_point t0;
 };
@@ -100,9 +114,18 @@ static size_t request_bytes(const mpwos_request& r, int n) {
 }
 
 static mpwos_status admit(mpwos_server* s, SrvReq* R) {
-  hipError_t e = hipMalloc((void**)&R->dev, R->bytes);
+  hipStream_t st = s->done_stream;
+  // the stream-ordered allocator: freeing a request does not wait for the
+  // device (a plain hipFree would synchronise with the slices of others)
+  hipError_t e = hipMallocAsync((void**)&R->dev, R->bytes, st);
+  R->async_alloc = e == hipSuccess;
   if (e != hipSuccess) {
     (void)hipGetLastError();
+    e = hipMalloc((void**)&R->dev, R->bytes);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    R->dev = nullptr;
     return fail(MPWOS_ENOMEM, "server: device allocation failed");
   }
   const int n = R->args.n;
@@ -115,12 +138,13 @@ static mpwos_status admit(mpwos_server* s, SrvReq* R) {
   R->d_se = (double*)take((size_t)R->r.n_queries * sizeof(double));
   R->d_stats = (unsigned long long*)take(8 * sizeof(unsigned long long));
   if (!R->table.empty()) R->d_table = (double*)take(R->table.size() * sizeof(double));
-  hipStream_t st = s->streams[R->stream];
   e = hipMemcpyAsync(R->d_queries, R->r.queries, (size_t)R->r.n_queries * n * sizeof(double),
                      hipMemcpyHostToDevice, st);
   if (e == hipSuccess && R->d_table)
     e = hipMemcpyAsync(R->d_table, R->table.data(), R->table.size() * sizeof(double), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = launch_zero_u64(R->d_stats, 8, st);
+  // slices run on other streams: the uploads complete before the first launch
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "server: admission copies");
   WalkArgs& a = R->args;
   a.queries = R->d_queries;
@@ -133,8 +157,10 @@ static mpwos_status admit(mpwos_server* s, SrvReq* R) {
   return MPWOS_OK;
 }
 
+// Every slice of R has completed (its events were observed): the reduction
+// runs on the completion stream, which carries nothing else.
 static mpwos_status finish(mpwos_server* s, SrvReq* R) {
-  hipStream_t st = s->streams[R->stream];
+  hipStream_t st = s->done_stream;
   hipError_t e = launch_reduce(R->d_S, R->d_K, R->r.n_queries, R->r.n_walks, R->opt.max_steps, R->d_u, R->d_se,
                                R->d_stats + 0, (int32_t*)(R->d_stats + 1), R->d_stats + 2, st);
   if (e == hipSuccess)
@@ -149,20 +175,49 @@ static mpwos_status finish(mpwos_server* s, SrvReq* R) {
   return hs[2] ? MPWOS_WTRUNC : MPWOS_OK;
 }
 
-static void release(SrvReq* R) {
-  if (R->dev) (void)hipFree(R->dev);
+static void release(mpwos_server* s, SrvReq* R) {
+  if (R->dev) {
+    if (R->async_alloc) (void)hipFreeAsync(R->dev, s->done_stream);
+    else (void)hipFree(R->dev);
+  }
   R->dev = nullptr;
   manifold_ref(R->r.manifold, -1);
 }
 
+// Walks of R in one slice: a share of the slice budget by the request's cost
+// per walk, at least what keeps the device busy together with the other
+// slots, at most what is left.
+static int64_t slice_walks(const mpwos_server* s, const SrvReq* R, int nact) {
+  const double share = (double)s->slice / std::max(1, nact) / std::max(1.0, R->k_est * R->step_cost);
+  int64_t walks = std::max<int64_t>((int64_t)share, R->min_walks / kSlots);
+  walks = std::max<int64_t>(walks, 1);
+  return std::min<int64_t>(walks, R->total - R->next);
+}
+
 static void worker_main(mpwos_server* s) {
   (void)hipSetDevice(s->device);
+  Slot slots[kSlots];
+  for (auto& sl : slots) (void)hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+  size_t rr = 0;
+  auto last = std::chrono::steady_clock::now();
   for (;;) {
-    std::vector<SrvReq*> fresh, round;
+    std::vector<SrvReq*> fresh;
+    std::vector<SrvReq*> active;
+    bool busy_slot = false;
+    for (auto& sl : slots) busy_slot = busy_slot || sl.R != nullptr;
+    {
+      const auto now = std::chrono::steady_clock::now();
+      if (busy_slot) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->st.busy_seconds += std::chrono::duration<double>(now - last).count();
+      }
+      last = now;
+    }
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty() || !s->active.empty(); });
-      if (s->stop && s->pending.empty() && s->active.empty()) break;
+      if (!busy_slot)
+        s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty() || !s->active.empty(); });
+      if (s->stop && s->pending.empty() && s->active.empty() && !busy_slot) break;
       while (!s->pending.empty()) {
         SrvReq* R = s->pending.front();
         if (!s->active.empty() && s->in_flight + R->bytes > s->budget) break;
@@ -172,10 +227,9 @@ static void worker_main(mpwos_server* s) {
         fresh.push_back(R);
         s->st.admitted += 1;
       }
-      round = s->active;
+      active = s->active;
       s->st.in_flight_bytes = (int64_t)s->in_flight;
     }
-    const auto tr0 = std::chrono::steady_clock::now();
     for (SrvReq* R : fresh) {
       mpwos_status st = admit(s, R);
       if (st) {
@@ -183,54 +237,85 @@ static void worker_main(mpwos_server* s) {
         R->next = R->total;
       }
     }
-    // one slice per request: a fair share of the round's work, at least what fills the device
-    const int nact = (int)round.size();
-    const int conc = std::min(nact, kStreams);
-    for (SrvReq* R : round) {
-      if (R->status < 0 || R->next >= R->total) continue;
-      const double share = (double)s->slice / nact / std::max(1.0, R->k_est * R->step_cost);
-      int64_t walks = (int64_t)share;
-      walks = std::max<int64_t>(walks, R->min_walks / conc);
-      walks = std::max<int64_t>(walks, 1);
-      walks = std::min<int64_t>(walks, R->total - R->next);
+    bool progress = !fresh.empty();
+    // completed slices free their slots
+    for (auto& sl : slots) {
+      if (!sl.R) continue;
+      const hipError_t q = hipEventQuery(sl.ev);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess && sl.R->status >= 0) sl.R->status = hip_fail(q, "server: slice");
+      sl.R->inflight -= 1;
+      sl.R->queue_busy[sl.queue] = false;
+      sl.R = nullptr;
+      progress = true;
+    }
+    // requests whose walks have all completed: reduce, copy out, release
+    std::vector<SrvReq*> done;
+    for (SrvReq* R : active) {
+      if (R->next < R->total || R->inflight > 0) continue;
+      if (R->status >= 0) R->status = finish(s, R);
+      release(s, R);
+      done.push_back(R);
+    }
+    // fill free slots round-robin over the requests with walks left
+    std::vector<SrvReq*> open;
+    for (SrvReq* R : active)
+      if (R->status >= 0 && R->next < R->total) open.push_back(R);
+    const int nact = (int)open.size();
+    for (int k = 0; k < kSlots && !open.empty(); ++k) {
+      Slot& sl = slots[k];
+      if (sl.R) continue;
+      SrvReq* R = nullptr;
+      int q = -1;
+      for (size_t t = 0; t < open.size() && !R; ++t) {
+        SrvReq* c = open[(rr + t) % open.size()];
+        if (c->next >= c->total) continue;
+        for (int j = 0; j < kDepth; ++j)
+          if (!c->queue_busy[j]) { q = j; break; }
+        if (q >= 0) { R = c; rr = (rr + t + 1) % open.size(); }
+      }
+      if (!R) break;
       WalkArgs a = R->args;
       a.idx_base = R->next;
-      a.count = walks;
-      mpwos_status st = launch_walks(a, R->opt, s->streams[R->stream], R->d_stats + 3);
-      if (st) {
-        R->status = st;
+      a.count = slice_walks(s, R, nact);
+      hipStream_t st = s->streams[k % kStreams];
+      mpwos_status ls = launch_walks(a, R->opt, st, R->d_stats + 3 + q);
+      hipError_t e = ls ? hipErrorUnknown : hipEventRecord(sl.ev, st);
+      if (ls || e != hipSuccess) {
+        R->status = ls ? ls : hip_fail(e, "server: slice event");
         R->next = R->total;
         continue;
       }
-      R->next += walks;
-    }
-    for (int i = 0; i < kStreams; ++i) (void)hipStreamSynchronize(s->streams[i]);
-    std::vector<SrvReq*> done;
-    for (SrvReq* R : round) {
-      if (R->next < R->total) continue;
-      if (R->status >= 0) {
-        (void)launch_zero_u64(R->d_stats, 3, s->streams[R->stream]);
-        R->status = finish(s, R);
-      }
-      release(R);
-      done.push_back(R);
-    }
-    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - tr0).count();
-    {
+      R->next += a.count;
+      R->inflight += 1;
+      R->queue_busy[q] = true;
+      sl.R = R;
+      sl.queue = q;
+      progress = true;
       std::lock_guard<std::mutex> lk(s->mu);
       s->st.rounds += 1;
-      s->st.busy_seconds += dt;
-      for (SrvReq* R : done) {
-        R->finished = true;
-        s->in_flight -= R->bytes;
-        s->st.completed += 1;
-        s->st.walk_steps += R->walk_steps;
-        s->active.erase(std::find(s->active.begin(), s->active.end(), R));
-      }
-      s->st.in_flight_bytes = (int64_t)s->in_flight;
     }
-    if (!done.empty()) s->cv_done.notify_all();
+    if (!done.empty()) {
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (SrvReq* R : done) {
+          R->finished = true;
+          s->in_flight -= R->bytes;
+          s->st.completed += 1;
+          s->st.walk_steps += R->walk_steps;
+          s->active.erase(std::find(s->active.begin(), s->active.end(), R));
+        }
+        s->st.in_flight_bytes = (int64_t)s->in_flight;
+      }
+      s->cv_done.notify_all();
+    }
+    if (!progress) {
+      // slices still running: look again shortly, or sooner when work arrives
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_work.wait_for(lk, std::chrono::microseconds(100));
+    }
   }
+  for (auto& sl : slots) (void)hipEventDestroy(sl.ev);
 }
 
 }  // namespace mpwos
@@ -251,6 +336,7 @@ mpwos_status mpwos_server_create(size_t hbm_budget_bytes, int64_t slice_walk_ste
   hipDeviceProp_t prop;
   if (e == hipSuccess) e = hipGetDeviceProperties(&prop, s->device);
   for (int i = 0; e == hipSuccess && i < kStreams; ++i) e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->done_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete s;
     return hip_fail(e, "server: stream creation");
@@ -298,7 +384,7 @@ mpwos_status mpwos_submit(mpwos_server* s, const mpwos_request* req, uint64_t* t
   if (R->args.const_r) R->k_est = std::ceil(std::log(R->opt.tau_w) / std::log(R->args.c0));
   R->step_cost = 1.0 + (double)((n + 3) / 4) * (1 + R->opt.n_v);
   const int lanes = (n <= 3) ? 1 : 64;
-  R->min_walks = (int64_t)s->n_cu * 16 * 64 / lanes;
+  R->min_walks = (int64_t)s->n_cu * 16 * 64 / lanes;   // walks that fill the device alone
   manifold_ref(req->manifold, +1);
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -308,7 +394,6 @@ mpwos_status mpwos_submit(mpwos_server* s, const mpwos_request* req, uint64_t* t
       return fail(MPWOS_EBUSY, "server is shutting down");
     }
     R->ticket = s->next_ticket++;
-    R->stream = (int)(R->ticket % kStreams);
     s->reqs[R->ticket] = R;
     s->pending.push_back(R);
     *ticket = R->ticket;
@@ -359,6 +444,10 @@ mpwos_status mpwos_server_destroy(mpwos_server* s) {
   for (auto& kv : s->reqs) delete kv.second;
   for (auto& st : s->streams)
     if (st) (void)hipStreamDestroy(st);
+  if (s->done_stream) {
+    (void)hipStreamSynchronize(s->done_stream);
+    (void)hipStreamDestroy(s->done_stream);
+  }
   delete s;
   return MPWOS_OK;
 }
