@@ -130,7 +130,7 @@ def make_workload(name, scale=1.0):
     return [(name, p, Q, nw)]
 
 
-def run_gpu(work, steps, warmup, precision, persistent):
+def run_gpu(work, steps, warmup, precision, persistent, block_size=0):
     import torch
 
     from paper_2606_21883_amd import inputs, mpwos
@@ -148,7 +148,8 @@ def run_gpu(work, steps, warmup, precision, persistent):
         st = []
         for name, prob, q, nw, m, u, se in items:
             s = mpwos.solve_device(m, prob, q.data_ptr(), q.shape[0], nw, 0, u.data_ptr(), se.data_ptr(),
-                                   stream=stream, precision=precision, persistent=persistent)
+                                   stream=stream, precision=precision, persistent=persistent,
+                                   block_size=block_size)
             st.append(s)
         return st
 
@@ -342,6 +343,7 @@ def main():
                     choices=["sphere", "circle", "torus", "cloud", "hyper100", "hyper1000"],
                     help="sphere (closed + cap) is the headline workload; the others are for profiling")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink queries and walks (profiling only)")
+    ap.add_argument("--block-size", type=int, default=0, help="workgroup size of the walk kernels (0 = default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--no-roofline", action="store_true", help="skip the VALU probe (profiling runs)")
@@ -372,7 +374,7 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     work = make_workload(args.workload, args.scale)
     prec = "fp64" if args.only == "fp64" else "fp32"
-    fast = run_gpu(work, args.steps, args.warmup, prec, 0 if prec == "fp64" else 1)
+    fast = run_gpu(work, args.steps, args.warmup, prec, 0 if prec == "fp64" else 1, args.block_size)
     slow = None
     if not args.no_fp64 and args.only is None:
         slow = run_gpu(work, max(1, min(args.steps, 3)), 1, "fp64", 0)

@@ -96,7 +96,7 @@ typedef struct {
   double p[4];              /* SPHERE: R; SPHERE_CAP: R, h (|h| < R); TORUS / POINT_CLOUD: R, a
                                (the torus the source families refer to) */
   const float* points;      /* POINT_CLOUD: n_points x 3 FP32 */
-  int64_t n_points;         /* POINT_CLOUD: >= k_nn */
+  int64_t n_points;         /* POINT_CLOUD: k_nn .. 2^27 */
   int32_t k_nn;             /* POINT_CLOUD: neighbours of the local fit, 6..32 (default 16) */
   int32_t points_on_device; /* 1: `points` is a device pointer */
 } mpwos_manifold_desc;
@@ -123,7 +123,8 @@ typedef struct {
   int64_t max_steps;        /* per-walk step cap, >= 1 (default 1e7); hitting it -> MPWOS_WTRUNC */
   void* stream;             /* hipStream_t or NULL */
   int32_t device_io;        /* 1: queries / outputs / walk_S / walk_K are device pointers */
-  int32_t block_size;       /* threads per workgroup, 0 = default (256); else 64, 128, 192 or 256 */
+  int32_t block_size;       /* threads per workgroup, 0 = default (256; 128 on a POINT_CLOUD);
+                               else 64, 128, 192 or 256 (at most 128 on a POINT_CLOUD) */
   int32_t lanes_per_walk;   /* 0 = default; 1 for n <= 3; else 8, 16, 32 or 64 */
   int32_t persistent;       /* 1: persistent kernel refilling lanes from a global queue;
                                0: plain launch, one walk per lane (or per lane group) */

@@ -38,6 +38,7 @@ struct CloudState {
   Patch<double>* patch64 = nullptr;
   Patch<float>* patch32 = nullptr;
   int32_t n_nodes = 0;
+  int32_t root = 0;
   double hmean_max = 0.0;
   int64_t fallback_points = 0;
 };
@@ -199,11 +200,11 @@ __global__ __launch_bounds__(64) void knn_tile_kernel(GridArgs g) {
     for (int t = 0; t < g.k; ++t) g.knn[(int64_t)self * g.k + t] = ei[t];
 }
 
-// Exact k nearest points of each flagged point: depth-first KD-tree search,
-// nearer child first, pruning boxes strictly farther than the current k-th
-// distance (equal distances are still visited so that index ties resolve
-// exactly).  Ordered by (distance^2, original index).
-__global__ void knn_kd_kernel(const KdNode* __restrict__ nodes, const float4* __restrict__ kd_pts,
+// Exact k nearest points of each flagged point: the depth-first KD-tree
+// search of the walk's nearest-point query, keeping the k best (ordered by
+// distance^2, then original index) and pruning boxes strictly farther than the
+// current k-th distance.
+__global__ void knn_kd_kernel(const KdNode* __restrict__ nodes, int32_t root, const float4* __restrict__ kd_pts,
                               const float4* __restrict__ orig, int32_t k, const int32_t* list, int32_t nlist,
                               int32_t* knn) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -214,14 +215,15 @@ __global__ void knn_kd_kernel(const KdNode* __restrict__ nodes, const float4* __
   double ed[kMaxK];
   int32_t ei[kMaxK];
   int nk = 0;
-  int32_t stack[64];
+  int32_t sref[kKdStack];
+  double sdist[kKdStack];
   int sp = 0;
-  stack[sp++] = 0;
-  while (sp > 0) {
-    const KdNode nd = nodes[stack[--sp]];
-    if (nk == k && box_dist2<double>(nd, xq) > ed[k - 1]) continue;
-    if (nd.left < 0) {
-      for (int32_t i = nd.start; i < nd.start + nd.count; ++i) {
+  int32_t ref = root;
+  auto bound = [&]() { return nk == k ? ed[k - 1] : 1e300; };
+  for (;;) {
+    if (ref < 0) {
+      const int32_t start = leaf_start(ref), end = start + leaf_count(ref);
+      for (int32_t i = start; i < end; ++i) {
         const float4 p = kd_pts[i];
         const double d2 = dist2_exact(xq, p.x, p.y, p.z);
         const int32_t id = __float_as_int(p.w);
@@ -237,16 +239,31 @@ __global__ void knn_kd_kernel(const KdNode* __restrict__ nodes, const float4* __
         if (nk < k) ++nk;
       }
     } else {
-      const double dl = box_dist2<double>(nodes[nd.left], xq);
-      const double dr = box_dist2<double>(nodes[nd.right], xq);
-      if (dl <= dr) {
-        stack[sp++] = nd.right;
-        stack[sp++] = nd.left;
-      } else {
-        stack[sp++] = nd.left;
-        stack[sp++] = nd.right;
+      const KdNode nd = nodes[ref];
+      const double d0 = box_dist2<double>(nd.lo[0], nd.hi[0], xq);
+      const double d1 = box_dist2<double>(nd.lo[1], nd.hi[1], xq);
+      const bool first = d0 <= d1;
+      const double dn = first ? d0 : d1, df = first ? d1 : d0;
+      if (df <= bound() && sp < kKdStack) {
+        sref[sp] = first ? nd.child[1] : nd.child[0];
+        sdist[sp] = df;
+        ++sp;
+      }
+      if (dn <= bound()) {
+        ref = first ? nd.child[0] : nd.child[1];
+        continue;
       }
     }
+    bool more = false;
+    while (sp > 0) {
+      --sp;
+      if (sdist[sp] <= bound()) {
+        ref = sref[sp];
+        more = true;
+        break;
+      }
+    }
+    if (!more) break;
   }
   for (int m = 0; m < k; ++m) knn[(int64_t)self * k + m] = ei[m];
 }
@@ -410,37 +427,43 @@ struct HostKd {
   std::vector<int32_t> order;
 };
 
-int kd_build(HostKd& t, const std::vector<float>& P, int lo, int hi, int depth) {
-  KdNode nd;
-  for (int d = 0; d < 3; ++d) { nd.lo[d] = 3e38f; nd.hi[d] = -3e38f; }
+struct HostBox {
+  float lo[3], hi[3];
+};
+
+// Median split on the widest axis of the subtree's box, leaves of at most 8
+// points.  Returns the subtree's reference (internal node index, or a leaf
+// reference) and its box.
+int32_t kd_build(HostKd& t, const std::vector<float>& P, int lo, int hi, HostBox& bx) {
+  for (int d = 0; d < 3; ++d) { bx.lo[d] = 3e38f; bx.hi[d] = -3e38f; }
   for (int i = lo; i < hi; ++i)
     for (int d = 0; d < 3; ++d) {
-      nd.lo[d] = std::min(nd.lo[d], P[3 * t.order[i] + d]);
-      nd.hi[d] = std::max(nd.hi[d], P[3 * t.order[i] + d]);
+      bx.lo[d] = std::min(bx.lo[d], P[3 * t.order[i] + d]);
+      bx.hi[d] = std::max(bx.hi[d], P[3 * t.order[i] + d]);
     }
-  const int id = (int)t.nodes.size();
-  t.nodes.push_back(nd);
-  if (hi - lo <= 8 || depth >= kKdDepth) {
-    t.nodes[id].left = -1;
-    t.nodes[id].right = -1;
-    t.nodes[id].start = lo;
-    t.nodes[id].count = hi - lo;
-    return id;
-  }
+  if (hi - lo <= 8) return -(lo * 16 + (hi - lo)) - 1;
   int dim = 0;
   for (int d = 1; d < 3; ++d)
-    if (nd.hi[d] - nd.lo[d] > nd.hi[dim] - nd.lo[dim]) dim = d;
+    if (bx.hi[d] - bx.lo[d] > bx.hi[dim] - bx.lo[dim]) dim = d;
   const int mid = (lo + hi) / 2;
   std::nth_element(t.order.begin() + lo, t.order.begin() + mid, t.order.begin() + hi, [&](int a, int b) {
     const float va = P[3 * a + dim], vb = P[3 * b + dim];
     return va < vb || (va == vb && a < b);
   });
-  const int l = kd_build(t, P, lo, mid, depth + 1);
-  const int r = kd_build(t, P, mid, hi, depth + 1);
-  t.nodes[id].left = l;
-  t.nodes[id].right = r;
-  t.nodes[id].start = lo;
-  t.nodes[id].count = hi - lo;
+  const int id = (int)t.nodes.size();
+  t.nodes.emplace_back();
+  HostBox bl, br;
+  const int32_t l = kd_build(t, P, lo, mid, bl);
+  const int32_t r = kd_build(t, P, mid, hi, br);
+  KdNode& nd = t.nodes[id];
+  for (int d = 0; d < 3; ++d) {
+    nd.lo[0][d] = bl.lo[d]; nd.hi[0][d] = bl.hi[d];
+    nd.lo[1][d] = br.lo[d]; nd.hi[1][d] = br.hi[d];
+  }
+  nd.child[0] = l;
+  nd.child[1] = r;
+  nd.count[0] = l < 0 ? mid - lo : 0;
+  nd.count[1] = r < 0 ? hi - mid : 0;
   return id;
 }
 
@@ -525,7 +548,8 @@ mpwos_status cloud_create(const mpwos_manifold_desc& d, hipStream_t s, CloudStat
   kd.order.resize((size_t)n);
   std::iota(kd.order.begin(), kd.order.end(), 0);
   kd.nodes.reserve((size_t)(n / 4 + 16));
-  kd_build(kd, P, 0, (int)n, 0);
+  HostBox root_box;
+  const int32_t root = kd_build(kd, P, 0, (int)n, root_box);
   std::vector<float4> kdp((size_t)n);
   for (int64_t i = 0; i < n; ++i) kdp[i] = orig[kd.order[i]];
 
@@ -533,6 +557,7 @@ mpwos_status cloud_create(const mpwos_manifold_desc& d, hipStream_t s, CloudStat
   C->n = n;
   C->k = k;
   C->n_nodes = (int32_t)kd.nodes.size();
+  C->root = root;
   float4 *d_sorted = upload(sorted, e), *d_orig = upload(orig, e);
   int32_t* d_cstart = upload(cstart, e);
   int4* d_tiles = upload(tiles, e);
@@ -569,7 +594,7 @@ mpwos_status cloud_create(const mpwos_manifold_desc& d, hipStream_t s, CloudStat
   int32_t* d_redo = upload(redo, e);
   if (e == hipSuccess && !redo.empty()) {
     hipLaunchKernelGGL(knn_kd_kernel, dim3((unsigned)((redo.size() + 63) / 64)), dim3(64), 0, s, C->nodes,
-                       C->kd_pts, d_orig, k, d_redo, (int32_t)redo.size(), d_knn);
+                       C->root, C->kd_pts, d_orig, k, d_redo, (int32_t)redo.size(), d_knn);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
@@ -610,6 +635,7 @@ void cloud_fill_args(const CloudState* c, const mpwos_options& o, WalkArgs& a) {
   a.cloud.patch32 = c->patch32;
   a.cloud.n_points = c->n;
   a.cloud.n_nodes = c->n_nodes;
+  a.cloud.root = c->root;
   a.cloud.k = c->k;
   a.cloud.newton_iters = o.newton_iters;
   a.cloud.radius_rule = o.radius_rule == MPWOS_RADIUS_SPACING ? 1 : 0;
@@ -629,7 +655,8 @@ mpwos_status cloud_check_queries(const WalkArgs& a, const double* dq, int64_t nq
     return fail(MPWOS_ENOMEM, "query check buffer");
   }
   std::vector<double> out((size_t)nq * 2);
-  hipLaunchKernelGGL(cloud_query_check_kernel, dim3((unsigned)((nq + 127) / 128)), dim3(128), 0, s, a.cloud, dq,
+  hipLaunchKernelGGL(cloud_query_check_kernel, dim3((unsigned)((nq + kCloudBlock - 1) / kCloudBlock)),
+                     dim3(kCloudBlock), 0, s, a.cloud, dq,
                      dout, nq);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(out.data(), dout, bytes, hipMemcpyDeviceToHost, s);

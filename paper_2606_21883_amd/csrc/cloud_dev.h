@@ -24,44 +24,56 @@ __device__ __forceinline__ float dist2_exact(const float* x, float px, float py,
 }
 
 template <class T>
-__device__ __forceinline__ T box_dist2(const KdNode& nd, const T* x) {
+__device__ __forceinline__ T box_dist2(const float* lo, const float* hi, const T* x) {
   T s = (T)0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     T e = (T)0;
-    if (x[d] < (T)nd.lo[d]) e = (T)nd.lo[d] - x[d];
-    else if (x[d] > (T)nd.hi[d]) e = x[d] - (T)nd.hi[d];
+    if (x[d] < (T)lo[d]) e = (T)lo[d] - x[d];
+    else if (x[d] > (T)hi[d]) e = x[d] - (T)hi[d];
     s += e * e;
   }
   return s;
 }
 
-// The KD-tree is at most kKdDepth levels deep (leaves below that depth hold
-// more points), so a depth-first search holds at most kKdDepth + 1 deferred
-// nodes: one per level above the current node plus its two children.
-constexpr int kKdDepth = 30;
-constexpr int kKdStack = 32;
+// A leaf reference packs its first point and its size (at most 8 points):
+// ref = -(start * 16 + count) - 1.
+__device__ __forceinline__ int32_t leaf_start(int32_t ref) { return (-ref - 1) >> 4; }
+__device__ __forceinline__ int32_t leaf_count(int32_t ref) { return (-ref - 1) & 15; }
 
-// Nearest cloud point of x: depth-first search, nearer child first, pruning
-// boxes farther than the best distance (a box at exactly the best distance is
-// still visited so that the index tie-break is exact).  Returns the original
-// index.  The per-lane stack lives in LDS (column threadIdx.x of a
-// kKdStack x 256 array: 32 KB per workgroup of at most 256 lanes).
+// Median splits give leaves at depth at most ceil(log2(n / 8)) <= 24 for
+// n <= 2^27 points, and the search defers at most one far child per internal
+// node on its current path: 24 entries always suffice.
+constexpr int kKdStack = 24;
+// Workgroups of the kernels that search the cloud hold at most this many lanes.
+constexpr int kCloudBlock = 128;
+
+// Distance stored on the stack: rounded down, so a deferred box is never
+// pruned when its exact distance is within the best one.
+__device__ __forceinline__ float stack_dist(float d) { return d; }
+__device__ __forceinline__ float stack_dist(double d) { return __double2float_rd(d); }
+
+// Nearest cloud point of x: depth-first search that descends into the nearer
+// child and defers the farther one with its box distance, pruning boxes
+// farther than the best distance (a box at exactly the best distance is still
+// visited, so the index tie-break is exact).  Returns the original index.
+// The deferred nodes live in LDS: column threadIdx.x of kKdStack x
+// kCloudBlock arrays (24 KB per workgroup).
 template <class T>
 __device__ __forceinline__ int32_t kd_nearest(const CloudDev& c, const T* x) {
-  __shared__ int32_t stack[kKdStack][256];
+  __shared__ int32_t sref[kKdStack][kCloudBlock];
+  __shared__ float sdist[kKdStack][kCloudBlock];
   const int lane = threadIdx.x;
   // a non-finite x matches no point: skip the search (it would visit every node)
   if (!(abs_(x[0]) + abs_(x[1]) + abs_(x[2]) < (T)3.0e38)) return 0;
-  int sp = 0;
-  stack[sp++][lane] = 0;
   T best = (T)3.0e38;
   int32_t bidx = 0x7fffffff;
-  while (sp > 0) {
-    const KdNode nd = c.nodes[stack[--sp][lane]];
-    if (box_dist2(nd, x) > best) continue;
-    if (nd.left < 0) {
-      for (int32_t i = nd.start; i < nd.start + nd.count; ++i) {
+  int sp = 0;
+  int32_t ref = c.root;
+  for (;;) {
+    if (ref < 0) {
+      const int32_t start = leaf_start(ref), end = start + leaf_count(ref);
+      for (int32_t i = start; i < end; ++i) {
         const float4 p = c.kd_pts[i];
         const T d2 = dist2_exact(x, p.x, p.y, p.z);
         const int32_t id = __float_as_int(p.w);
@@ -71,17 +83,32 @@ __device__ __forceinline__ int32_t kd_nearest(const CloudDev& c, const T* x) {
         }
       }
     } else {
-      const T dl = box_dist2(c.nodes[nd.left], x);
-      const T dr = box_dist2(c.nodes[nd.right], x);
-      // the nearer child is pushed last, so it is searched first
-      if (dl <= dr) {
-        if (dr <= best && sp < kKdStack) stack[sp++][lane] = nd.right;
-        if (dl <= best && sp < kKdStack) stack[sp++][lane] = nd.left;
-      } else {
-        if (dl <= best && sp < kKdStack) stack[sp++][lane] = nd.left;
-        if (dr <= best && sp < kKdStack) stack[sp++][lane] = nd.right;
+      const KdNode nd = c.nodes[ref];
+      const T d0 = box_dist2<T>(nd.lo[0], nd.hi[0], x);
+      const T d1 = box_dist2<T>(nd.lo[1], nd.hi[1], x);
+      const bool first = d0 <= d1;
+      const T dn = first ? d0 : d1, df = first ? d1 : d0;
+      const int32_t cn = first ? nd.child[0] : nd.child[1], cf = first ? nd.child[1] : nd.child[0];
+      if (df <= best && sp < kKdStack) {
+        sref[sp][lane] = cf;
+        sdist[sp][lane] = stack_dist(df);
+        ++sp;
+      }
+      if (dn <= best) {
+        ref = cn;
+        continue;
       }
     }
+    bool more = false;
+    while (sp > 0) {
+      --sp;
+      if ((T)sdist[sp][lane] <= best) {
+        ref = sref[sp][lane];
+        more = true;
+        break;
+      }
+    }
+    if (!more) break;
   }
   // a non-finite x matches no point: fall back to point 0 so the caller's
   // patch read stays in bounds (the walk then ends on its non-finite state)

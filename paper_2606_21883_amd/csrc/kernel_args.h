@@ -65,12 +65,14 @@ struct InvTable {
   double x2scale;         // (mx - 1) / x2max: X^2 -> slice position
 };
 
-// KD-tree node over the cloud: bounding box of its points, children (internal
-// node) or a range of the KD-ordered point array (leaf: left < 0).
+// Internal node of the KD-tree over the cloud, holding its two children's
+// bounding boxes (so a visit costs one 64-byte load): child[c] >= 0 is an
+// internal node; child[c] < 0 is a leaf, the points kd_pts[-child[c] - 1 ..
+// -child[c] - 1 + count[c]).
 struct KdNode {
-  float lo[3], hi[3];
-  int32_t left, right;   // children; left = -1 marks a leaf
-  int32_t start, count;  // leaf points: kd_pts[start .. start + count)
+  float lo[2][3], hi[2][3];
+  int32_t child[2];
+  int32_t count[2];
 };
 
 // Local quadratic patch of one cloud point: centroid, tangent frame e1, e2,
@@ -90,6 +92,7 @@ struct CloudDev {
   const Patch<float>* patch32;
   int64_t n_points;
   int32_t n_nodes;
+  int32_t root;                // internal node 0, or the leaf reference of a one-leaf cloud
   int32_t k;                   // neighbours of the reconstruction
   int32_t newton_iters;
   int32_t radius_rule;         // 1 = spacing, otherwise curvature of the fitted patch

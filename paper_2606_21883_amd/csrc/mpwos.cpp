@@ -337,8 +337,8 @@ static mpwos_status check_manifold_desc(const mpwos_manifold_desc* d) {
       if (d->n != 3) return fail(MPWOS_EINVAL, "point cloud: n must be 3");
       if (!d->points) return fail(MPWOS_EINVAL, "point cloud: points is NULL");
       if (d->k_nn < 6 || d->k_nn > kMaxK) return fail(MPWOS_EINVAL, "point cloud: k_nn must be in [6, 32]");
-      if (d->n_points < d->k_nn || d->n_points > (int64_t)1 << 30)
-        return fail(MPWOS_EINVAL, "point cloud: n_points must be in [k_nn, 2^30]");
+      if (d->n_points < d->k_nn || d->n_points > (int64_t)1 << 27)
+        return fail(MPWOS_EINVAL, "point cloud: n_points must be in [k_nn, 2^27]");
       return MPWOS_OK;
   }
   return fail(MPWOS_EINVAL, "unknown manifold kind");
@@ -608,7 +608,10 @@ mpwos_status launch_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, un
   const int64_t total = a.count;
   const int n_cu = device_cu_count();
   if (a.n <= 3) {
-    const int block = o.block_size ? o.block_size : 256;
+    // the point-cloud search keeps a per-lane stack in LDS sized for 128-lane workgroups
+    const int block = a.kind == MPWOS_POINT_CLOUD ? (o.block_size ? o.block_size : 128) : (o.block_size ? o.block_size : 256);
+    if (a.kind == MPWOS_POINT_CLOUD && block > 128)
+      return fail(MPWOS_EINVAL, "point clouds take block_size 0, 64 or 128");
     hipError_t e;
     if (a.persistent) {
       const int occ = lane_occupancy(a, block);

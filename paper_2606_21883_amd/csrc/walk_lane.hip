@@ -542,7 +542,7 @@ hipError_t launch_valu_probe(int op, uint32_t seed, int32_t iters, uint32_t* out
 // ---- host launchers -----------------------------------------------------------
 template <class T, int N, int KIND>
 static hipError_t launch_cp_t(const WalkArgs& a, const double* x, double* y, int64_t m, hipStream_t s) {
-  hipLaunchKernelGGL((cp_points_kernel<T, N, KIND>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a, x, y, m);
+  hipLaunchKernelGGL((cp_points_kernel<T, N, KIND>), dim3((unsigned)((m + 127) / 128)), dim3(128), 0, s, a, x, y, m);
   return hipGetLastError();
 }
 
