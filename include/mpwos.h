@@ -186,6 +186,51 @@ mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_fn* f, cons
 /* Message of the last failed call on this thread ("" if none). */
 const char* mpwos_last_error(void);
 
+/* ---- graph-captured solves -----------------------------------------------
+ * A plan captures the device work of one solve shape (manifold, f, g, c,
+ * n_queries, n_walks, eps, options) in a HIP graph once; each execute then
+ * replays it for new device-resident queries and a new seed with a handful of
+ * launches.  Results equal mpwos_solve's for the same arguments bit for bit.
+ * The plan owns n_queries x n_walks x 12 bytes of per-walk scores plus the
+ * queries and estimates, and holds a reference to the manifold. */
+typedef struct mpwos_plan mpwos_plan;
+
+/* Validates like mpwos_solve (except the queries, which execute takes) and
+ * captures the graph.  opt->stream, device_io and walk_S / walk_K are
+ * ignored.  EINVAL above 2^30 walks. */
+mpwos_status mpwos_plan_create(const mpwos_manifold* manifold, const mpwos_fn* f, const mpwos_fn* g, double c,
+                               int64_t n_queries, int64_t n_walks, double eps, const mpwos_options* opt,
+                               mpwos_plan** out);
+
+/* Enqueues one solve on `stream` (a hipStream_t; NULL = the plan's own
+ * stream): copies the device array `queries` (n_queries x n, each on M: not
+ * checked here) into the plan, replays the graph with `seed`, and copies the
+ * estimates to the device arrays u_out and stderr_out (nullable).
+ * Asynchronous; executes of one plan must not overlap (use one stream). */
+mpwos_status mpwos_plan_execute(mpwos_plan* p, const double* queries, double* u_out, double* stderr_out,
+                                uint64_t seed, void* stream);
+
+/* Waits for `stream` and reports the last execute's walk counts (walk_steps,
+ * truncated, k_max, k_mean; times are not measured here).  WTRUNC when walks
+ * were cut at max_steps. */
+mpwos_status mpwos_plan_stats(mpwos_plan* p, void* stream, mpwos_stats* stats);
+
+/* Waits for the plan's own stream and frees the plan. */
+mpwos_status mpwos_plan_destroy(mpwos_plan* p);
+
+/* ---- launch autotuner ----------------------------------------------------
+ * Times the launch shapes of a solve on a sample of it (whole queries, walks
+ * per query capped so that a trial is a fraction of a second) and returns the
+ * fastest options: block_size and persistent for n <= 3, also lanes_per_walk
+ * for n >= 4.  Other fields are copied from opt.  Walk results do not depend
+ * on block_size or persistent; for n >= 4 they depend on lanes_per_walk
+ * through the order of the lane-group sums, so a caller that needs
+ * reproducible bits keeps the returned options.  best_ms (nullable): kernel
+ * time of the best trial. */
+mpwos_status mpwos_autotune(const mpwos_manifold* manifold, const mpwos_fn* f, const mpwos_fn* g, double c,
+                            const double* queries, int64_t n_queries, int64_t n_walks, double eps,
+                            const mpwos_options* opt, mpwos_options* best, double* best_ms);
+
 /* ---- serving: continuous batching of solves (one device) ----------------
  * Requests are admitted in arrival order against an HBM budget.  Admitted
  * requests share the device through a fixed number of in-flight slices of

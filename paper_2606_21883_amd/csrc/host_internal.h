@@ -15,6 +15,7 @@ mpwos_status fail(mpwos_status st, const std::string& msg);
 mpwos_status hip_fail(hipError_t e, const char* what);
 int device_cu_count();
 void manifold_ref(const mpwos_manifold* m, int d);
+const mpwos_manifold_desc& manifold_desc(const mpwos_manifold* m);
 
 mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const mpwos_fn* g, double sigma,
                            int64_t nq, int64_t nw, double eps, uint64_t seed, const mpwos_options& o,
@@ -30,6 +31,7 @@ hipError_t launch_reduce(const double* walk_S, const int32_t* walk_K, int64_t nq
                          double* u, double* se, unsigned long long* ksum, int32_t* kmax,
                          unsigned long long* ntrunc, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+hipError_t launch_set_u64(unsigned long long* p, unsigned long long v, hipStream_t s);
 hipError_t launch_cp_points(const WalkArgs& a, const double* x, double* y, int64_t m, hipStream_t s);
 hipError_t launch_radial_inv(const WalkArgs& a, const double* u, double* s_out, int64_t m, int fp64,
                              hipStream_t s);
@@ -39,6 +41,7 @@ hipError_t launch_valu_probe(int op, uint32_t seed, int32_t iters, uint32_t* out
 
 // walk_group.hip
 mpwos_status launch_group_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue);
+void group_shape(int n, int lanes_req, int& L, int& mb, int& nblk, int& rblk, int& rword);
 
 // cloud.hip
 mpwos_status cloud_create(const mpwos_manifold_desc& d, hipStream_t s, CloudState** out);

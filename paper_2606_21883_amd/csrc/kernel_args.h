@@ -121,6 +121,7 @@ struct WalkArgs {
   int64_t idx_base;            // first walk (linear index q_local * nw + w) of this launch
   int64_t count;               // walks in this launch
   uint64_t seed;
+  const uint64_t* seed_dev;    // non-null: the seed is read from device memory (graph replays)
   double* walk_S;
   int32_t* walk_K;
   unsigned long long* queue;   // persistent work counter

@@ -482,6 +482,7 @@ mpwos_status mpwos_manifold_destroy(mpwos_manifold* m) {
 namespace mpwos {
 
 void manifold_ref(const mpwos_manifold* m, int d) { const_cast<mpwos_manifold*>(m)->refs += d; }
+const mpwos_manifold_desc& manifold_desc(const mpwos_manifold* m) { return m->desc; }
 
 // Validates a solve and fills the kernel arguments (except buffers).
 mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const mpwos_fn* g, double sigma,

@@ -81,7 +81,8 @@ __device__ __forceinline__ T coord_of(const T* v, int i, int gl) {
 
 template <class T, int L, int MB>
 __device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB>& st, int gl) {
-  const Stream rs{st.q, st.w, (uint32_t)a.seed, (uint32_t)(a.seed >> 32)};
+  const uint64_t seed = a.seed_dev ? *a.seed_dev : a.seed;
+  const Stream rs{st.q, st.w, (uint32_t)seed, (uint32_t)(seed >> 32)};
   const double r = a.r0;
   const T rT = (T)r;
   const T R = (T)a.p[0];

@@ -146,7 +146,8 @@ __device__ __forceinline__ T green_sample(const WalkArgs& a, const T* Y, uint4 b
 
 template <class T, int N, int KIND, bool RICH>
 __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st) {
-  const Stream rs{st.q, st.w, (uint32_t)a.seed, (uint32_t)(a.seed >> 32)};
+  const uint64_t seed = a.seed_dev ? *a.seed_dev : a.seed;
+  const Stream rs{st.q, st.w, (uint32_t)seed, (uint32_t)(seed >> 32)};
   // (i) radius r(Y) = theta min(delta_Gamma, rho_geo) and the weights
   double r, c, om, X2, norm = 0.0;
   if constexpr (KIND == kCap) {
@@ -363,6 +364,10 @@ __global__ __launch_bounds__(256) void reduce_queries_kernel(const double* __res
 __global__ void zero_u64_kernel(unsigned long long* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0ull;
+}
+
+__global__ void set_u64_kernel(unsigned long long* p, unsigned long long v) {
+  if (threadIdx.x == 0) p[0] = v;
 }
 
 // ---- inspection kernels -------------------------------------------------------
@@ -632,6 +637,11 @@ hipError_t launch_reduce(const double* walk_S, const int32_t* walk_K, int64_t nq
 
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
   hipLaunchKernelGGL(zero_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_u64(unsigned long long* p, unsigned long long v, hipStream_t s) {
+  hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(64), 0, s, p, v);
   return hipGetLastError();
 }
 

@@ -74,7 +74,8 @@ EXPORTS = ["mpwos_options_default", "mpwos_manifold_create", "mpwos_manifold_des
            "mpwos_last_error", "mpwos_server_create", "mpwos_submit", "mpwos_poll", "mpwos_wait",
            "mpwos_server_stats_get", "mpwos_server_destroy", "mpwos_debug_cp", "mpwos_debug_cloud_info",
            "mpwos_debug_radial_inv",
-           "mpwos_debug_philox", "mpwos_copy_probe", "mpwos_valu_probe", "mpwos_version"]
+           "mpwos_debug_philox", "mpwos_copy_probe", "mpwos_valu_probe", "mpwos_version",
+           "mpwos_plan_create", "mpwos_plan_execute", "mpwos_plan_stats", "mpwos_plan_destroy", "mpwos_autotune"]
 
 _lib = None
 
@@ -113,6 +114,11 @@ def lib():
         L.mpwos_debug_philox.argtypes = [vp, ctypes.c_uint64, i64, vp]
         L.mpwos_copy_probe.argtypes = [i64, i32, vp]
         L.mpwos_valu_probe.argtypes = [i32, vp]
+        L.mpwos_plan_create.argtypes = [vp, vp, vp, d, i64, i64, d, vp, vp]
+        L.mpwos_plan_execute.argtypes = [vp, vp, vp, vp, ctypes.c_uint64, vp]
+        L.mpwos_plan_stats.argtypes = [vp, vp, vp]
+        L.mpwos_plan_destroy.argtypes = [vp]
+        L.mpwos_autotune.argtypes = [vp, vp, vp, d, vp, i64, i64, d, vp, vp, vp]
         for nm in EXPORTS:
             if nm not in ("mpwos_options_default", "mpwos_last_error", "mpwos_version"):
                 getattr(L, nm).restype = ctypes.c_int
@@ -318,6 +324,58 @@ def valu_probe(op):
 
 def version():
     return lib().mpwos_version().decode()
+
+
+class Plan:
+    """mpwos_plan_*: one solve shape captured in a HIP graph; execute() replays
+    it for device-resident queries and outputs (raw device pointers)."""
+
+    def __init__(self, manifold, prob, n_queries, n_walks, **optkw):
+        self._keep = []
+        f = make_fn(prob.get("f", {"kind": "zero"}), self._keep)
+        g = make_fn(prob.get("g"), self._keep) if prob["manifold"] == "sphere_cap" else None
+        o = make_options(prob, **optkw)
+        self.handle = ctypes.c_void_p()
+        _check(lib().mpwos_plan_create(manifold.handle, ctypes.byref(f), ctypes.byref(g) if g is not None else None,
+                                       float(prob["sigma"]), int(n_queries), int(n_walks),
+                                       float(prob.get("eps", 1e-3)), ctypes.byref(o), ctypes.byref(self.handle)))
+
+    def execute(self, queries_ptr, u_ptr, se_ptr, seed, stream=None):
+        _check(lib().mpwos_plan_execute(self.handle, ctypes.c_void_p(queries_ptr), ctypes.c_void_p(u_ptr),
+                                        ctypes.c_void_p(se_ptr) if se_ptr else None, int(seed),
+                                        ctypes.c_void_p(int(stream)) if stream else None))
+
+    def stats(self, stream=None):
+        st = Stats()
+        rc = lib().mpwos_plan_stats(self.handle, ctypes.c_void_p(int(stream)) if stream else None, ctypes.byref(st))
+        _check(rc)
+        return {k: getattr(st, k) for k, _ in Stats._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(lib().mpwos_plan_destroy(self.handle))
+            self.handle = ctypes.c_void_p()
+
+
+def autotune(prob, queries, n_walks, manifold=None, **optkw):
+    """mpwos_autotune: returns (options dict of the fastest launch shape, its kernel ms)."""
+    own = manifold is None
+    m = Manifold(prob) if own else manifold
+    keep = []
+    Q = np.ascontiguousarray(queries, dtype=np.float64)
+    f = make_fn(prob.get("f", {"kind": "zero"}), keep)
+    g = make_fn(prob.get("g"), keep) if prob["manifold"] == "sphere_cap" else None
+    o = make_options(prob, **optkw)
+    best = Options()
+    ms = ctypes.c_double()
+    rc = lib().mpwos_autotune(m.handle, ctypes.byref(f), ctypes.byref(g) if g is not None else None,
+                              float(prob["sigma"]), _ptr(Q), Q.shape[0], int(n_walks),
+                              float(prob.get("eps", 1e-3)), ctypes.byref(o), ctypes.byref(best), ctypes.byref(ms))
+    if own:
+        m.close()
+    _check(rc)
+    return {"block_size": best.block_size, "lanes_per_walk": best.lanes_per_walk,
+            "persistent": best.persistent}, ms.value
 
 
 class Server:
