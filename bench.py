@@ -41,16 +41,16 @@ METRIC = "walk-steps/s and queries/s at fixed RMSE vs FP64 oracle; served p50/p9
 # FMA.  The VALU probe reaches about 72% of it with a pure fma_f32 stream.
 PEAK_SLOTS = 256 * 128 * 2.4e9
 
-# HBM bytes of one launch of the closed-sphere FP32 persistent walk kernel on
-# the headline workload (4096 x 4096 walks), from rocprofv3 --pmc FETCH_SIZE
+# HBM bytes of one launch of the closed-sphere FP32 walk kernel on the
+# headline workload (4096 x 4096 walks, plain lanes, 256 per block), from rocprofv3 --pmc FETCH_SIZE
 # and WRITE_SIZE (KiB per dispatch), each scaled by the reading of a plain
 # copy kernel of known size (FETCH_SIZE reads half the bytes a copy moves,
 # WRITE_SIZE all of them).  Valid only for the kernel sources they were taken
 # on (their SHA-256 below); any change to those sources makes traffic null.
 TRAFFIC = {
-    "kernel_sha256": "ca4eb42cae273149b42c638a6419b067aa1b17be94afe6f2795bc06accd34d9a",
-    "fetch_kib": 303.8125, "fetch_factor": 2.0,
-    "write_kib": 198880.0, "write_factor": 1.0,
+    "kernel_sha256": "5645fe1f9d92dc43738a8497061e476d3d259d5075944e5eb6630b3fa3f84b68",
+    "fetch_kib": 472.875, "fetch_factor": 2.0,
+    "write_kib": 196608.0, "write_factor": 1.0,
 }
 KERNEL_SOURCES = ["walk_lane.hip", "mpwos_dev.h", "kernel_args.h", "cloud_dev.h"]
 
@@ -130,27 +130,60 @@ def make_workload(name, scale=1.0):
     return [(name, p, Q, nw)]
 
 
-def run_gpu(work, steps, warmup, precision, persistent, block_size=0):
+def parse_launch(spec):
+    """NAME=FORM:BLOCK[,...] (FORM plain or persistent) -> {NAME: launch options}."""
+    out = {}
+    for part in filter(None, (spec or "").split(",")):
+        name, shape = part.split("=")
+        form, block = shape.split(":")
+        out[name] = {"persistent": 1 if form == "persistent" else 0, "block_size": int(block)}
+    return out
+
+
+def run_gpu(work, steps, warmup, precision, persistent, block_size=0, graph=False, tune=False, launch=None):
+    """Times `steps` passes over the workload.  graph: each solve is a captured
+    plan (mpwos_plan_*) replayed per step, with its device time from HIP events
+    around the replay on the launch stream; otherwise one mpwos_solve per solve
+    and step, with the library's own kernel time.  tune: the launch shape of
+    each solve comes from mpwos_autotune first (untimed)."""
     import torch
 
     from paper_2606_21883_amd import inputs, mpwos
     dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream().cuda_stream
+    # a stream of its own (default priority): torch's events and the library's
+    # launches then share it (the legacy default stream has handle 0, which the
+    # library would read as "use your own stream")
+    tstream = torch.cuda.Stream()
+    torch.cuda.set_stream(tstream)
+    stream = tstream.cuda_stream
     items = []
     for name, prob, Q, nw in work:
         m = mpwos.Manifold(prob)
+        opt = dict(precision=precision, persistent=persistent, block_size=block_size)
+        if launch and name in launch:
+            opt.update(launch[name])
+        elif tune:
+            best, _ = mpwos.autotune(prob, Q, nw, manifold=m, precision=precision)
+            opt.update(best)
+            print(f"[bench] {name}: tuned launch shape {best}", file=sys.stderr, flush=True)
         q = torch.from_numpy(np.ascontiguousarray(Q)).to(dev)
         u = torch.zeros(len(Q), dtype=torch.float64, device=dev)
         se = torch.zeros(len(Q), dtype=torch.float64, device=dev)
-        items.append((name, prob, q, nw, m, u, se))
+        plan = mpwos.Plan(m, prob, len(Q), nw, **opt) if graph else None
+        items.append(dict(name=name, prob=prob, q=q, nw=nw, m=m, u=u, se=se, opt=opt, plan=plan))
 
     def one_step():
         st = []
-        for name, prob, q, nw, m, u, se in items:
-            s = mpwos.solve_device(m, prob, q.data_ptr(), q.shape[0], nw, 0, u.data_ptr(), se.data_ptr(),
-                                   stream=stream, precision=precision, persistent=persistent,
-                                   block_size=block_size)
-            st.append(s)
+        for it in items:
+            if it["plan"] is not None:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(tstream)
+                it["plan"].execute(it["q"].data_ptr(), it["u"].data_ptr(), it["se"].data_ptr(), 0, stream)
+                e1.record(tstream)
+                st.append((e0, e1))
+            else:
+                st.append(mpwos.solve_device(it["m"], it["prob"], it["q"].data_ptr(), it["q"].shape[0], it["nw"], 0,
+                                             it["u"].data_ptr(), it["se"].data_ptr(), stream=stream, **it["opt"]))
         return st
 
     t0 = time.perf_counter()
@@ -168,24 +201,37 @@ def run_gpu(work, steps, warmup, precision, persistent, block_size=0):
               flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    res = {"seconds": dt, "steps": steps}
-    res["walk_steps_per_step"] = sum(s["walk_steps"] for s in stats[0])
+    res = {"seconds": dt, "steps": steps, "form": ("graph replay" if graph else "mpwos_solve per step") +
+           (", autotuned launch shape" if tune else "")}
     per = {}
-    for i, (name, prob, q, nw, m, u, se) in enumerate(items):
-        kms = float(np.mean([s[i]["kernel_ms"] for s in stats]))
-        ws = stats[0][i]["walk_steps"]
-        Qh = q.cpu().numpy()
-        if prob["manifold"] == "point_cloud":
-            Qh = mpwos.debug_cp(m, Qh, "fp64")       # the estimate refers to cp_h(q)
-        exact = inputs.exact_u(prob, Qh)
-        per[name] = {"kernel_ms": kms, "walk_steps": ws, "k_mean": stats[0][i]["k_mean"],
-                     "walk_steps_per_s": ws / (kms * 1e-3),
-                     "rmse": inputs.rmse(u.cpu().numpy(), exact),
-                     "mean_stderr": float(np.sqrt(np.mean(se.cpu().numpy() ** 2))),
-                     "n_queries": int(q.shape[0]), "n_walks": int(nw)}
+    total_ws = 0
+    for i, it in enumerate(items):
+        if it["plan"] is not None:
+            kms = float(np.mean([s[i][0].elapsed_time(s[i][1]) for s in stats]))
+            pst = it["plan"].stats(stream)
+            ws, k_mean = pst["walk_steps"], pst["k_mean"]
+        else:
+            kms = float(np.mean([s[i]["kernel_ms"] for s in stats]))
+            ws, k_mean = stats[0][i]["walk_steps"], stats[0][i]["k_mean"]
+        total_ws += ws
+        Qh = it["q"].cpu().numpy()
+        if it["prob"]["manifold"] == "point_cloud":
+            Qh = mpwos.debug_cp(it["m"], Qh, "fp64")       # the estimate refers to cp_h(q)
+        exact = inputs.exact_u(it["prob"], Qh)
+        per[it["name"]] = {"kernel_ms": kms, "walk_steps": ws, "k_mean": k_mean,
+                           "walk_steps_per_s": ws / (kms * 1e-3),
+                           "rmse": inputs.rmse(it["u"].cpu().numpy(), exact),
+                           "mean_stderr": float(np.sqrt(np.mean(it["se"].cpu().numpy() ** 2))),
+                           "n_queries": int(it["q"].shape[0]), "n_walks": int(it["nw"]),
+                           "launch": {k: v for k, v in it["opt"].items() if k != "precision"}}
+    res["walk_steps_per_step"] = total_ws
     res["per"] = per
     for it in items:
-        it[4].close()
+        if it["plan"] is not None:
+            it["plan"].close()
+        it["m"].close()
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(torch.cuda.default_stream())
     return res
 
 
@@ -326,8 +372,13 @@ def roofline(fast, dom_name, kind, n, n_v, precision):
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "Tslot/s",
             "frac": achieved / PEAK_SLOTS, "traffic": traffic,
             "traffic_unit": "HBM bytes per launch",
-            "kernel": f"walk_lane_kernel<float,{n},{kind}> persistent" if precision == "fp32"
+            "kernel": ("walk_lane_kernel<float,%d,%s> %s" % (n, kind, "persistent" if dom["launch"].get("persistent")
+                                                              else "plain")) if precision == "fp32"
             else f"walk_lane_kernel<double,{n},{kind}>",
+            "launch": dom["launch"],
+            "timing": "HIP events on the launch stream around each " + ("graph replay (copy in, seed, counter "
+                      "reset, walk kernel, per-query reduction, copy out)" if "graph" in fast["form"] else
+                      "walk launch"),
             "launch_walk_steps": dom["walk_steps"], "launch_ms": dom["kernel_ms"],
             "ops_per_walk_step": ops, "slot_weights": {k: round(v, 3) for k, v in w.items()},
             "slots_per_walk_step": slots,
@@ -343,7 +394,11 @@ def main():
                     choices=["sphere", "circle", "torus", "cloud", "hyper100", "hyper1000"],
                     help="sphere (closed + cap) is the headline workload; the others are for profiling")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink queries and walks (profiling only)")
-    ap.add_argument("--block-size", type=int, default=0, help="workgroup size of the walk kernels (0 = default)")
+    ap.add_argument("--block-size", type=int, default=0, help="workgroup size of the walk kernels (0 = autotuned)")
+    ap.add_argument("--launch", default="", metavar="NAME=FORM:BLOCK,...",
+                    help="fixed launch shapes instead of the autotuner, e.g. sphere=plain:256,cap=persistent:192")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time the FP32 form through mpwos_solve per step instead of graph replays")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--no-roofline", action="store_true", help="skip the VALU probe (profiling runs)")
@@ -374,7 +429,9 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     work = make_workload(args.workload, args.scale)
     prec = "fp64" if args.only == "fp64" else "fp32"
-    fast = run_gpu(work, args.steps, args.warmup, prec, 0 if prec == "fp64" else 1, args.block_size)
+    headline = prec == "fp32" and not args.no_graph
+    fast = run_gpu(work, args.steps, args.warmup, prec, 0 if prec == "fp64" else 1, args.block_size,
+                   graph=headline, tune=headline and not args.block_size, launch=parse_launch(args.launch))
     slow = None
     if not args.no_fp64 and args.only is None:
         slow = run_gpu(work, max(1, min(args.steps, 3)), 1, "fp64", 0)
@@ -403,7 +460,7 @@ def main():
         "config": {"workload": desc,
                    "precision": "f32 walk arithmetic, f64 weights/scores/per-query sums" if prec == "fp32"
                    else "f64",
-                   "form": "persistent queue-refill" if prec == "fp32" else "plain one launch per solve",
+                   "form": fast["form"] if prec == "fp32" else "plain one launch per solve",
                    "n_v": prob0.get("n_v", 1), "tau_w": prob0.get("tau_w"), "theta": prob0.get("theta"),
                    "c_kappa": prob0.get("c_kappa"), "seed": 0},
         "queries_per_s": nq_total * fast["steps"] / fast["seconds"],
