@@ -233,11 +233,14 @@ mpwos_status mpwos_autotune(const mpwos_manifold* manifold, const mpwos_fn* f, c
 
 /* ---- serving: continuous batching of solves (one device) ----------------
  * Requests are admitted in arrival order against an HBM budget.  Admitted
- * requests share the device through a fixed number of in-flight slices of
- * walks (two per stream on four streams); whenever a slice completes its slot
- * takes the next slice, round-robin over the admitted requests, so a request
- * that arrives while others run starts as soon as a slot frees.  A request's
- * result is identical to the same solve run alone. */
+ * requests that run the same kernel on the same problem data (manifold, f,
+ * g, c, eps, options; queries, n_walks and seed may differ) form a class, and
+ * one launch carries walks of every request of a class, each with its own
+ * queries, seed and outputs.  A fixed number of launches is in flight (two
+ * per stream on four streams); whenever one completes its slot takes the next
+ * class round-robin, so a request that arrives while others run joins the
+ * next launch of its class.  A request's result is identical to the same
+ * solve run alone. */
 typedef struct mpwos_server mpwos_server;
 
 typedef struct {
@@ -259,13 +262,15 @@ typedef struct {
   int64_t walk_steps;
   double busy_seconds;        /* time with at least one request on the device */
   int64_t in_flight_bytes;    /* HBM held by admitted requests */
-  int32_t rounds;             /* slices of walks launched */
+  int32_t rounds;             /* batched launches */
 } mpwos_server_stats;
 
 /* hbm_budget_bytes: device memory the server may hold for admitted requests
- * (queries, per-walk scores, outputs).  slice_walk_steps: work of one slice,
- * shared by the admitted requests, in three-dimensional walk-steps (0 = about
- * 9e7); a slice holds at least an eighth of the walks that fill the device. */
+ * (queries, per-walk scores, outputs).  slice_walk_steps: work of one launch,
+ * shared by the requests of its class, in three-dimensional walk-steps (0 =
+ * about 9e7); a launch holds at least the walks that fill the device, or all
+ * that its class has left, and at least one wavefront's walks per request.
+ * The library allocates 8 launch tables of 512 entries at creation. */
 mpwos_status mpwos_server_create(size_t hbm_budget_bytes, int64_t slice_walk_steps, mpwos_server** out);
 
 /* Queues a request (non-blocking); returns its ticket.  EINVAL for bad

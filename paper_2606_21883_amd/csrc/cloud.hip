@@ -651,7 +651,7 @@ mpwos_status cloud_check_queries(const WalkArgs& a, const double* dq, int64_t nq
   const size_t bytes = (size_t)nq * 2 * sizeof(double);
   hipError_t e = hipMalloc((void**)&dout, bytes);
   if (e != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return fail(MPWOS_ENOMEM, "query check buffer");
   }
   std::vector<double> out((size_t)nq * 2);

@@ -21,6 +21,8 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
                            int64_t nq, int64_t nw, double eps, uint64_t seed, const mpwos_options& o,
                            WalkArgs& a);
 mpwos_status launch_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue);
+// Walks per batch unit of a batched launch: every entry begins on a multiple.
+int64_t batch_unit(const WalkArgs& a, const mpwos_options& o);
 mpwos_status cloud_check_queries(const WalkArgs& a, const double* dq, int64_t nq, hipStream_t s);
 mpwos_status check_queries_host(const mpwos_manifold* man, const WalkArgs& a, const double* q, int64_t nq);
 

@@ -98,6 +98,19 @@ struct CloudDev {
   int32_t radius_rule;         // 1 = spacing, otherwise curvature of the fitted patch
 };
 
+// One request of a batched launch (serving).  Launch walks [begin, begin +
+// count) are the request's walks idx0 .. idx0 + count - 1, where a request
+// walk index is q * nw + w.  Entries are sorted by begin, and each begins on a
+// whole batch unit (64 walks for lane kernels, the walks of one wavefront for
+// group kernels): a wavefront then never holds walks of two requests at once.
+struct BatchEntry {
+  int64_t begin, count, idx0, nw;
+  const double* queries;       // the request's queries (device)
+  double* walk_S;              // the request's per-walk outputs, indexed by request walk index
+  int32_t* walk_K;
+  uint64_t seed;
+};
+
 struct WalkArgs {
   // problem
   int32_t kind, n;
@@ -129,6 +142,10 @@ struct WalkArgs {
   int32_t lanes;               // lanes per walk (group kernels)
   int32_t nblk;                // Philox blocks per Green sub-stream (group kernels)
   int32_t rblk, rword;         // block / word of the Green radius uniform
+  // batched launches: count is the padded launch size; queries, nw, seed,
+  // idx_base, q_offset and the per-walk outputs come from the entries
+  const BatchEntry* batch;
+  int32_t n_batch;
 };
 
 }  // namespace mpwos

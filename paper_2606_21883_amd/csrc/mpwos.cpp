@@ -72,7 +72,7 @@ static mpwos_status ensure(DevBuf& b, size_t bytes) {
   const size_t want = std::max<size_t>(bytes, 256);
   hipError_t e = hipMalloc(&b.p, want);
   if (e != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return fail(MPWOS_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
   }
   b.cap = want;
@@ -614,7 +614,7 @@ mpwos_status launch_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, un
     if (a.kind == MPWOS_POINT_CLOUD && block > 128)
       return fail(MPWOS_EINVAL, "point clouds take block_size 0, 64 or 128");
     hipError_t e;
-    if (a.persistent) {
+    if (a.persistent || a.n_batch) {
       const int occ = lane_occupancy(a, block);
       const int64_t grid_max = (int64_t)occ * n_cu;
       const int64_t need = (total + block - 1) / block;
@@ -634,7 +634,15 @@ mpwos_status launch_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, un
     if (e != hipSuccess) return hip_fail(e, "walk kernel launch");
     return MPWOS_OK;
   }
+  if (a.n_batch) a.persistent = 1;
   return launch_group_walks(a, o, s, queue);
+}
+
+int64_t batch_unit(const WalkArgs& a, const mpwos_options& o) {
+  if (a.n <= 3) return 64;
+  int L, mb, nblk, rblk, rword;
+  group_shape(a.n, o.lanes_per_walk, L, mb, nblk, rblk, rword);
+  return L >= 4 && L <= 64 ? 64 / L : 1;
 }
 
 }  // namespace mpwos

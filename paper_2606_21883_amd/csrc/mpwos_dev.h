@@ -653,4 +653,16 @@ __device__ __forceinline__ double boundary_value(const WalkArgs& a, const T* y, 
   return 0.0;
 }
 
+// Entry of a batched launch that holds launch walk x (x < the padded size):
+// the last entry whose begin is at most x.  Uniform when x is.
+__device__ __forceinline__ int batch_entry(const WalkArgs& a, int64_t x) {
+  int lo = 0, hi = a.n_batch - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.batch[mid].begin <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 }  // namespace mpwos

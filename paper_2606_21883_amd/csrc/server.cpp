@@ -2,14 +2,17 @@
 //
 // Requests are validated and costed at submit time and queued.  A worker
 // thread admits queued requests in arrival order while their device
-// footprint fits the HBM budget and keeps a fixed number of walk slices in
-// flight: two per stream on a few streams of default priority.  Whenever a
-// slice completes (its event, polled by the host) the stream's slot takes the
-// next slice, chosen round-robin over the admitted requests, so slices of
-// different requests overlap on the device and a request that arrives while
-// others run gets slots as soon as slices drain, without waiting for the
-// others.  A request whose walks have all completed is reduced per query on a
-// separate completion stream, copied out, released and signalled.
+// footprint fits the HBM budget and keeps a fixed number of batched launches
+// in flight: two per stream on a few streams of default priority.  Admitted
+// requests that run the same kernel with the same problem data (manifold, f,
+// g, sigma, eps, options) form a class; one launch carries slices of every
+// request of a class, each request with its own queries, seed and outputs
+// (a table of entries read by the kernel).  Whenever a launch completes (its
+// event, polled by the host) its slot takes the next class round-robin, so
+// small requests share the device instead of queueing behind each other and
+// a request that arrives while others run joins the next launch of its class.
+// A request whose walks have all completed is reduced per query on a separate
+// completion stream, copied out, released and signalled.
 //
 // A walk's score depends only on (request, query, walk) through the Philox
 // counter, and the per-query reduction runs in a fixed order, so a served
@@ -23,6 +26,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -37,8 +41,9 @@ namespace mpwos {
 namespace {
 
 constexpr int kStreams = 4;
-constexpr int kDepth = 2;                  // slices in flight per stream
+constexpr int kDepth = 2;                  // launches in flight per stream
 constexpr int kSlots = kStreams * kDepth;
+constexpr int kMaxBatch = 512;             // requests per launch
 
 struct SrvReq {
   uint64_t ticket = 0;
@@ -63,16 +68,20 @@ struct SrvReq {
   int32_t status = MPWOS_OK;
   bool finished = false;
   bool async_alloc = false;    // device memory from the stream-ordered allocator
-  int inflight = 0;            // slices launched and not yet completed
-  bool queue_busy[kDepth] = {};  // per-slice work counters of the persistent kernels
+  int inflight = 0;            // launches holding walks of this request, not yet completed
   int64_t walk_steps = 0;
+  std::string cls;             // batch class: the launch arguments less the per-request fields
+  int64_t unit = 64;           // batch unit (walks) of the class's kernel
 };
 
-// One slot of in-flight work: a slice of walks of a request on a stream.
+// One slot of in-flight work: a batched launch on a stream, with its entry
+// table (pinned host staging and device copy) and work counter.
 struct Slot {
-  SrvReq* R = nullptr;
+  std::vector<SrvReq*> members;
   hipEvent_t ev = nullptr;
-  int queue = 0;
+  BatchEntry* h_tab = nullptr;
+  BatchEntry* d_tab = nullptr;
+  unsigned long long* d_queue = nullptr;
 };
 
 }  // namespace
@@ -94,6 +103,7 @@ struct mpwos_server {
   size_t in_flight = 0;
   hipStream_t streams[mpwos::kStreams] = {};
   hipStream_t done_stream = nullptr;   // per-query reductions and copies out
+  mpwos::Slot slots[mpwos::kSlots];
   mpwos_server_stats st = {};
   std::chrono::steady_clock::time_point t0;
 };
@@ -154,6 +164,24 @@ static mpwos_status admit(mpwos_server* s, SrvReq* R) {
   a.walk_S = R->d_S;
   a.walk_K = R->d_K;
   if (R->d_table) a.f.values = R->d_table;
+  // the batch class: every launch argument except those an entry carries
+  WalkArgs k = a;
+  k.queries = nullptr;
+  k.nq = k.nw = k.q_offset = k.idx_base = k.count = 0;
+  k.seed = 0;
+  k.seed_dev = nullptr;
+  k.walk_S = nullptr;
+  k.walk_K = nullptr;
+  k.queue = nullptr;
+  k.chunk = 0;
+  k.persistent = 0;
+  k.batch = nullptr;
+  k.n_batch = 0;
+  const int32_t shape[2] = {R->opt.block_size, R->opt.lanes_per_walk};
+  R->cls.assign((const char*)&k, sizeof(k));
+  R->cls.append((const char*)shape, sizeof(shape));
+  R->unit = batch_unit(a, R->opt);
+  R->min_walks = (int64_t)s->n_cu * 16 * R->unit;   // walks that fill the device
   return MPWOS_OK;
 }
 
@@ -184,27 +212,78 @@ static void release(mpwos_server* s, SrvReq* R) {
   manifold_ref(R->r.manifold, -1);
 }
 
-// Walks of R in one slice: a share of the slice budget by the request's cost
-// per walk, at least what keeps the device busy together with the other
-// slots, at most what is left.
-static int64_t slice_walks(const mpwos_server* s, const SrvReq* R, int nact) {
-  const double share = (double)s->slice / std::max(1, nact) / std::max(1.0, R->k_est * R->step_cost);
-  int64_t walks = std::max<int64_t>((int64_t)share, R->min_walks / kSlots);
-  walks = std::max<int64_t>(walks, 1);
-  return std::min<int64_t>(walks, R->total - R->next);
+// Walks per launch for a class: the larger of the slice budget (in Philox
+// blocks) and what fills the device, shared out over the class's requests in
+// arrival order; a request that needs less than its share leaves the rest to
+// the later ones.  Every request with walks left gets at least one batch unit.
+static std::vector<int64_t> batch_walks(const mpwos_server* s, const std::vector<SrvReq*>& cls) {
+  const SrvReq* R0 = cls.front();
+  const double cost = std::max(1.0, R0->k_est * R0->step_cost);
+  int64_t cap = std::max<int64_t>((int64_t)((double)s->slice / cost), R0->min_walks);
+  std::vector<int64_t> take(cls.size(), 0);
+  size_t left = cls.size();
+  for (size_t i = 0; i < cls.size(); ++i) {
+    const SrvReq* R = cls[i];
+    const int64_t share = std::max<int64_t>(cap / (int64_t)left, R->unit);
+    take[i] = std::min<int64_t>(R->total - R->next, share);
+    cap = std::max<int64_t>(0, cap - take[i]);
+    left -= 1;
+  }
+  return take;
+}
+
+// One batched launch of the class `cls` on slot `sl`.
+static mpwos_status launch_batch(mpwos_server* s, Slot& sl, const std::vector<SrvReq*>& cls, hipStream_t st) {
+  const std::vector<int64_t> take = batch_walks(s, cls);
+  const int64_t unit = cls.front()->unit;
+  int64_t pos = 0;
+  int nb = 0;
+  sl.members.clear();
+  for (size_t i = 0; i < cls.size(); ++i) {
+    SrvReq* R = cls[i];
+    if (take[i] <= 0) continue;
+    BatchEntry& E = sl.h_tab[nb++];
+    E.begin = pos;
+    E.count = take[i];
+    E.idx0 = R->next;
+    E.nw = R->r.n_walks;
+    E.queries = R->d_queries;
+    E.walk_S = R->d_S;
+    E.walk_K = R->d_K;
+    E.seed = R->r.seed;
+    pos += (take[i] + unit - 1) / unit * unit;
+    sl.members.push_back(R);
+  }
+  WalkArgs a = cls.front()->args;
+  a.batch = sl.d_tab;
+  a.n_batch = nb;
+  a.count = pos;
+  a.idx_base = 0;
+  a.persistent = 1;
+  hipError_t e = hipMemcpyAsync(sl.d_tab, sl.h_tab, (size_t)nb * sizeof(BatchEntry), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "server: batch table upload");
+  mpwos_status ls = launch_walks(a, cls.front()->opt, st, sl.d_queue);
+  if (ls) return ls;
+  e = hipEventRecord(sl.ev, st);
+  if (e != hipSuccess) return hip_fail(e, "server: launch event");
+  for (size_t i = 0; i < cls.size(); ++i) {
+    if (take[i] <= 0) continue;
+    cls[i]->next += take[i];
+    cls[i]->inflight += 1;
+  }
+  return MPWOS_OK;
 }
 
 static void worker_main(mpwos_server* s) {
   (void)hipSetDevice(s->device);
-  Slot slots[kSlots];
-  for (auto& sl : slots) (void)hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+  Slot* slots = s->slots;
   size_t rr = 0;
   auto last = std::chrono::steady_clock::now();
   for (;;) {
     std::vector<SrvReq*> fresh;
     std::vector<SrvReq*> active;
     bool busy_slot = false;
-    for (auto& sl : slots) busy_slot = busy_slot || sl.R != nullptr;
+    for (int k = 0; k < kSlots; ++k) busy_slot = busy_slot || !slots[k].members.empty();
     {
       const auto now = std::chrono::steady_clock::now();
       if (busy_slot) {
@@ -238,15 +317,17 @@ static void worker_main(mpwos_server* s) {
       }
     }
     bool progress = !fresh.empty();
-    // completed slices free their slots
-    for (auto& sl : slots) {
-      if (!sl.R) continue;
+    // completed launches free their slots
+    for (int k = 0; k < kSlots; ++k) {
+      Slot& sl = slots[k];
+      if (sl.members.empty()) continue;
       const hipError_t q = hipEventQuery(sl.ev);
       if (q == hipErrorNotReady) continue;
-      if (q != hipSuccess && sl.R->status >= 0) sl.R->status = hip_fail(q, "server: slice");
-      sl.R->inflight -= 1;
-      sl.R->queue_busy[sl.queue] = false;
-      sl.R = nullptr;
+      for (SrvReq* R : sl.members) {
+        if (q != hipSuccess && R->status >= 0) R->status = hip_fail(q, "server: batched launch");
+        R->inflight -= 1;
+      }
+      sl.members.clear();
       progress = true;
     }
     // requests whose walks have all completed: reduce, copy out, release
@@ -257,40 +338,45 @@ static void worker_main(mpwos_server* s) {
       release(s, R);
       done.push_back(R);
     }
-    // fill free slots round-robin over the requests with walks left
-    std::vector<SrvReq*> open;
-    for (SrvReq* R : active)
-      if (R->status >= 0 && R->next < R->total) open.push_back(R);
-    const int nact = (int)open.size();
-    for (int k = 0; k < kSlots && !open.empty(); ++k) {
-      Slot& sl = slots[k];
-      if (sl.R) continue;
-      SrvReq* R = nullptr;
-      int q = -1;
-      for (size_t t = 0; t < open.size() && !R; ++t) {
-        SrvReq* c = open[(rr + t) % open.size()];
-        if (c->next >= c->total) continue;
-        for (int j = 0; j < kDepth; ++j)
-          if (!c->queue_busy[j]) { q = j; break; }
-        if (q >= 0) { R = c; rr = (rr + t + 1) % open.size(); }
+    // classes of the requests with walks left, in order of their oldest request
+    std::vector<std::vector<SrvReq*>> classes;
+    {
+      std::map<std::string, size_t> where;
+      for (SrvReq* R : active) {
+        if (R->status < 0 || R->next >= R->total) continue;
+        auto it = where.find(R->cls);
+        if (it == where.end()) {
+          where.emplace(R->cls, classes.size());
+          classes.push_back({R});
+        } else if (classes[it->second].size() < (size_t)kMaxBatch) {
+          classes[it->second].push_back(R);
+        }
       }
-      if (!R) break;
-      WalkArgs a = R->args;
-      a.idx_base = R->next;
-      a.count = slice_walks(s, R, nact);
+    }
+    // free slots take classes round-robin
+    for (int k = 0; k < kSlots; ++k) {
+      Slot& sl = slots[k];
+      if (!sl.members.empty()) continue;
+      std::vector<SrvReq*>* cls = nullptr;
+      for (size_t t = 0; t < classes.size() && !cls; ++t) {
+        auto& c = classes[(rr + t) % classes.size()];
+        c.erase(std::remove_if(c.begin(), c.end(), [](SrvReq* R) { return R->next >= R->total; }), c.end());
+        if (!c.empty()) {
+          cls = &c;
+          rr = (rr + t + 1) % classes.size();
+        }
+      }
+      if (!cls) break;
       hipStream_t st = s->streams[k % kStreams];
-      mpwos_status ls = launch_walks(a, R->opt, st, R->d_stats + 3 + q);
-      hipError_t e = ls ? hipErrorUnknown : hipEventRecord(sl.ev, st);
-      if (ls || e != hipSuccess) {
-        R->status = ls ? ls : hip_fail(e, "server: slice event");
-        R->next = R->total;
+      mpwos_status ls = launch_batch(s, sl, *cls, st);
+      if (ls) {
+        for (SrvReq* R : *cls) {
+          if (R->status >= 0) R->status = ls;
+          R->next = R->total;
+        }
+        sl.members.clear();
         continue;
       }
-      R->next += a.count;
-      R->inflight += 1;
-      R->queue_busy[q] = true;
-      sl.R = R;
-      sl.queue = q;
       progress = true;
       std::lock_guard<std::mutex> lk(s->mu);
       s->st.rounds += 1;
@@ -310,17 +396,34 @@ static void worker_main(mpwos_server* s) {
       s->cv_done.notify_all();
     }
     if (!progress) {
-      // slices still running: look again shortly, or sooner when work arrives
+      // launches still running: look again shortly, or sooner when work arrives
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv_work.wait_for(lk, std::chrono::microseconds(100));
     }
   }
-  for (auto& sl : slots) (void)hipEventDestroy(sl.ev);
 }
 
 }  // namespace mpwos
 
 using namespace mpwos;
+
+// Streams, slot tables and the server object (the worker has ended).
+static void free_server(mpwos_server* s) {
+  for (auto& st : s->streams)
+    if (st) (void)hipStreamSynchronize(st);
+  if (s->done_stream) (void)hipStreamSynchronize(s->done_stream);
+  for (int k = 0; k < kSlots; ++k) {
+    Slot& sl = s->slots[k];
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+    if (sl.h_tab) (void)hipHostFree(sl.h_tab);
+    if (sl.d_tab) (void)hipFree(sl.d_tab);
+    if (sl.d_queue) (void)hipFree(sl.d_queue);
+  }
+  for (auto& st : s->streams)
+    if (st) (void)hipStreamDestroy(st);
+  if (s->done_stream) (void)hipStreamDestroy(s->done_stream);
+  delete s;
+}
 
 extern "C" {
 
@@ -337,9 +440,16 @@ mpwos_status mpwos_server_create(size_t hbm_budget_bytes, int64_t slice_walk_ste
   if (e == hipSuccess) e = hipGetDeviceProperties(&prop, s->device);
   for (int i = 0; e == hipSuccess && i < kStreams; ++i) e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->done_stream, hipStreamNonBlocking);
+  for (int k = 0; e == hipSuccess && k < kSlots; ++k) {
+    Slot& sl = s->slots[k];
+    e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_tab, kMaxBatch * sizeof(BatchEntry), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&sl.d_tab, kMaxBatch * sizeof(BatchEntry));
+    if (e == hipSuccess) e = hipMalloc((void**)&sl.d_queue, 256);
+  }
   if (e != hipSuccess) {
-    delete s;
-    return hip_fail(e, "server: stream creation");
+    free_server(s);
+    return hip_fail(e, "server: streams and launch tables");
   }
   s->n_cu = prop.multiProcessorCount;
   s->t0 = std::chrono::steady_clock::now();
@@ -383,8 +493,6 @@ mpwos_status mpwos_submit(mpwos_server* s, const mpwos_request* req, uint64_t* t
   }
   if (R->args.const_r) R->k_est = std::ceil(std::log(R->opt.tau_w) / std::log(R->args.c0));
   R->step_cost = 1.0 + (double)((n + 3) / 4) * (1 + R->opt.n_v);
-  const int lanes = (n <= 3) ? 1 : 64;
-  R->min_walks = (int64_t)s->n_cu * 16 * 64 / lanes;   // walks that fill the device alone
   manifold_ref(req->manifold, +1);
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -442,13 +550,7 @@ mpwos_status mpwos_server_destroy(mpwos_server* s) {
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   for (auto& kv : s->reqs) delete kv.second;
-  for (auto& st : s->streams)
-    if (st) (void)hipStreamDestroy(st);
-  if (s->done_stream) {
-    (void)hipStreamSynchronize(s->done_stream);
-    (void)hipStreamDestroy(s->done_stream);
-  }
-  delete s;
+  free_server(s);
   return MPWOS_OK;
 }
 

@@ -80,8 +80,7 @@ __device__ __forceinline__ T coord_of(const T* v, int i, int gl) {
 }
 
 template <class T, int L, int MB>
-__device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB>& st, int gl) {
-  const uint64_t seed = a.seed_dev ? *a.seed_dev : a.seed;
+__device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB>& st, int gl, uint64_t seed) {
   const Stream rs{st.q, st.w, (uint32_t)seed, (uint32_t)(seed >> 32)};
   const double r = a.r0;
   const T rT = (T)r;
@@ -159,12 +158,13 @@ __device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB
 }
 
 template <class T, int L, int MB>
-__device__ __forceinline__ void group_init(const WalkArgs& a, int64_t idx, GroupWalk<T, L, MB>& st, int gl) {
+__device__ __forceinline__ void group_init(const WalkArgs& a, const double* queries, int64_t nw, int64_t q_offset,
+                                           int64_t idx, GroupWalk<T, L, MB>& st, int gl) {
   st.idx = idx;
-  const int64_t ql = idx / a.nw;
-  st.q = (uint32_t)(ql + a.q_offset);
-  st.w = (uint32_t)(idx - ql * a.nw);
-  const double* y0 = a.queries + ql * a.n;
+  const int64_t ql = idx / nw;
+  st.q = (uint32_t)(ql + q_offset);
+  st.w = (uint32_t)(idx - ql * nw);
+  const double* y0 = queries + ql * a.n;
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
     const int b = gl + L * m;
@@ -182,6 +182,10 @@ __device__ __forceinline__ void group_init(const WalkArgs& a, int64_t idx, Group
 
 // plain: group id -> walk; persistent: grid-stride over walks (closed
 // spheres have one deterministic walk length, so a static split is balanced).
+// Batched launches (serving) take the grid-stride form; every entry begins on
+// a whole wavefront of groups and the stride is a whole number of wavefronts,
+// so the groups of a wavefront always share one request (its seed stays
+// uniform); launch walks past an entry's count are padding.
 template <class T, int L, int MB>
 __global__ __launch_bounds__(256) void walk_group_kernel(WalkArgs a) {
   const int64_t total = a.count;
@@ -190,12 +194,32 @@ __global__ __launch_bounds__(256) void walk_group_kernel(WalkArgs a) {
   const int64_t ngroups = (int64_t)gridDim.x * blockDim.x / L;
   GroupWalk<T, L, MB> st;
   for (int64_t idx = gid; idx < total; idx += (a.persistent ? ngroups : total)) {
-    group_init<T, L, MB>(a, a.idx_base + idx, st, gl);
-    while (!group_step<T, L, MB>(a, st, gl)) {
+    const double* queries = a.queries;
+    int64_t nw = a.nw, q_offset = a.q_offset, widx = a.idx_base + idx;
+    uint64_t seed;
+    double* walk_S = a.walk_S;
+    int32_t* walk_K = a.walk_K;
+    if (a.n_batch) {
+      const int64_t first = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)idx) |
+                            ((int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(idx >> 32)) << 32);
+      const BatchEntry& E = a.batch[batch_entry(a, first)];
+      if (idx >= E.begin + E.count) continue;
+      queries = E.queries;
+      nw = E.nw;
+      q_offset = 0;
+      widx = E.idx0 + (idx - E.begin);
+      seed = E.seed;
+      walk_S = E.walk_S;
+      walk_K = E.walk_K;
+    } else {
+      seed = a.seed_dev ? *a.seed_dev : a.seed;
+    }
+    group_init<T, L, MB>(a, queries, nw, q_offset, widx, st, gl);
+    while (!group_step<T, L, MB>(a, st, gl, seed)) {
     }
     if (gl == 0) {
-      a.walk_S[st.idx] = st.S + st.C;
-      a.walk_K[st.idx] = (int32_t)st.k;
+      walk_S[st.idx] = st.S + st.C;
+      walk_K[st.idx] = (int32_t)st.k;
     }
   }
 }

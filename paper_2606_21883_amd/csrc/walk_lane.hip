@@ -87,13 +87,16 @@ __device__ __forceinline__ void closest_point(const WalkArgs& a, const T* x, T* 
 }
 
 // ---- one walk ---------------------------------------------------------------
+// Walk idx (= q_local * nw + w) of a launch whose queries start at global
+// query q_offset.
 template <class T, int N, int KIND>
-__device__ __forceinline__ bool walk_init(const WalkArgs& a, int64_t idx, LaneState<T, N>& st) {
+__device__ __forceinline__ bool walk_init(const WalkArgs& a, const double* queries, int64_t nw, int64_t q_offset,
+                                          int64_t idx, LaneState<T, N>& st) {
   st.idx = idx;
-  const int64_t ql = idx / a.nw;
-  st.q = (uint32_t)(ql + a.q_offset);
-  st.w = (uint32_t)(idx - ql * a.nw);
-  const double* y0 = a.queries + ql * N;
+  const int64_t ql = idx / nw;
+  st.q = (uint32_t)(ql + q_offset);
+  st.w = (uint32_t)(idx - ql * nw);
+  const double* y0 = queries + ql * N;
   for (int i = 0; i < N; ++i) st.Y[i] = (T)y0[i];
   st.W = 1.0;
   st.S = 0.0;
@@ -118,9 +121,9 @@ __device__ __forceinline__ bool walk_init(const WalkArgs& a, int64_t idx, LaneSt
 }
 
 template <class T, int N>
-__device__ __forceinline__ void walk_store(const WalkArgs& a, const LaneState<T, N>& st) {
-  a.walk_S[st.idx] = st.S + st.C;
-  a.walk_K[st.idx] = (int32_t)st.k;
+__device__ __forceinline__ void walk_store(double* walk_S, int32_t* walk_K, const LaneState<T, N>& st) {
+  walk_S[st.idx] = st.S + st.C;
+  walk_K[st.idx] = (int32_t)st.k;
 }
 
 // One Green sample Z = Y + t zeta' (t = r s, s from the radial law for the
@@ -145,8 +148,7 @@ __device__ __forceinline__ T green_sample(const WalkArgs& a, const T* Y, uint4 b
 }
 
 template <class T, int N, int KIND, bool RICH>
-__device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st) {
-  const uint64_t seed = a.seed_dev ? *a.seed_dev : a.seed;
+__device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st, uint64_t seed) {
   const Stream rs{st.q, st.w, (uint32_t)seed, (uint32_t)(seed >> 32)};
   // (i) radius r(Y) = theta min(delta_Gamma, rho_geo) and the weights
   double r, c, om, X2, norm = 0.0;
@@ -229,17 +231,18 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 template <class T, int N, int KIND, bool PERSIST, bool RICH>
 __global__ __launch_bounds__(256) void walk_lane_kernel(WalkArgs a) {
   const int64_t total = a.count;
+  const uint64_t seed = a.seed_dev ? *a.seed_dev : a.seed;
   LaneState<T, N> st;
   if constexpr (!PERSIST) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    if (walk_init<T, N, KIND>(a, a.idx_base + idx, st)) {
-      walk_store(a, st);
+    if (walk_init<T, N, KIND>(a, a.queries, a.nw, a.q_offset, a.idx_base + idx, st)) {
+      walk_store(a.walk_S, a.walk_K, st);
       return;
     }
-    while (!walk_step<T, N, KIND, RICH>(a, st)) {
+    while (!walk_step<T, N, KIND, RICH>(a, st, seed)) {
     }
-    walk_store(a, st);
+    walk_store(a.walk_S, a.walk_K, st);
     return;
   } else {
     // persistent form: per-wave chunks of the global queue
@@ -270,17 +273,109 @@ __global__ __launch_bounds__(256) void walk_lane_kernel(WalkArgs a) {
         const int64_t avail = end - next;
         const int64_t cnt = (int64_t)__popcll(want) < avail ? (int64_t)__popcll(want) : avail;
         if (!active && rank < cnt) {
-          if (walk_init<T, N, KIND>(a, a.idx_base + next + rank, st)) walk_store(a, st);
+          if (walk_init<T, N, KIND>(a, a.queries, a.nw, a.q_offset, a.idx_base + next + rank, st))
+            walk_store(a.walk_S, a.walk_K, st);
           else active = true;
         }
         next += cnt;
       }
       if (__ballot(active) == 0) break;
       if (active) {
-        if (walk_step<T, N, KIND, RICH>(a, st)) {
-          walk_store(a, st);
+        if (walk_step<T, N, KIND, RICH>(a, st, seed)) {
+          walk_store(a.walk_S, a.walk_K, st);
           active = false;
         }
+      }
+    }
+  }
+}
+
+// Batched persistent form (serving): the launch holds the walks of several
+// requests (a.batch), each starting on a whole chunk of 64 launch walks, so a
+// chunk belongs to one request.  A wave runs walks of one request at a time:
+// its seed, queries and outputs stay wave-uniform.  Free lanes refill from
+// the wave's chunk; a used-up chunk is replaced from the global counter, and
+// a new chunk of another request waits until the wave's running walks end.
+// Every wave leaves once the counter passes the last chunk and its lanes are
+// idle.
+template <class T, int N, int KIND, bool RICH>
+__global__ __launch_bounds__(256) void walk_lane_batch_kernel(WalkArgs a) {
+  constexpr int64_t kChunk = 64;
+  const int64_t nchunks = a.count / kChunk;
+  const uint32_t lane = lane_id();
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  LaneState<T, N> st;
+  bool active = false;
+  bool exhausted = false;
+  int cur = -1;                // entry of the walks the wave runs
+  int64_t held = -1;           // chunk of another entry, started once the wave is idle
+  int64_t next = 0, end = 0;
+  // entry fields of `cur` (uniform)
+  int64_t e_begin = 0, e_end = 0, e_idx0 = 0, e_nw = 1;
+  const double* e_q = nullptr;
+  double* e_S = nullptr;
+  int32_t* e_K = nullptr;
+  uint64_t e_seed = 0;
+  auto enter = [&](int64_t c) {
+    cur = batch_entry(a, c * kChunk);
+    const BatchEntry& E = a.batch[cur];
+    e_begin = E.begin;
+    e_idx0 = E.idx0;
+    e_nw = E.nw;
+    e_q = E.queries;
+    e_S = E.walk_S;
+    e_K = E.walk_K;
+    e_seed = E.seed;
+    e_end = E.begin + E.count;
+    next = c * kChunk;
+    end = next + kChunk < e_end ? next + kChunk : e_end;
+  };
+  for (;;) {
+    for (;;) {
+      const uint64_t want = __ballot(!active);
+      if (want == 0 || exhausted || held >= 0) break;
+      if (next >= end) {
+        const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)want) - 1);
+        unsigned long long c = 0;
+        if (lane == leader) c = atomicAdd(a.queue, 1ull);
+        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)c, leader);
+        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(c >> 32), leader);
+        const int64_t cb = (int64_t)(((uint64_t)hi << 32) | lo);
+        if (cb >= nchunks) {
+          exhausted = true;
+          break;
+        }
+        if (cur >= 0 && cb * kChunk < e_end) {
+          // chunks are handed out in increasing order: cb lies past the wave's
+          // earlier chunks, hence at or after e_begin
+          next = cb * kChunk;
+          end = next + kChunk < e_end ? next + kChunk : e_end;
+        } else if (__ballot(active) != 0) {
+          held = cb;
+          break;
+        } else {
+          enter(cb);
+        }
+      }
+      const int rank = __popcll(want & lt_mask);
+      const int64_t avail = end - next;
+      const int64_t cnt = (int64_t)__popcll(want) < avail ? (int64_t)__popcll(want) : avail;
+      if (!active && rank < cnt) {
+        if (walk_init<T, N, KIND>(a, e_q, e_nw, 0, e_idx0 + (next + rank - e_begin), st)) walk_store(e_S, e_K, st);
+        else active = true;
+      }
+      next += cnt;
+    }
+    if (__ballot(active) == 0) {
+      if (held < 0) break;
+      enter(held);
+      held = -1;
+      continue;
+    }
+    if (active) {
+      if (walk_step<T, N, KIND, RICH>(a, st, e_seed)) {
+        walk_store(e_S, e_K, st);
+        active = false;
       }
     }
   }
@@ -416,7 +511,7 @@ template <int OP>
 __global__ __launch_bounds__(256) void valu_probe_kernel(uint32_t seed, int32_t iters, uint32_t* out) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t acc = 0;
-  if constexpr (OP == 0 || OP >= 4 && OP <= 8) {
+  if constexpr (OP == 0 || (OP >= 4 && OP <= 8)) {
     float a[8];
     const float b = 0.999f + (float)(seed & 7) * 1e-6f, c = 1e-3f;
 #pragma unroll
@@ -587,26 +682,30 @@ template <class T, int N, int KIND>
 static hipError_t launch_lane_t(const WalkArgs& a, int grid, int block, hipStream_t s) {
   const dim3 g(grid), b(block);
   if (rich_source(a)) {
-    if (a.persistent) hipLaunchKernelGGL((walk_lane_kernel<T, N, KIND, true, true>), g, b, 0, s, a);
+    if (a.n_batch) hipLaunchKernelGGL((walk_lane_batch_kernel<T, N, KIND, true>), g, b, 0, s, a);
+    else if (a.persistent) hipLaunchKernelGGL((walk_lane_kernel<T, N, KIND, true, true>), g, b, 0, s, a);
     else hipLaunchKernelGGL((walk_lane_kernel<T, N, KIND, false, true>), g, b, 0, s, a);
   } else {
-    if (a.persistent) hipLaunchKernelGGL((walk_lane_kernel<T, N, KIND, true, false>), g, b, 0, s, a);
+    if (a.n_batch) hipLaunchKernelGGL((walk_lane_batch_kernel<T, N, KIND, false>), g, b, 0, s, a);
+    else if (a.persistent) hipLaunchKernelGGL((walk_lane_kernel<T, N, KIND, true, false>), g, b, 0, s, a);
     else hipLaunchKernelGGL((walk_lane_kernel<T, N, KIND, false, false>), g, b, 0, s, a);
   }
   return hipGetLastError();
 }
 
 template <class T, int N, int KIND>
-static int occupancy_t(int block, bool rich) {
+static int occupancy_t(int block, bool rich, bool batch) {
   int nb = 0;
-  const hipError_t e = rich ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                  &nb, walk_lane_kernel<T, N, KIND, true, true>, block, 0)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                  &nb, walk_lane_kernel<T, N, KIND, true, false>, block, 0);
+  hipError_t e;
+  if (batch)
+    e = rich ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_lane_batch_kernel<T, N, KIND, true>, block, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_lane_batch_kernel<T, N, KIND, false>, block, 0);
+  else
+    e = rich ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_lane_kernel<T, N, KIND, true, true>, block, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_lane_kernel<T, N, KIND, true, false>, block, 0);
   if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
-
 
 hipError_t launch_walk_lane(const WalkArgs& a, int grid, int block, hipStream_t s) {
   const bool fp64 = a.precision == 0;
@@ -616,9 +715,9 @@ hipError_t launch_walk_lane(const WalkArgs& a, int grid, int block, hipStream_t 
 }
 
 int lane_occupancy(const WalkArgs& a, int block) {
-  const bool fp64 = a.precision == 0, rich = rich_source(a);
+  const bool fp64 = a.precision == 0, rich = rich_source(a), batch = a.n_batch > 0;
   const int kind = a.kind, n = a.n;
-  MPWOS_LANE_DISPATCH(occupancy_t, block, rich);
+  MPWOS_LANE_DISPATCH(occupancy_t, block, rich, batch);
   return 1;
 }
 

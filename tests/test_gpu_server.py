@@ -120,3 +120,64 @@ def test_invalid_requests_are_rejected_at_submit():
     assert srv.stats()["rejected"] == 2
     srv.close()
     m.close()
+
+
+def test_small_requests_share_launches():
+    """Many small requests of a few classes (same manifold and problem; their
+    own queries, walk counts and seeds) run in shared launches: far fewer
+    launches than requests, and every result equals its solo solve bit for
+    bit.  Covers the lane kernels (FP32 closed sphere, FP64 cap with two Green
+    samples, whose walks have uneven lengths), the lane-group kernel at
+    n = 100 (eight walks per wavefront) and TABLE_S1 sources (one class per
+    request)."""
+    sph, _, _ = inputs.config("sphere", scale=0.01)
+    cap = dict(inputs.cap_problem(), n_v=2)
+    hyp = dict(inputs.hypersphere_problem(100), tau_w=1e-3)
+    M = 64
+    th = 2 * np.pi * np.arange(M) / M
+    f = np.exp(np.cos(th))
+    tab = inputs.problem(manifold="sphere", n=2, p=[1.0], sigma=1.0,
+                         f=dict(kind="table_s1", values=np.concatenate([f, f / 2.0])))
+    kinds = [(sph, dict(precision="fp32", persistent=1)), (cap, dict(precision="fp64")),
+             (hyp, dict(precision="fp32")), (tab, dict(precision="fp64"))]
+    mans = [mpwos.Manifold(p) for p, _ in kinds]
+    rng = np.random.default_rng(8)
+    reqs = []
+    for i in range(48):
+        j = i % 4
+        p, kw = kinds[j]
+        nq = int(rng.integers(1, 6))
+        qs = int(rng.integers(1 << 20))
+        if j == 0:
+            Q = inputs.sphere_uniform(nq, 3, qs)
+        elif j == 1:
+            Q = inputs.cap_uniform(nq, 3, 0.0, qs)
+        elif j == 2:
+            Q = inputs.hypersphere_queries(max(nq, 2), 100, qs)
+        else:
+            t = np.random.default_rng(qs).uniform(0, 2 * np.pi, nq)
+            Q = np.stack([np.cos(t), np.sin(t)], 1)
+        nw = int(rng.integers(1, 100)) if j != 2 else int(rng.integers(1, 12))
+        reqs.append((j, Q, nw, int(rng.integers(1 << 62))))
+    announce("server small requests served")
+    srv = mpwos.Server(8 << 30)
+    # a long request of another class holds the launch slots (8 launches of
+    # 32768 walks) while the small ones arrive, so these queue up and share
+    blocker = srv.submit(mans[2], hyp, inputs.hypersphere_queries(64, 100, 99), 4096, 1, precision="fp64")
+    tickets = [srv.submit(mans[j], kinds[j][0], Q, nw, sd, **kinds[j][1]) for j, Q, nw, sd in reqs]
+    outs = [srv.wait(t, 120_000) for t in tickets]
+    srv.wait(blocker, 120_000)
+    st = srv.stats()
+    srv.close()
+    announce("server small requests solo")
+    for (j, Q, nw, sd), o in zip(reqs, outs):
+        p, kw = kinds[j]
+        solo = mpwos.solve(p, Q, nw, sd, manifold=mans[j], **kw)
+        assert np.array_equal(solo["u"], o["u"]), (j, len(Q), nw)
+        assert np.array_equal(solo["stderr"], o["stderr"]), (j, len(Q), nw)
+    assert st["completed"] == len(reqs) + 1
+    # the 36 requests of the three shared classes go out in a few launches;
+    # the 12 TABLE_S1 requests each form a class of their own
+    assert st["rounds"] < 8 + 12 + 18, st
+    for m in mans:
+        m.close()
