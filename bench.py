@@ -260,14 +260,16 @@ def cpu_baseline(work):
 SERVED_KINDS = {"circle": 232, "sphere": 174, "cap": 29, "torus": 1601, "hyper100": 11340, "hyper1000": 113393}
 
 
-def served_mix(rate=200.0, window=3.0, seed=2, work_range=(1e4, 1e7), q_range=(1, 16), min_walks=8):
+def served_mix(rate=200.0, window=3.0, seed=2, work_range=(1e4, 1e7), q_range=(1, 16), min_walks=8, solo=True):
     """Poisson arrivals at `rate` per second for `window` seconds, served by the
     continuous-batching server (FP32 persistent kernels).  Each request draws a
     manifold uniformly, a query count log-uniform in q_range and a total work
     log-uniform in work_range walk-steps (walks per query = work / (queries K),
-    at least min_walks).  Latency = completion - arrival.  The same requests run alone
-    and first-in first-out through mpwos_solve give the per-solve comparison
-    (its latencies from the measured service times) and the bitwise check."""
+    at least min_walks).  Latency = completion - arrival.  Every estimate is
+    checked against the closed-form solution at its query.  With `solo`, the
+    same requests run alone and first-in first-out through mpwos_solve give
+    the per-solve comparison (its latencies from the measured service times)
+    and the bitwise check."""
     import torch  # noqa: F401  (one HIP runtime with torch)
 
     from paper_2606_21883_amd import inputs, mpwos
@@ -327,8 +329,44 @@ def served_mix(rate=200.0, window=3.0, seed=2, work_range=(1e4, 1e7), q_range=(1
     wall = time.perf_counter() - t0
     outs = [srv.wait(tk) for tk in tickets]
     st = srv.stats()
+    tl = [srv.times(tk) for tk in tickets]
     srv.close()
     lat = np.array([done_at[tk] - r[0] for tk, r in zip(tickets, reqs)])
+    # accuracy against the closed form: Monte Carlo error within 4 standard
+    # errors, plus 1e-3 for the tau_W truncation and the cap's eps-layer bias
+    ok, nqs, zs = 0, 0, []
+    for (ta, name, Q, nw, sd), o in zip(reqs, outs):
+        ex = inputs.exact_u(probs[name], Q)
+        err = np.abs(o["u"] - ex)
+        ok += int(np.sum(err <= 4 * o["stderr"] + 1e-3))
+        nqs += len(Q)
+        zs.extend((err / np.maximum(o["stderr"], 1e-300)).tolist())
+    res = {"rate_req_per_s": rate, "window_s": window, "requests": len(reqs),
+           "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+           "drain_s": max(0.0, wall - window), "backlog_growth": backlog_growth(reqs, lat),
+           "walk_steps": int(st["walk_steps"]),
+           "walk_steps_per_s": st["walk_steps"] / wall, "launches": st["rounds"],
+           "closed_form_check": {"queries": nqs, "within_4se_plus_1e-3": ok / nqs,
+                                 "median_abs_z": float(np.median(zs))},
+           "by_manifold": {}}
+    # where the time goes (server timeline, medians): admission wait, wait for
+    # the first launch, walks, reduction and delivery
+    phases = {"admit": (0, 1), "start": (1, 2), "walks": (2, 3), "deliver": (3, 4)}
+    for name in SERVED_KINDS:
+        sel = [i for i, r in enumerate(reqs) if r[1] == name]
+        if not sel:
+            continue
+        ln = lat[sel]
+        d = {"requests": len(sel), "p50_ms": float(np.percentile(ln, 50) * 1e3),
+             "p99_ms": float(np.percentile(ln, 99) * 1e3)}
+        for ph, (a, b) in phases.items():
+            d[ph + "_p50_ms"] = float(np.median([(tl[i][list(tl[i])[b]] - tl[i][list(tl[i])[a]]) * 1e3
+                                                 for i in sel]))
+        res["by_manifold"][name] = d
+    if not solo:
+        for m in mans.values():
+            m.close()
+        return res
     print(f"[bench] served: {len(reqs)} requests done in {wall:.1f} s; solving them alone", file=sys.stderr,
           flush=True)
     # the same requests alone, first in first out, with the per-solve entry point
@@ -345,17 +383,47 @@ def served_mix(rate=200.0, window=3.0, seed=2, work_range=(1e4, 1e7), q_range=(1
     fifo = np.array(fifo)
     for m in mans.values():
         m.close()
-    return {"rate_req_per_s": rate, "window_s": window, "requests": len(reqs),
-            "request_mix": "manifold uniform over S^1, S^2, S^2 cap, implicit torus, S^99, S^999; queries "
-                           f"log-uniform in [{q_range[0]}, {q_range[1]}]; work log-uniform in "
-                           f"[{work_range[0]:.0e}, {work_range[1]:.0e}] walk-steps per request, at least "
-                           f"{min_walks} walks per query",
-            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "walk_steps": int(st["walk_steps"]), "walk_steps_per_s": st["walk_steps"] / wall,
-            "rounds": st["rounds"], "results_equal_alone": f"{same}/{len(reqs)}",
-            "per_solve_fifo": {"p50_ms": float(np.percentile(fifo, 50) * 1e3),
-                               "p99_ms": float(np.percentile(fifo, 99) * 1e3),
-                               "busy_s": float(sum(service))}}
+    res.update({"request_mix": "manifold uniform over S^1, S^2, S^2 cap, implicit torus, S^99, S^999; queries "
+                               f"log-uniform in [{q_range[0]}, {q_range[1]}]; work log-uniform in "
+                               f"[{work_range[0]:.0e}, {work_range[1]:.0e}] walk-steps per request, at least "
+                               f"{min_walks} walks per query",
+                "results_equal_alone": f"{same}/{len(reqs)}",
+                "per_solve_fifo": {"p50_ms": float(np.percentile(fifo, 50) * 1e3),
+                                   "p99_ms": float(np.percentile(fifo, 99) * 1e3),
+                                   "busy_s": float(sum(service))}})
+    return res
+
+
+def backlog_growth(reqs, lat):
+    """Median latency of the requests that arrived in the last third of the
+    window over that of the first third, per manifold, the largest: near 1
+    while the server keeps up, growing with the backlog when it does not."""
+    t = np.array([r[0] for r in reqs])
+    lo, hi = np.percentile(t, 100 / 3), np.percentile(t, 200 / 3)
+    worst = 0.0
+    for name in SERVED_KINDS:
+        sel = np.array([r[1] == name for r in reqs])
+        a, b = lat[sel & (t <= lo)], lat[sel & (t >= hi)]
+        if len(a) >= 3 and len(b) >= 3:
+            worst = max(worst, float(np.median(b) / np.median(a)))
+    return worst
+
+
+def served_sweep(rates, window=3.0):
+    """The served mix at several arrival rates (no solo runs).  A rate is
+    stable when no manifold's median latency grows by more than half from
+    the first third of the arrivals to the last (backlog_growth <= 1.5)."""
+    runs = []
+    for r in rates:
+        runs.append(served_mix(rate=r, window=window, solo=False))
+        print(f"[bench] served sweep: {r:g} req/s p50 {runs[-1]['p50_ms']:.0f} ms p99 {runs[-1]['p99_ms']:.0f} ms "
+              f"drain {runs[-1]['drain_s']:.2f} s backlog growth {runs[-1]['backlog_growth']:.2f}", file=sys.stderr,
+              flush=True)
+    stable = [x["rate_req_per_s"] for x in runs if x["backlog_growth"] <= 1.5]
+    return {"runs": [{k: x[k] for k in ("rate_req_per_s", "requests", "p50_ms", "p99_ms", "drain_s", "backlog_growth",
+                                        "walk_steps_per_s", "launches", "closed_form_check", "by_manifold")}
+                     for x in runs],
+            "max_stable_rate_req_per_s": max(stable) if stable else None}
 
 
 def roofline(fast, dom_name, kind, n, n_v, precision):
@@ -407,6 +475,8 @@ def main():
                     help="time the library's plain copy kernel on BYTES (HBM calibration) and exit")
     ap.add_argument("--valu-probe", action="store_true", help="print the VALU operation rates and exit")
     ap.add_argument("--no-served", action="store_true", help="skip the served-mix leg")
+    ap.add_argument("--served-rates", default="100,400,800",
+                    help="arrival rates (req/s) of the served sweep besides 200; empty to skip")
     ap.add_argument("--served-only", action="store_true", help="run only the served-mix leg and print it")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -424,7 +494,10 @@ def main():
         print(json.dumps({"lane_ops_per_s": r, "weights": w, "peak_lane_ops_per_s": PEAK_SLOTS}), flush=True)
         return
     if args.served_only:
-        print(json.dumps(served_mix()), flush=True)
+        out = served_mix()
+        if args.served_rates:
+            out["sweep"] = served_sweep([float(x) for x in args.served_rates.split(",")])
+        print(json.dumps(out), flush=True)
         return
     rank = int(os.environ.get("RANK", "0"))
     work = make_workload(args.workload, args.scale)
@@ -478,6 +551,8 @@ def main():
                                             for k in fast["per"]}
     if not args.no_served and args.workload == "sphere" and args.only is None:
         out["served"] = served_mix()
+        if args.served_rates:
+            out["served"]["sweep"] = served_sweep([float(x) for x in args.served_rates.split(",")])
     if not args.no_cpu and rank == 0:
         out["cpu_baseline"] = cpu_baseline(work)
     if rank == 0:

@@ -270,7 +270,11 @@ typedef struct {
  * shared by the requests of its class, in three-dimensional walk-steps (0 =
  * about 9e7); a launch holds at least the walks that fill the device, or all
  * that its class has left, and at least one wavefront's walks per request.
- * The library allocates 8 launch tables of 512 entries at creation. */
+ * The library allocates 8 launch tables of 512 entries and 64 MiB of pinned
+ * staging at creation; admission, uploads, reductions and copies out are
+ * asynchronous (events), so the scheduling thread never waits for the
+ * device.  A request whose staging does not fit waits for completions to
+ * free it; one above 16 MiB takes pinned memory of its own. */
 mpwos_status mpwos_server_create(size_t hbm_budget_bytes, int64_t slice_walk_steps, mpwos_server** out);
 
 /* Queues a request (non-blocking); returns its ticket.  EINVAL for bad
@@ -282,6 +286,12 @@ mpwos_status mpwos_poll(mpwos_server* s, uint64_t ticket, int32_t* done, int32_t
 
 /* Blocks until the request finished (timeout_ms < 0: no limit); EBUSY on timeout. */
 mpwos_status mpwos_wait(mpwos_server* s, uint64_t ticket, int64_t timeout_ms, int32_t* result);
+
+/* Timeline of a request, in seconds since the server was created:
+ * times[0] submitted, [1] admitted, [2] first launch holding its walks
+ * enqueued, [3] last such launch observed complete, [4] results delivered.
+ * Entries not reached yet are -1.  EINVAL for an unknown ticket. */
+mpwos_status mpwos_request_times(mpwos_server* s, uint64_t ticket, double times[5]);
 
 mpwos_status mpwos_server_stats_get(mpwos_server* s, mpwos_server_stats* out);
 

@@ -44,6 +44,8 @@ hipError_t launch_valu_probe(int op, uint32_t seed, int32_t iters, uint32_t* out
 // walk_group.hip
 mpwos_status launch_group_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue);
 void group_shape(int n, int lanes_req, int& L, int& mb, int& nblk, int& rblk, int& rword);
+// Bytes of the state record of one time-sliced walk (0 for an unsupported shape).
+int64_t group_record_bytes(int n, int lanes_req, bool fp64);
 
 // cloud.hip
 mpwos_status cloud_create(const mpwos_manifold_desc& d, hipStream_t s, CloudState** out);

@@ -103,12 +103,22 @@ struct CloudDev {
 // walk index is q * nw + w.  Entries are sorted by begin, and each begins on a
 // whole batch unit (64 walks for lane kernels, the walks of one wavefront for
 // group kernels): a wavefront then never holds walks of two requests at once.
+//
+// Time slicing (lane-group kernels): with a state buffer, a walk runs at most
+// step_budget steps per launch; an unfinished walk saves its state (one
+// record per request walk) and counts itself in `pending`, and a later launch
+// of the same range with `resume` set continues it (finished walks of the
+// range are marked in their records and skipped).
 struct BatchEntry {
   int64_t begin, count, idx0, nw;
   const double* queries;       // the request's queries (device)
   double* walk_S;              // the request's per-walk outputs, indexed by request walk index
   int32_t* walk_K;
   uint64_t seed;
+  char* state;                 // per-walk records, or null (the walks run to the end)
+  int32_t resume;              // 1: continue the walks from their records
+  int32_t pad;
+  unsigned long long pending;  // walks of the entry saved unfinished (written by the kernel)
 };
 
 struct WalkArgs {
@@ -146,6 +156,7 @@ struct WalkArgs {
   // idx_base, q_offset and the per-walk outputs come from the entries
   const BatchEntry* batch;
   int32_t n_batch;
+  int32_t step_budget;         // steps per launch of walks with a state record (0: no limit)
 };
 
 }  // namespace mpwos

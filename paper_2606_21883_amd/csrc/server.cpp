@@ -63,8 +63,15 @@ struct SrvReq {
   int32_t* d_K = nullptr;
   double* d_u = nullptr;
   double* d_se = nullptr;
-  unsigned long long* d_stats = nullptr;  // ksum, kmax, ntrunc, queue
+  unsigned long long* d_stats = nullptr;  // ksum, kmax, ntrunc
   double* d_table = nullptr;
+  char* h_io = nullptr;        // pinned staging: queries and table in, estimates and counters out
+  size_t h_io_bytes = 0;
+  bool h_io_own = false;       // staging of its own (too large for the shared block)
+  hipEvent_t ready_ev = nullptr;  // uploads done (on the completion stream)
+  hipEvent_t done_ev = nullptr;   // reduction and copies out done
+  bool ready = false;          // ready_ev observed complete
+  bool completing = false;     // reduction enqueued, done_ev pending
   int32_t status = MPWOS_OK;
   bool finished = false;
   bool async_alloc = false;    // device memory from the stream-ordered allocator
@@ -72,12 +79,63 @@ struct SrvReq {
   int64_t walk_steps = 0;
   std::string cls;             // batch class: the launch arguments less the per-request fields
   int64_t unit = 64;           // batch unit (walks) of the class's kernel
+  char* d_state = nullptr;     // state records of time-sliced walks (or null)
+  int64_t rec_bytes = 0;
+  std::deque<std::pair<int64_t, int64_t>> resume;   // (first walk, count) of unfinished sliced walks
+  double times[5] = {-1, -1, -1, -1, -1};           // submitted, admitted, first launch, walks done, delivered
 };
+
+// Pinned host memory for the asynchronous copies of admission and completion:
+// one block allocated at creation and carved first-fit, so that no request
+// calls the allocator (whose frees may wait for the device).
+struct HostArena {
+  char* base = nullptr;
+  size_t size = 0;
+  std::map<size_t, size_t> free_;   // offset -> length
+  static size_t round(size_t b) { return (b + 63) & ~(size_t)63; }
+  char* alloc(size_t bytes) {
+    bytes = round(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      const size_t off = it->first, len = it->second;
+      free_.erase(it);
+      if (len > bytes) free_[off + bytes] = len - bytes;
+      return base + off;
+    }
+    return nullptr;
+  }
+  void release(char* p, size_t bytes) {
+    bytes = round(bytes);
+    auto it = free_.emplace((size_t)(p - base), bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+constexpr size_t kArenaBytes = (size_t)64 << 20;
+constexpr double kSliceBlocks = 1e6;       // Philox blocks per time-sliced walk and launch
 
 // One slot of in-flight work: a batched launch on a stream, with its entry
 // table (pinned host staging and device copy) and work counter.
+struct ClassInfo {
+  int inflight = 0;
+  double last = -1.0;
+};
+
 struct Slot {
   std::vector<SrvReq*> members;
+  std::string cls;             // class of the launch in flight
+  double issued = 0.0;         // when it was enqueued
   hipEvent_t ev = nullptr;
   BatchEntry* h_tab = nullptr;
   BatchEntry* d_tab = nullptr;
@@ -104,11 +162,17 @@ struct mpwos_server {
   hipStream_t streams[mpwos::kStreams] = {};
   hipStream_t done_stream = nullptr;   // per-query reductions and copies out
   mpwos::Slot slots[mpwos::kSlots];
+  mpwos::HostArena arena;
+  std::vector<hipEvent_t> events;      // idle events for requests
   mpwos_server_stats st = {};
   std::chrono::steady_clock::time_point t0;
 };
 
 namespace mpwos {
+
+static double since(const mpwos_server* s) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t0).count();
+}
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -123,10 +187,45 @@ static size_t request_bytes(const mpwos_request& r, int n) {
   return b;
 }
 
+static hipEvent_t take_event(mpwos_server* s) {
+  if (!s->events.empty()) {
+    hipEvent_t e = s->events.back();
+    s->events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Staging bytes of R: queries and table in; u, stderr and 8 counters out.
+static size_t staging_bytes(const SrvReq* R) {
+  return HostArena::round((size_t)R->r.n_queries * R->args.n * sizeof(double)) +
+         HostArena::round(R->table.size() * sizeof(double)) +
+         HostArena::round((size_t)R->r.n_queries * 2 * sizeof(double)) + 8 * sizeof(unsigned long long);
+}
+
+// Admission without waiting: device memory from the stream-ordered allocator
+// and uploads from pinned staging, all on the completion stream, then an
+// event that the first launch holding R's walks waits on.  Returns EBUSY
+// (nothing done) when the staging block is full for now.
 static mpwos_status admit(mpwos_server* s, SrvReq* R) {
   hipStream_t st = s->done_stream;
-  // the stream-ordered allocator: freeing a request does not wait for the
-  // device (a plain hipFree would synchronise with the slices of others)
+  R->h_io_bytes = staging_bytes(R);
+  if (R->h_io_bytes > kArenaBytes / 4) {
+    if (hipHostMalloc((void**)&R->h_io, R->h_io_bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      R->h_io = nullptr;
+      return fail(MPWOS_ENOMEM, "server: pinned staging allocation failed");
+    }
+    R->h_io_own = true;
+  } else {
+    R->h_io = s->arena.alloc(R->h_io_bytes);
+    if (!R->h_io) return MPWOS_EBUSY;
+  }
+  R->ready_ev = take_event(s);
+  R->done_ev = take_event(s);
+  if (!R->ready_ev || !R->done_ev) return fail(MPWOS_EDEVICE, "server: event creation failed");
   hipError_t e = hipMallocAsync((void**)&R->dev, R->bytes, st);
   R->async_alloc = e == hipSuccess;
   if (e != hipSuccess) {
@@ -148,13 +247,16 @@ static mpwos_status admit(mpwos_server* s, SrvReq* R) {
   R->d_se = (double*)take((size_t)R->r.n_queries * sizeof(double));
   R->d_stats = (unsigned long long*)take(8 * sizeof(unsigned long long));
   if (!R->table.empty()) R->d_table = (double*)take(R->table.size() * sizeof(double));
-  e = hipMemcpyAsync(R->d_queries, R->r.queries, (size_t)R->r.n_queries * n * sizeof(double),
-                     hipMemcpyHostToDevice, st);
+  if (R->rec_bytes) R->d_state = take((size_t)R->total * R->rec_bytes);
+  const size_t qb = (size_t)R->r.n_queries * n * sizeof(double);
+  std::memcpy(R->h_io, R->r.queries, qb);
+  char* ht = R->h_io + HostArena::round(qb);
+  if (!R->table.empty()) std::memcpy(ht, R->table.data(), R->table.size() * sizeof(double));
+  e = hipMemcpyAsync(R->d_queries, R->h_io, qb, hipMemcpyHostToDevice, st);
   if (e == hipSuccess && R->d_table)
-    e = hipMemcpyAsync(R->d_table, R->table.data(), R->table.size() * sizeof(double), hipMemcpyHostToDevice, st);
+    e = hipMemcpyAsync(R->d_table, ht, R->table.size() * sizeof(double), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = launch_zero_u64(R->d_stats, 8, st);
-  // slices run on other streams: the uploads complete before the first launch
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = hipEventRecord(R->ready_ev, st);
   if (e != hipSuccess) return hip_fail(e, "server: admission copies");
   WalkArgs& a = R->args;
   a.queries = R->d_queries;
@@ -185,74 +287,132 @@ static mpwos_status admit(mpwos_server* s, SrvReq* R) {
   return MPWOS_OK;
 }
 
-// Every slice of R has completed (its events were observed): the reduction
-// runs on the completion stream, which carries nothing else.
-static mpwos_status finish(mpwos_server* s, SrvReq* R) {
-  hipStream_t st = s->done_stream;
-  hipError_t e = launch_reduce(R->d_S, R->d_K, R->r.n_queries, R->r.n_walks, R->opt.max_steps, R->d_u, R->d_se,
-                               R->d_stats + 0, (int32_t*)(R->d_stats + 1), R->d_stats + 2, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(R->r.u_out, R->d_u, (size_t)R->r.n_queries * sizeof(double), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess && R->r.stderr_out)
-    e = hipMemcpyAsync(R->r.stderr_out, R->d_se, (size_t)R->r.n_queries * sizeof(double), hipMemcpyDeviceToHost, st);
-  unsigned long long hs[8] = {};
-  if (e == hipSuccess) e = hipMemcpyAsync(hs, R->d_stats, sizeof(hs), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_fail(e, "server: completion");
-  R->walk_steps = (int64_t)hs[0];
-  return hs[2] ? MPWOS_WTRUNC : MPWOS_OK;
+static double* staging_out(const SrvReq* R) {
+  return (double*)(R->h_io + HostArena::round((size_t)R->r.n_queries * R->args.n * sizeof(double)) +
+                   HostArena::round(R->table.size() * sizeof(double)));
 }
 
-static void release(mpwos_server* s, SrvReq* R) {
+// Every launch holding walks of R has completed (their events were
+// observed): the reduction and the copies out are enqueued on the completion
+// stream, followed by R's done event; nothing waits here.
+static mpwos_status begin_finish(mpwos_server* s, SrvReq* R) {
+  hipStream_t st = s->done_stream;
+  double* out = staging_out(R);
+  const size_t nq = (size_t)R->r.n_queries;
+  hipError_t e = launch_reduce(R->d_S, R->d_K, R->r.n_queries, R->r.n_walks, R->opt.max_steps, R->d_u, R->d_se,
+                               R->d_stats + 0, (int32_t*)(R->d_stats + 1), R->d_stats + 2, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, R->d_u, nq * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(out + nq, R->d_se, nq * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out + 2 * nq, R->d_stats, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipEventRecord(R->done_ev, st);
+  if (e != hipSuccess) return hip_fail(e, "server: completion");
+  R->completing = true;
+  return MPWOS_OK;
+}
+
+// R's done event completed: results to the caller's buffers.
+static void end_finish(SrvReq* R) {
+  const double* out = staging_out(R);
+  const size_t nq = (size_t)R->r.n_queries;
+  std::memcpy(R->r.u_out, out, nq * sizeof(double));
+  if (R->r.stderr_out) std::memcpy(R->r.stderr_out, out + nq, nq * sizeof(double));
+  unsigned long long hs[8];
+  std::memcpy(hs, out + 2 * nq, sizeof(hs));
+  R->walk_steps = (int64_t)hs[0];
+  if (R->status == MPWOS_OK && hs[2]) R->status = MPWOS_WTRUNC;
+}
+
+// Device memory, staging and events back; the manifold reference dropped.
+// Runs after R's done event completed, or after a failure (then the device
+// may still use R's memory: the completion stream is drained first).
+static void release(mpwos_server* s, SrvReq* R, bool failed) {
+  if (failed) (void)hipStreamSynchronize(s->done_stream);
   if (R->dev) {
     if (R->async_alloc) (void)hipFreeAsync(R->dev, s->done_stream);
     else (void)hipFree(R->dev);
   }
   R->dev = nullptr;
+  if (R->h_io) {
+    if (R->h_io_own) (void)hipHostFree(R->h_io);
+    else s->arena.release(R->h_io, R->h_io_bytes);
+  }
+  R->h_io = nullptr;
+  for (hipEvent_t* ev : {&R->ready_ev, &R->done_ev}) {
+    if (*ev) s->events.push_back(*ev);
+    *ev = nullptr;
+  }
   manifold_ref(R->r.manifold, -1);
 }
 
+static int64_t walks_left(const SrvReq* R) {
+  int64_t n = R->total - R->next;
+  for (const auto& rg : R->resume) n += rg.second;
+  return n;
+}
+
 // Walks per launch for a class: the larger of the slice budget (in Philox
-// blocks) and what fills the device, shared out over the class's requests in
-// arrival order; a request that needs less than its share leaves the rest to
-// the later ones.  Every request with walks left gets at least one batch unit.
+// blocks; a time-sliced walk costs at most its step budget per launch) and
+// what fills the device, shared out over the class's requests in arrival
+// order; a request that needs less than its share leaves the rest to the
+// later ones.  Every request with walks left gets at least one batch unit.
 static std::vector<int64_t> batch_walks(const mpwos_server* s, const std::vector<SrvReq*>& cls) {
   const SrvReq* R0 = cls.front();
-  const double cost = std::max(1.0, R0->k_est * R0->step_cost);
+  const double k = R0->args.step_budget > 0 ? std::min(R0->k_est, (double)R0->args.step_budget) : R0->k_est;
+  const double cost = std::max(1.0, k * R0->step_cost);
   int64_t cap = std::max<int64_t>((int64_t)((double)s->slice / cost), R0->min_walks);
   std::vector<int64_t> take(cls.size(), 0);
   size_t left = cls.size();
   for (size_t i = 0; i < cls.size(); ++i) {
     const SrvReq* R = cls[i];
     const int64_t share = std::max<int64_t>(cap / (int64_t)left, R->unit);
-    take[i] = std::min<int64_t>(R->total - R->next, share);
+    take[i] = std::min<int64_t>(walks_left(R), share);
     cap = std::max<int64_t>(0, cap - take[i]);
     left -= 1;
   }
   return take;
 }
 
-// One batched launch of the class `cls` on slot `sl`.
+// One batched launch of the class `cls` on slot `sl`: per request, ranges of
+// unfinished time-sliced walks first (resumed from their records), then new
+// walks.
 static mpwos_status launch_batch(mpwos_server* s, Slot& sl, const std::vector<SrvReq*>& cls, hipStream_t st) {
   const std::vector<int64_t> take = batch_walks(s, cls);
   const int64_t unit = cls.front()->unit;
   int64_t pos = 0;
   int nb = 0;
   sl.members.clear();
-  for (size_t i = 0; i < cls.size(); ++i) {
-    SrvReq* R = cls[i];
-    if (take[i] <= 0) continue;
+  auto add = [&](SrvReq* R, int64_t idx0, int64_t count, bool resume) {
     BatchEntry& E = sl.h_tab[nb++];
     E.begin = pos;
-    E.count = take[i];
-    E.idx0 = R->next;
+    E.count = count;
+    E.idx0 = idx0;
     E.nw = R->r.n_walks;
     E.queries = R->d_queries;
     E.walk_S = R->d_S;
     E.walk_K = R->d_K;
     E.seed = R->r.seed;
-    pos += (take[i] + unit - 1) / unit * unit;
+    E.state = R->d_state;
+    E.resume = resume ? 1 : 0;
+    E.pad = 0;
+    E.pending = 0;
+    pos += (count + unit - 1) / unit * unit;
     sl.members.push_back(R);
+  };
+  for (size_t i = 0; i < cls.size() && nb < kMaxBatch; ++i) {
+    SrvReq* R = cls[i];
+    int64_t want = take[i];
+    while (want > 0 && !R->resume.empty() && nb < kMaxBatch) {
+      const auto rg = R->resume.front();
+      R->resume.pop_front();
+      add(R, rg.first, rg.second, true);
+      want -= rg.second;
+    }
+    if (want > 0 && R->next < R->total && nb < kMaxBatch) {
+      const int64_t c = std::min<int64_t>(want, R->total - R->next);
+      add(R, R->next, c, false);
+      R->next += c;
+    }
   }
   WalkArgs a = cls.front()->args;
   a.batch = sl.d_tab;
@@ -260,27 +420,33 @@ static mpwos_status launch_batch(mpwos_server* s, Slot& sl, const std::vector<Sr
   a.count = pos;
   a.idx_base = 0;
   a.persistent = 1;
-  hipError_t e = hipMemcpyAsync(sl.d_tab, sl.h_tab, (size_t)nb * sizeof(BatchEntry), hipMemcpyHostToDevice, st);
+  hipError_t e = hipSuccess;
+  const double now = since(s);
+  for (SrvReq* R : sl.members) {
+    R->inflight += 1;
+    if (R->times[2] < 0) R->times[2] = now;
+  }
+  // members whose uploads are not known to be done: the launch waits for them
+  for (SrvReq* R : sl.members)
+    if (!R->ready && e == hipSuccess) e = hipStreamWaitEvent(st, R->ready_ev, 0);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sl.d_tab, sl.h_tab, (size_t)nb * sizeof(BatchEntry), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_fail(e, "server: batch table upload");
   mpwos_status ls = launch_walks(a, cls.front()->opt, st, sl.d_queue);
   if (ls) return ls;
-  e = hipEventRecord(sl.ev, st);
+  // the entries come back with their counts of unfinished walks
+  e = hipMemcpyAsync(sl.h_tab, sl.d_tab, (size_t)nb * sizeof(BatchEntry), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipEventRecord(sl.ev, st);
   if (e != hipSuccess) return hip_fail(e, "server: launch event");
-  for (size_t i = 0; i < cls.size(); ++i) {
-    if (take[i] <= 0) continue;
-    cls[i]->next += take[i];
-    cls[i]->inflight += 1;
-  }
   return MPWOS_OK;
 }
 
 static void worker_main(mpwos_server* s) {
   (void)hipSetDevice(s->device);
   Slot* slots = s->slots;
-  size_t rr = 0;
+  std::map<std::string, ClassInfo> cinfo;   // per class: launches in flight, last launch time
   auto last = std::chrono::steady_clock::now();
   for (;;) {
-    std::vector<SrvReq*> fresh;
     std::vector<SrvReq*> active;
     bool busy_slot = false;
     for (int k = 0; k < kSlots; ++k) busy_slot = busy_slot || !slots[k].members.empty();
@@ -292,58 +458,78 @@ static void worker_main(mpwos_server* s) {
       }
       last = now;
     }
+    bool progress = false;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       if (!busy_slot)
         s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty() || !s->active.empty(); });
       if (s->stop && s->pending.empty() && s->active.empty() && !busy_slot) break;
+      // admission in arrival order while the budget allows
       while (!s->pending.empty()) {
         SrvReq* R = s->pending.front();
         if (!s->active.empty() && s->in_flight + R->bytes > s->budget) break;
+        const mpwos_status st = admit(s, R);
+        if (st == MPWOS_EBUSY) break;   // staging full: retried once completions free it
         s->pending.pop_front();
+        R->times[1] = since(s);
         s->in_flight += R->bytes;
         s->active.push_back(R);
-        fresh.push_back(R);
         s->st.admitted += 1;
+        progress = true;
+        if (st) {
+          R->status = st;
+          R->next = R->total;
+        }
       }
       active = s->active;
       s->st.in_flight_bytes = (int64_t)s->in_flight;
     }
-    for (SrvReq* R : fresh) {
-      mpwos_status st = admit(s, R);
-      if (st) {
-        R->status = st;
-        R->next = R->total;
-      }
-    }
-    bool progress = !fresh.empty();
     // completed launches free their slots
     for (int k = 0; k < kSlots; ++k) {
       Slot& sl = slots[k];
       if (sl.members.empty()) continue;
       const hipError_t q = hipEventQuery(sl.ev);
       if (q == hipErrorNotReady) continue;
-      for (SrvReq* R : sl.members) {
+      auto ci = cinfo.find(sl.cls);
+      if (ci != cinfo.end() && --ci->second.inflight <= 0 && ci->second.last < since(s) - 60.0) cinfo.erase(ci);
+      for (size_t i = 0; i < sl.members.size(); ++i) {
+        SrvReq* R = sl.members[i];
         if (q != hipSuccess && R->status >= 0) R->status = hip_fail(q, "server: batched launch");
+        if (q == hipSuccess && sl.h_tab[i].pending > 0) R->resume.emplace_back(sl.h_tab[i].idx0, sl.h_tab[i].count);
         R->inflight -= 1;
       }
       sl.members.clear();
       progress = true;
     }
-    // requests whose walks have all completed: reduce, copy out, release
+    // uploads observed done; requests whose walks have all completed start
+    // their reduction; those whose copies out are done finish
     std::vector<SrvReq*> done;
     for (SrvReq* R : active) {
-      if (R->next < R->total || R->inflight > 0) continue;
-      if (R->status >= 0) R->status = finish(s, R);
-      release(s, R);
+      if (!R->ready && R->ready_ev && hipEventQuery(R->ready_ev) == hipSuccess) R->ready = true;
+      if (R->status >= 0 && (R->next < R->total || !R->resume.empty())) continue;
+      if (R->inflight > 0) continue;
+      if (R->times[3] < 0) R->times[3] = since(s);
+      if (!R->completing && R->status >= 0) {
+        const mpwos_status st = begin_finish(s, R);
+        if (st) R->status = st;
+        else continue;
+      }
+      if (R->completing && R->status >= 0) {
+        const hipError_t q = hipEventQuery(R->done_ev);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) R->status = hip_fail(q, "server: completion");
+        else end_finish(R);
+      }
+      release(s, R, R->status < 0);
       done.push_back(R);
+      progress = true;
     }
     // classes of the requests with walks left, in order of their oldest request
     std::vector<std::vector<SrvReq*>> classes;
     {
       std::map<std::string, size_t> where;
       for (SrvReq* R : active) {
-        if (R->status < 0 || R->next >= R->total) continue;
+        if (R->status < 0 || walks_left(R) == 0) continue;
         auto it = where.find(R->cls);
         if (it == where.end()) {
           where.emplace(R->cls, classes.size());
@@ -353,30 +539,59 @@ static void worker_main(mpwos_server* s) {
         }
       }
     }
-    // free slots take classes round-robin
-    for (int k = 0; k < kSlots; ++k) {
-      Slot& sl = slots[k];
-      if (!sl.members.empty()) continue;
-      std::vector<SrvReq*>* cls = nullptr;
-      for (size_t t = 0; t < classes.size() && !cls; ++t) {
-        auto& c = classes[(rr + t) % classes.size()];
-        c.erase(std::remove_if(c.begin(), c.end(), [](SrvReq* R) { return R->next >= R->total; }), c.end());
-        if (!c.empty()) {
-          cls = &c;
-          rr = (rr + t + 1) % classes.size();
+    // Free slots go to the classes least recently served: those with fewer
+    // launches in flight first, then the one whose last launch is oldest.  A
+    // launch prefers a stream with nothing in flight; otherwise it queues
+    // behind the stream's launch that was issued first.  Time slicing keeps
+    // launches short, so no class holds a stream for long.
+    for (;;) {
+      int best = -1;
+      for (size_t t = 0; t < classes.size(); ++t) {
+        auto& c = classes[t];
+        c.erase(std::remove_if(c.begin(), c.end(), [](SrvReq* R) { return walks_left(R) == 0; }), c.end());
+        if (c.empty()) continue;
+        if (best < 0) {
+          best = (int)t;
+          continue;
+        }
+        const ClassInfo& a = cinfo[c.front()->cls];
+        const ClassInfo& b = cinfo[classes[best].front()->cls];
+        if (a.inflight < b.inflight || (a.inflight == b.inflight && a.last < b.last)) best = (int)t;
+      }
+      if (best < 0) break;
+      int k = -1;
+      double oldest = 1e300;
+      for (int j = 0; j < kSlots; ++j) {
+        if (!slots[j].members.empty()) continue;
+        const Slot& partner = slots[(j + kStreams) % kSlots];
+        if (partner.members.empty()) {
+          k = j;
+          break;
+        }
+        if (partner.issued < oldest) {
+          oldest = partner.issued;
+          k = j;
         }
       }
-      if (!cls) break;
-      hipStream_t st = s->streams[k % kStreams];
-      mpwos_status ls = launch_batch(s, sl, *cls, st);
+      if (k < 0) break;
+      auto& c = classes[best];
+      Slot& sl = slots[k];
+      mpwos_status ls = launch_batch(s, sl, c, s->streams[k % kStreams]);
+      ClassInfo& ci = cinfo[c.front()->cls];
+      ci.last = since(s);
       if (ls) {
-        for (SrvReq* R : *cls) {
+        for (SrvReq* R : c) {
           if (R->status >= 0) R->status = ls;
           R->next = R->total;
+          R->resume.clear();
         }
+        for (SrvReq* R : sl.members) R->inflight -= 1;
         sl.members.clear();
         continue;
       }
+      sl.cls = c.front()->cls;
+      sl.issued = ci.last;
+      ci.inflight += 1;
       progress = true;
       std::lock_guard<std::mutex> lk(s->mu);
       s->st.rounds += 1;
@@ -384,7 +599,9 @@ static void worker_main(mpwos_server* s) {
     if (!done.empty()) {
       {
         std::lock_guard<std::mutex> lk(s->mu);
+        const double now = since(s);
         for (SrvReq* R : done) {
+          R->times[4] = now;
           R->finished = true;
           s->in_flight -= R->bytes;
           s->st.completed += 1;
@@ -419,6 +636,8 @@ static void free_server(mpwos_server* s) {
     if (sl.d_tab) (void)hipFree(sl.d_tab);
     if (sl.d_queue) (void)hipFree(sl.d_queue);
   }
+  for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+  if (s->arena.base) (void)hipHostFree(s->arena.base);
   for (auto& st : s->streams)
     if (st) (void)hipStreamDestroy(st);
   if (s->done_stream) (void)hipStreamDestroy(s->done_stream);
@@ -446,6 +665,11 @@ mpwos_status mpwos_server_create(size_t hbm_budget_bytes, int64_t slice_walk_ste
     if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_tab, kMaxBatch * sizeof(BatchEntry), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void**)&sl.d_tab, kMaxBatch * sizeof(BatchEntry));
     if (e == hipSuccess) e = hipMalloc((void**)&sl.d_queue, 256);
+  }
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->arena.base, kArenaBytes, hipHostMallocDefault);
+  if (e == hipSuccess) {
+    s->arena.size = kArenaBytes;
+    s->arena.free_[0] = kArenaBytes;
   }
   if (e != hipSuccess) {
     free_server(s);
@@ -493,6 +717,19 @@ mpwos_status mpwos_submit(mpwos_server* s, const mpwos_request* req, uint64_t* t
   }
   if (R->args.const_r) R->k_est = std::ceil(std::log(R->opt.tau_w) / std::log(R->args.c0));
   R->step_cost = 1.0 + (double)((n + 3) / 4) * (1 + R->opt.n_v);
+  // Long lane-group walks are time-sliced: a launch runs each for at most
+  // kSliceBlocks Philox blocks of work, so that no launch holds a stream (and
+  // whatever shares its hardware queue) for long.  The state records must fit
+  // an eighth of the budget; otherwise the walks run to the end in one launch.
+  if (n >= 4) {
+    const double budget = std::max(256.0, kSliceBlocks / R->step_cost);
+    const int64_t rec = group_record_bytes(n, R->opt.lanes_per_walk, R->args.precision == 0);
+    if (R->k_est > 1.5 * budget && rec > 0 && (size_t)(R->total * rec) <= s->budget / 8) {
+      R->args.step_budget = (int32_t)budget;
+      R->rec_bytes = rec;
+      R->bytes += align256((size_t)R->total * rec);
+    }
+  }
   manifold_ref(req->manifold, +1);
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -502,6 +739,7 @@ mpwos_status mpwos_submit(mpwos_server* s, const mpwos_request* req, uint64_t* t
       return fail(MPWOS_EBUSY, "server is shutting down");
     }
     R->ticket = s->next_ticket++;
+    R->times[0] = since(s);
     s->reqs[R->ticket] = R;
     s->pending.push_back(R);
     *ticket = R->ticket;
@@ -531,6 +769,15 @@ mpwos_status mpwos_wait(mpwos_server* s, uint64_t ticket, int64_t timeout_ms, in
   else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred))
     return fail(MPWOS_EBUSY, "timed out");
   if (result) *result = R->status;
+  return MPWOS_OK;
+}
+
+mpwos_status mpwos_request_times(mpwos_server* s, uint64_t ticket, double times[5]) {
+  if (!s || !times) return fail(MPWOS_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(MPWOS_EINVAL, "unknown ticket");
+  for (int i = 0; i < 5; ++i) times[i] = it->second->times[i];
   return MPWOS_OK;
 }
 

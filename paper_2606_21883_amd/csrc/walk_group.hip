@@ -180,6 +180,47 @@ __device__ __forceinline__ void group_init(const WalkArgs& a, const double* quer
   st.k = 0;
 }
 
+// State record of a time-sliced walk: W, S, C, k and a done flag (written by
+// the group's lane 0), then each lane's 4 MB coordinates.
+template <class T, int L, int MB>
+struct GroupRecord {
+  static constexpr int64_t kBytes = (32 + (int64_t)L * 4 * MB * (int64_t)sizeof(T) + 63) / 64 * 64;
+};
+
+template <class T, int L, int MB>
+__device__ __forceinline__ void group_save(char* rec, const GroupWalk<T, L, MB>& st, int gl, uint32_t flag) {
+  if (gl == 0) {
+    double* d = (double*)rec;
+    d[0] = st.W;
+    d[1] = st.S;
+    d[2] = st.C;
+    uint32_t* u = (uint32_t*)(rec + 24);
+    u[0] = st.k;
+    u[1] = flag;
+  }
+  if (flag) return;
+  T* y = (T*)(rec + 32) + gl * 4 * MB;
+#pragma unroll
+  for (int i = 0; i < 4 * MB; ++i) y[i] = st.Y[i];
+}
+
+template <class T, int L, int MB>
+__device__ __forceinline__ void group_load(const char* rec, int64_t idx, int64_t nw, GroupWalk<T, L, MB>& st,
+                                           int gl) {
+  st.idx = idx;
+  const int64_t ql = idx / nw;
+  st.q = (uint32_t)ql;
+  st.w = (uint32_t)(idx - ql * nw);
+  const double* d = (const double*)rec;
+  st.W = d[0];
+  st.S = d[1];
+  st.C = d[2];
+  st.k = ((const uint32_t*)(rec + 24))[0];
+  const T* y = (const T*)(rec + 32) + gl * 4 * MB;
+#pragma unroll
+  for (int i = 0; i < 4 * MB; ++i) st.Y[i] = y[i];
+}
+
 // plain: group id -> walk; persistent: grid-stride over walks (closed
 // spheres have one deterministic walk length, so a static split is balanced).
 // Batched launches (serving) take the grid-stride form; every entry begins on
@@ -199,10 +240,14 @@ __global__ __launch_bounds__(256) void walk_group_kernel(WalkArgs a) {
     uint64_t seed;
     double* walk_S = a.walk_S;
     int32_t* walk_K = a.walk_K;
+    char* rec = nullptr;
+    bool resume = false;
+    unsigned long long* pending = nullptr;
     if (a.n_batch) {
       const int64_t first = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)idx) |
                             ((int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(idx >> 32)) << 32);
-      const BatchEntry& E = a.batch[batch_entry(a, first)];
+      const int e = batch_entry(a, first);
+      const BatchEntry& E = a.batch[e];
       if (idx >= E.begin + E.count) continue;
       queries = E.queries;
       nw = E.nw;
@@ -211,15 +256,37 @@ __global__ __launch_bounds__(256) void walk_group_kernel(WalkArgs a) {
       seed = E.seed;
       walk_S = E.walk_S;
       walk_K = E.walk_K;
+      if (E.state && a.step_budget > 0) {
+        rec = E.state + widx * GroupRecord<T, L, MB>::kBytes;
+        resume = E.resume != 0;
+        pending = const_cast<unsigned long long*>(&a.batch[e].pending);
+      }
     } else {
       seed = a.seed_dev ? *a.seed_dev : a.seed;
     }
-    group_init<T, L, MB>(a, queries, nw, q_offset, widx, st, gl);
-    while (!group_step<T, L, MB>(a, st, gl, seed)) {
+    if (resume) {
+      if (((const uint32_t*)(rec + 24))[1]) continue;   // finished in an earlier launch
+      group_load<T, L, MB>(rec, widx, nw, st, gl);
+    } else {
+      group_init<T, L, MB>(a, queries, nw, q_offset, widx, st, gl);
     }
-    if (gl == 0) {
-      walk_S[st.idx] = st.S + st.C;
-      walk_K[st.idx] = (int32_t)st.k;
+    bool done = false;
+    if (rec) {
+      for (int32_t j = 0; j < a.step_budget && !done; ++j) done = group_step<T, L, MB>(a, st, gl, seed);
+    } else {
+      while (!group_step<T, L, MB>(a, st, gl, seed)) {
+      }
+      done = true;
+    }
+    if (done) {
+      if (gl == 0) {
+        walk_S[st.idx] = st.S + st.C;
+        walk_K[st.idx] = (int32_t)st.k;
+      }
+      if (rec) group_save<T, L, MB>(rec, st, gl, 1u);
+    } else {
+      group_save<T, L, MB>(rec, st, gl, 0u);
+      if (gl == 0) atomicAdd(pending, 1ull);
     }
   }
 }
@@ -291,6 +358,22 @@ void group_shape(int n, int lanes_req, int& L, int& mb, int& nblk, int& rblk, in
   const int per = (nblk + L - 1) / L;
   mb = 1;
   while (mb < per) mb *= 2;
+}
+
+template <class T, int L, int MB>
+static int64_t group_record_t() {
+  return GroupRecord<T, L, MB>::kBytes;
+}
+
+int64_t group_record_bytes(int n, int lanes_req, bool fp64) {
+  int L, mb, nblk, rblk, rword;
+  group_shape(n, lanes_req, L, mb, nblk, rblk, rword);
+  if (fp64) {
+    MPWOS_GROUP_L(double, group_record_t)
+  } else {
+    MPWOS_GROUP_L(float, group_record_t)
+  }
+  return 0;
 }
 
 mpwos_status launch_group_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue) {

@@ -72,6 +72,7 @@ class ServerStats(ctypes.Structure):
 
 EXPORTS = ["mpwos_options_default", "mpwos_manifold_create", "mpwos_manifold_destroy", "mpwos_solve",
            "mpwos_last_error", "mpwos_server_create", "mpwos_submit", "mpwos_poll", "mpwos_wait",
+           "mpwos_request_times",
            "mpwos_server_stats_get", "mpwos_server_destroy", "mpwos_debug_cp", "mpwos_debug_cloud_info",
            "mpwos_debug_radial_inv",
            "mpwos_debug_philox", "mpwos_copy_probe", "mpwos_valu_probe", "mpwos_version",
@@ -106,6 +107,7 @@ def lib():
         L.mpwos_submit.argtypes = [vp, vp, vp]
         L.mpwos_poll.argtypes = [vp, ctypes.c_uint64, vp, vp]
         L.mpwos_wait.argtypes = [vp, ctypes.c_uint64, i64, vp]
+        L.mpwos_request_times.argtypes = [vp, ctypes.c_uint64, vp]
         L.mpwos_server_stats_get.argtypes = [vp, vp]
         L.mpwos_server_destroy.argtypes = [vp]
         L.mpwos_debug_cp.argtypes = [vp, vp, i64, i32, vp]
@@ -426,6 +428,13 @@ class Server:
         Q, u, se, keep, req = self._live.pop(ticket)
         _check(res.value)
         return {"u": u, "stderr": se, "status": STATUS_NAMES[res.value]}
+
+    def times(self, ticket):
+        """Timeline of a request (seconds since the server was created; -1 if
+        not reached): submitted, admitted, first launch, walks done, delivered."""
+        t = (ctypes.c_double * 5)()
+        _check(lib().mpwos_request_times(self.handle, int(ticket), t))
+        return dict(zip(("submitted", "admitted", "first_launch", "walks_done", "delivered"), list(t)))
 
     def stats(self):
         st = ServerStats()

@@ -181,3 +181,26 @@ def test_small_requests_share_launches():
     assert st["rounds"] < 8 + 12 + 18, st
     for m in mans:
         m.close()
+
+
+@pytest.mark.parametrize("n,tau_w,prec", [(1000, 1e-3, "fp32"), (200, 1e-8, "fp64")])
+def test_long_walks_are_time_sliced(n, tau_w, prec):
+    """Lane-group walks longer than the per-launch step budget save their state
+    and continue in later launches: the served result still equals the solo
+    solve bit for bit, and the request took many launches.  At n = 200 a
+    wavefront holds four walks, so ranges resume with padding."""
+    p = dict(inputs.hypersphere_problem(n), tau_w=tau_w)
+    Q = inputs.hypersphere_queries(3, n, seed=4)
+    m = mpwos.Manifold(p)
+    announce(f"server time-sliced S^{n - 1} {prec}")
+    solo = mpwos.solve(p, Q, 7, 21, manifold=m, precision=prec)
+    srv = mpwos.Server(4 << 30)
+    out = srv.wait(srv.submit(m, p, Q, 7, 21, precision=prec), 120_000)
+    st = srv.stats()
+    srv.close()
+    m.close()
+    assert np.array_equal(solo["u"], out["u"]) and np.array_equal(solo["stderr"], out["stderr"])
+    assert st["walk_steps"] == solo["stats"]["walk_steps"]
+    k = solo["stats"]["walk_steps"] / (len(Q) * 7)
+    budget = max(256, 1e6 / (1 + 2 * ((n + 3) // 4)))
+    assert st["rounds"] >= int(k // budget), (st, k, budget)
