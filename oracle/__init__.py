@@ -64,6 +64,7 @@ def lib():
         L.orc_uniform.argtypes = [u32]; L.orc_uniform.restype = d
         L.orc_box_muller.argtypes = [u32, u32, vp]
         L.orc_normals.argtypes = [u64, u32, u32, u32, u32, ctypes.c_int, vp]
+        L.orc_direction.argtypes = [u64, u32, u32, u32, u32, ctypes.c_int, vp]
         L.orc_radius_uniform.argtypes = [u64, u32, u32, u32, u32, ctypes.c_int]
         L.orc_radius_uniform.restype = d
         for nm in ("orc_c_sigma_r", "orc_omega"):
@@ -156,6 +157,12 @@ def normals(seed, q, w, k, sub, n):
     g = np.zeros(n, dtype=np.float64)
     lib().orc_normals(seed, q, w, k, sub, n, _ptr(g))
     return g
+
+
+def direction(seed, q, w, k, sub, n):
+    z = np.zeros(n, dtype=np.float64)
+    lib().orc_direction(seed, q, w, k, sub, n, _ptr(z))
+    return z
 
 
 def radius_uniform(seed, q, w, k, sub, n):

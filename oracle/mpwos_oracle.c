@@ -12,6 +12,7 @@
  *   - Philox4x32-10: Salmon, Moraes, Dror, Shaw, "Parallel random numbers:
  *     as easy as 1, 2, 3", SC'11.
  *   - Box-Muller transform (Box & Muller 1958).
+ *   - Archimedes' hat-box theorem for uniform directions on S^2.
  *   - Jacobi eigenvalue iteration (textbook) for the point-cloud frame.
  *
  * Floating point: IEEE binary64, built with -ffp-contract=off and no
@@ -126,10 +127,45 @@ void orc_normals(uint64_t seed, uint32_t q, uint32_t w, uint32_t k, uint32_t sub
   }
 }
 
-/* The uniform that picks the radius of Green sample `sub`: the first word
- * after the direction pairs, word index 2*ceil(n/2). */
+/* Uniform direction on S^{n-1} from sub-stream `sub` (the zeta of eq.
+ * projected_chain_update and the direction of a Green sample).
+ *   n = 2: angle 2 pi u0 (word 0): zeta = (cos, sin).
+ *   n = 3: Archimedes' hat-box theorem: the last coordinate z = 1 - 2 u0 is
+ *          uniform on [-1, 1] and the azimuth 2 pi u1 is uniform and
+ *          independent of it (words 0, 1): zeta = (rho cos, rho sin, z) with
+ *          rho = sqrt(1 - z^2) = 2 sqrt(u0 (1 - u0)).
+ *   n >= 4: n standard normals (orc_normals) divided by their norm.
+ * Every form is an exact sample of the uniform law. */
+void orc_direction(uint64_t seed, uint32_t q, uint32_t w, uint32_t k, uint32_t sub, int n, double* zeta) {
+  if (n == 2 || n == 3) {
+    uint32_t x[4];
+    orc_block(seed, q, w, k, sub, 0, x);
+    if (n == 2) {
+      double ang = 6.283185307179586 * orc_uniform(x[0]);
+      zeta[0] = cos(ang);
+      zeta[1] = sin(ang);
+    } else {
+      double u = orc_uniform(x[0]);
+      double ang = 6.283185307179586 * orc_uniform(x[1]);
+      double rho = 2.0 * sqrt(u * (1.0 - u));
+      zeta[0] = rho * cos(ang);
+      zeta[1] = rho * sin(ang);
+      zeta[2] = 1.0 - 2.0 * u;
+    }
+    return;
+  }
+  orc_normals(seed, q, w, k, sub, n, zeta);
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += zeta[i] * zeta[i];
+  s = sqrt(s);
+  for (int i = 0; i < n; ++i) zeta[i] = zeta[i] / s;
+}
+
+/* The uniform that picks the radius of Green sample `sub`: word 3 of the
+ * sub-stream for n <= 3 (after the direction words); for n >= 4 the first
+ * word after the normal pairs, word index 2*ceil(n/2). */
 double orc_radius_uniform(uint64_t seed, uint32_t q, uint32_t w, uint32_t k, uint32_t sub, int n) {
-  int word = 2 * ((n + 1) / 2);
+  int word = n <= 3 ? 3 : 2 * ((n + 1) / 2);
   uint32_t x[4];
   orc_block(seed, q, w, k, sub, (uint32_t)(word / 4), x);
   return orc_uniform(x[word % 4]);
@@ -858,10 +894,10 @@ static int orc_walk(const orc_ctx* C, const double* y0, uint32_t q, uint32_t w, 
     double om = orc_omega(n, P->sigma, r);
     double X = sqrt(P->sigma) * r;
     if (!(X <= orc_radial_xmax(n))) { free(buf); return ORC_EINVAL; }
-    /* (ii) projected state: Theta = Y + r zeta, zeta = g/|g| (eq. projected_chain_update) */
-    orc_normals(C->seed, q, w, k, 0, n, g);
-    double gn = orc_norm(g, n);
-    for (int i = 0; i < n; ++i) Th[i] = Y[i] + r * (g[i] / gn);
+    /* (ii) projected state: Theta = Y + r zeta, zeta uniform on the unit
+     * sphere (eq. projected_chain_update) */
+    orc_direction(C->seed, q, w, k, 0, n, g);
+    for (int i = 0; i < n; ++i) Th[i] = Y[i] + r * g[i];
     if (P->manifold == ORC_POINT_CLOUD) {
       if (orc_pc_project(P, Th, &pc_next)) { free(buf); return ORC_EINVAL; }
       for (int i = 0; i < 3; ++i) Yn[i] = pc_next.y[i];
@@ -875,9 +911,8 @@ static int orc_walk(const orc_ctx* C, const double* y0, uint32_t q, uint32_t w, 
     for (int l = 1; l <= P->n_v; ++l) {
       double u = orc_radius_uniform(C->seed, q, w, k, (uint32_t)l, n);
       double s = orc_radial_inv_r(&C->rad, X, u);
-      orc_normals(C->seed, q, w, k, (uint32_t)l, n, g);
-      double gz = orc_norm(g, n);
-      for (int i = 0; i < n; ++i) Z[i] = Y[i] + (r * s) * (g[i] / gz);
+      orc_direction(C->seed, q, w, k, (uint32_t)l, n, g);
+      for (int i = 0; i < n; ++i) Z[i] = Y[i] + (r * s) * g[i];
       F += orc_source(P, Z);
     }
     F = F / (double)P->n_v;

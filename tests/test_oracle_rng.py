@@ -102,25 +102,48 @@ def test_substreams_are_independent(orc):
 
 @pytest.mark.parametrize("n", [2, 3, 10])
 def test_sphere_direction_uniform(orc, n):
-    z = []
-    for w in range(6000):
-        g = orc.normals(11, 0, w, 0, 0, n)
-        z.append(g / np.linalg.norm(g))
-    z = np.array(z)
+    z = np.array([orc.direction(11, 0, w, 0, 0, n) for w in range(6000)])
+    assert np.max(np.abs(np.linalg.norm(z, axis=1) - 1.0)) < 1e-14
     if n == 2:
         ang = np.arctan2(z[:, 1], z[:, 0])
         assert stats.kstest(ang, stats.uniform(loc=-np.pi, scale=2 * np.pi).cdf).pvalue > 1e-4
     elif n == 3:
-        # Archimedes: one coordinate of a uniform point on S^2 is uniform on [-1, 1]
-        assert stats.kstest(z[:, 2], stats.uniform(loc=-1, scale=2).cdf).pvalue > 1e-4
+        # every coordinate of a uniform point on S^2 is uniform on [-1, 1]
+        # (Archimedes), not only the one the sampler draws directly
+        for i in range(3):
+            assert stats.kstest(z[:, i], stats.uniform(loc=-1, scale=2).cdf).pvalue > 1e-4, i
+        # the azimuth about any axis is uniform: about x1 here
+        ang = np.arctan2(z[:, 2], z[:, 1])
+        assert stats.kstest(ang, stats.uniform(loc=-np.pi, scale=2 * np.pi).cdf).pvalue > 1e-4
     else:
         # x1^2 ~ Beta(1/2, (n-1)/2) on S^{n-1}
         assert stats.kstest(z[:, 0] ** 2, stats.beta(0.5, (n - 1) / 2).cdf).pvalue > 1e-4
+    # rotation invariance: mean 0 and second moment I/n
+    m2 = z.T @ z / len(z)
+    assert np.max(np.abs(z.mean(0))) < 4.5 / np.sqrt(len(z))
+    assert np.max(np.abs(m2 - np.eye(n) / n)) < 5.0 / np.sqrt(len(z)) / n
+
+
+def test_direction_of_high_dimension_is_normalised_normals(orc):
+    for n in (4, 7, 100):
+        g = orc.normals(5, 1, 2, 3, 1, n)
+        assert np.allclose(orc.direction(5, 1, 2, 3, 1, n), g / np.linalg.norm(g), rtol=0, atol=1e-15)
+
+
+def test_direction_and_radius_words_are_independent(orc):
+    # n <= 3: direction from words 0 (and 1), the Green radius from word 3
+    for n in (2, 3):
+        u = np.array([orc.radius_uniform(2, 0, w, 1, 1, n) for w in range(6000)])
+        z = np.array([orc.direction(2, 0, w, 1, 1, n) for w in range(6000)])
+        assert stats.kstest(u, stats.uniform().cdf).pvalue > 1e-4
+        for i in range(n):
+            assert abs(np.corrcoef(u, z[:, i])[0, 1]) < 0.05, (n, i)
 
 
 def test_radius_uniform_word_position(orc):
-    # The Green-sample radius uses word 2*ceil(n/2) of its sub-stream.
-    for n, blk, word in [(2, 0, 2), (3, 1, 0), (4, 1, 0), (5, 1, 2), (100, 25, 0)]:
+    # The Green-sample radius uses word 3 of its sub-stream for n <= 3, word
+    # 2*ceil(n/2) for n >= 4.
+    for n, blk, word in [(2, 0, 3), (3, 0, 3), (4, 1, 0), (5, 1, 2), (100, 25, 0)]:
         u = orc.radius_uniform(9, 3, 4, 5, 1, n)
         x = orc.philox([3, 4, 5, (1 << 24) | blk], [9, 0])
         assert u == orc.uniform(x[word])
