@@ -66,33 +66,29 @@ def kernel_sha256():
 def step_ops(kind, n, n_v=1):
     """Algorithmic VALU operations of one FP32-mixed walk-step (n <= 3, one lane
     per walk), by issue class.  Counts what the method as specified must do:
-      - Philox4x32-10 blocks: the direction needs one block, each Green sample
-        2 ceil(n/2) normal words plus one radius word; 10 rounds of two 32x32->64
+      - Philox4x32-10 blocks: one for the direction and one per Green sample
+        (direction words and the radius word); 10 rounds of two 32x32->64
         multiplies and four xors per block (the key schedule is scalar);
-      - two operations per uniform, and per Box-Muller pair log, sqrt, cos and
-        sin (one of cos/sin dropped for odd n) plus three multiplies;
-      - per n-vector: a squared norm (n), a reciprocal square root and a scaled
-        update or projection (n + 1), for the direction, Theta, cp(Theta), the
-        Green direction, Z and cp(Z);
+      - two operations per uniform; per direction cos and sin of the angle,
+        and on S^2 the axis coordinate and its radius (one square root, three
+        multiply-adds, two multiplies);
+      - per n-vector update Y + r zeta (n) and projection: a squared norm (n),
+        a reciprocal square root and the scaling (n + 1), for Theta and for
+        each Green point Z;
       - the Green radius from the inverse-CDF table (w = sqrt(min(u, 1-u)),
         index, two loads, one interpolation);
       - the source (the pair product, its compensation with one reciprocal);
       - FP64: the score update W omega F with Neumaier compensation, W c, the
         stop test.
     """
-    half = (n + 1) // 2
-    odd = n % 2
-    green_words = 2 * half + 1
-    blocks = 1 + n_v * math.ceil(green_words / 4)
-    ops = {"mad_u64_u32": 20 * blocks, "xor_b32": 40 * blocks, "f32": 0, "trans": 0, "f64": 13}
-    words = 2 * half + n_v * green_words
+    sets = 1 + n_v                        # the direction of Theta and each Green sample
+    ops = {"mad_u64_u32": 20 * sets, "xor_b32": 40 * sets, "f32": 0, "trans": 0, "f64": 13}
+    words = (n - 1) + n_v * n             # direction words, plus the radius word per sample
     ops["f32"] += 2 * words
-    sets = 1 + n_v
-    ops["trans"] += sets * (4 * half - odd)
-    ops["f32"] += sets * (3 * half - odd)
-    vec = n + 1 + n                       # norm, scale, update / projection
-    ops["f32"] += vec * (2 + 2 * n_v)     # direction, cp(Theta), and per sample: direction, cp(Z)
-    ops["trans"] += 2 + 2 * n_v
+    ops["trans"] += sets * (3 if n == 3 else 2)
+    ops["f32"] += sets * (5 if n == 3 else 0)
+    ops["f32"] += sets * (3 * n + 1)      # update and projection
+    ops["trans"] += sets
     ops["f32"] += n_v * (10 + 8)          # radius table, source
     ops["trans"] += n_v * (1 + 1)
     ops["f32"] += 2                       # step counter and bound

@@ -23,6 +23,9 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
 mpwos_status launch_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue);
 // Walks per batch unit of a batched launch: every entry begins on a multiple.
 int64_t batch_unit(const WalkArgs& a, const mpwos_options& o);
+// Philox blocks one walk-step draws (a cost estimate for sizing work): one
+// per sub-stream for n <= 3, the normal pairs and radius word for n >= 4.
+double philox_blocks_per_step(int n, int n_v);
 mpwos_status cloud_check_queries(const WalkArgs& a, const double* dq, int64_t nq, hipStream_t s);
 mpwos_status check_queries_host(const mpwos_manifold* man, const WalkArgs& a, const double* q, int64_t nq);
 

@@ -638,6 +638,11 @@ mpwos_status launch_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, un
   return launch_group_walks(a, o, s, queue);
 }
 
+double philox_blocks_per_step(int n, int n_v) {
+  if (n <= 3) return 1.0 + n_v;
+  return (double)((n + 3) / 4) + (double)n_v * ((n + 3) / 4 + 1);
+}
+
 int64_t batch_unit(const WalkArgs& a, const mpwos_options& o) {
   if (a.n <= 3) return 64;
   int L, mb, nblk, rblk, rword;

@@ -72,6 +72,43 @@ __device__ __forceinline__ void box_muller(uint32_t x0, uint32_t x1, float& g0, 
   g1 = rad * __builtin_amdgcn_sinf(t);
 }
 
+// Uniform direction on S^{N-1}, N = 2 or 3, from the words of one Philox
+// block: the angle 2 pi u0 (N = 2), or Archimedes' hat-box construction
+// (N = 3): the last coordinate 1 - 2 u0 is uniform on [-1, 1], the azimuth
+// 2 pi u1 is uniform and independent of it, and the radius about the axis is
+// sqrt(1 - z^2) = 2 sqrt(u0 (1 - u0)).  Exact, of unit length up to rounding,
+// with no normals and no normalisation.
+template <int N>
+__device__ __forceinline__ void lane_direction(uint32_t x0, uint32_t x1, double* z) {
+  if constexpr (N == 2) {
+    sincos(6.283185307179586 * u01_64(x0), &z[1], &z[0]);
+  } else {
+    const double u = u01_64(x0);
+    double sn, cs;
+    sincos(6.283185307179586 * u01_64(x1), &sn, &cs);
+    const double rho = 2.0 * sqrt(u * (1.0 - u));
+    z[0] = rho * cs;
+    z[1] = rho * sn;
+    z[2] = 1.0 - 2.0 * u;
+  }
+}
+template <int N>
+__device__ __forceinline__ void lane_direction(uint32_t x0, uint32_t x1, float* z) {
+  // v_sin_f32 / v_cos_f32 take their argument in turns
+  if constexpr (N == 2) {
+    const float t = u01_32(x0);
+    z[0] = __builtin_amdgcn_cosf(t);
+    z[1] = __builtin_amdgcn_sinf(t);
+  } else {
+    const float u = u01_32(x0);
+    const float t = u01_32(x1);
+    const float rho = 2.0f * __builtin_amdgcn_sqrtf(fmaf(-u, u, u));
+    z[0] = rho * __builtin_amdgcn_cosf(t);
+    z[1] = rho * __builtin_amdgcn_sinf(t);
+    z[2] = fmaf(-2.0f, u, 1.0f);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // precision helpers
 // ---------------------------------------------------------------------------

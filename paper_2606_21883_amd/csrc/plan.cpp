@@ -206,9 +206,12 @@ extern "C" mpwos_status mpwos_autotune(const mpwos_manifold* manifold, const mpw
   mpwos_status st = prepare_solve(manifold, f, g, c, n_queries, n_walks, eps, 0, base, probe);
   if (st) return st;
   const double k_est = probe.const_r ? std::ceil(std::log(base.tau_w) / std::log(probe.c0)) : 32.0;
-  const double cost = 1.0 + (double)((n + 3) / 4) * (1 + base.n_v);
-  const int64_t want_walks = n <= 3 ? ((int64_t)1 << 19) : (int64_t)device_cu_count() * 16;
-  const int64_t budget = (int64_t)4e9;  // Philox blocks of work per trial
+  const double cost = philox_blocks_per_step(n, base.n_v);
+  // Up to 2^24 walks (the whole solve at the headline sizes): the launch
+  // forms differ in how they absorb uneven walk lengths, which a small
+  // sample's tail hides.
+  const int64_t want_walks = n <= 3 ? ((int64_t)1 << 24) : (int64_t)device_cu_count() * 16;
+  const int64_t budget = (int64_t)1e10;  // Philox blocks of work per trial
   int64_t sample = std::min<int64_t>(want_walks, std::max<int64_t>(64, (int64_t)(budget / (k_est * cost))));
   sample = std::min<int64_t>(sample, n_queries * n_walks);
   const int64_t sw = std::min<int64_t>(n_walks, sample);

@@ -716,7 +716,7 @@ mpwos_status mpwos_submit(mpwos_server* s, const mpwos_request* req, uint64_t* t
     return fail(MPWOS_ENOMEM, "request needs " + std::to_string(R->bytes) + " bytes, above the HBM budget");
   }
   if (R->args.const_r) R->k_est = std::ceil(std::log(R->opt.tau_w) / std::log(R->args.c0));
-  R->step_cost = 1.0 + (double)((n + 3) / 4) * (1 + R->opt.n_v);
+  R->step_cost = philox_blocks_per_step(n, R->opt.n_v);
   // Long lane-group walks are time-sliced: a launch runs each for at most
   // kSliceBlocks Philox blocks of work, so that no launch holds a stream (and
   // whatever shares its hardware queue) for long.  The state records must fit

@@ -127,22 +127,18 @@ __device__ __forceinline__ void walk_store(double* walk_S, int32_t* walk_K, cons
 }
 
 // One Green sample Z = Y + t zeta' (t = r s, s from the radial law for the
-// uniform word ux, zeta' from the normals of block b) and (f + m)(Z).
+// uniform word ux, zeta' from words x, y of block b) and (f + m)(Z).
 template <class T, int N, int KIND, bool RICH>
 __device__ __forceinline__ T green_sample(const WalkArgs& a, const T* Y, uint4 b, uint32_t ux, T rT, double X2,
                                           double norm) {
-  T g[4];
-  box_muller(b.x, b.y, g[0], g[1]);
-  if (N > 2) box_muller(b.z, b.w, g[2], g[3]);
+  T zeta[N];
+  lane_direction<N>(b.x, b.y, zeta);
   T s;
   if constexpr (sizeof(T) == 8) s = radial_inv64(a, u01_64(ux), X2, norm);
   else s = radial_inv32(a, u01_32(ux), (float)X2);
-  T gg = (T)0;
-  for (int i = 0; i < N; ++i) gg += g[i] * g[i];
-  const T ig = rsqrt_(gg);
   const T t = rT * s;
   T Z[N], Zc[N];
-  for (int i = 0; i < N; ++i) Z[i] = Y[i] + t * (g[i] * ig);
+  for (int i = 0; i < N; ++i) Z[i] = Y[i] + t * zeta[i];
   closest_point<T, N, KIND>(a, Z, Zc);
   return source<T, RICH>(a, Z, Zc, N);
 }
@@ -172,23 +168,19 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
   }
   const T rT = (T)r;
   // Each Philox block is drawn where it is used.  (Drawing the first Green
-  // sample's blocks together with the direction block, to interleave their
+  // sample's block together with the direction block, to interleave their
   // rounds, changed FP64 cap results with this toolchain although the values
   // are the same by construction; the multiple-Green-sample parity test
   // guards the form kept here.)
   const uint4 bd = rs.block(st.k, 0, 0);
-  // (ii) Theta = Y + r g/|g| and Y' = cp(Theta)
+  // (ii) Theta = Y + r zeta and Y' = cp(Theta)
   T Yn[N];
   double rg_next = 0.0;
   {
-    T g[4];
-    box_muller(bd.x, bd.y, g[0], g[1]);
-    if (N > 2) box_muller(bd.z, bd.w, g[2], g[3]);
-    T gg = (T)0;
-    for (int i = 0; i < N; ++i) gg += g[i] * g[i];
-    const T ig = rsqrt_(gg);
+    T zeta[N];
+    lane_direction<N>(bd.x, bd.y, zeta);
     T Th[N];
-    for (int i = 0; i < N; ++i) Th[i] = st.Y[i] + rT * (g[i] * ig);
+    for (int i = 0; i < N; ++i) Th[i] = st.Y[i] + rT * zeta[i];
     if constexpr (KIND == kCloud) {
       const CloudProj<T> p = cloud_cp<T>(a.cloud, Th);
       for (int i = 0; i < N; ++i) Yn[i] = p.y[i];
@@ -201,8 +193,7 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
   T Fsum = (T)0;
   for (int l = 1; l <= a.n_v; ++l) {
     const uint4 b = rs.block(st.k, (uint32_t)l, 0);
-    const uint32_t ux = (N > 2) ? rs.block(st.k, (uint32_t)l, 1).x : b.z;
-    Fsum += green_sample<T, N, KIND, RICH>(a, st.Y, b, ux, rT, X2, norm);
+    Fsum += green_sample<T, N, KIND, RICH>(a, st.Y, b, b.w, rT, X2, norm);
   }
   const double F = a.n_v == 1 ? (double)Fsum : (double)Fsum / (double)a.n_v;
   kahan_add(st.S, st.C, (st.W * om) * F);
