@@ -128,6 +128,9 @@ struct WalkArgs {
   double sigma, lam_sqrt, eps, theta, c_kappa, c_h, tau_w;
   int32_t n_v, comp, precision, persistent;
   double inv_R;                // 1 / p[0] (the radius the source families scale by)
+  double inv_sigma;            // 1 / sigma
+  double rho_geo;              // c_kappa / (1 + kappa) with the manifold's constant curvature bound
+  double cap_rg;               // sphere cap: radius sqrt(R^2 - h^2) of the boundary circle
   int64_t max_steps;
   FnDev f, g;
   // constant-radius data (closed analytic manifolds)

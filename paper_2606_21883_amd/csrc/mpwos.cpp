@@ -535,6 +535,9 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
   a.sigma = sigma;
   a.inv_R = 1.0 / d.p[0];
   a.lam_sqrt = std::sqrt(sigma);
+  a.inv_sigma = 1.0 / sigma;
+  a.rho_geo = o.c_kappa / (1.0 + const_kappa(d));
+  if (d.kind == MPWOS_SPHERE_CAP) a.cap_rg = std::sqrt(d.p[0] * d.p[0] - d.p[1] * d.p[1]);
   a.eps = eps;
   a.theta = o.theta;
   a.c_kappa = o.c_kappa;

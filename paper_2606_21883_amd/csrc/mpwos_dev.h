@@ -148,16 +148,15 @@ __device__ __forceinline__ void kahan_add(double& s, double& c, double x) {
 // (Lemma 3.1 series; eq. omega_explicit_formula).  s1 = sum_{j>=1}
 // (sigma r^2/4)^j / (j! (nu+1)_j);  c = 1/(1+s1);  omega = s1/(sigma(1+s1)).
 // ---------------------------------------------------------------------------
+// s1 = S_nu(X) - 1 by Horner in z = X^2 = sigma r^2 with the law's
+// coefficients alpha_j = 1/(4^j j! (nu+1)_j), kept while alpha_j z^j can
+// exceed 1e-18 over the solve's radii: one division per step.
 __device__ __forceinline__ void weights(const WalkArgs& a, double r, double& c, double& om) {
-  const double q = 0.25 * a.sigma * r * r;
-  double term = 1.0, s1 = 0.0;
-  for (int j = 1; j < 64; ++j) {
-    term = term * q / ((double)j * (a.law.nu + (double)j));
-    s1 += term;
-    if (term <= 1e-18 * s1) break;
-  }
+  const double z = a.sigma * r * r;
+  double s1 = 0.0;
+  for (int j = a.law.js - 1; j >= 1; --j) s1 = (s1 + a.law.alpha[j]) * z;
   c = 1.0 / (1.0 + s1);
-  om = s1 / (a.sigma * (1.0 + s1));
+  om = s1 * c * a.inv_sigma;
 }
 
 // ---------------------------------------------------------------------------

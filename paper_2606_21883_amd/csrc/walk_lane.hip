@@ -18,7 +18,7 @@ template <class T, int N>
 struct LaneState {
   T Y[N];
   double W, S, C;
-  double rg;           // point cloud: rho_geo from the reconstruction that produced Y
+  double rg;           // point cloud: rho_geo from the reconstruction that produced Y; cap: delta_Gamma(Y)
   uint32_t k, q, w;
   int64_t idx;
 };
@@ -27,15 +27,15 @@ struct LaneState {
 // Gamma = S_R cap {x_n = h}; y_Gamma is the nearest point of Gamma; the
 // effective distance is the distance to the normal disk of radius ell at
 // y_Gamma (eq. extended_boundary_disk, eq. delta_Gamma_general).
+// The uniform constants (sqrt(R^2 - h^2), 1/R, ell) come precomputed.
 template <class T, int N>
 __device__ __forceinline__ void cap_gamma_point(const WalkArgs& a, const T* y, T* yg) {
-  const T R = (T)a.p[0], h = (T)a.p[1];
-  const T rg = sqrt_(R * R - h * h);
+  const T rg = (T)a.cap_rg;
   T s = (T)0;
   for (int i = 0; i < N - 1; ++i) s += y[i] * y[i];
-  const T is = (T)1 / sqrt_(s);
+  const T is = rsqrt_(s);
   for (int i = 0; i < N - 1; ++i) yg[i] = rg * y[i] * is;
-  yg[N - 1] = h;
+  yg[N - 1] = (T)a.p[1];
 }
 
 template <class T, int N>
@@ -46,7 +46,7 @@ __device__ __forceinline__ T cap_delta(const WalkArgs& a, const T* y) {
   T rn = (T)0;
   for (int i = 0; i < N; ++i) {
     rG[i] = yg[i] - y[i];
-    nr[i] = yg[i] / R;
+    nr[i] = over_(yg[i], R);
     rn += rG[i] * nr[i];
   }
   T rt2 = (T)0;
@@ -54,16 +54,20 @@ __device__ __forceinline__ T cap_delta(const WalkArgs& a, const T* y) {
     const T v = rG[i] - rn * nr[i];
     rt2 += v * v;
   }
-  const T ell = (T)(a.c_kappa / (1.0 + 1.0 / a.p[0]));
+  // ell = c_kappa / (1 + kappa) with kappa = 1/R, the same as rho_geo
+  const T ell = (T)a.rho_geo;
   T tn = abs_(rn) - ell;
   tn = tn > (T)0 ? tn : (T)0;
   return sqrt_(rt2 + tn * tn);
 }
 
+// Membership of the boundary layer; dg receives delta_Gamma(y) when y is
+// above the cutting plane (the next step's radius reuses it).
 template <class T, int N>
-__device__ __forceinline__ bool cap_in_layer(const WalkArgs& a, const T* y) {
+__device__ __forceinline__ bool cap_in_layer(const WalkArgs& a, const T* y, double& dg) {
   if ((double)y[N - 1] <= a.p[1]) return true;
-  return (double)cap_delta<T, N>(a, y) < a.eps;
+  dg = (double)cap_delta<T, N>(a, y);
+  return dg < a.eps;
 }
 
 // ---- closest point ----------------------------------------------------------
@@ -110,7 +114,7 @@ __device__ __forceinline__ bool walk_init(const WalkArgs& a, const double* queri
     if (!a.const_r) st.rg = cloud_rho_geo(a, p);
   }
   if constexpr (KIND == kCap) {
-    if (cap_in_layer<T, N>(a, st.Y)) {
+    if (cap_in_layer<T, N>(a, st.Y, st.rg)) {
       T yg[N];
       cap_gamma_point<T, N>(a, st.Y, yg);
       st.S = boundary_value<T>(a, yg, N);
@@ -149,8 +153,9 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
   // (i) radius r(Y) = theta min(delta_Gamma, rho_geo) and the weights
   double r, c, om, X2, norm = 0.0;
   if constexpr (KIND == kCap) {
-    const double dg = (double)cap_delta<T, N>(a, st.Y);
-    const double rg = a.c_kappa / (1.0 + 1.0 / a.p[0]);
+    // delta_Gamma(Y) from the previous step's stop test (or the start)
+    const double dg = st.rg;
+    const double rg = a.rho_geo;
     r = a.theta * (dg < rg ? dg : rg);
     weights(a, r, c, om);
     X2 = a.sigma * r * r;
@@ -202,7 +207,7 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
   if constexpr (KIND == kCloud) st.rg = rg_next;
   st.k += 1;
   if constexpr (KIND == kCap) {
-    if (cap_in_layer<T, N>(a, st.Y)) {
+    if (cap_in_layer<T, N>(a, st.Y, st.rg)) {
       T yg[N];
       cap_gamma_point<T, N>(a, st.Y, yg);
       kahan_add(st.S, st.C, st.W * boundary_value<T>(a, yg, N));
