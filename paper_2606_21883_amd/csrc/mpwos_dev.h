@@ -566,7 +566,7 @@ __device__ __forceinline__ T torus_neg_lap(T R, T tube, T sphi, T cpsi, T spsi) 
   const T c2 = cpsi * cpsi - spsi * spsi;
   const T s2 = (T)2 * spsi * cpsi;
   const T u = sphi * c2;
-  return (T)4 * u / (tube * tube) + u / (rt * rt) - (T)2 * sphi * spsi * s2 / (tube * rt);
+  return over_((T)4 * u, tube * tube) + over_(u, rt * rt) - over_((T)2 * sphi * spsi * s2, tube * rt);
 }
 
 // f_Omega(y) + m(z) for a point z of the ball and y = cp(z): the families
