@@ -24,9 +24,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_HERE, "libmpwos_oracle.so")
 
-MANIFOLDS = {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3}
+MANIFOLDS = {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3, "dumbbell": 4}
 FN_KINDS = {"zero": 0, "const": 1, "sph_pair": 2, "circle_mode": 3, "legendre": 4,
-            "torus_mode": 5, "table_s1": 6}
+            "torus_mode": 5, "table_s1": 6, "dumbbell_poly": 7}
 COMP = {"none": 0, "exact": 1}
 RADIUS_RULES = {"curvature": 0, "spacing": 1, "curvature_fit": 2, "curvature_bound": 3}
 STATUS = {0: "OK", -1: "EINVAL", -2: "EOFFMANIFOLD", -3: "ENOMEM", 1: "WTRUNC"}
@@ -65,6 +65,9 @@ def lib():
         L.orc_box_muller.argtypes = [u32, u32, vp]
         L.orc_normals.argtypes = [u64, u32, u32, u32, u32, ctypes.c_int, vp]
         L.orc_direction.argtypes = [u64, u32, u32, u32, u32, ctypes.c_int, vp]
+        L.orc_db_phi.argtypes = [d, d, d, d]
+        L.orc_db_phi.restype = d
+        L.orc_db_curvatures.argtypes = [d, d, d, vp, vp]
         L.orc_radius_uniform.argtypes = [u64, u32, u32, u32, u32, ctypes.c_int]
         L.orc_radius_uniform.restype = d
         for nm in ("orc_c_sigma_r", "orc_omega"):
@@ -163,6 +166,18 @@ def direction(seed, q, w, k, sub, n):
     z = np.zeros(n, dtype=np.float64)
     lib().orc_direction(seed, q, w, k, sub, n, _ptr(z))
     return z
+
+
+def db_phi(alpha, kc, rho, zs):
+    """Profile parameter of the dumbbell point nearest to (|xh|, xs) = (rho, zs)."""
+    return lib().orc_db_phi(alpha, kc, rho, zs)
+
+
+def db_curvatures(alpha, kc, phi):
+    """(k1, k2): profile and cross-section principal curvatures at phi."""
+    k1, k2 = ctypes.c_double(), ctypes.c_double()
+    lib().orc_db_curvatures(alpha, kc, phi, ctypes.byref(k1), ctypes.byref(k2))
+    return k1.value, k2.value
 
 
 def radius_uniform(seed, q, w, k, sub, n):

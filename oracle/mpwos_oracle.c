@@ -30,10 +30,10 @@
 /* ------------------------------------------------------------------------- */
 /* Codes (numeric values fixed by the solver's public interface).             */
 /* ------------------------------------------------------------------------- */
-enum { ORC_SPHERE = 0, ORC_SPHERE_CAP = 1, ORC_TORUS = 2, ORC_POINT_CLOUD = 3 };
+enum { ORC_SPHERE = 0, ORC_SPHERE_CAP = 1, ORC_TORUS = 2, ORC_POINT_CLOUD = 3, ORC_DUMBBELL = 4 };
 enum {
   ORC_FN_ZERO = 0, ORC_FN_CONST = 1, ORC_FN_SPH_PAIR = 2, ORC_FN_CIRCLE_MODE = 3,
-  ORC_FN_LEGENDRE = 4, ORC_FN_TORUS_MODE = 5, ORC_FN_TABLE_S1 = 6
+  ORC_FN_LEGENDRE = 4, ORC_FN_TORUS_MODE = 5, ORC_FN_TABLE_S1 = 6, ORC_FN_DUMBBELL_POLY = 7
 };
 enum { ORC_COMP_NONE = 0, ORC_COMP_EXACT = 1 };
 enum { ORC_RADIUS_CURVATURE = 0, ORC_RADIUS_SPACING = 1, ORC_RADIUS_CURVATURE_FIT = 2,
@@ -47,7 +47,7 @@ enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_EOFFMANIFOLD = -2, ORC_ENOMEM = -3, ORC_
 typedef struct {
   int32_t manifold;      /* ORC_SPHERE ... */
   int32_t n;             /* ambient dimension */
-  double p[4];           /* sphere: R; cap: R, h; torus: R, a */
+  double p[4];           /* sphere: R; cap: R, h; torus: R, a; dumbbell: alpha, kappa (half-length) */
   const double* points;  /* point cloud, n_points x 3, row-major */
   int64_t n_points;
   int32_t k_nn;          /* neighbours used by the local reconstruction */
@@ -584,9 +584,127 @@ static void orc_torus_angles(double R, const double* x, double* phi, double* psi
   *dist = sqrt((rho - R) * (rho - R) + x[2] * x[2]);
 }
 
+/* ------------------------------------------------------------------------- */
+/* Implicit dumbbell hypersurface (Sec. 4, Example 2): x = (xh, xs) with      */
+/* xh in R^{n-1}; M = { |xh| = R(xs) },                                       */
+/*   R(xs) = sqrt(1 - (xs/kc)^2) (1 - a + 2 a (xs/kc)^2).                     */
+/* With xs = kc cos(phi), phi in [0, pi], the profile is                      */
+/*   r(phi) = sin(phi) g(phi), g = 1 - a + 2 a cos^2(phi),  z(phi) = kc cos(phi), */
+/* smooth up to the poles; M is the surface of revolution of (r, z) about the */
+/* xs axis with cross-sections S^{n-2}.                                       */
+/* ------------------------------------------------------------------------- */
+typedef struct { double r, r1, r2, z, z1, z2, g; } orc_profile;
+
+static orc_profile orc_db_profile(double a, double kc, double phi) {
+  orc_profile p;
+  double s = sin(phi), c = cos(phi);
+  double g = 1.0 - a + 2.0 * a * c * c;
+  double g1 = -4.0 * a * c * s;
+  double g2 = -4.0 * a * (c * c - s * s);
+  p.g = g;
+  p.r = s * g;
+  p.r1 = c * g + s * g1;
+  p.r2 = -s * g + 2.0 * c * g1 + s * g2;
+  p.z = kc * c;
+  p.z1 = -kc * s;
+  p.z2 = -kc * c;
+  return p;
+}
+
+/* Profile parameter of the point of M nearest to (|xh|, xs) = (rho, zs): the
+ * global minimum of D(phi) = (rho - r)^2 + (zs - z)^2 on a 2048-cell grid,
+ * then Newton on D' = 0 kept inside the neighbouring cells by bisection. */
+double orc_db_phi(double a, double kc, double rho, double zs) {
+  const int M = 2048;
+  const double pi = 3.141592653589793;
+  const double h = pi / M;
+  int best = 0;
+  double bd = INFINITY;
+  for (int i = 0; i <= M; ++i) {
+    orc_profile p = orc_db_profile(a, kc, i * h);
+    double d = (rho - p.r) * (rho - p.r) + (zs - p.z) * (zs - p.z);
+    if (d < bd) { bd = d; best = i; }
+  }
+  double lo = best > 0 ? (best - 1) * h : 0.0;
+  double hi = best < M ? (best + 1) * h : pi;
+  double phi = best * h;
+  for (int it = 0; it < 200; ++it) {
+    orc_profile p = orc_db_profile(a, kc, phi);
+    double d1 = -2.0 * ((rho - p.r) * p.r1 + (zs - p.z) * p.z1);
+    double d2 = 2.0 * (p.r1 * p.r1 + p.z1 * p.z1) - 2.0 * ((rho - p.r) * p.r2 + (zs - p.z) * p.z2);
+    if (d1 > 0.0) hi = phi; else lo = phi;
+    double nx = d2 > 0.0 ? phi - d1 / d2 : NAN;
+    if (!(nx >= lo && nx <= hi)) nx = 0.5 * (lo + hi);
+    double step = fabs(nx - phi);
+    phi = nx;
+    if (step <= 1e-16 * (1.0 + phi) || hi - lo <= 1e-16 * (1.0 + phi)) break;
+  }
+  return phi;
+}
+
+/* cp onto the dumbbell; phi_out (nullable) receives the profile parameter. */
+static int orc_db_cp(const orc_problem* P, const double* x, double* y, double* phi_out) {
+  int n = P->n;
+  double rho = 0.0;
+  for (int i = 0; i < n - 1; ++i) rho += x[i] * x[i];
+  rho = sqrt(rho);
+  double phi = orc_db_phi(P->p[0], P->p[1], rho, x[n - 1]);
+  orc_profile p = orc_db_profile(P->p[0], P->p[1], phi);
+  for (int i = 0; i < n - 1; ++i) y[i] = rho > 0.0 ? p.r * (x[i] / rho) : 0.0;
+  y[n - 1] = p.z;
+  if (phi_out) *phi_out = phi;
+  return ORC_OK;
+}
+
+/* Principal curvatures of the dumbbell at profile parameter phi, for the
+ * outward normal: k1 of the profile curve, k2 (multiplicity n-2) of the
+ * cross-section sphere, -z'/(L r) = kc/(g L). */
+void orc_db_curvatures(double a, double kc, double phi, double* k1, double* k2) {
+  orc_profile p = orc_db_profile(a, kc, phi);
+  double L = sqrt(p.r1 * p.r1 + p.z1 * p.z1);
+  *k1 = (p.z1 * p.r2 - p.r1 * p.z2) / (L * L * L);
+  *k2 = kc / (p.g * L);
+}
+
+/* f_Omega = -Lap_M u + sigma u for the polynomial
+ *   U(x) = c0 xs + c1 xs^2 + b1 (1.xh)/sqrt(n-1) + b2 xh^T diag(A) xh
+ * at the point y of M with profile parameter phi, by the extrinsic formula
+ * Lap_M U = Lap U - nu^T Hess(U) nu - H dU/dnu (H = k1 + (n-2) k2, nu the
+ * outward unit normal (N_r e, N_z), e = xh/|xh|). */
+static double orc_db_f(const orc_problem* P, const double* y, double phi) {
+  int n = P->n, m = n - 1;
+  const double* c = P->f_coef;
+  const double* A = P->f_values;
+  orc_profile p = orc_db_profile(P->p[0], P->p[1], phi);
+  double L = sqrt(p.r1 * p.r1 + p.z1 * p.z1);
+  double Nr = -p.z1 / L, Nz = p.r1 / L;
+  double k1, k2;
+  orc_db_curvatures(P->p[0], P->p[1], phi, &k1, &k2);
+  double rho = 0.0;
+  for (int i = 0; i < m; ++i) rho += y[i] * y[i];
+  rho = sqrt(rho);
+  double s1 = 0.0, sA = 0.0, tr = 0.0;
+  for (int i = 0; i < m; ++i) {
+    double e = rho > 0.0 ? y[i] / rho : 0.0;
+    s1 += e;
+    sA += A[i] * e * e;
+    tr += A[i];
+  }
+  double z = y[n - 1];
+  double isq = 1.0 / sqrt((double)m);
+  double U = c[0] * z + c[1] * z * z + c[2] * rho * s1 * isq + c[3] * rho * rho * sA;
+  double lapU = 2.0 * c[1] + 2.0 * c[3] * tr;
+  double hess = 2.0 * c[1] * Nz * Nz + 2.0 * c[3] * Nr * Nr * sA;
+  double dnu = Nz * (c[0] + 2.0 * c[1] * z) + Nr * (c[2] * s1 * isq + 2.0 * c[3] * rho * sA);
+  double H = k1 + (double)(m - 1) * k2;
+  double lapM = lapU - hess - H * dnu;
+  return -lapM + P->sigma * U;
+}
+
 int orc_cp(const orc_problem* P, const double* x, double* y) {
   int n = P->n;
   switch (P->manifold) {
+    case ORC_DUMBBELL: return orc_db_cp(P, x, y, NULL);
     case ORC_SPHERE:
     case ORC_SPHERE_CAP: {
       double nx = orc_norm(x, n);
@@ -810,6 +928,12 @@ static double orc_g_omega(const orc_problem* P, const double* y) {
 /* Source term of one Green sample at ambient point z: f(z) + m(z). */
 double orc_source(const orc_problem* P, const double* z) {
   double y[ORC_MAXN];
+  if (P->manifold == ORC_DUMBBELL) {
+    double phi;
+    orc_db_cp(P, z, y, &phi);
+    if (P->f_kind == ORC_FN_DUMBBELL_POLY) return orc_db_f(P, y, phi);
+    return orc_f_omega(P, y);
+  }
   if (orc_cp(P, z, y)) return NAN;
   double v = orc_f_omega(P, y);
   if (P->compensation == ORC_COMP_EXACT) v += orc_m_exact(P, z, y);
@@ -822,6 +946,9 @@ double orc_source(const orc_problem* P, const double* z) {
 /* For point clouds rho_geo comes from the reconstruction that produced y.    */
 /* ------------------------------------------------------------------------- */
 static double orc_rho_geo(const orc_problem* P, const double* y, const orc_pc_result* pc) {
+  /* a bound of kappa over M in eq. rho_geo_curvature: a radius no larger than
+   * the local rule gives anywhere */
+  if (P->radius_rule == ORC_RADIUS_CURVATURE_BOUND) return P->c_kappa / (1.0 + P->kappa_bound);
   if (P->manifold == ORC_POINT_CLOUD) {
     if (P->radius_rule == ORC_RADIUS_SPACING) return P->c_h * pc->h_mean;
     /* a bound of kappa over M in eq. rho_geo_curvature: a radius no larger
@@ -991,13 +1118,27 @@ static int orc_check(const orc_problem* P) {
   if (P->manifold == ORC_POINT_CLOUD && (P->k_nn < 6 || P->k_nn > ORC_MAXK || P->n_points < P->k_nn))
     return ORC_EINVAL;
   if (P->radius_rule == ORC_RADIUS_CURVATURE_BOUND &&
-      (P->manifold != ORC_POINT_CLOUD || !(P->kappa_bound >= 0.0) || !isfinite(P->kappa_bound)))
+      ((P->manifold != ORC_POINT_CLOUD && P->manifold != ORC_DUMBBELL) || !(P->kappa_bound >= 0.0) ||
+       !isfinite(P->kappa_bound)))
     return ORC_EINVAL;
+  if (P->manifold == ORC_DUMBBELL) {
+    /* closed; the radius takes a curvature bound; no exact compensation is
+     * known for this manifold (the paper sets m = 0 here) */
+    if (P->n < 3 || P->radius_rule != ORC_RADIUS_CURVATURE_BOUND || P->compensation != ORC_COMP_NONE)
+      return ORC_EINVAL;
+    if (!(P->p[0] >= 0.0 && P->p[0] < 0.5) || !(P->p[1] > 0.0)) return ORC_EINVAL;
+    if (P->f_kind != ORC_FN_ZERO && P->f_kind != ORC_FN_CONST && P->f_kind != ORC_FN_DUMBBELL_POLY)
+      return ORC_EINVAL;
+    if (P->f_kind == ORC_FN_DUMBBELL_POLY && (!P->f_values || P->f_nvalues != P->n - 1)) return ORC_EINVAL;
+  } else if (P->f_kind == ORC_FN_DUMBBELL_POLY) {
+    return ORC_EINVAL;
+  }
   return ORC_OK;
 }
 
 /* Largest X = sqrt(sigma) r the solve can reach (constant radius bound). */
 static double orc_max_radius(const orc_problem* P) {
+  if (P->radius_rule == ORC_RADIUS_CURVATURE_BOUND) return P->theta * P->c_kappa / (1.0 + P->kappa_bound);
   if (P->manifold == ORC_POINT_CLOUD) {
     if (P->radius_rule == ORC_RADIUS_SPACING) return INFINITY;
     if (P->radius_rule == ORC_RADIUS_CURVATURE_BOUND) return P->theta * P->c_kappa / (1.0 + P->kappa_bound);

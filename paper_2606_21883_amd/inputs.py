@@ -7,7 +7,8 @@ closed-form solutions u that the estimates are scored against.
 
 Problem shapes follow the paper's experiments (Sec. 4): unit circle and unit
 sphere problems with spherical-harmonic solutions, hyperspheres up to
-n = 1000, a torus (R = 1, a = 0.3) given implicitly and as a noisy point cloud.
+n = 1000, a torus (R = 1, a = 0.3) given implicitly and as a noisy point cloud,
+and the 1000-dimensional implicit dumbbell of Example 2 in R^1001.
 """
 import math
 
@@ -199,7 +200,77 @@ def exact_u(prob, y):
         rho = np.hypot(y[:, 0], y[:, 1])
         psi = np.arctan2(y[:, 2], rho - Rt)
         return f["coef"][0] * np.sin(phi) * np.cos(2.0 * psi)
+    if kind == "dumbbell_poly":
+        c = f["coef"]
+        a = np.asarray(f["values"])
+        xh, xs = y[:, :-1], y[:, -1]
+        return (c[0] * xs + c[1] * xs * xs + c[2] * xh.sum(axis=1) / math.sqrt(xh.shape[1])
+                + c[3] * (xh * xh * a).sum(axis=1))
     raise ValueError(kind)
+
+
+# ---------------------------------------------------------------------------
+# the implicit dumbbell of Example 2: |xh| = R(xs) in R^n, xh in R^{n-1},
+# R(xs) = sqrt(1 - (xs/kc)^2) (1 - a + 2 a (xs/kc)^2), a = 0.35, kc = 1.2
+# ---------------------------------------------------------------------------
+
+
+def dumbbell_profile_radius(xs, alpha=0.35, kc=1.2):
+    """R(xs) as the paper defines it."""
+    t = (np.asarray(xs, dtype=np.float64) / kc) ** 2
+    return np.sqrt(np.maximum(0.0, 1.0 - t)) * (1.0 - alpha + 2.0 * alpha * t)
+
+
+def dumbbell_kappa_max(alpha=0.35, kc=1.2, m=400001):
+    """Largest principal curvature magnitude over the dumbbell, from the profile
+    (sin t g(t), kc cos t), g = 1 - a + 2 a cos^2 t, on a fine grid: the profile
+    curvature and kc / (g |profile'|), the curvature of the cross-sections.
+    2.9294 for the paper's a = 0.35, kc = 1.2."""
+    t = np.linspace(0.0, np.pi, m)
+    s, c = np.sin(t), np.cos(t)
+    g = 1.0 - alpha + 2.0 * alpha * c * c
+    g1 = -4.0 * alpha * c * s
+    g2 = -4.0 * alpha * (c * c - s * s)
+    r1 = c * g + s * g1
+    r2 = -s * g + 2.0 * c * g1 + s * g2
+    z1, z2 = -kc * s, -kc * c
+    L = np.sqrt(r1 * r1 + z1 * z1)
+    k1 = (z1 * r2 - r1 * z2) / L ** 3
+    k2 = kc / (g * L)
+    return float(max(np.abs(k1).max(), np.abs(k2).max()))
+
+
+def dumbbell_diag(n):
+    """The trace-free diagonal A_2 (the paper leaves its entries open):
+    +1, -1, +1, ... over the n-1 coordinates of xh, the last one 0 when n-1 is
+    odd."""
+    a = np.ones(n - 1)
+    a[1::2] = -1.0
+    if (n - 1) % 2:
+        a[-1] = 0.0
+    return a
+
+
+def dumbbell_problem(n=1001, alpha=0.35, kc=1.2, n_v=1, sigma=None):
+    """Example 2: u = 0.15 xs + 0.05 xs^2 + (1.xh)/sqrt(n-1) + 0.2 xh^T A_2 xh on
+    the dumbbell in R^n, sigma = 2 d (d = n - 1), theta = 0.95, c_kappa = 1.2, no
+    compensation (as in the paper), the radius from the curvature bound."""
+    return problem(manifold="dumbbell", n=n, p=[alpha, kc], sigma=2.0 * (n - 1) if sigma is None else sigma,
+                   f=dict(kind="dumbbell_poly", coef=[0.15, 0.05, 1.0, 0.2], values=dumbbell_diag(n)),
+                   radius_rule="curvature_bound", kappa_bound=dumbbell_kappa_max(alpha, kc),
+                   compensation="none", n_v=n_v)
+
+
+def dumbbell_points(nq, n=1001, alpha=0.35, kc=1.2, seed=1, phi_margin=0.1):
+    """Points of the dumbbell: profile angle uniform in [margin, pi - margin],
+    cross-section direction uniform on S^{n-2}."""
+    rng = np.random.default_rng(seed)
+    t = rng.uniform(phi_margin, np.pi - phi_margin, nq)
+    e = rng.standard_normal((nq, n - 1))
+    e /= np.linalg.norm(e, axis=1, keepdims=True)
+    xs = kc * np.cos(t)
+    r = dumbbell_profile_radius(xs, alpha, kc)
+    return np.concatenate([e * r[:, None], xs[:, None]], axis=1)
 
 
 # ---------------------------------------------------------------------------
