@@ -265,15 +265,24 @@ static double orc_radial_D(const orc_radial* R, double X, double s) {
   double X2 = X * X;
   double s2 = s * s;
   double s2nu = (R->n == 2) ? 1.0 : pow(s, (double)(R->n - 2));
+  /* Each term is at most |b_j| X^{2j} in size (|s^{2j} - s^{2nu}| <= 1,
+   * |2(nu - j)| >= 1), and the b_j X^{2j} decay geometrically inside the
+   * series' disc, so the sum stops after three terms below 1e-19 of it. */
   double acc = 0.0, Xp = 1.0, sp = 1.0;
+  int small = 0;
   for (int j = 0; j < ORC_NSERIES; ++j) {
     if (j > 0) { Xp *= X2; sp *= s2; }
+    if (!isfinite(Xp)) break;
     double bx = R->beta[j] * Xp;
     double t;
     if (j == R->nu_int) t = bx * (-s2nu * log(s));
     else t = bx * (sp - s2nu) / (2.0 * (R->nu - (double)j));
     acc += t;
-    if (j > R->nu + 2 && fabs(bx) <= 1e-19 * fabs(acc)) break;
+    if (fabs(bx) <= 1e-19 * fabs(acc)) {
+      if (++small >= 3 && j >= 2) break;
+    } else {
+      small = 0;
+    }
   }
   return acc;
 }

@@ -129,16 +129,17 @@ def test_radial_cdf_endpoints_and_monotone(orc):
         assert np.all(np.diff(F) >= 0)
 
 
-@pytest.mark.parametrize("n", [2, 3, 5, 100, 1000])
-def test_radial_inverse_roundtrip(orc, n):
-    X = 0.8
+@pytest.mark.parametrize("n,X", [(2, 0.8), (3, 0.8), (5, 0.8), (100, 0.8), (1000, 0.8), (1001, 12.975)])
+def test_radial_inverse_roundtrip(orc, n, X):
     for u in [1e-9, 0.01, 0.3, 0.5, 0.77, 0.999, 1 - 1e-9]:
         s = orc.radial_inv(n, X, u)
         assert orc.radial_cdf(n, X, s) == pytest.approx(u, rel=1e-12, abs=1e-15)
 
 
-@pytest.mark.parametrize("n", [2, 3, 10, 100, 1000])
-@pytest.mark.parametrize("sigma,r", [(1.0, 0.57), (2.0, 0.57), (0.5, 0.3)])
+@pytest.mark.parametrize("n,sigma,r", [(n, s, r) for n in (2, 3, 10, 100, 1000)
+                                       for s, r in ((1.0, 0.57), (2.0, 0.57), (0.5, 0.3))]
+                         # the dumbbell's regime: sigma = 2 (n - 1), r = 0.95 * 1.2 / (1 + 2.9294)
+                         + [(11, 20.0, 0.290121), (101, 200.0, 0.290121), (1001, 2000.0, 0.290121)])
 def test_radial_moments_from_local_representation(orc, n, sigma, r):
     """Lemma 2.1 applied to v = |z-y|^{2m} (for which -Lap v + sigma v is explicit)
     fixes every even moment of |Z - y| under the Green density:
