@@ -236,7 +236,7 @@ def cpu_baseline(work):
     (about 10-20 s of CPU work)."""
     import oracle
     threads = min(16, os.cpu_count() or 1)
-    sample = {"sphere": (64, 4096), "cap": (64, 4096)}
+    sample = {"sphere": (64, 4096), "cap": (64, 4096), "dumbbell": (1, 32)}
     total_steps, total_t, parts = 0, 0.0, []
     for name, prob, Q, nw in work:
         nq, nws = sample.get(name, (8, 256))
@@ -455,7 +455,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="sphere",
-                    choices=["sphere", "circle", "torus", "cloud", "hyper100", "hyper1000"],
+                    choices=["sphere", "circle", "torus", "cloud", "hyper100", "hyper1000", "dumbbell"],
                     help="sphere (closed + cap) is the headline workload; the others are for profiling")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink queries and walks (profiling only)")
     ap.add_argument("--block-size", type=int, default=0, help="workgroup size of the walk kernels (0 = autotuned)")
@@ -518,6 +518,8 @@ def main():
         "cloud": "point-cloud torus, 1e6 points, noise 1e-4, k=16 + quadratic fit: 8192 queries x 1024 walks",
         "hyper100": "S^99 in R^100: u=x1x2, sigma=1, 1024 queries x 2048 walks",
         "hyper1000": "S^999 in R^1000: u=x1x2, sigma=1, 1024 queries x 2048 walks",
+        "dumbbell": "1000-dimensional implicit dumbbell in R^1001 (a=0.35, kc=1.2), sigma=2000, m=0, "
+                    "N_V=50, 20 points x 1000 paths",
     }[args.workload]
     if args.scale != 1.0:
         desc += f" (scaled by {args.scale})"
@@ -545,6 +547,16 @@ def main():
         out["speedup_vs_fp64_plain"] = value / v64
         out["rmse_ratio_fp32_over_fp64"] = {k: fast["per"][k]["rmse"] / slow["per"][k]["rmse"]
                                             for k in fast["per"]}
+    if args.workload == "dumbbell":
+        # Table 1 of the paper (N = 1000 paths, N_V = 50, one point at a time,
+        # 24 laptop CPU cores): 11.43 s per point, 1.78e4 walk-steps/s derived;
+        # another machine's number, quoted for context
+        per = next(iter(fast["per"].values()))
+        out["paper_table1"] = {"seconds_per_point": 11.43, "walk_steps_per_s": 1.78e4, "avg_steps": 204,
+                               "hardware": "24 CPU cores, MATLAB"}
+        out["ms_per_point"] = per["kernel_ms"] / per["n_queries"]
+        out["avg_steps"] = per["k_mean"]
+        out["vs_baseline"] = value / 1.78e4
     if not args.no_served and args.workload == "sphere" and args.only is None:
         out["served"] = served_mix()
         if args.served_rates:

@@ -56,8 +56,14 @@ typedef enum {
   MPWOS_SPHERE_CAP = 1,      /* Omega = S^{n-1}_R cap {x_n > h}, Gamma = {x_n = h} (boundary case) */
   MPWOS_TORUS_IMPLICIT = 2,  /* {((|x|^2 + R^2 - a^2)^2 - 4R^2(x1^2 + x2^2)) = 0} in R^3; cp by a
                                 local Newton solve on the level set (Sec. 2.3.2) */
-  MPWOS_POINT_CLOUD = 3      /* points p_i in R^3; cp by k-nearest-neighbour search and a local
+  MPWOS_POINT_CLOUD = 3,     /* points p_i in R^3; cp by k-nearest-neighbour search and a local
                                 quadratic reconstruction (Sec. 2.3.2) */
+  MPWOS_DUMBBELL = 4         /* implicit dumbbell of Sec. 4, Example 2: {|x_h| = R(x_n)} in R^n,
+                                x_h = (x_1 .. x_{n-1}), R(s) = sqrt(1 - (s/k)^2)(1 - a + 2a (s/k)^2),
+                                a = p[0] in [0, 1/2), k = p[1] > 0; closed; cp by Newton in the
+                                profile parameter; n in [4, 4096]; takes the CURVATURE_BOUND rule
+                                (kappa_bound >= its largest principal curvature) and no
+                                compensation */
 } mpwos_kind;
 
 /* Source and boundary-data families.  For f the family describes f_Omega;
@@ -73,9 +79,12 @@ typedef enum {
   MPWOS_FN_TORUS_MODE = 5,   /* torus / point-cloud torus (R = p[0], a = p[1]):
                                 u = coef[0] sin(phi) cos(2 psi), f = -Lap_T u + sigma u;
                                 as g: g = u */
-  MPWOS_FN_TABLE_S1 = 6      /* S^1_R, f: values[0..M) = f at th_i = 2 pi i/M (linear
+  MPWOS_FN_TABLE_S1 = 6,     /* S^1_R, f: values[0..M) = f at th_i = 2 pi i/M (linear
                                 interpolation), values[M..2M) = predictor u_* used by
                                 the compensation; n_values = 2M (host memory) */
+  MPWOS_FN_DUMBBELL_POLY = 7 /* dumbbell, f: u = coef[0] x_n + coef[1] x_n^2 + coef[2] (sum x_h)/sqrt(n-1)
+                                + coef[3] sum_i values[i] x_i^2 (n_values = n - 1, host memory),
+                                f = -Lap_M u + sigma u (Example 2's family; A = diag(values)) */
 } mpwos_fn_kind;
 
 typedef enum { MPWOS_FP64_PLAIN = 0, MPWOS_FP32_MIXED = 1 } mpwos_precision;
@@ -84,8 +93,8 @@ typedef enum {
   MPWOS_RADIUS_CURVATURE = 0,     /* rho_geo = c_kappa/(1 + kappa(y)) (eq. rho_geo_curvature) */
   MPWOS_RADIUS_SPACING = 1,       /* rho_geo = c_h h(y), h = mean kNN distance (eq. rho_geo_spacing) */
   MPWOS_RADIUS_CURVATURE_FIT = 2, /* point cloud: kappa from the fitted patch, then eq. rho_geo_curvature */
-  MPWOS_RADIUS_CURVATURE_BOUND = 3 /* point cloud: eq. rho_geo_curvature with a bound kappa_bound of kappa
-                                      over M (a constant radius no larger than the local rule's) */
+  MPWOS_RADIUS_CURVATURE_BOUND = 3 /* point cloud, dumbbell: eq. rho_geo_curvature with a bound kappa_bound of
+                                      kappa over M (a constant radius no larger than the local rule's) */
 } mpwos_radius_rule;
 
 typedef struct mpwos_manifold mpwos_manifold;
@@ -105,7 +114,7 @@ typedef struct {
   int32_t kind;             /* mpwos_fn_kind */
   int32_t idx[3];
   double coef[8];
-  const double* values;     /* TABLE_S1 only, host memory, copied at solve time */
+  const double* values;     /* TABLE_S1 and DUMBBELL_POLY only, host memory, copied at solve time */
   int64_t n_values;
 } mpwos_fn;
 
@@ -219,8 +228,9 @@ mpwos_status mpwos_plan_stats(mpwos_plan* p, void* stream, mpwos_stats* stats);
 mpwos_status mpwos_plan_destroy(mpwos_plan* p);
 
 /* ---- launch autotuner ----------------------------------------------------
- * Times the launch shapes of a solve on a sample of it (whole queries, walks
- * per query capped so that a trial is a fraction of a second) and returns the
+ * Times the launch shapes of a solve on a sample of it (up to 2^24 walks;
+ * with a constant radius, walks of equal length cut to a step count that keeps
+ * a trial to a fraction of a second, otherwise fewer walks) and returns the
  * fastest options: block_size and persistent for n <= 3, also lanes_per_walk
  * for n >= 4.  Other fields are copied from opt.  Walk results do not depend
  * on block_size or persistent; for n >= 4 they depend on lanes_per_walk

@@ -8,9 +8,10 @@ namespace mpwos {
 constexpr int kMaxJ = 32;       // series terms kept for the radial law
 constexpr int kMaxK = 32;       // point-cloud neighbours
 
-enum Kind : int32_t { kSphere = 0, kCap = 1, kTorus = 2, kCloud = 3 };
+enum Kind : int32_t { kSphere = 0, kCap = 1, kTorus = 2, kCloud = 3, kDumbbell = 4 };
 enum FnKind : int32_t {
-  kFnZero = 0, kFnConst = 1, kFnSphPair = 2, kFnCircle = 3, kFnLegendre = 4, kFnTorus = 5, kFnTableS1 = 6
+  kFnZero = 0, kFnConst = 1, kFnSphPair = 2, kFnCircle = 3, kFnLegendre = 4, kFnTorus = 5, kFnTableS1 = 6,
+  kFnDumbbell = 7
 };
 
 // A source / boundary family as the device sees it.
@@ -18,9 +19,9 @@ struct FnDev {
   int32_t kind;
   int32_t idx[3];
   double coef[8];
-  const double* values;   // device copy of a TABLE_S1 table (2M doubles)
-  int64_t m;              // M (table length of one half)
-  double lam;             // eigenvalue of the family (sphere families), 0 otherwise
+  const double* values;   // device copy of a TABLE_S1 table (2M doubles) or the dumbbell diagonal (n-1)
+  int64_t m;              // M (table length of one half); n - 1 for the dumbbell diagonal
+  double lam;             // eigenvalue of the family (sphere families); trace of the dumbbell diagonal
   double u_scale;         // u = u_scale * f for eigen families
 };
 

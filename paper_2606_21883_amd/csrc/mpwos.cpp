@@ -333,6 +333,11 @@ static mpwos_status check_manifold_desc(const mpwos_manifold_desc* d) {
       if (!(d->p[1] > 0 && d->p[1] <= 0.5 * d->p[0]))
         return fail(MPWOS_EINVAL, "torus: need 0 < a <= R/2 (constant curvature indicator 1/a)");
       return MPWOS_OK;
+    case MPWOS_DUMBBELL:
+      if (d->n < 4 || d->n > 4096) return fail(MPWOS_EINVAL, "dumbbell: n must be in [4, 4096]");
+      if (!(d->p[0] >= 0.0 && d->p[0] < 0.5)) return fail(MPWOS_EINVAL, "dumbbell: a = p[0] must be in [0, 1/2)");
+      if (!(d->p[1] > 0.0) || !std::isfinite(d->p[1])) return fail(MPWOS_EINVAL, "dumbbell: k = p[1] must be > 0");
+      return MPWOS_OK;
     case MPWOS_POINT_CLOUD:
       if (d->n != 3) return fail(MPWOS_EINVAL, "point cloud: n must be 3");
       if (!d->points) return fail(MPWOS_EINVAL, "point cloud: points is NULL");
@@ -382,6 +387,10 @@ static mpwos_status check_fn(const mpwos_fn* f, const mpwos_manifold_desc& d, bo
       if (!sph || d.n != 2 || is_g) return bad("TABLE_S1 is a source on S^1");
       if (!f->values || f->n_values < 4 || (f->n_values % 2)) return bad("TABLE_S1 needs 2M >= 4 values");
       return MPWOS_OK;
+    case MPWOS_FN_DUMBBELL_POLY:
+      if (d.kind != MPWOS_DUMBBELL || is_g) return bad("DUMBBELL_POLY is a source on the dumbbell");
+      if (!f->values || f->n_values != d.n - 1) return bad("DUMBBELL_POLY needs n - 1 values");
+      return MPWOS_OK;
   }
   return bad("unknown function kind");
 }
@@ -397,9 +406,54 @@ static void fill_fn(const mpwos_fn* f, const mpwos_manifold_desc& d, double sigm
   if (f->kind == MPWOS_FN_CIRCLE_MODE) o.lam = (double)f->idx[0] * f->idx[0] / (R * R);
   o.u_scale = 1.0 / (o.lam + sigma);
   if (f->kind == MPWOS_FN_TABLE_S1) o.m = f->n_values / 2;
+  if (f->kind == MPWOS_FN_DUMBBELL_POLY) {
+    o.m = f->n_values;
+    double tr = 0.0;
+    for (int64_t i = 0; i < f->n_values; ++i) tr += f->values[i];
+    o.lam = tr;
+  }
+}
+
+// Nearest profile parameter of the dumbbell to (|x_h|, x_n) = (rho, zs), on
+// the host (query checks): the best point of a fine grid, then Newton on the
+// derivative of the squared planar distance, bracketed.
+static double dumbbell_phi_host(double a, double k, double rho, double zs) {
+  auto prof = [&](double t, double* v) {
+    const double s = std::sin(t), c = std::cos(t);
+    const double g = 1.0 - a + 2.0 * a * c * c, g1 = -4.0 * a * c * s, g2 = -4.0 * a * (c * c - s * s);
+    v[0] = s * g;
+    v[1] = c * g + s * g1;
+    v[2] = -s * g + 2.0 * c * g1 + s * g2;
+    v[3] = k * c;
+    v[4] = -k * s;
+    v[5] = -k * c;
+  };
+  const int G = 1024;
+  const double pi = 3.141592653589793, h = pi / G;
+  int best = 0;
+  double bd = INFINITY, v[6];
+  for (int j = 0; j <= G; ++j) {
+    prof(j * h, v);
+    const double d = (rho - v[0]) * (rho - v[0]) + (zs - v[3]) * (zs - v[3]);
+    if (d < bd) { bd = d; best = j; }
+  }
+  double lo = best > 0 ? (best - 1) * h : 0.0, hi = best < G ? (best + 1) * h : pi, t = best * h;
+  for (int it = 0; it < 100; ++it) {
+    prof(t, v);
+    const double d1 = -2.0 * ((rho - v[0]) * v[1] + (zs - v[3]) * v[4]);
+    const double d2 = 2.0 * (v[1] * v[1] + v[4] * v[4]) - 2.0 * ((rho - v[0]) * v[2] + (zs - v[3]) * v[5]);
+    if (d1 > 0.0) hi = t; else lo = t;
+    double nx = d2 > 0.0 ? t - d1 / d2 : lo - 1.0;
+    if (!(nx >= lo && nx <= hi)) nx = 0.5 * (lo + hi);
+    const double step = std::fabs(nx - t);
+    t = nx;
+    if (step <= 1e-16 * (1.0 + t) || hi - lo <= 1e-16 * (1.0 + t)) break;
+  }
+  return t;
 }
 
 // on-manifold test of a query (host side, analytic manifolds)
+// (the dumbbell's: the distance to its nearest point)
 static bool query_on_manifold(const mpwos_manifold_desc& d, const double* y) {
   const int n = d.n;
   double s = 0.0;
@@ -412,6 +466,14 @@ static bool query_on_manifold(const mpwos_manifold_desc& d, const double* y) {
       const double rho = std::hypot(y[0], y[1]);
       const double dc = std::hypot(rho - d.p[0], y[2]);
       return std::fabs(dc - d.p[1]) <= tol;
+    }
+    case MPWOS_DUMBBELL: {
+      double hh = 0.0;
+      for (int i = 0; i < n - 1; ++i) hh += y[i] * y[i];
+      const double rho = std::sqrt(hh), zs = y[n - 1];
+      const double t = dumbbell_phi_host(d.p[0], d.p[1], rho, zs);
+      const double pr = std::sin(t) * (1.0 - d.p[0] + 2.0 * d.p[0] * std::cos(t) * std::cos(t));
+      return std::hypot(rho - pr, zs - d.p[1] * std::cos(t)) <= tol;
     }
   }
   return true;
@@ -510,8 +572,14 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
     return fail(MPWOS_EINVAL, "unknown compensation");
   if (o.radius_rule < MPWOS_RADIUS_CURVATURE || o.radius_rule > MPWOS_RADIUS_CURVATURE_BOUND)
     return fail(MPWOS_EINVAL, "unknown radius_rule");
-  if (d.kind != MPWOS_POINT_CLOUD && o.radius_rule != MPWOS_RADIUS_CURVATURE)
-    return fail(MPWOS_EINVAL, "radius rules other than CURVATURE apply to point clouds only");
+  if (d.kind == MPWOS_DUMBBELL) {
+    if (o.radius_rule != MPWOS_RADIUS_CURVATURE_BOUND)
+      return fail(MPWOS_EINVAL, "the dumbbell takes the CURVATURE_BOUND radius rule");
+    if (o.compensation != MPWOS_COMP_NONE)
+      return fail(MPWOS_EINVAL, "the dumbbell has no exact compensation: set compensation NONE");
+  } else if (d.kind != MPWOS_POINT_CLOUD && o.radius_rule != MPWOS_RADIUS_CURVATURE) {
+    return fail(MPWOS_EINVAL, "radius rules other than CURVATURE apply to point clouds and the dumbbell");
+  }
   if (o.radius_rule == MPWOS_RADIUS_CURVATURE_BOUND && !(o.kappa_bound >= 0.0 && std::isfinite(o.kappa_bound)))
     return fail(MPWOS_EINVAL, "kappa_bound must be finite and >= 0");
   if (o.block_size != 0 && (o.block_size < 64 || o.block_size > 256 || o.block_size % 64))
@@ -557,7 +625,7 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
   // largest X^2 = sigma r^2 the walk can reach
   double rmax;
   const bool cloud_bound = d.kind == MPWOS_POINT_CLOUD && o.radius_rule == MPWOS_RADIUS_CURVATURE_BOUND;
-  if (cloud_bound) {
+  if (cloud_bound || d.kind == MPWOS_DUMBBELL) {
     rmax = o.theta * o.c_kappa / (1.0 + o.kappa_bound);
   } else if (d.kind == MPWOS_POINT_CLOUD) {
     rmax = o.radius_rule == MPWOS_RADIUS_SPACING ? cloud_spacing_rmax(man->cloud, o) : o.theta * o.c_kappa;
@@ -570,7 +638,8 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
     return fail(MPWOS_EINVAL, "sqrt(sigma) r_max = " + std::to_string(std::sqrt(x2max)) +
                                   " is beyond the range of the series radial law for this n");
   fill_law(h, js, jd, a.law);
-  a.const_r = (d.kind == MPWOS_SPHERE || d.kind == MPWOS_TORUS_IMPLICIT || cloud_bound) ? 1 : 0;
+  a.const_r = (d.kind == MPWOS_SPHERE || d.kind == MPWOS_TORUS_IMPLICIT || d.kind == MPWOS_DUMBBELL || cloud_bound)
+                  ? 1 : 0;
   if (a.const_r) {
     a.r0 = rmax;
     host_weights(d.n, sigma, a.r0, a.c0, a.om0);
@@ -690,9 +759,9 @@ extern "C" mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_
         return fail(MPWOS_EOFFMANIFOLD, "query " + std::to_string(q) + " is not on the manifold");
   }
 
-  // TABLE_S1 values to the device
+  // TABLE_S1 / DUMBBELL_POLY values to the device
   DevBuf& tmp = g_ctx.tmp;
-  if (f->kind == MPWOS_FN_TABLE_S1) {
+  if (fn_has_values(f->kind)) {
     st = ensure(tmp, (size_t)f->n_values * sizeof(double));
     if (st) return st;
     HIP_TRY(hipMemcpyAsync(tmp.p, f->values, (size_t)f->n_values * sizeof(double), hipMemcpyHostToDevice, s));
@@ -803,7 +872,7 @@ extern "C" mpwos_status mpwos_debug_cp(const mpwos_manifold* m, const double* x,
   double* dx = (double*)g_ctx.tmp.p;
   double* dy = dx + (size_t)n_points * a.n;
   HIP_TRY(hipMemcpyAsync(dx, x, bytes, hipMemcpyHostToDevice, s));
-  hipError_t e = launch_cp_points(a, dx, dy, n_points, s);
+  hipError_t e = a.n >= 4 ? launch_cp_group(a, dx, dy, n_points, s) : launch_cp_points(a, dx, dy, n_points, s);
   if (e != hipSuccess) return hip_fail(e, "cp kernel");
   HIP_TRY(hipMemcpyAsync(y, dy, bytes, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));

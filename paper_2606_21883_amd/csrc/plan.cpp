@@ -86,7 +86,7 @@ extern "C" mpwos_status mpwos_plan_create(const mpwos_manifold* manifold, const 
   p->nw = n_walks;
   p->n = manifold_desc(manifold).n;
   const int64_t total = n_queries * n_walks;
-  const bool table = f->kind == MPWOS_FN_TABLE_S1;
+  const bool table = fn_has_values(f->kind);
   size_t bytes = align256((size_t)n_queries * p->n * sizeof(double)) + align256((size_t)total * sizeof(double)) +
                  align256((size_t)total * sizeof(int32_t)) + 2 * align256((size_t)n_queries * sizeof(double)) +
                  align256(8 * sizeof(unsigned long long)) +
@@ -208,12 +208,20 @@ extern "C" mpwos_status mpwos_autotune(const mpwos_manifold* manifold, const mpw
   const double k_est = probe.const_r ? std::ceil(std::log(base.tau_w) / std::log(probe.c0)) : 32.0;
   const double cost = philox_blocks_per_step(n, base.n_v);
   // Up to 2^24 walks (the whole solve at the headline sizes): the launch
-  // forms differ in how they absorb uneven walk lengths, which a small
-  // sample's tail hides.
-  const int64_t want_walks = n <= 3 ? ((int64_t)1 << 24) : (int64_t)device_cu_count() * 16;
+  // forms differ in how they absorb uneven walk lengths and in how they fill
+  // the device, which a small sample hides.  With a constant radius every
+  // walk has the same length, so the trials keep the walks and cut their
+  // length instead (max_steps) when the work would exceed the trial budget.
   const int64_t budget = (int64_t)1e10;  // Philox blocks of work per trial
-  int64_t sample = std::min<int64_t>(want_walks, std::max<int64_t>(64, (int64_t)(budget / (k_est * cost))));
-  sample = std::min<int64_t>(sample, n_queries * n_walks);
+  const int64_t want_walks = (int64_t)1 << 24;
+  const int64_t caller_max_steps = base.max_steps;
+  int64_t sample = std::min<int64_t>(want_walks, n_queries * n_walks);
+  if (probe.const_r) {
+    const double steps = std::floor((double)budget / ((double)sample * cost));
+    if (steps < k_est) base.max_steps = (int64_t)std::max(16.0, steps);
+  } else {
+    sample = std::min<int64_t>(sample, std::max<int64_t>(64, (int64_t)(budget / (k_est * cost))));
+  }
   const int64_t sw = std::min<int64_t>(n_walks, sample);
   const int64_t sq = std::max<int64_t>(1, std::min<int64_t>(n_queries, sample / sw));
   std::vector<mpwos_options> cand;
@@ -254,6 +262,7 @@ extern "C" mpwos_status mpwos_autotune(const mpwos_manifold* manifold, const mpw
   }
   if (best_i < 0) return fail(MPWOS_EINVAL, "autotune: no launch shape ran");
   *best = cand[(size_t)best_i];
+  best->max_steps = caller_max_steps;
   if (opt) {
     best->stream = opt->stream;
     best->device_io = opt->device_io;

@@ -48,7 +48,7 @@ constexpr int kMaxBatch = 512;             // requests per launch
 struct SrvReq {
   uint64_t ticket = 0;
   mpwos_request r;
-  std::vector<double> table;   // TABLE_S1 values (host copy)
+  std::vector<double> table;   // TABLE_S1 / DUMBBELL_POLY values (host copy)
   WalkArgs args;
   mpwos_options opt;
   int64_t total = 0;           // n_queries * n_walks
@@ -183,7 +183,7 @@ static size_t request_bytes(const mpwos_request& r, int n) {
   b += align256((size_t)r.n_queries * r.n_walks * sizeof(int32_t));
   b += 2 * align256((size_t)r.n_queries * sizeof(double));
   b += align256(8 * sizeof(unsigned long long));
-  if (r.f.kind == MPWOS_FN_TABLE_S1) b += align256((size_t)r.f.n_values * sizeof(double));
+  if (fn_has_values(r.f.kind)) b += align256((size_t)r.f.n_values * sizeof(double));
   return b;
 }
 
@@ -695,7 +695,7 @@ mpwos_status mpwos_submit(mpwos_server* s, const mpwos_request* req, uint64_t* t
   R->opt.walk_S = nullptr;
   R->opt.walk_K = nullptr;
   const mpwos_fn* g = req->has_g ? &R->r.g : nullptr;
-  if (req->f.kind == MPWOS_FN_TABLE_S1 && req->f.values && req->f.n_values > 0)
+  if (fn_has_values(req->f.kind) && req->f.values && req->f.n_values > 0)
     R->table.assign(req->f.values, req->f.values + req->f.n_values);
   mpwos_status st = prepare_solve(req->manifold, &R->r.f, g, req->c, req->n_queries, req->n_walks, req->eps,
                                   req->seed, R->opt, R->args);

@@ -23,6 +23,7 @@ __device__ __forceinline__ T group_sum(T v) {
 template <class T, int L, int MB>
 struct GroupWalk {
   T Y[4 * MB];
+  T A[4 * MB];         // dumbbell source: this lane's entries of the diagonal
   double W, S, C;
   uint32_t k, q, w;
   int64_t idx;
@@ -66,6 +67,178 @@ __device__ __forceinline__ void group_normals(const WalkArgs& a, const Stream& r
   }
 }
 
+// ---- implicit dumbbell (Sec. 4, Example 2) ---------------------------------
+// M = {|x_h| = R(x_n)}, x_h the first n-1 coordinates; with x_n = kc cos(phi)
+// the profile is (r, z)(phi) = (sin(phi) g, kc cos(phi)), g = 1 - a + 2a
+// cos^2(phi), smooth up to the poles.
+__device__ __forceinline__ void sincos_(double x, double& s, double& c) { sincos(x, &s, &c); }
+__device__ __forceinline__ void sincos_(float x, float& s, float& c) {
+  // v_sin_f32 / v_cos_f32 take turns
+  const float t = x * 0.15915494309189535f;
+  s = __builtin_amdgcn_sinf(t);
+  c = __builtin_amdgcn_cosf(t);
+}
+
+template <class T>
+struct DbProfile {
+  T r, r1, r2, z, z1, z2, g;
+};
+
+template <class T>
+__device__ __forceinline__ DbProfile<T> db_profile(T a, T kc, T phi) {
+  T s, c;
+  sincos_(phi, s, c);
+  DbProfile<T> p;
+  const T g = (T)1 - a + (T)2 * a * c * c;
+  const T g1 = (T)-4 * a * c * s;
+  const T g2 = (T)-4 * a * (c * c - s * s);
+  p.g = g;
+  p.r = s * g;
+  p.r1 = c * g + s * g1;
+  p.r2 = -s * g + (T)2 * c * g1 + s * g2;
+  p.z = kc * c;
+  p.z1 = -kc * s;
+  p.z2 = -kc * c;
+  return p;
+}
+
+// Profile parameter of the point of M nearest to (|x_h|, x_n) = (rho, zs):
+// the best of a 128-point grid over [0, pi] (the group's lanes share the
+// grid; ties go to the lower index), then Newton on D'(phi) = 0 with D the
+// squared planar distance, kept by bisection inside the neighbouring cells.
+// Every lane of the group returns the same value.
+template <class T, int L>
+__device__ __forceinline__ T db_phi(T a, T kc, T rho, T zs, int gl) {
+  constexpr int G = 128;
+  const T pi = (T)3.141592653589793;
+  const T h = pi / (T)(G - 1);
+  float bd = 3.0e38f;
+  int bj = G;
+  for (int j = gl; j < G; j += L) {
+    // the scan only places the basin: FP32 is enough
+    float s, c;
+    sincos_((float)j * (float)h, s, c);
+    const float r = s * ((float)1 - (float)a + (float)2 * (float)a * c * c);
+    const float d = ((float)rho - r) * ((float)rho - r) + ((float)zs - (float)kc * c) * ((float)zs - (float)kc * c);
+    if (d < bd) {
+      bd = d;
+      bj = j;
+    }
+  }
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) {
+    const float od = __shfl_xor(bd, o, L);
+    const int oj = __shfl_xor(bj, o, L);
+    if (od < bd || (od == bd && oj < bj)) {
+      bd = od;
+      bj = oj;
+    }
+  }
+  T lo = bj > 0 ? (T)(bj - 1) * h : (T)0;
+  T hi = bj < G - 1 ? (T)(bj + 1) * h : pi;
+  T phi = (T)bj * h;
+  const T tol = sizeof(T) == 8 ? (T)1e-16 : (T)1e-7;
+  for (int it = 0; it < 64; ++it) {
+    const DbProfile<T> p = db_profile<T>(a, kc, phi);
+    const T d1 = (T)-2 * ((rho - p.r) * p.r1 + (zs - p.z) * p.z1);
+    const T d2 = (T)2 * (p.r1 * p.r1 + p.z1 * p.z1) - (T)2 * ((rho - p.r) * p.r2 + (zs - p.z) * p.z2);
+    if (d1 > (T)0) hi = phi;
+    else lo = phi;
+    T nx = d2 > (T)0 ? phi - d1 / d2 : lo - (T)1;
+    if (!(nx >= lo && nx <= hi)) nx = (T)0.5 * (lo + hi);
+    const T step = abs_(nx - phi);
+    phi = nx;
+    if (step <= tol * ((T)1 + phi) || hi - lo <= tol * ((T)1 + phi)) break;
+  }
+  return phi;
+}
+
+// Group sums over the first n-1 coordinates (x_h) and the last one (x_n).
+template <class T, int L, int MB>
+__device__ __forceinline__ void db_split(const WalkArgs& a, const T* x, int gl, T& hh, T& zs) {
+  T s = (T)0, z = (T)0;
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = 4 * (gl + L * m) + j;
+      const T v = x[4 * m + j];
+      if (i == a.n - 1) z = v;
+      else s += v * v;
+    }
+  hh = group_sum<L>(s);
+  zs = group_sum<L>(z);
+}
+
+// cp onto the dumbbell, in place on the group's coordinates.
+template <class T, int L, int MB>
+__device__ __forceinline__ void db_project(const WalkArgs& a, T* x, int gl) {
+  T hh, zs;
+  db_split<T, L, MB>(a, x, gl, hh, zs);
+  const T rho = sqrt_(hh);
+  const T phi = db_phi<T, L>((T)a.p[0], (T)a.p[1], rho, zs, gl);
+  const DbProfile<T> p = db_profile<T>((T)a.p[0], (T)a.p[1], phi);
+  const T sc = rho > (T)0 ? over_(p.r, rho) : (T)0;
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = 4 * (gl + L * m) + j;
+      x[4 * m + j] = (i == a.n - 1) ? p.z : x[4 * m + j] * sc;
+    }
+}
+
+// f_Omega(cp z) for the dumbbell polynomial family
+//   u = c0 x_n + c1 x_n^2 + c2 (1.x_h)/sqrt(n-1) + c3 x_h^T diag(A) x_h,
+// -Lap_M u + sigma u by the extrinsic formula Lap_M U = Lap U - nu^T Hess U nu
+// - H dU/dnu (H = k1 + (n-2) k2, outward normal nu = (N_r e, N_z)).  Only the
+// sums over z's coordinates are needed, not the projected point itself.
+template <class T, int L, int MB>
+__device__ __forceinline__ T db_source(const WalkArgs& a, const T* z, const T* A, int gl) {
+  const FnDev& f = a.f;
+  if (f.kind == kFnConst) return (T)f.coef[0];
+  if (f.kind != kFnDumbbell) return (T)0;
+  T s1 = (T)0, sa = (T)0, s2 = (T)0, zl = (T)0;
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = 4 * (gl + L * m) + j;
+      const T v = z[4 * m + j];
+      if (i == a.n - 1) {
+        zl = v;
+      } else {
+        s1 += v;
+        s2 += v * v;
+        sa += A[4 * m + j] * v * v;
+      }
+    }
+  s1 = group_sum<L>(s1);
+  s2 = group_sum<L>(s2);
+  sa = group_sum<L>(sa);
+  zl = group_sum<L>(zl);
+  const T rho = sqrt_(s2);
+  const T phi = db_phi<T, L>((T)a.p[0], (T)a.p[1], rho, zl, gl);
+  // the scalar tail in FP64 in both precisions
+  const double kc = a.p[1];
+  const DbProfile<double> p = db_profile<double>(a.p[0], kc, (double)phi);
+  const double Lp = sqrt(p.r1 * p.r1 + p.z1 * p.z1);
+  const double Nr = -p.z1 / Lp, Nz = p.r1 / Lp;
+  const double k1 = (p.z1 * p.r2 - p.r1 * p.z2) / (Lp * Lp * Lp);
+  const double k2 = kc / (p.g * Lp);
+  const double ir = rho > (T)0 ? 1.0 / (double)rho : 0.0;
+  const double e1 = (double)s1 * ir, ea = (double)sa * ir * ir;
+  const double isq = 1.0 / sqrt((double)(a.n - 1));
+  const double* c = f.coef;
+  const double zz = p.z, rr = p.r;
+  const double U = c[0] * zz + c[1] * zz * zz + c[2] * rr * e1 * isq + c[3] * rr * rr * ea;
+  const double lapU = 2.0 * c[1] + 2.0 * c[3] * f.lam;
+  const double hess = 2.0 * c[1] * Nz * Nz + 2.0 * c[3] * Nr * Nr * ea;
+  const double dnu = Nz * (c[0] + 2.0 * c[1] * zz) + Nr * (c[2] * e1 * isq + 2.0 * c[3] * rr * ea);
+  const double H = k1 + (double)(a.n - 2) * k2;
+  return (T)(-(lapU - hess - H * dnu) + a.sigma * U);
+}
+
 template <class T, int L, int MB>
 __device__ __forceinline__ T coord_of(const T* v, int i, int gl) {
   // value of coordinate i, broadcast from its owner lane
@@ -86,7 +259,8 @@ __device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB
   const T rT = (T)r;
   const T R = (T)a.p[0];
   uint32_t dummy = 0;
-  // sphere sample and projection: Theta = Y + r g/|g|, Y' = R Theta/|Theta|
+  // sphere sample and projection: Theta = Y + r g/|g|, Y' = cp(Theta) (the
+  // sphere: R Theta/|Theta|; the dumbbell: Newton in the profile parameter)
   T Yn[4 * MB];
   {
     T g[4 * MB];
@@ -102,10 +276,14 @@ __device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB
       Yn[i] = st.Y[i] + rT * (g[i] * ig);
       tt += Yn[i] * Yn[i];
     }
-    tt = group_sum<L>(tt);
-    const T f = R * rsqrt_(tt);
+    if (a.kind == kDumbbell) {
+      db_project<T, L, MB>(a, Yn, gl);
+    } else {
+      tt = group_sum<L>(tt);
+      const T f = R * rsqrt_(tt);
 #pragma unroll
-    for (int i = 0; i < 4 * MB; ++i) Yn[i] *= f;
+      for (int i = 0; i < 4 * MB; ++i) Yn[i] *= f;
+    }
   }
   // Green samples
   T Fsum = (T)0;
@@ -130,10 +308,12 @@ __device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB
       Z[i] = st.Y[i] + t * (g[i] * ig);
       zz += Z[i] * Z[i];
     }
-    zz = group_sum<L>(zz);
     const FnDev& f = a.f;
     T v;
-    if (f.kind == kFnSphPair) {
+    if (a.kind == kDumbbell) {
+      v = db_source<T, L, MB>(a, Z, st.A, gl);
+    } else if (f.kind == kFnSphPair) {
+      zz = group_sum<L>(zz);
       const T zi = coord_of<T, L, MB>(Z, f.idx[0], gl);
       const T zj = coord_of<T, L, MB>(Z, f.idx[1], gl);
       // cp(Z) = R Z/|Z|; f_Omega(cp Z) = coef (Z_i/|Z|)(Z_j/|Z|)
@@ -155,6 +335,19 @@ __device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB
   st.k += 1;
   if (!(st.W >= a.tau_w)) return true;  // NaN ends the walk too
   return (int64_t)st.k >= a.max_steps;
+}
+
+// This lane's entries of the dumbbell source's diagonal (zero elsewhere).
+template <class T, int L, int MB>
+__device__ __forceinline__ void group_coefs(const WalkArgs& a, GroupWalk<T, L, MB>& st, int gl) {
+  const bool db = a.kind == kDumbbell && a.f.kind == kFnDumbbell;
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = 4 * (gl + L * m) + j;
+      st.A[4 * m + j] = (db && i < a.n - 1) ? (T)a.f.values[i] : (T)0;
+    }
 }
 
 template <class T, int L, int MB>
@@ -270,6 +463,7 @@ __global__ __launch_bounds__(256) void walk_group_kernel(WalkArgs a) {
     } else {
       group_init<T, L, MB>(a, queries, nw, q_offset, widx, st, gl);
     }
+    group_coefs<T, L, MB>(a, st, gl);
     bool done = false;
     if (rec) {
       for (int32_t j = 0; j < a.step_budget && !done; ++j) done = group_step<T, L, MB>(a, st, gl, seed);
@@ -289,6 +483,47 @@ __global__ __launch_bounds__(256) void walk_group_kernel(WalkArgs a) {
       if (gl == 0) atomicAdd(pending, 1ull);
     }
   }
+}
+
+// cp of m points (n >= 4), one lane group per point (inspection).
+template <class T, int L, int MB>
+__global__ __launch_bounds__(256) void cp_group_kernel(WalkArgs a, const double* x, double* y, int64_t m) {
+  const int gl = threadIdx.x % L;
+  const int64_t pt = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / L;
+  if (pt >= m) return;
+  T v[4 * MB];
+#pragma unroll
+  for (int k = 0; k < MB; ++k)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = 4 * (gl + L * k) + j;
+      v[4 * k + j] = i < a.n ? (T)x[pt * a.n + i] : (T)0;
+    }
+  if (a.kind == kDumbbell) {
+    db_project<T, L, MB>(a, v, gl);
+  } else {
+    T s = (T)0;
+#pragma unroll
+    for (int i = 0; i < 4 * MB; ++i) s += v[i] * v[i];
+    s = group_sum<L>(s);
+    const T f = (T)a.p[0] * rsqrt_(s);
+#pragma unroll
+    for (int i = 0; i < 4 * MB; ++i) v[i] *= f;
+  }
+#pragma unroll
+  for (int k = 0; k < MB; ++k)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = 4 * (gl + L * k) + j;
+      if (i < a.n) y[pt * a.n + i] = (double)v[4 * k + j];
+    }
+}
+
+template <class T, int L, int MB>
+static hipError_t launch_cp_group_t(const WalkArgs& a, const double* x, double* y, int64_t m, hipStream_t s) {
+  const int64_t grid = (m * L + 255) / 256;
+  hipLaunchKernelGGL((cp_group_kernel<T, L, MB>), dim3((unsigned)grid), dim3(256), 0, s, a, x, y, m);
+  return hipGetLastError();
 }
 
 template <class T, int L, int MB>
@@ -327,6 +562,17 @@ static hipError_t group_launch(bool fp64, int L, int mb, const WalkArgs& a, int6
     MPWOS_GROUP_L(double, launch_group_t, a, grid, block, s)
   } else {
     MPWOS_GROUP_L(float, launch_group_t, a, grid, block, s)
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_cp_group(const WalkArgs& a, const double* x, double* y, int64_t m, hipStream_t s) {
+  int L, mb, nblk, rblk, rword;
+  group_shape(a.n, 0, L, mb, nblk, rblk, rword);
+  if (a.precision == 0) {
+    MPWOS_GROUP_L(double, launch_cp_group_t, a, x, y, m, s)
+  } else {
+    MPWOS_GROUP_L(float, launch_cp_group_t, a, x, y, m, s)
   }
   return hipErrorInvalidValue;
 }
@@ -378,9 +624,12 @@ int64_t group_record_bytes(int n, int lanes_req, bool fp64) {
 
 mpwos_status launch_group_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue) {
   (void)queue;
-  if (a.kind != kSphere) return fail(MPWOS_EINVAL, "n >= 4 is supported on the closed sphere only");
-  if (a.f.kind != kFnSphPair && a.f.kind != kFnConst && a.f.kind != kFnZero)
-    return fail(MPWOS_EINVAL, "n >= 4 supports the ZERO, CONST and SPH_PAIR sources");
+  if (a.kind != kSphere && a.kind != kDumbbell)
+    return fail(MPWOS_EINVAL, "n >= 4 is supported on the closed sphere and the dumbbell");
+  if (a.kind == kSphere && a.f.kind != kFnSphPair && a.f.kind != kFnConst && a.f.kind != kFnZero)
+    return fail(MPWOS_EINVAL, "n >= 4 spheres support the ZERO, CONST and SPH_PAIR sources");
+  if (a.kind == kDumbbell && a.f.kind != kFnDumbbell && a.f.kind != kFnConst && a.f.kind != kFnZero)
+    return fail(MPWOS_EINVAL, "the dumbbell supports the ZERO, CONST and DUMBBELL_POLY sources");
   int L, mb, nblk, rblk, rword;
   group_shape(a.n, o.lanes_per_walk, L, mb, nblk, rblk, rword);
   if (L < 4) return fail(MPWOS_EINVAL, "lanes_per_walk must be >= 4 for n >= 4");

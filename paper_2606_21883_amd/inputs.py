@@ -307,6 +307,10 @@ def config(name, scale=1.0, seed=1):
         pts = torus_point_cloud(1_000_000, 1.0, 0.3, 1e-4, seed)
         prob = point_cloud_problem(pts, radius_rule="curvature_bound", kappa_bound=1.0 / 0.3)
         return prob, torus_area_uniform(sz(8192), 1.0, 0.3, seed + 7), sz(1024)
+    if name == "dumbbell":
+        # Table 1's setting: 20 points of the 1000-dimensional dumbbell, N = 1000
+        # paths each, N_V = 50 Green samples per step, tau_W = 1e-8
+        return dumbbell_problem(1001, n_v=50), dumbbell_points(sz(20), 1001, seed=seed), sz(1000)
     raise ValueError(name)
 
 

@@ -58,10 +58,11 @@ def test_oracle_philox_matches_rocrand():
             assert np.array_equal(got[j], ref), (seed, j, got[j], ref)
 
 
-@pytest.mark.parametrize("n", [2, 3, 10, 100, 1000])
+@pytest.mark.parametrize("n", [2, 3, 10, 100, 1000, 11, 1001])
 def test_device_radial_inverse_matches_oracle(n):
     announce(f"radial inverse n={n}")
-    X = {2: 0.57, 3: 0.806, 10: 0.57, 100: 0.57, 1000: 0.57}[n]
+    # n = 11, 1001: the dumbbell's X = sqrt(2(n-1)) r with r = 0.95 * 1.2 / (1 + 2.9294)
+    X = {2: 0.57, 3: 0.806, 10: 0.57, 100: 0.57, 1000: 0.57, 11: 1.2975, 1001: 12.975}[n]
     rng = np.random.default_rng(n)
     u = np.concatenate([rng.uniform(size=200), [1e-9, 1e-6, 0.5, 1 - 1e-6, 1 - 2 ** -32]])
     s64 = mpwos.debug_radial_inv(n, X, u, "fp64")
