@@ -14,7 +14,8 @@ Problems are plain dicts (the same dict a test also hands to the GPU binding):
      "tau_w": 1e-8, "n_v": 1, "compensation": "exact" | "none",
      "max_steps": int, "points": ndarray (point cloud), "k_nn": 16,
      "radius_rule": "curvature" | "spacing" | "curvature_fit" | "curvature_bound", "c_h": 2.4,
-     "kappa_bound": float (curvature_bound only)}
+     "kappa_bound": float (curvature_bound only),
+     "reconstruction": "patch" | "nearest" (point cloud)}
 """
 import ctypes
 import os
@@ -44,7 +45,7 @@ class _Problem(ctypes.Structure):
         ("c_kappa", ctypes.c_double), ("c_h", ctypes.c_double), ("tau_w", ctypes.c_double),
         ("n_v", ctypes.c_int32), ("compensation", ctypes.c_int32), ("max_steps", ctypes.c_int64),
         ("k_spacing", ctypes.c_int32), ("newton_iters", ctypes.c_int32),
-        ("kappa_bound", ctypes.c_double),
+        ("kappa_bound", ctypes.c_double), ("reconstruction", ctypes.c_int32),
     ]
 
 
@@ -141,6 +142,7 @@ class Problem:
         s.k_spacing = int(d.get("k_spacing", d.get("k_nn", 16)))
         s.newton_iters = int(d.get("newton_iters", 6))
         s.kappa_bound = float(d.get("kappa_bound", 0.0))
+        s.reconstruction = {"patch": 0, "nearest": 1}[d.get("reconstruction", "patch")]
         self.s = s
 
     @property

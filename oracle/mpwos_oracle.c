@@ -61,6 +61,7 @@ typedef struct {
   int32_t k_spacing;     /* neighbours for the spacing rule h(y) */
   int32_t newton_iters;  /* foot-point Newton iterations on the fitted patch */
   double kappa_bound;    /* point cloud, CURVATURE_BOUND rule: a bound of kappa over M */
+  int32_t reconstruction; /* point cloud: 0 = quadratic patch, 1 = the nearest cloud point */
 } orc_problem;
 
 /* ------------------------------------------------------------------------- */
@@ -476,6 +477,12 @@ int orc_pc_project(const orc_problem* P, const double* x, orc_pc_result* res) {
   double hsum = 0.0;
   for (int j = 1; j < k; ++j) hsum += sqrt(d2[j]);
   res->h_mean = hsum / (double)(k - 1);
+  if (P->reconstruction == 1) {
+    /* the pure nearest-neighbour projection (Sec. 4, Example 4) */
+    for (int c = 0; c < 3; ++c) res->y[c] = pn[c];
+    res->kappa = 0.0;
+    return ORC_OK;
+  }
   double cen[3] = {0, 0, 0};
   for (int j = 0; j < k; ++j)
     for (int c = 0; c < 3; ++c) cen[c] += P->points[3 * idx[j] + c];
@@ -1125,6 +1132,10 @@ static int orc_check(const orc_problem* P) {
   }
   if ((P->manifold == ORC_TORUS || P->manifold == ORC_POINT_CLOUD) && P->n != 3) return ORC_EINVAL;
   if (P->manifold == ORC_POINT_CLOUD && (P->k_nn < 6 || P->k_nn > ORC_MAXK || P->n_points < P->k_nn))
+    return ORC_EINVAL;
+  /* the nearest point carries no curvature: its radius comes from the spacing or a bound */
+  if (P->manifold == ORC_POINT_CLOUD && P->reconstruction == 1 && P->radius_rule != ORC_RADIUS_SPACING &&
+      P->radius_rule != ORC_RADIUS_CURVATURE_BOUND)
     return ORC_EINVAL;
   if (P->radius_rule == ORC_RADIUS_CURVATURE_BOUND &&
       ((P->manifold != ORC_POINT_CLOUD && P->manifold != ORC_DUMBBELL) || !(P->kappa_bound >= 0.0) ||

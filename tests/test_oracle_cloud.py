@@ -168,3 +168,46 @@ def test_foot_point_stays_on_its_patch_for_far_points(orc):
     err = np.array([np.linalg.norm(orc.cp(P, xi) - orc.cp(T, xi)) for xi in x])
     assert np.all(np.isfinite(err))
     assert err.max() < 0.03, err.max()
+
+
+# -- the pure nearest-neighbour projection of Example 4 -----------------------
+
+
+def test_nearest_point_projection_and_spacing(orc):
+    """cp is the nearest cloud point (cKDTree), and rho_geo = c_h h with h the
+    mean distance to the 6 nearest other points."""
+    pts = inputs.sphere_point_cloud(2000, seed=11)
+    prob = inputs.sphere_cloud_problem(pts)
+    P = orc.Problem(prob)
+    tree = cKDTree(pts)
+    rng = np.random.default_rng(12)
+    x = inputs.sphere_uniform(200, 3, seed=13) * rng.uniform(0.9, 1.1, (200, 1))
+    for xi in x:
+        _, i = tree.query(xi)
+        assert np.array_equal(orc.cp(P, xi), pts[i])
+    for i in rng.choice(len(pts), 30, replace=False):
+        d, _ = tree.query(pts[i], k=7)
+        h = d[1:].mean()
+        assert orc.radius(P, pts[i]) == pytest.approx(0.95 * 2.4 * h, rel=1e-13)
+
+
+def test_nearest_point_rejects_curvature_rules(orc):
+    pts = inputs.sphere_point_cloud(500, seed=11)
+    Q = inputs.sphere_uniform(2, 3, seed=2)
+    with pytest.raises(ValueError):
+        orc.solve(dict(inputs.sphere_cloud_problem(pts), radius_rule="curvature_fit"), Q, 2, seed=1)
+
+
+def test_sphere_cloud_estimator_near_closed_form(orc):
+    """Example 4's setting on 2000 points (tau_W = 1e-3 to keep it short): the
+    estimate at each query is within Monte Carlo error plus the O(h^2) error
+    of the nearest-point source and the truncation bias of the closed form."""
+    pts = inputs.sphere_point_cloud(2000, seed=14)
+    prob = dict(inputs.sphere_cloud_problem(pts), tau_w=1e-3)
+    Q = inputs.sphere_uniform(8, 3, seed=15)
+    res = orc.solve(prob, Q, 96, seed=3)
+    P = orc.Problem(prob)
+    y = np.array([orc.cp(P, q) for q in Q])
+    u = inputs.exact_u(prob, y)
+    err = np.abs(res["u"] - u)
+    assert np.all(err < 4 * res["stderr"] + 0.05), (err, res["stderr"])
