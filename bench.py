@@ -236,7 +236,7 @@ def cpu_baseline(work):
     (about 10-20 s of CPU work)."""
     import oracle
     threads = min(16, os.cpu_count() or 1)
-    sample = {"sphere": (64, 4096), "cap": (64, 4096), "dumbbell": (1, 32)}
+    sample = {"sphere": (64, 4096), "cap": (64, 4096), "dumbbell": (1, 32), "sphere_cloud": (2, 8)}
     total_steps, total_t, parts = 0, 0.0, []
     for name, prob, Q, nw in work:
         nq, nws = sample.get(name, (8, 256))
@@ -455,7 +455,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="sphere",
-                    choices=["sphere", "circle", "torus", "cloud", "hyper100", "hyper1000", "dumbbell"],
+                    choices=["sphere", "circle", "torus", "cloud", "hyper100", "hyper1000", "dumbbell",
+                             "sphere_cloud"],
                     help="sphere (closed + cap) is the headline workload; the others are for profiling")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink queries and walks (profiling only)")
     ap.add_argument("--block-size", type=int, default=0, help="workgroup size of the walk kernels (0 = autotuned)")
@@ -520,6 +521,8 @@ def main():
         "hyper1000": "S^999 in R^1000: u=x1x2, sigma=1, 1024 queries x 2048 walks",
         "dumbbell": "1000-dimensional implicit dumbbell in R^1001 (a=0.35, kc=1.2), sigma=2000, m=0, "
                     "N_V=50, 20 points x 1000 paths",
+        "sphere_cloud": "point-cloud S^2, 8000 points, nearest-point projection, spacing rule (6 neighbours, "
+                        "c_h=2.4), u=P1+0.2P3+0.1P5, sigma=1, m=0: 1024 queries x 1024 walks",
     }[args.workload]
     if args.scale != 1.0:
         desc += f" (scaled by {args.scale})"

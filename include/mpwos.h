@@ -75,7 +75,7 @@ typedef enum {
   MPWOS_FN_SPH_PAIR = 2,     /* S^{n-1}_R: coef[0] (y_i/R)(y_j/R), i = idx[0] != j = idx[1];
                                 eigenvalue 2n/R^2, so u = f/(2n/R^2 + sigma) */
   MPWOS_FN_CIRCLE_MODE = 3,  /* S^1_R: coef[0] cos(k th) + coef[1] sin(k th), k = idx[0] */
-  MPWOS_FN_LEGENDRE = 4,     /* S^2_R: sum_{l<8} coef[l] P_l(y_3/R) */
+  MPWOS_FN_LEGENDRE = 4,     /* S^2_R, or a point cloud of it (R = p[0]): sum_{l<8} coef[l] P_l(y_3/R) */
   MPWOS_FN_TORUS_MODE = 5,   /* torus / point-cloud torus (R = p[0], a = p[1]):
                                 u = coef[0] sin(phi) cos(2 psi), f = -Lap_T u + sigma u;
                                 as g: g = u */
@@ -108,6 +108,10 @@ typedef struct {
   int64_t n_points;         /* POINT_CLOUD: k_nn .. 2^27 */
   int32_t k_nn;             /* POINT_CLOUD: neighbours of the local fit, 6..32 (default 16) */
   int32_t points_on_device; /* 1: `points` is a device pointer */
+  int32_t reconstruction;   /* POINT_CLOUD: 0 = local quadratic patch of the k_nn points (default);
+                               1 = the nearest cloud point itself (the pure nearest-neighbour
+                               projection of Sec. 4, Example 4), with rho_geo from the spacing or a
+                               curvature bound */
 } mpwos_manifold_desc;
 
 typedef struct {

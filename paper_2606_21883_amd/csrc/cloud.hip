@@ -41,6 +41,8 @@ struct CloudState {
   int32_t root = 0;
   double hmean_max = 0.0;
   int64_t fallback_points = 0;
+  int32_t nn_only = 0;
+  float4* pts = nullptr;       // nn_only: the points by original index (kept from the build)
 };
 
 struct GridArgs {
@@ -602,6 +604,12 @@ mpwos_status cloud_create(const mpwos_manifold_desc& d, hipStream_t s, CloudStat
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  // the nearest-point projection reads the points by original index
+  if (d.reconstruction == 1) {
+    C->nn_only = 1;
+    C->pts = d_orig;
+    d_orig = nullptr;
+  }
   for (void* p : {(void*)d_sorted, (void*)d_orig, (void*)d_cstart, (void*)d_tiles, (void*)d_knn, (void*)d_flag,
                   (void*)d_redo})
     if (p) (void)hipFree(p);
@@ -621,7 +629,7 @@ mpwos_status cloud_create(const mpwos_manifold_desc& d, hipStream_t s, CloudStat
 
 void cloud_destroy(CloudState* c) {
   if (!c) return;
-  for (void* p : {(void*)c->nodes, (void*)c->kd_pts, (void*)c->patch64, (void*)c->patch32})
+  for (void* p : {(void*)c->nodes, (void*)c->kd_pts, (void*)c->patch64, (void*)c->patch32, (void*)c->pts})
     if (p) (void)hipFree(p);
   delete c;
 }
@@ -639,7 +647,11 @@ void cloud_fill_args(const CloudState* c, const mpwos_options& o, WalkArgs& a) {
   a.cloud.k = c->k;
   a.cloud.newton_iters = o.newton_iters;
   a.cloud.radius_rule = o.radius_rule == MPWOS_RADIUS_SPACING ? 1 : 0;
+  a.cloud.nn_only = c->nn_only;
+  a.cloud.pts = c->pts;
 }
+
+int cloud_nn_only(const CloudState* c) { return c->nn_only; }
 
 int64_t cloud_fallback_points(const CloudState* c) { return c->fallback_points; }
 double cloud_max_spacing(const CloudState* c) { return c->hmean_max; }

@@ -188,6 +188,17 @@ __device__ __forceinline__ const Patch<float>& patch_of<float>(const CloudDev& c
 template <class T>
 __device__ __forceinline__ CloudProj<T> cloud_cp(const CloudDev& c, const T* x) {
   const int32_t nn = kd_nearest<T>(c, x);
+  if (c.nn_only) {
+    // the nearest cloud point itself; its patch supplies only the spacing
+    const float4 p = c.pts[nn];
+    CloudProj<T> r;
+    r.y[0] = (T)p.x;
+    r.y[1] = (T)p.y;
+    r.y[2] = (T)p.z;
+    r.kappa = (T)0;
+    r.hmean = patch_of<T>(c, nn).hmean;
+    return r;
+  }
   const Patch<T> P = patch_of<T>(c, nn);
   return patch_project<T>(P, x, c.newton_iters);
 }

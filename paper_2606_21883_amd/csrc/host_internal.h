@@ -60,5 +60,6 @@ double cloud_spacing_rmax(const CloudState* c, const mpwos_options& o);
 void cloud_fill_args(const CloudState* c, const mpwos_options& o, WalkArgs& a);
 int64_t cloud_fallback_points(const CloudState* c);
 double cloud_max_spacing(const CloudState* c);
+int cloud_nn_only(const CloudState* c);
 
 }  // namespace mpwos

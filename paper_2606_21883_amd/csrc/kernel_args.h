@@ -97,6 +97,8 @@ struct CloudDev {
   int32_t k;                   // neighbours of the reconstruction
   int32_t newton_iters;
   int32_t radius_rule;         // 1 = spacing, otherwise curvature of the fitted patch
+  int32_t nn_only;             // 1: cp is the nearest cloud point itself (no patch)
+  const float4* pts;           // nn_only: the points by original index
 };
 
 // One request of a batched launch (serving).  Launch walks [begin, begin +

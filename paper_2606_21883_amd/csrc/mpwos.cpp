@@ -344,6 +344,8 @@ static mpwos_status check_manifold_desc(const mpwos_manifold_desc* d) {
       if (d->k_nn < 6 || d->k_nn > kMaxK) return fail(MPWOS_EINVAL, "point cloud: k_nn must be in [6, 32]");
       if (d->n_points < d->k_nn || d->n_points > (int64_t)1 << 27)
         return fail(MPWOS_EINVAL, "point cloud: n_points must be in [k_nn, 2^27]");
+      if (d->reconstruction != 0 && d->reconstruction != 1)
+        return fail(MPWOS_EINVAL, "point cloud: reconstruction must be 0 (patch) or 1 (nearest point)");
       return MPWOS_OK;
   }
   return fail(MPWOS_EINVAL, "unknown manifold kind");
@@ -377,7 +379,7 @@ static mpwos_status check_fn(const mpwos_fn* f, const mpwos_manifold_desc& d, bo
       if (f->idx[0] < 0 || f->idx[0] > 64) return bad("CIRCLE_MODE: k must be in [0, 64]");
       return MPWOS_OK;
     case MPWOS_FN_LEGENDRE:
-      if (!sph || d.n != 3) return bad("LEGENDRE needs S^2");
+      if (!((sph || d.kind == MPWOS_POINT_CLOUD) && d.n == 3)) return bad("LEGENDRE needs S^2 or a cloud of it");
       return MPWOS_OK;
     case MPWOS_FN_TORUS_MODE:
       if (is_g || (d.kind != MPWOS_TORUS_IMPLICIT && d.kind != MPWOS_POINT_CLOUD))
@@ -580,6 +582,9 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
   } else if (d.kind != MPWOS_POINT_CLOUD && o.radius_rule != MPWOS_RADIUS_CURVATURE) {
     return fail(MPWOS_EINVAL, "radius rules other than CURVATURE apply to point clouds and the dumbbell");
   }
+  if (d.kind == MPWOS_POINT_CLOUD && man->cloud && cloud_nn_only(man->cloud) &&
+      o.radius_rule != MPWOS_RADIUS_SPACING && o.radius_rule != MPWOS_RADIUS_CURVATURE_BOUND)
+    return fail(MPWOS_EINVAL, "the nearest-point projection has no fitted curvature: use SPACING or CURVATURE_BOUND");
   if (o.radius_rule == MPWOS_RADIUS_CURVATURE_BOUND && !(o.kappa_bound >= 0.0 && std::isfinite(o.kappa_bound)))
     return fail(MPWOS_EINVAL, "kappa_bound must be finite and >= 0");
   if (o.block_size != 0 && (o.block_size < 64 || o.block_size > 256 || o.block_size % 64))

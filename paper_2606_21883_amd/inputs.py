@@ -210,6 +210,34 @@ def exact_u(prob, y):
 
 
 # ---------------------------------------------------------------------------
+# the sphere point cloud of Example 4: 8000 points uniform on S^2, the pure
+# nearest-neighbour projection, u = P1 + 0.2 P3 + 0.1 P5 of x3
+# ---------------------------------------------------------------------------
+
+
+def sphere_point_cloud(npts, seed=1):
+    """Uniform points on the unit sphere, rounded to binary32 (the library's
+    point format)."""
+    p = sphere_uniform(npts, 3, seed)
+    return p.astype(np.float32).astype(np.float64)
+
+
+def sphere_cloud_problem(points, sigma=1.0, k_others=6, c_h=2.4):
+    """Example 4: f = (sigma + 2) P1 + 0.2 (sigma + 12) P3 + 0.1 (sigma + 30) P5
+    of x3 (so u = P1 + 0.2 P3 + 0.1 P5), the spacing rule with h the mean
+    distance to the k_others nearest other points (k_nn counts the point
+    itself), c_h = 2.4, the nearest cloud point as the projection, no
+    compensation.  sigma is not stated in the paper: 1 here."""
+    c = [0.0] * 8
+    c[1] = sigma + 2.0
+    c[3] = 0.2 * (sigma + 12.0)
+    c[5] = 0.1 * (sigma + 30.0)
+    return problem(manifold="point_cloud", n=3, p=[1.0], sigma=sigma, points=np.asarray(points, dtype=np.float64),
+                   k_nn=k_others + 1, radius_rule="spacing", c_h=c_h, reconstruction="nearest",
+                   compensation="none", f=dict(kind="legendre", coef=c))
+
+
+# ---------------------------------------------------------------------------
 # the implicit dumbbell of Example 2: |xh| = R(xs) in R^n, xh in R^{n-1},
 # R(xs) = sqrt(1 - (xs/kc)^2) (1 - a + 2 a (xs/kc)^2), a = 0.35, kc = 1.2
 # ---------------------------------------------------------------------------
@@ -307,6 +335,10 @@ def config(name, scale=1.0, seed=1):
         pts = torus_point_cloud(1_000_000, 1.0, 0.3, 1e-4, seed)
         prob = point_cloud_problem(pts, radius_rule="curvature_bound", kappa_bound=1.0 / 0.3)
         return prob, torus_area_uniform(sz(8192), 1.0, 0.3, seed + 7), sz(1024)
+    if name == "sphere_cloud":
+        # Example 4: 8000 points on S^2, queries on the sphere
+        prob = sphere_cloud_problem(sphere_point_cloud(8000, seed))
+        return prob, sphere_uniform(sz(1024), 3, seed + 7), sz(1024)
     if name == "dumbbell":
         # Table 1's setting: 20 points of the 1000-dimensional dumbbell, N = 1000
         # paths each, N_V = 50 Green samples per step, tau_W = 1e-8

@@ -19,6 +19,7 @@ KINDS = {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3, "dumbbell":
 FN_KINDS = {"zero": 0, "const": 1, "sph_pair": 2, "circle_mode": 3, "legendre": 4, "torus_mode": 5,
             "table_s1": 6, "dumbbell_poly": 7}
 PRECISION = {"fp64": 0, "fp32": 1}
+RECONSTRUCTIONS = {"patch": 0, "nearest": 1}
 COMP = {"none": 0, "exact": 1}
 RADIUS_RULES = {"curvature": 0, "spacing": 1, "curvature_fit": 2, "curvature_bound": 3}
 
@@ -32,7 +33,7 @@ class MpwosError(RuntimeError):
 class ManifoldDesc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32), ("p", ctypes.c_double * 4),
                 ("points", ctypes.c_void_p), ("n_points", ctypes.c_int64), ("k_nn", ctypes.c_int32),
-                ("points_on_device", ctypes.c_int32)]
+                ("points_on_device", ctypes.c_int32), ("reconstruction", ctypes.c_int32)]
 
 
 class Fn(ctypes.Structure):
@@ -207,6 +208,7 @@ class Manifold:
             d.points = pts.ctypes.data
             d.n_points = pts.shape[0]
             d.k_nn = int(prob.get("k_nn", 16))
+            d.reconstruction = RECONSTRUCTIONS[prob.get("reconstruction", "patch")]
         self.handle = ctypes.c_void_p()
         _check(lib().mpwos_manifold_create(ctypes.byref(d), ctypes.byref(self.handle)))
         self._keep = []

@@ -161,3 +161,36 @@ def test_server_serves_cloud_requests():
     srv.close()
     assert np.array_equal(out["u"], solo["u"])
     m.close()
+
+
+# -- the pure nearest-neighbour projection of Example 4 -----------------------
+
+
+def test_nearest_point_cloud_matches_oracle():
+    """Example 4's sphere cloud (8000 points, cp = nearest point, spacing
+    rule): cp against the oracle bit for bit, FP64 walks walk by walk
+    (tau_W = 0.05 to keep the oracle's brute-force search short), FP32
+    statistics against FP64."""
+    prob = inputs.sphere_cloud_problem(inputs.sphere_point_cloud(8000, seed=21))
+    P = oracle.Problem(prob)
+    m = mpwos.Manifold(prob)
+    x = inputs.sphere_uniform(300, 3, seed=22) * np.random.default_rng(23).uniform(0.9, 1.1, (300, 1))
+    announce("nearest-point cloud cp")
+    y64 = mpwos.debug_cp(m, x, "fp64")
+    y32 = mpwos.debug_cp(m, x, "fp32")
+    yo = np.array([oracle.cp(P, v) for v in x])
+    assert np.array_equal(y64, yo)
+    assert np.mean(np.all(y32 == yo, axis=1)) > 0.99
+    short = dict(prob, tau_w=0.05)
+    Q = inputs.sphere_uniform(3, 3, seed=24)
+    announce("nearest-point cloud walks fp64 3x8")
+    gpu = mpwos.solve(short, Q, 8, 5, manifold=m, walk_outputs=True, precision="fp64", persistent=1)
+    orc = oracle.solve(oracle.Problem(short), Q, 8, 5)
+    assert compare_walks(gpu, orc, short, tol=1e-9, min_frac=0.999) == 1.0
+    announce("nearest-point cloud fp64 vs fp32 8x1024")
+    Q = inputs.sphere_uniform(8, 3, seed=25)
+    r64 = mpwos.solve(prob, Q, 1024, 6, manifold=m, precision="fp64", persistent=1)
+    r32 = mpwos.solve(prob, Q, 1024, 6, manifold=m, precision="fp32", persistent=1)
+    m.close()
+    se = np.sqrt(r64["stderr"] ** 2 + r32["stderr"] ** 2)
+    assert np.all(np.abs(r64["u"] - r32["u"]) < 5 * se + 1e-6), (r64["u"] - r32["u"], se)
