@@ -25,9 +25,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_HERE, "libmpwos_oracle.so")
 
-MANIFOLDS = {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3, "dumbbell": 4}
+MANIFOLDS = {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3, "dumbbell": 4, "product": 5}
 FN_KINDS = {"zero": 0, "const": 1, "sph_pair": 2, "circle_mode": 3, "legendre": 4,
-            "torus_mode": 5, "table_s1": 6, "dumbbell_poly": 7}
+            "torus_mode": 5, "table_s1": 6, "dumbbell_poly": 7, "product_modes": 8}
 COMP = {"none": 0, "exact": 1}
 RADIUS_RULES = {"curvature": 0, "spacing": 1, "curvature_fit": 2, "curvature_bound": 3}
 STATUS = {0: "OK", -1: "EINVAL", -2: "EOFFMANIFOLD", -3: "ENOMEM", 1: "WTRUNC"}
@@ -69,6 +69,8 @@ def lib():
         L.orc_db_phi.argtypes = [d, d, d, d]
         L.orc_db_phi.restype = d
         L.orc_db_curvatures.argtypes = [d, d, d, vp, vp]
+        L.orc_pr_phi.argtypes = [vp]
+        L.orc_pr_phi.restype = d
         L.orc_radius_uniform.argtypes = [u64, u32, u32, u32, u32, ctypes.c_int]
         L.orc_radius_uniform.restype = d
         for nm in ("orc_c_sigma_r", "orc_omega"):
@@ -180,6 +182,12 @@ def db_curvatures(alpha, kc, phi):
     k1, k2 = ctypes.c_double(), ctypes.c_double()
     lib().orc_db_curvatures(alpha, kc, phi, ctypes.byref(k1), ctypes.byref(k2))
     return k1.value, k2.value
+
+
+def pr_phi(xc):
+    """Curve parameter of the Fourier-curve point nearest to x_c (6 coordinates)."""
+    x = np.ascontiguousarray(xc, dtype=np.float64)
+    return lib().orc_pr_phi(_ptr(x))
 
 
 def radius_uniform(seed, q, w, k, sub, n):

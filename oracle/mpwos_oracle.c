@@ -30,10 +30,11 @@
 /* ------------------------------------------------------------------------- */
 /* Codes (numeric values fixed by the solver's public interface).             */
 /* ------------------------------------------------------------------------- */
-enum { ORC_SPHERE = 0, ORC_SPHERE_CAP = 1, ORC_TORUS = 2, ORC_POINT_CLOUD = 3, ORC_DUMBBELL = 4 };
+enum { ORC_SPHERE = 0, ORC_SPHERE_CAP = 1, ORC_TORUS = 2, ORC_POINT_CLOUD = 3, ORC_DUMBBELL = 4, ORC_PRODUCT = 5 };
 enum {
   ORC_FN_ZERO = 0, ORC_FN_CONST = 1, ORC_FN_SPH_PAIR = 2, ORC_FN_CIRCLE_MODE = 3,
-  ORC_FN_LEGENDRE = 4, ORC_FN_TORUS_MODE = 5, ORC_FN_TABLE_S1 = 6, ORC_FN_DUMBBELL_POLY = 7
+  ORC_FN_LEGENDRE = 4, ORC_FN_TORUS_MODE = 5, ORC_FN_TABLE_S1 = 6, ORC_FN_DUMBBELL_POLY = 7,
+  ORC_FN_PRODUCT_MODES = 8
 };
 enum { ORC_COMP_NONE = 0, ORC_COMP_EXACT = 1 };
 enum { ORC_RADIUS_CURVATURE = 0, ORC_RADIUS_SPACING = 1, ORC_RADIUS_CURVATURE_FIT = 2,
@@ -47,7 +48,8 @@ enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_EOFFMANIFOLD = -2, ORC_ENOMEM = -3, ORC_
 typedef struct {
   int32_t manifold;      /* ORC_SPHERE ... */
   int32_t n;             /* ambient dimension */
-  double p[4];           /* sphere: R; cap: R, h; torus: R, a; dumbbell: alpha, kappa (half-length) */
+  double p[4];           /* sphere: R; cap: R, h; torus: R, a; dumbbell: alpha, kappa (half-length);
+                            product: R (Fourier curve), a (sphere) */
   const double* points;  /* point cloud, n_points x 3, row-major */
   int64_t n_points;
   int32_t k_nn;          /* neighbours used by the local reconstruction */
@@ -717,10 +719,83 @@ static double orc_db_f(const orc_problem* P, const double* y, double phi) {
   return -lapM + P->sigma * U;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Product manifold of Sec. 4, Example 3: M = S^1_Fourier(R) x S^2(a) in R^9, */
+/* X(phi, w) = (R C(phi), a w), C(phi) = (cos phi, sin phi, cos 2phi / 2,     */
+/* sin 2phi / 2, cos 3phi / 3, sin 3phi / 3).  |C'| = sqrt(3) and            */
+/* |C| = const, so the nearest curve point of x_c maximises                   */
+/* g(phi) = x_c . C(phi) = sum_k (a_k cos k phi + b_k sin k phi) / k with     */
+/* a_k = x_c[2k-2], b_k = x_c[2k-1]; the sphere factor is normalised.         */
+/* ------------------------------------------------------------------------- */
+static void orc_pr_g(const double* xc, double phi, double* g, double* g1, double* g2) {
+  *g = *g1 = *g2 = 0.0;
+  for (int k = 1; k <= 3; ++k) {
+    double c = cos(k * phi), s = sin(k * phi);
+    double ak = xc[2 * k - 2], bk = xc[2 * k - 1];
+    *g += (ak * c + bk * s) / k;
+    *g1 += -ak * s + bk * c;
+    *g2 += -k * (ak * c + bk * s);
+  }
+}
+
+/* Curve parameter of the point of the Fourier curve nearest to x_c: the best
+ * of a 2048-point grid over [0, 2 pi), then Newton on g' = 0 kept inside the
+ * neighbouring cells by bisection. */
+double orc_pr_phi(const double* xc) {
+  const int M = 2048;
+  const double h = 6.283185307179586 / M;
+  int best = 0;
+  double bg = -INFINITY, g, g1, g2;
+  for (int i = 0; i < M; ++i) {
+    orc_pr_g(xc, i * h, &g, &g1, &g2);
+    if (g > bg) { bg = g; best = i; }
+  }
+  double lo = (best - 1) * h, hi = (best + 1) * h, phi = best * h;
+  for (int it = 0; it < 200; ++it) {
+    orc_pr_g(xc, phi, &g, &g1, &g2);
+    if (g1 > 0.0) lo = phi; else hi = phi;
+    double nx = g2 < 0.0 ? phi - g1 / g2 : NAN;
+    if (!(nx >= lo && nx <= hi)) nx = 0.5 * (lo + hi);
+    double step = fabs(nx - phi);
+    phi = nx;
+    if (step <= 1e-16 * (1.0 + fabs(phi)) || hi - lo <= 1e-16 * (1.0 + fabs(phi))) break;
+  }
+  return phi;
+}
+
+static int orc_pr_cp(const orc_problem* P, const double* x, double* y, double* phi_out) {
+  double R = P->p[0], a = P->p[1];
+  double phi = orc_pr_phi(x);
+  for (int k = 1; k <= 3; ++k) {
+    y[2 * k - 2] = R * cos(k * phi) / k;
+    y[2 * k - 1] = R * sin(k * phi) / k;
+  }
+  double ns = sqrt(x[6] * x[6] + x[7] * x[7] + x[8] * x[8]);
+  if (ns == 0.0) return ORC_EINVAL;
+  for (int i = 6; i < 9; ++i) y[i] = a * x[i] / ns;
+  if (phi_out) *phi_out = phi;
+  return ORC_OK;
+}
+
+/* f_Omega = -Lap_M u + sigma u for u = c0 cos(phi) w1 + c1 sin(2 phi) w2 +
+ * c2 cos(3 phi) (w1^2 - w2^2): Lap_M is the sum of the factors' operators,
+ * d^2/ds^2 = (1/(3 R^2)) d^2/dphi^2 on the curve (speed R sqrt 3), and the
+ * degree-1 and degree-2 harmonics w1, w2, w1^2 - w2^2 on S^2(a) (eigenvalues
+ * 2/a^2, 2/a^2, 6/a^2). */
+static double orc_pr_f(const orc_problem* P, const double* y, double phi) {
+  const double* c = P->f_coef;
+  double R = P->p[0], a = P->p[1], sg = P->sigma;
+  double w1 = y[6] / a, w2 = y[7] / a;
+  double q = 1.0 / (3.0 * R * R), s2 = 1.0 / (a * a);
+  return c[0] * (sg + q + 2.0 * s2) * cos(phi) * w1 + c[1] * (sg + 4.0 * q + 2.0 * s2) * sin(2.0 * phi) * w2 +
+         c[2] * (sg + 9.0 * q + 6.0 * s2) * cos(3.0 * phi) * (w1 * w1 - w2 * w2);
+}
+
 int orc_cp(const orc_problem* P, const double* x, double* y) {
   int n = P->n;
   switch (P->manifold) {
     case ORC_DUMBBELL: return orc_db_cp(P, x, y, NULL);
+    case ORC_PRODUCT: return orc_pr_cp(P, x, y, NULL);
     case ORC_SPHERE:
     case ORC_SPHERE_CAP: {
       double nx = orc_norm(x, n);
@@ -740,9 +815,15 @@ int orc_cp(const orc_problem* P, const double* x, double* y) {
   return ORC_EINVAL;
 }
 
-/* Curvature indicator kappa(y): largest |principal curvature|. */
+/* Curvature indicator kappa(y): largest |principal curvature|.  On the
+ * product: the larger of the curve's curvature sqrt(14)/(3R) (|C''|^2 = 14,
+ * C'' normal to C', speed sqrt 3) and the sphere's 1/a, both constant. */
 static double orc_kappa(const orc_problem* P, const double* y) {
   switch (P->manifold) {
+    case ORC_PRODUCT: {
+      double kc = sqrt(14.0) / (3.0 * P->p[0]), ks = 1.0 / P->p[1];
+      return kc > ks ? kc : ks;
+    }
     case ORC_SPHERE:
     case ORC_SPHERE_CAP: return 1.0 / P->p[0];
     case ORC_TORUS: {
@@ -950,6 +1031,12 @@ double orc_source(const orc_problem* P, const double* z) {
     if (P->f_kind == ORC_FN_DUMBBELL_POLY) return orc_db_f(P, y, phi);
     return orc_f_omega(P, y);
   }
+  if (P->manifold == ORC_PRODUCT) {
+    double phi;
+    if (orc_pr_cp(P, z, y, &phi)) return NAN;
+    if (P->f_kind == ORC_FN_PRODUCT_MODES) return orc_pr_f(P, y, phi);
+    return orc_f_omega(P, y);
+  }
   if (orc_cp(P, z, y)) return NAN;
   double v = orc_f_omega(P, y);
   if (P->compensation == ORC_COMP_EXACT) v += orc_m_exact(P, z, y);
@@ -1153,6 +1240,15 @@ static int orc_check(const orc_problem* P) {
   } else if (P->f_kind == ORC_FN_DUMBBELL_POLY) {
     return ORC_EINVAL;
   }
+  if (P->manifold == ORC_PRODUCT) {
+    /* R^9; no exact compensation is known here (the paper sets m = 0) */
+    if (P->n != 9 || P->compensation != ORC_COMP_NONE || P->radius_rule != ORC_RADIUS_CURVATURE) return ORC_EINVAL;
+    if (!(P->p[0] > 0.0) || !(P->p[1] > 0.0)) return ORC_EINVAL;
+    if (P->f_kind != ORC_FN_ZERO && P->f_kind != ORC_FN_CONST && P->f_kind != ORC_FN_PRODUCT_MODES)
+      return ORC_EINVAL;
+  } else if (P->f_kind == ORC_FN_PRODUCT_MODES) {
+    return ORC_EINVAL;
+  }
   return ORC_OK;
 }
 
@@ -1166,6 +1262,7 @@ static double orc_max_radius(const orc_problem* P) {
   }
   double kmin = 1.0 / P->p[0];
   if (P->manifold == ORC_TORUS) kmin = 1.0 / P->p[1];
+  if (P->manifold == ORC_PRODUCT) kmin = orc_kappa(P, NULL);
   return P->theta * P->c_kappa / (1.0 + kmin);
 }
 

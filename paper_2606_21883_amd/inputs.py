@@ -200,6 +200,12 @@ def exact_u(prob, y):
         rho = np.hypot(y[:, 0], y[:, 1])
         psi = np.arctan2(y[:, 2], rho - Rt)
         return f["coef"][0] * np.sin(phi) * np.cos(2.0 * psi)
+    if kind == "product_modes":
+        c = f["coef"]
+        a = prob["p"][1]
+        phi = np.arctan2(y[:, 1], y[:, 0])
+        w1, w2 = y[:, 6] / a, y[:, 7] / a
+        return c[0] * np.cos(phi) * w1 + c[1] * np.sin(2 * phi) * w2 + c[2] * np.cos(3 * phi) * (w1 * w1 - w2 * w2)
     if kind == "dumbbell_poly":
         c = f["coef"]
         a = np.asarray(f["values"])
@@ -207,6 +213,38 @@ def exact_u(prob, y):
         return (c[0] * xs + c[1] * xs * xs + c[2] * xh.sum(axis=1) / math.sqrt(xh.shape[1])
                 + c[3] * (xh * xh * a).sum(axis=1))
     raise ValueError(kind)
+
+
+# ---------------------------------------------------------------------------
+# the product manifold of Example 3: S^1_Fourier(R) x S^2(a) in R^9,
+# X(phi, w) = (R C(phi), a w), C = (cos, sin, cos 2/2, sin 2/2, cos 3/3, sin 3/3)
+# ---------------------------------------------------------------------------
+
+
+def product_point(phi, w, R=1.0, a=0.65):
+    """X(phi, w) for angles phi (m,) and unit vectors w (m, 3)."""
+    phi = np.asarray(phi, dtype=np.float64)
+    cols = []
+    for k in (1, 2, 3):
+        cols += [R * np.cos(k * phi) / k, R * np.sin(k * phi) / k]
+    return np.concatenate([np.stack(cols, axis=1), a * np.asarray(w)], axis=1)
+
+
+def product_points(nq, R=1.0, a=0.65, seed=1):
+    """phi uniform on [0, 2 pi), w uniform on S^2."""
+    rng = np.random.default_rng(seed)
+    phi = rng.uniform(0.0, 2.0 * np.pi, nq)
+    w = rng.standard_normal((nq, 3))
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    return product_point(phi, w, R, a)
+
+
+def product_problem(R=1.0, a=0.65, sigma=1.0, coef=(1.0, 0.3, 0.2)):
+    """Example 3: u = cos(phi) w1 + 0.3 sin(2 phi) w2 + 0.2 cos(3 phi) (w1^2 - w2^2)
+    on S^1_Fourier(R) x S^2(a) in R^9, no compensation (as in the paper).  sigma
+    is not stated in the paper: 1 here."""
+    return problem(manifold="product", n=9, p=[R, a], sigma=sigma, compensation="none",
+                   f=dict(kind="product_modes", coef=list(coef)))
 
 
 # ---------------------------------------------------------------------------
@@ -335,6 +373,9 @@ def config(name, scale=1.0, seed=1):
         pts = torus_point_cloud(1_000_000, 1.0, 0.3, 1e-4, seed)
         prob = point_cloud_problem(pts, radius_rule="curvature_bound", kappa_bound=1.0 / 0.3)
         return prob, torus_area_uniform(sz(8192), 1.0, 0.3, seed + 7), sz(1024)
+    if name == "product":
+        # Example 3: S^1_Fourier x S^2(0.65) in R^9
+        return product_problem(), product_points(sz(4096), seed=seed), sz(1024)
     if name == "sphere_cloud":
         # Example 4: 8000 points on S^2, queries on the sphere
         prob = sphere_cloud_problem(sphere_point_cloud(8000, seed))
