@@ -236,7 +236,7 @@ def cpu_baseline(work):
     (about 10-20 s of CPU work)."""
     import oracle
     threads = min(16, os.cpu_count() or 1)
-    sample = {"sphere": (64, 4096), "cap": (64, 4096), "dumbbell": (1, 32), "sphere_cloud": (2, 8)}
+    sample = {"sphere": (64, 4096), "cap": (64, 4096), "dumbbell": (1, 32), "sphere_cloud": (2, 8), "product": (4, 64)}
     total_steps, total_t, parts = 0, 0.0, []
     for name, prob, Q, nw in work:
         nq, nws = sample.get(name, (8, 256))
@@ -456,7 +456,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="sphere",
                     choices=["sphere", "circle", "torus", "cloud", "hyper100", "hyper1000", "dumbbell",
-                             "sphere_cloud"],
+                             "sphere_cloud", "product"],
                     help="sphere (closed + cap) is the headline workload; the others are for profiling")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink queries and walks (profiling only)")
     ap.add_argument("--block-size", type=int, default=0, help="workgroup size of the walk kernels (0 = autotuned)")
@@ -523,6 +523,8 @@ def main():
                     "N_V=50, 20 points x 1000 paths",
         "sphere_cloud": "point-cloud S^2, 8000 points, nearest-point projection, spacing rule (6 neighbours, "
                         "c_h=2.4), u=P1+0.2P3+0.1P5, sigma=1, m=0: 1024 queries x 1024 walks",
+        "product": "S^1_Fourier(1) x S^2(0.65) in R^9, u=cos(phi)w1+0.3sin(2phi)w2+0.2cos(3phi)(w1^2-w2^2), "
+                   "sigma=1, m=0: 4096 queries x 1024 walks",
     }[args.workload]
     if args.scale != 1.0:
         desc += f" (scaled by {args.scale})"

@@ -58,12 +58,17 @@ typedef enum {
                                 local Newton solve on the level set (Sec. 2.3.2) */
   MPWOS_POINT_CLOUD = 3,     /* points p_i in R^3; cp by k-nearest-neighbour search and a local
                                 quadratic reconstruction (Sec. 2.3.2) */
-  MPWOS_DUMBBELL = 4         /* implicit dumbbell of Sec. 4, Example 2: {|x_h| = R(x_n)} in R^n,
+  MPWOS_DUMBBELL = 4,        /* implicit dumbbell of Sec. 4, Example 2: {|x_h| = R(x_n)} in R^n,
                                 x_h = (x_1 .. x_{n-1}), R(s) = sqrt(1 - (s/k)^2)(1 - a + 2a (s/k)^2),
                                 a = p[0] in [0, 1/2), k = p[1] > 0; closed; cp by Newton in the
                                 profile parameter; n in [4, 4096]; takes the CURVATURE_BOUND rule
                                 (kappa_bound >= its largest principal curvature) and no
                                 compensation */
+  MPWOS_PRODUCT = 5          /* product manifold of Sec. 4, Example 3: S^1_Fourier(R) x S^2(a) in R^9,
+                                X(phi, w) = (R C(phi), a w), C = (cos phi, sin phi, cos 2phi/2,
+                                sin 2phi/2, cos 3phi/3, sin 3phi/3); R = p[0], a = p[1]; n = 9;
+                                cp by Newton on the curve and normalisation; curvature indicator
+                                max(sqrt(14)/(3R), 1/a); no compensation */
 } mpwos_kind;
 
 /* Source and boundary-data families.  For f the family describes f_Omega;
@@ -82,9 +87,12 @@ typedef enum {
   MPWOS_FN_TABLE_S1 = 6,     /* S^1_R, f: values[0..M) = f at th_i = 2 pi i/M (linear
                                 interpolation), values[M..2M) = predictor u_* used by
                                 the compensation; n_values = 2M (host memory) */
-  MPWOS_FN_DUMBBELL_POLY = 7 /* dumbbell, f: u = coef[0] x_n + coef[1] x_n^2 + coef[2] (sum x_h)/sqrt(n-1)
+  MPWOS_FN_DUMBBELL_POLY = 7, /* dumbbell, f: u = coef[0] x_n + coef[1] x_n^2 + coef[2] (sum x_h)/sqrt(n-1)
                                 + coef[3] sum_i values[i] x_i^2 (n_values = n - 1, host memory),
                                 f = -Lap_M u + sigma u (Example 2's family; A = diag(values)) */
+  MPWOS_FN_PRODUCT_MODES = 8 /* product manifold, f: u = coef[0] cos(phi) w1 + coef[1] sin(2 phi) w2
+                                + coef[2] cos(3 phi) (w1^2 - w2^2), f = -Lap_M u + sigma u
+                                (Example 3's family) */
 } mpwos_fn_kind;
 
 typedef enum { MPWOS_FP64_PLAIN = 0, MPWOS_FP32_MIXED = 1 } mpwos_precision;

@@ -8,10 +8,10 @@ namespace mpwos {
 constexpr int kMaxJ = 32;       // series terms kept for the radial law
 constexpr int kMaxK = 32;       // point-cloud neighbours
 
-enum Kind : int32_t { kSphere = 0, kCap = 1, kTorus = 2, kCloud = 3, kDumbbell = 4 };
+enum Kind : int32_t { kSphere = 0, kCap = 1, kTorus = 2, kCloud = 3, kDumbbell = 4, kProduct = 5 };
 enum FnKind : int32_t {
   kFnZero = 0, kFnConst = 1, kFnSphPair = 2, kFnCircle = 3, kFnLegendre = 4, kFnTorus = 5, kFnTableS1 = 6,
-  kFnDumbbell = 7
+  kFnDumbbell = 7, kFnProduct = 8
 };
 
 // A source / boundary family as the device sees it.

@@ -333,6 +333,11 @@ static mpwos_status check_manifold_desc(const mpwos_manifold_desc* d) {
       if (!(d->p[1] > 0 && d->p[1] <= 0.5 * d->p[0]))
         return fail(MPWOS_EINVAL, "torus: need 0 < a <= R/2 (constant curvature indicator 1/a)");
       return MPWOS_OK;
+    case MPWOS_PRODUCT:
+      if (d->n != 9) return fail(MPWOS_EINVAL, "product manifold: n must be 9");
+      if (!(d->p[0] > 0.0) || !(d->p[1] > 0.0) || !std::isfinite(d->p[0]) || !std::isfinite(d->p[1]))
+        return fail(MPWOS_EINVAL, "product manifold: R = p[0] and a = p[1] must be > 0");
+      return MPWOS_OK;
     case MPWOS_DUMBBELL:
       if (d->n < 4 || d->n > 4096) return fail(MPWOS_EINVAL, "dumbbell: n must be in [4, 4096]");
       if (!(d->p[0] >= 0.0 && d->p[0] < 0.5)) return fail(MPWOS_EINVAL, "dumbbell: a = p[0] must be in [0, 1/2)");
@@ -357,6 +362,8 @@ static double const_kappa(const mpwos_manifold_desc& d) {
     case MPWOS_SPHERE:
     case MPWOS_SPHERE_CAP: return 1.0 / d.p[0];
     case MPWOS_TORUS_IMPLICIT: return 1.0 / d.p[1];
+    // the Fourier curve's curvature (|C''|^2 = 14, speed sqrt 3) and the sphere's
+    case MPWOS_PRODUCT: return std::max(std::sqrt(14.0) / (3.0 * d.p[0]), 1.0 / d.p[1]);
   }
   return 0.0;
 }
@@ -388,6 +395,9 @@ static mpwos_status check_fn(const mpwos_fn* f, const mpwos_manifold_desc& d, bo
     case MPWOS_FN_TABLE_S1:
       if (!sph || d.n != 2 || is_g) return bad("TABLE_S1 is a source on S^1");
       if (!f->values || f->n_values < 4 || (f->n_values % 2)) return bad("TABLE_S1 needs 2M >= 4 values");
+      return MPWOS_OK;
+    case MPWOS_FN_PRODUCT_MODES:
+      if (d.kind != MPWOS_PRODUCT || is_g) return bad("PRODUCT_MODES is a source on the product manifold");
       return MPWOS_OK;
     case MPWOS_FN_DUMBBELL_POLY:
       if (d.kind != MPWOS_DUMBBELL || is_g) return bad("DUMBBELL_POLY is a source on the dumbbell");
@@ -468,6 +478,42 @@ static bool query_on_manifold(const mpwos_manifold_desc& d, const double* y) {
       const double rho = std::hypot(y[0], y[1]);
       const double dc = std::hypot(rho - d.p[0], y[2]);
       return std::fabs(dc - d.p[1]) <= tol;
+    }
+    case MPWOS_PRODUCT: {
+      // nearest point of the Fourier curve: maximise x_c . C(phi) (fine grid, Newton)
+      auto g = [&](double t, double* d) {
+        d[0] = d[1] = d[2] = 0.0;
+        for (int k = 1; k <= 3; ++k) {
+          const double c = std::cos(k * t), s = std::sin(k * t), ak = y[2 * k - 2], bk = y[2 * k - 1];
+          d[0] += (ak * c + bk * s) / k;
+          d[1] += -ak * s + bk * c;
+          d[2] += -k * (ak * c + bk * s);
+        }
+      };
+      const int G = 1024;
+      const double h = 6.283185307179586 / G;
+      double best = -INFINITY, t = 0.0, v[3];
+      for (int j = 0; j < G; ++j) {
+        g(j * h, v);
+        if (v[0] > best) { best = v[0]; t = j * h; }
+      }
+      double lo = t - h, hi = t + h;
+      for (int it = 0; it < 100; ++it) {
+        g(t, v);
+        if (v[1] > 0.0) lo = t; else hi = t;
+        double nx = v[2] < 0.0 ? t - v[1] / v[2] : lo - 1.0;
+        if (!(nx >= lo && nx <= hi)) nx = 0.5 * (lo + hi);
+        const double step = std::fabs(nx - t);
+        t = nx;
+        if (step <= 1e-16 * (1.0 + std::fabs(t)) || hi - lo <= 1e-16 * (1.0 + std::fabs(t))) break;
+      }
+      double d2 = 0.0;
+      for (int k = 1; k <= 3; ++k) {
+        const double ex = y[2 * k - 2] - d.p[0] * std::cos(k * t) / k, ey = y[2 * k - 1] - d.p[0] * std::sin(k * t) / k;
+        d2 += ex * ex + ey * ey;
+      }
+      const double ns = std::sqrt(y[6] * y[6] + y[7] * y[7] + y[8] * y[8]);
+      return std::sqrt(d2) + std::fabs(ns - d.p[1]) <= tol;
     }
     case MPWOS_DUMBBELL: {
       double hh = 0.0;
@@ -574,6 +620,11 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
     return fail(MPWOS_EINVAL, "unknown compensation");
   if (o.radius_rule < MPWOS_RADIUS_CURVATURE || o.radius_rule > MPWOS_RADIUS_CURVATURE_BOUND)
     return fail(MPWOS_EINVAL, "unknown radius_rule");
+  if (d.kind == MPWOS_PRODUCT && o.compensation != MPWOS_COMP_NONE)
+    return fail(MPWOS_EINVAL, "the product manifold has no exact compensation: set compensation NONE");
+  if ((d.kind == MPWOS_DUMBBELL || d.kind == MPWOS_PRODUCT) && f->kind != MPWOS_FN_ZERO &&
+      f->kind != MPWOS_FN_CONST && f->kind != MPWOS_FN_DUMBBELL_POLY && f->kind != MPWOS_FN_PRODUCT_MODES)
+    return fail(MPWOS_EINVAL, "f: this manifold takes ZERO, CONST or its own source family");
   if (d.kind == MPWOS_DUMBBELL) {
     if (o.radius_rule != MPWOS_RADIUS_CURVATURE_BOUND)
       return fail(MPWOS_EINVAL, "the dumbbell takes the CURVATURE_BOUND radius rule");
@@ -643,7 +694,8 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
     return fail(MPWOS_EINVAL, "sqrt(sigma) r_max = " + std::to_string(std::sqrt(x2max)) +
                                   " is beyond the range of the series radial law for this n");
   fill_law(h, js, jd, a.law);
-  a.const_r = (d.kind == MPWOS_SPHERE || d.kind == MPWOS_TORUS_IMPLICIT || d.kind == MPWOS_DUMBBELL || cloud_bound)
+  a.const_r = (d.kind == MPWOS_SPHERE || d.kind == MPWOS_TORUS_IMPLICIT || d.kind == MPWOS_DUMBBELL ||
+               d.kind == MPWOS_PRODUCT || cloud_bound)
                   ? 1 : 0;
   if (a.const_r) {
     a.r0 = rmax;

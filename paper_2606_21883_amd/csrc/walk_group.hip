@@ -252,6 +252,117 @@ __device__ __forceinline__ T coord_of(const T* v, int i, int gl) {
   return __shfl(mine, owner, L);
 }
 
+// ---- product manifold S^1_Fourier(R) x S^2(a) in R^9 (Sec. 4, Example 3) -----
+// X(phi, w) = (R C(phi), a w), C = (cos, sin, cos 2/2, sin 2/2, cos 3/3, sin 3/3)
+// of phi.  |C| is constant, so the nearest curve point of x_c maximises
+// g(phi) = sum_k (a_k cos k phi + b_k sin k phi)/k, a_k = x_c[2k-2], b_k =
+// x_c[2k-1]; the sphere factor is normalised.
+template <class T>
+__device__ __forceinline__ void pr_g(const T* xc, T phi, T& g, T& g1, T& g2) {
+  T s1, c1;
+  sincos_(phi, s1, c1);
+  const T c2 = c1 * c1 - s1 * s1, s2 = (T)2 * s1 * c1;
+  const T c3 = c2 * c1 - s2 * s1, s3 = s2 * c1 + c2 * s1;
+  const T e1 = xc[0] * c1 + xc[1] * s1, e2 = xc[2] * c2 + xc[3] * s2, e3 = xc[4] * c3 + xc[5] * s3;
+  g = e1 + e2 / (T)2 + e3 / (T)3;
+  g1 = (-xc[0] * s1 + xc[1] * c1) + (-xc[2] * s2 + xc[3] * c2) + (-xc[4] * s3 + xc[5] * c3);
+  g2 = -(e1 + (T)2 * e2 + (T)3 * e3);
+}
+
+// Curve parameter of the nearest curve point: the best of a 64-point grid
+// over [0, 2 pi) shared by the group's lanes (FP32; ties to the lower index),
+// then Newton on g' = 0 kept inside the neighbouring cells by bisection.
+template <class T, int L>
+__device__ __forceinline__ T pr_phi(const T* xc, int gl) {
+  constexpr int G = 64;
+  const T h = (T)6.283185307179586 / (T)G;
+  float xf[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) xf[i] = (float)xc[i];
+  float bg = -3.0e38f;
+  int bj = G;
+  for (int j = gl; j < G; j += L) {
+    float g, g1, g2;
+    pr_g<float>(xf, (float)j * (float)h, g, g1, g2);
+    if (g > bg) {
+      bg = g;
+      bj = j;
+    }
+  }
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) {
+    const float og = __shfl_xor(bg, o, L);
+    const int oj = __shfl_xor(bj, o, L);
+    if (og > bg || (og == bg && oj < bj)) {
+      bg = og;
+      bj = oj;
+    }
+  }
+  T lo = (T)(bj - 1) * h, hi = (T)(bj + 1) * h, phi = (T)bj * h;
+  const T tol = sizeof(T) == 8 ? (T)1e-16 : (T)1e-7;
+  for (int it = 0; it < 64; ++it) {
+    T g, g1, g2;
+    pr_g<T>(xc, phi, g, g1, g2);
+    if (g1 > (T)0) lo = phi;
+    else hi = phi;
+    T nx = g2 < (T)0 ? phi - g1 / g2 : lo - (T)1;
+    if (!(nx >= lo && nx <= hi)) nx = (T)0.5 * (lo + hi);
+    const T step = abs_(nx - phi);
+    phi = nx;
+    if (step <= tol * ((T)1 + abs_(phi)) || hi - lo <= tol * ((T)1 + abs_(phi))) break;
+  }
+  return phi;
+}
+
+// cp onto the product, in place on the group's coordinates.
+template <class T, int L, int MB>
+__device__ __forceinline__ void pr_project(const WalkArgs& a, T* x, int gl) {
+  T v[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) v[i] = coord_of<T, L, MB>(x, i, gl);
+  const T phi = pr_phi<T, L>(v, gl);
+  T s1, c1;
+  sincos_(phi, s1, c1);
+  const T c2 = c1 * c1 - s1 * s1, s2 = (T)2 * s1 * c1;
+  const T c3 = c2 * c1 - s2 * s1, s3 = s2 * c1 + c2 * s1;
+  const T R = (T)a.p[0];
+  const T yc[6] = {R * c1, R * s1, R * c2 / (T)2, R * s2 / (T)2, R * c3 / (T)3, R * s3 / (T)3};
+  const T sc = (T)a.p[1] * rsqrt_(v[6] * v[6] + v[7] * v[7] + v[8] * v[8]);
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = 4 * (gl + L * m) + j;
+      T out = (T)0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        if (i == c) out = yc[c];
+      if (i >= 6 && i < 9) out = x[4 * m + j] * sc;
+      x[4 * m + j] = out;
+    }
+}
+
+// f_Omega(cp z) for u = c0 cos(phi) w1 + c1 sin(2 phi) w2 + c2 cos(3 phi)
+// (w1^2 - w2^2): Lap_M is the sum of the factors' operators, (1/(3 R^2))
+// d^2/dphi^2 on the curve (speed R sqrt 3) and the degree-1 and degree-2
+// harmonics on S^2(a) (eigenvalues 2/a^2 and 6/a^2).
+template <class T, int L, int MB>
+__device__ __forceinline__ T pr_source(const WalkArgs& a, const T* z, int gl) {
+  const FnDev& f = a.f;
+  if (f.kind == kFnConst) return (T)f.coef[0];
+  if (f.kind != kFnProduct) return (T)0;
+  T v[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) v[i] = coord_of<T, L, MB>(z, i, gl);
+  const double phi = (double)pr_phi<T, L>(v, gl);
+  const double ns = sqrt((double)v[6] * v[6] + (double)v[7] * v[7] + (double)v[8] * v[8]);
+  const double w1 = (double)v[6] / ns, w2 = (double)v[7] / ns;
+  const double R = a.p[0], q = 1.0 / (3.0 * R * R), s2 = 1.0 / (a.p[1] * a.p[1]), sg = a.sigma;
+  const double* c = f.coef;
+  return (T)(c[0] * (sg + q + 2.0 * s2) * cos(phi) * w1 + c[1] * (sg + 4.0 * q + 2.0 * s2) * sin(2.0 * phi) * w2 +
+             c[2] * (sg + 9.0 * q + 6.0 * s2) * cos(3.0 * phi) * (w1 * w1 - w2 * w2));
+}
+
 template <class T, int L, int MB>
 __device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB>& st, int gl, uint64_t seed) {
   const Stream rs{st.q, st.w, (uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -278,6 +389,8 @@ __device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB
     }
     if (a.kind == kDumbbell) {
       db_project<T, L, MB>(a, Yn, gl);
+    } else if (a.kind == kProduct) {
+      pr_project<T, L, MB>(a, Yn, gl);
     } else {
       tt = group_sum<L>(tt);
       const T f = R * rsqrt_(tt);
@@ -312,6 +425,8 @@ __device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB
     T v;
     if (a.kind == kDumbbell) {
       v = db_source<T, L, MB>(a, Z, st.A, gl);
+    } else if (a.kind == kProduct) {
+      v = pr_source<T, L, MB>(a, Z, gl);
     } else if (f.kind == kFnSphPair) {
       zz = group_sum<L>(zz);
       const T zi = coord_of<T, L, MB>(Z, f.idx[0], gl);
@@ -501,6 +616,8 @@ __global__ __launch_bounds__(256) void cp_group_kernel(WalkArgs a, const double*
     }
   if (a.kind == kDumbbell) {
     db_project<T, L, MB>(a, v, gl);
+  } else if (a.kind == kProduct) {
+    pr_project<T, L, MB>(a, v, gl);
   } else {
     T s = (T)0;
 #pragma unroll
@@ -624,8 +741,10 @@ int64_t group_record_bytes(int n, int lanes_req, bool fp64) {
 
 mpwos_status launch_group_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue) {
   (void)queue;
-  if (a.kind != kSphere && a.kind != kDumbbell)
-    return fail(MPWOS_EINVAL, "n >= 4 is supported on the closed sphere and the dumbbell");
+  if (a.kind != kSphere && a.kind != kDumbbell && a.kind != kProduct)
+    return fail(MPWOS_EINVAL, "n >= 4 is supported on the closed sphere, the dumbbell and the product manifold");
+  if (a.kind == kProduct && a.f.kind != kFnProduct && a.f.kind != kFnConst && a.f.kind != kFnZero)
+    return fail(MPWOS_EINVAL, "the product manifold supports the ZERO, CONST and PRODUCT_MODES sources");
   if (a.kind == kSphere && a.f.kind != kFnSphPair && a.f.kind != kFnConst && a.f.kind != kFnZero)
     return fail(MPWOS_EINVAL, "n >= 4 spheres support the ZERO, CONST and SPH_PAIR sources");
   if (a.kind == kDumbbell && a.f.kind != kFnDumbbell && a.f.kind != kFnConst && a.f.kind != kFnZero)

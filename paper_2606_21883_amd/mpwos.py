@@ -15,9 +15,9 @@ LIBPATH = os.path.join(_HERE, "libmpwos.so")
 OK, EINVAL, EOFFMANIFOLD, ENOMEM, EDEVICE, EBUSY, WTRUNC = 0, -1, -2, -3, -4, -5, 1
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EOFFMANIFOLD", -3: "ENOMEM", -4: "EDEVICE", -5: "EBUSY",
                 1: "WTRUNC"}
-KINDS = {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3, "dumbbell": 4}
+KINDS = {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3, "dumbbell": 4, "product": 5}
 FN_KINDS = {"zero": 0, "const": 1, "sph_pair": 2, "circle_mode": 3, "legendre": 4, "torus_mode": 5,
-            "table_s1": 6, "dumbbell_poly": 7}
+            "table_s1": 6, "dumbbell_poly": 7, "product_modes": 8}
 PRECISION = {"fp64": 0, "fp32": 1}
 RECONSTRUCTIONS = {"patch": 0, "nearest": 1}
 COMP = {"none": 0, "exact": 1}

@@ -91,9 +91,9 @@ def test_enum_values_match_header():
                       ("MPWOS_FN_TABLE_S1", 6), ("MPWOS_FN_DUMBBELL_POLY", 7),
                       ("MPWOS_FP32_MIXED", 1), ("MPWOS_EOFFMANIFOLD", -2), ("MPWOS_WTRUNC", 1)]:
         assert re.search(rf"\b{name}\s*=\s*{val}\b", txt), name
-    assert mpwos.KINDS == {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3, "dumbbell": 4}
+    assert mpwos.KINDS == {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3, "dumbbell": 4, "product": 5}
     assert mpwos.FN_KINDS["table_s1"] == 6 and mpwos.FN_KINDS["torus_mode"] == 5
-    assert mpwos.FN_KINDS["dumbbell_poly"] == 7
+    assert mpwos.FN_KINDS["dumbbell_poly"] == 7 and mpwos.FN_KINDS["product_modes"] == 8
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
