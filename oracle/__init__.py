@@ -15,7 +15,8 @@ Problems are plain dicts (the same dict a test also hands to the GPU binding):
      "max_steps": int, "points": ndarray (point cloud), "k_nn": 16,
      "radius_rule": "curvature" | "spacing" | "curvature_fit" | "curvature_bound", "c_h": 2.4,
      "kappa_bound": float (curvature_bound only),
-     "reconstruction": "patch" | "nearest" (point cloud)}
+     "reconstruction": "patch" | "nearest" (point cloud),
+     "predictor": {"idx": [ks, kt], "values": coef} and "h_eta" (second_order only)}
 """
 import ctypes
 import os
@@ -25,10 +26,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_HERE, "libmpwos_oracle.so")
 
-MANIFOLDS = {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3, "dumbbell": 4, "product": 5}
+MANIFOLDS = {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3, "dumbbell": 4, "product": 5,
+             "cut_torus": 6}
 FN_KINDS = {"zero": 0, "const": 1, "sph_pair": 2, "circle_mode": 3, "legendre": 4,
-            "torus_mode": 5, "table_s1": 6, "dumbbell_poly": 7, "product_modes": 8}
-COMP = {"none": 0, "exact": 1}
+            "torus_mode": 5, "table_s1": 6, "dumbbell_poly": 7, "product_modes": 8, "torus_sine": 9}
+COMP = {"none": 0, "exact": 1, "second_order": 2}
 RADIUS_RULES = {"curvature": 0, "spacing": 1, "curvature_fit": 2, "curvature_bound": 3}
 STATUS = {0: "OK", -1: "EINVAL", -2: "EOFFMANIFOLD", -3: "ENOMEM", 1: "WTRUNC"}
 
@@ -46,6 +48,8 @@ class _Problem(ctypes.Structure):
         ("n_v", ctypes.c_int32), ("compensation", ctypes.c_int32), ("max_steps", ctypes.c_int64),
         ("k_spacing", ctypes.c_int32), ("newton_iters", ctypes.c_int32),
         ("kappa_bound", ctypes.c_double), ("reconstruction", ctypes.c_int32),
+        ("pred_coef", ctypes.c_void_p), ("pred_ks", ctypes.c_int32), ("pred_kt", ctypes.c_int32),
+        ("h_eta", ctypes.c_double),
     ]
 
 
@@ -89,6 +93,9 @@ def lib():
         L.orc_solve.restype = ctypes.c_int
         L.orc_walk_one.argtypes = [vp, vp, u32, u32, u64, vp, vp, vp]
         L.orc_walk_one.restype = ctypes.c_int
+        L.orc_ts_fit.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+        L.orc_ts_fit.restype = ctypes.c_int
+        L.orc_ts_value.argtypes = [vp, ctypes.c_int, ctypes.c_int, d, d, vp]
         _lib = L
     return _lib
 
@@ -145,6 +152,12 @@ class Problem:
         s.newton_iters = int(d.get("newton_iters", 6))
         s.kappa_bound = float(d.get("kappa_bound", 0.0))
         s.reconstruction = {"patch": 0, "nearest": 1}[d.get("reconstruction", "patch")]
+        if "predictor" in d:
+            pc = np.ascontiguousarray(d["predictor"]["values"], dtype=np.float64)
+            self._keep.append(pc)
+            s.pred_coef = pc.ctypes.data
+            s.pred_ks, s.pred_kt = (int(v) for v in d["predictor"]["idx"])
+        s.h_eta = float(d.get("h_eta", 1e-3))
         self.s = s
 
     @property
@@ -299,3 +312,22 @@ def solve(problem, queries, n_walks, seed, threads=None):
         raise ValueError(STATUS.get(st, st))
     return {"u": u, "stderr": se, "walk_S": wS, "walk_K": wK, "status": STATUS[st],
             "truncated": ntr.value, "threads": int(threads)}
+
+
+def ts_fit(U, kt, ks):
+    """Fourier-sine coefficients (ks rows of 2 kt + 1) of node values U (nt, ns - 1)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    nt, ns = U.shape[0], U.shape[1] + 1
+    coef = np.zeros(ks * (2 * kt + 1), dtype=np.float64)
+    st = lib().orc_ts_fit(_ptr(U), nt, ns, kt, ks, _ptr(coef))
+    if st:
+        raise ValueError(STATUS.get(st, st))
+    return coef
+
+
+def ts_value(coef, ks, kt, th, s):
+    """(u, u_th, u_thth, u_ss) of the Fourier-sine series at (th, s)."""
+    c = np.ascontiguousarray(coef, dtype=np.float64)
+    out = np.zeros(4)
+    lib().orc_ts_value(_ptr(c), ks, kt, float(th), float(s), _ptr(out))
+    return out

@@ -30,13 +30,14 @@
 /* ------------------------------------------------------------------------- */
 /* Codes (numeric values fixed by the solver's public interface).             */
 /* ------------------------------------------------------------------------- */
-enum { ORC_SPHERE = 0, ORC_SPHERE_CAP = 1, ORC_TORUS = 2, ORC_POINT_CLOUD = 3, ORC_DUMBBELL = 4, ORC_PRODUCT = 5 };
+enum { ORC_SPHERE = 0, ORC_SPHERE_CAP = 1, ORC_TORUS = 2, ORC_POINT_CLOUD = 3, ORC_DUMBBELL = 4, ORC_PRODUCT = 5,
+       ORC_CUT_TORUS = 6 };
 enum {
   ORC_FN_ZERO = 0, ORC_FN_CONST = 1, ORC_FN_SPH_PAIR = 2, ORC_FN_CIRCLE_MODE = 3,
   ORC_FN_LEGENDRE = 4, ORC_FN_TORUS_MODE = 5, ORC_FN_TABLE_S1 = 6, ORC_FN_DUMBBELL_POLY = 7,
-  ORC_FN_PRODUCT_MODES = 8
+  ORC_FN_PRODUCT_MODES = 8, ORC_FN_TORUS_SINE = 9
 };
-enum { ORC_COMP_NONE = 0, ORC_COMP_EXACT = 1 };
+enum { ORC_COMP_NONE = 0, ORC_COMP_EXACT = 1, ORC_COMP_SECOND_ORDER = 2 };
 enum { ORC_RADIUS_CURVATURE = 0, ORC_RADIUS_SPACING = 1, ORC_RADIUS_CURVATURE_FIT = 2,
        ORC_RADIUS_CURVATURE_BOUND = 3 };
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_EOFFMANIFOLD = -2, ORC_ENOMEM = -3, ORC_WTRUNC = 1 };
@@ -49,7 +50,7 @@ typedef struct {
   int32_t manifold;      /* ORC_SPHERE ... */
   int32_t n;             /* ambient dimension */
   double p[4];           /* sphere: R; cap: R, h; torus: R, a; dumbbell: alpha, kappa (half-length);
-                            product: R (Fourier curve), a (sphere) */
+                            product: R (Fourier curve), a (sphere); cut torus: R, a, phi_c */
   const double* points;  /* point cloud, n_points x 3, row-major */
   int64_t n_points;
   int32_t k_nn;          /* neighbours used by the local reconstruction */
@@ -64,6 +65,9 @@ typedef struct {
   int32_t newton_iters;  /* foot-point Newton iterations on the fitted patch */
   double kappa_bound;    /* point cloud, CURVATURE_BOUND rule: a bound of kappa over M */
   int32_t reconstruction; /* point cloud: 0 = quadratic patch, 1 = the nearest cloud point */
+  /* second-order compensation: coefficients of the predictor u_* as a
+   * Fourier-sine series (layout of ORC_FN_TORUS_SINE), and the normal step */
+  const double* pred_coef; int32_t pred_ks, pred_kt; double h_eta;
 } orc_problem;
 
 /* ------------------------------------------------------------------------- */
@@ -603,6 +607,86 @@ static void orc_torus_angles(double R, const double* x, double* phi, double* psi
 }
 
 /* ------------------------------------------------------------------------- */
+/* Torus with a planar cut (Sec. 4, Example 1): the torus of radii R, a cut   */
+/* by the plane through its axis at angle phi_c; Omega is the half with       */
+/* s = phi - phi_c in (0, pi) (phi the angle about the axis, th the tube      */
+/* angle, as in the paper's parametrization X(th, phi)).  Its boundary Gamma  */
+/* is the two tube circles s = 0 and s = pi.                                  */
+/* ------------------------------------------------------------------------- */
+
+/* Tube angle th, s = phi - phi_c wrapped to (-pi, pi], distance rho to the
+ * core circle. */
+static void orc_ct_coords(const orc_problem* P, const double* x, double* th, double* s, double* rho) {
+  double phi;
+  orc_torus_angles(P->p[0], x, &phi, th, rho);
+  double d = phi - P->p[2];
+  d = d - 6.283185307179586 * floor(d / 6.283185307179586);  /* [0, 2 pi) */
+  if (d > 3.141592653589793) d -= 6.283185307179586;
+  *s = d;
+}
+
+/* u and its derivatives u_th, u_thth, u_ss of a Fourier-sine series
+ *   u(th, s) = sum_{k=1..ks} sin(k s) [c_k0 + sum_{j=1..kt} (c_kj cos j th + d_kj sin j th)],
+ * coefficients stored per k as (c_k0, c_k1, d_k1, ..., c_kkt, d_kkt). */
+typedef struct { double u, ut, utt, uss; } orc_ts_val;
+
+static orc_ts_val orc_ts_eval(const double* c, int ks, int kt, double th, double s) {
+  orc_ts_val v = {0.0, 0.0, 0.0, 0.0};
+  int stride = 2 * kt + 1;
+  for (int k = 1; k <= ks; ++k) {
+    const double* ck = c + (size_t)(k - 1) * stride;
+    double T = ck[0], T1 = 0.0, T2 = 0.0;
+    for (int j = 1; j <= kt; ++j) {
+      double cj = cos(j * th), sj = sin(j * th);
+      double a = ck[2 * j - 1], b = ck[2 * j];
+      T += a * cj + b * sj;
+      T1 += (double)j * (b * cj - a * sj);
+      T2 -= (double)(j * j) * (a * cj + b * sj);
+    }
+    double sk = sin(k * s);
+    v.u += sk * T;
+    v.ut += sk * T1;
+    v.utt += sk * T2;
+    v.uss -= (double)(k * k) * sk * T;
+  }
+  return v;
+}
+
+/* Ambient Laplacian of the closest-point extension of u at distance rho from
+ * the core circle: in toroidal coordinates (rho, th, phi) the extension does
+ * not depend on rho, leaving
+ *   u_thth / rho^2 - sin(th) u_th / (rho (R + rho cos th)) + u_phiphi / (R + rho cos th)^2;
+ * at rho = a this is the Laplace-Beltrami operator of the torus (eq.
+ * LB_cp_identity). */
+static double orc_ct_lap(double R, double rho, double th, orc_ts_val v) {
+  double q = R + rho * cos(th);
+  return v.utt / (rho * rho) - sin(th) * v.ut / (rho * q) + v.uss / (q * q);
+}
+
+/* Nearest point y_G of Gamma (the nearer of the two cut circles) and the
+ * torus normal there. */
+static void orc_ct_cp_gamma(const orc_problem* P, const double* y, double* yg, double* ng) {
+  double R = P->p[0], a = P->p[1];
+  double best = INFINITY;
+  for (int b = 0; b < 2; ++b) {
+    double ph = P->p[2] + (b ? 3.141592653589793 : 0.0);
+    double e[3] = {cos(ph), sin(ph), 0.0};
+    /* circle of radius a about R e in the plane spanned by e and the axis:
+     * the point of y in that plane, seen from the circle's centre */
+    double pe = y[0] * e[0] + y[1] * e[1] - R, pz = y[2];
+    double d = sqrt(pe * pe + pz * pz);
+    double n[3] = {e[0] * pe / d, e[1] * pe / d, pz / d};
+    double q[3] = {R * e[0] + a * n[0], R * e[1] + a * n[1], a * n[2]};
+    double dd = 0.0;
+    for (int i = 0; i < 3; ++i) dd += (q[i] - y[i]) * (q[i] - y[i]);
+    if (dd < best) {
+      best = dd;
+      for (int i = 0; i < 3; ++i) { yg[i] = q[i]; ng[i] = n[i]; }
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------- */
 /* Implicit dumbbell hypersurface (Sec. 4, Example 2): x = (xh, xs) with      */
 /* xh in R^{n-1}; M = { |xh| = R(xs) },                                       */
 /*   R(xs) = sqrt(1 - (xs/kc)^2) (1 - a + 2 a (xs/kc)^2).                     */
@@ -803,7 +887,8 @@ int orc_cp(const orc_problem* P, const double* x, double* y) {
       for (int i = 0; i < n; ++i) y[i] = P->p[0] * x[i] / nx;
       return ORC_OK;
     }
-    case ORC_TORUS: return orc_torus_cp(P->p[0], P->p[1], x, y);
+    case ORC_TORUS:
+    case ORC_CUT_TORUS: return orc_torus_cp(P->p[0], P->p[1], x, y);
     case ORC_POINT_CLOUD: {
       orc_pc_result res;
       int st = orc_pc_project(P, x, &res);
@@ -826,7 +911,8 @@ static double orc_kappa(const orc_problem* P, const double* y) {
     }
     case ORC_SPHERE:
     case ORC_SPHERE_CAP: return 1.0 / P->p[0];
-    case ORC_TORUS: {
+    case ORC_TORUS:
+    case ORC_CUT_TORUS: {
       double phi, psi, dist;
       orc_torus_angles(P->p[0], y, &phi, &psi, &dist);
       double k1 = 1.0 / P->p[1];
@@ -849,14 +935,29 @@ static void orc_cap_cp_gamma(const orc_problem* P, const double* y, double* yg) 
   yg[n - 1] = h;
 }
 
+/* Nearest boundary point y_G and the unit normal of M there. */
+static void orc_gamma_point(const orc_problem* P, const double* y, double* yg, double* nrm) {
+  if (P->manifold == ORC_CUT_TORUS) {
+    orc_ct_cp_gamma(P, y, yg, nrm);
+    return;
+  }
+  orc_cap_cp_gamma(P, y, yg);
+  for (int i = 0; i < P->n; ++i) nrm[i] = yg[i] / P->p[0];
+}
+
+static int orc_has_boundary(const orc_problem* P) {
+  return P->manifold == ORC_SPHERE_CAP || P->manifold == ORC_CUT_TORUS;
+}
+
 /* delta_Gamma(y) = dist(y, E_Gamma(y_Gamma)) with the normal disk of radius
- * ell = rho_geo(y_Gamma) (eq. extended_boundary_disk, eq. delta_Gamma_general). */
-static double orc_cap_delta(const orc_problem* P, const double* y) {
+ * ell = rho_geo(y_Gamma) (eq. extended_boundary_disk, eq. delta_Gamma_general).
+ * Both boundaries here have codimension one in M and M has codimension one,
+ * so the normal space of M at y_G is the line of its unit normal. */
+static double orc_bdry_delta(const orc_problem* P, const double* y) {
   int n = P->n;
   double yg[ORC_MAXN], rG[ORC_MAXN], nrm[ORC_MAXN], rT[ORC_MAXN];
-  orc_cap_cp_gamma(P, y, yg);
-  double R = P->p[0];
-  for (int i = 0; i < n; ++i) { rG[i] = yg[i] - y[i]; nrm[i] = yg[i] / R; }
+  orc_gamma_point(P, y, yg, nrm);
+  for (int i = 0; i < n; ++i) rG[i] = yg[i] - y[i];
   double rn = orc_dot(rG, nrm, n);
   for (int i = 0; i < n; ++i) rT[i] = rG[i] - rn * nrm[i];
   double ell = P->c_kappa / (1.0 + orc_kappa(P, yg));
@@ -866,15 +967,22 @@ static double orc_cap_delta(const orc_problem* P, const double* y) {
 }
 
 /* Membership of the boundary layer Gamma_eps (eq. boundary_layer).  A point
- * at or below the cutting plane counts as inside the layer. */
+ * on the far side of the cut (at or below the cap's plane, or outside
+ * 0 < s < pi on the cut torus) counts as inside the layer. */
 static int orc_in_layer(const orc_problem* P, const double* y) {
-  if (y[P->n - 1] <= P->p[1]) return 1;
-  return orc_cap_delta(P, y) < P->eps;
+  if (P->manifold == ORC_CUT_TORUS) {
+    double th, sv, rho;
+    orc_ct_coords(P, y, &th, &sv, &rho);
+    if (!(sv > 0.0 && sv < 3.141592653589793)) return 1;
+  } else if (y[P->n - 1] <= P->p[1]) {
+    return 1;
+  }
+  return orc_bdry_delta(P, y) < P->eps;
 }
 
 double orc_delta_gamma(const orc_problem* P, const double* y) {
-  if (P->manifold != ORC_SPHERE_CAP) return INFINITY;
-  return orc_cap_delta(P, y);
+  if (!orc_has_boundary(P)) return INFINITY;
+  return orc_bdry_delta(P, y);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -945,8 +1053,70 @@ static double orc_f_omega(const orc_problem* P, const double* y) {
       double th = atan2(y[1], y[0]);
       return orc_table_s1(P->f_values, P->f_nvalues / 2, th);
     }
+    case ORC_FN_TORUS_SINE: {
+      /* f = -Lap_T u + sigma u for the series u (Example 1's family) */
+      double th, sv, rho;
+      orc_ct_coords(P, y, &th, &sv, &rho);
+      orc_ts_val v = orc_ts_eval(P->f_values, P->f_idx[0], P->f_idx[1], th, sv);
+      return -orc_ct_lap(P->p[0], P->p[1], th, v) + P->sigma * v.u;
+    }
   }
   return NAN;
+}
+
+/* Second-order compensation from a predictor u_* (Sec. "Approximation of the
+ * compensation term"): with y = cp(x), x = y + eta n(y), eta the signed
+ * distance along the outward tube normal (eta = rho - a),
+ *   R_*(s; y) = -Lap(E u_*)(y + s n(y)) + sigma u_*(y) - f_Omega(y),
+ *   m1 = (R_*(h) - R_*(-h)) / (2h),  m2 = (R_*(h) - 2 R_*(0) + R_*(-h)) / h^2,
+ *   m_*(x) = eta m1 + eta^2 m2 / 2,  h = h_eta. */
+static double orc_m_second_order(const orc_problem* P, const double* x, const double* y) {
+  double th, sv, rho;
+  orc_ct_coords(P, x, &th, &sv, &rho);
+  double R = P->p[0], a = P->p[1], h = P->h_eta;
+  orc_ts_val v = orc_ts_eval(P->pred_coef, P->pred_ks, P->pred_kt, th, sv);
+  double base = P->sigma * v.u - orc_f_omega(P, y);
+  double Rp = -orc_ct_lap(R, a + h, th, v) + base;
+  double R0 = -orc_ct_lap(R, a, th, v) + base;
+  double Rm = -orc_ct_lap(R, a - h, th, v) + base;
+  double m1 = (Rp - Rm) / (2.0 * h);
+  double m2 = (Rp - 2.0 * R0 + Rm) / (h * h);
+  double eta = rho - a;
+  return eta * m1 + 0.5 * eta * eta * m2;
+}
+
+/* Predictor fit: the discrete orthogonal projection of node values onto the
+ * Fourier-sine series (discrete Fourier transform in th, discrete sine
+ * transform in s).  Nodes th_i = 2 pi i / nt (i < nt), s_j = pi j / ns
+ * (0 < j < ns; u vanishes at s = 0 and pi), U[i (ns - 1) + j - 1].  A series
+ * with ks < ns and 2 kt < nt is reproduced exactly. */
+int orc_ts_fit(const double* U, int nt, int ns, int kt, int ks, double* coef) {
+  if (nt < 1 || ns < 2 || kt < 0 || ks < 1 || ks >= ns || 2 * kt >= nt) return ORC_EINVAL;
+  int stride = 2 * kt + 1;
+  for (int k = 1; k <= ks; ++k) {
+    for (int c = 0; c < stride; ++c) {
+      int j = (c + 1) / 2;
+      double acc = 0.0;
+      for (int i = 0; i < nt; ++i) {
+        double th = 6.283185307179586 * (double)i / (double)nt;
+        double wth = (c == 0) ? 1.0 : ((c & 1) ? cos(j * th) : sin(j * th));
+        for (int jj = 1; jj < ns; ++jj) {
+          double sv = 3.141592653589793 * (double)jj / (double)ns;
+          acc += U[(size_t)i * (ns - 1) + (jj - 1)] * wth * sin(k * sv);
+        }
+      }
+      double norm = (c == 0 ? 1.0 : 2.0) * 2.0 / ((double)nt * (double)ns);
+      coef[(size_t)(k - 1) * stride + c] = acc * norm;
+    }
+  }
+  return ORC_OK;
+}
+
+/* Value and derivatives of a Fourier-sine series, for tests:
+ * out = (u, u_th, u_thth, u_ss). */
+void orc_ts_value(const double* coef, int ks, int kt, double th, double s, double* out) {
+  orc_ts_val v = orc_ts_eval(coef, ks, kt, th, s);
+  out[0] = v.u; out[1] = v.ut; out[2] = v.utt; out[3] = v.uss;
 }
 
 /* Exact compensation m(x), y = cp(x). */
@@ -997,6 +1167,14 @@ static double orc_m_exact(const orc_problem* P, const double* x, const double* y
       orc_torus_angles(P->p[0], x, &phi, &psi, &dist);
       return c[0] * (orc_torus_neg_lap(P->p[0], dist, phi, psi) - orc_torus_neg_lap(P->p[0], P->p[1], phi, psi));
     }
+    case ORC_FN_TORUS_SINE: {
+      /* m(x) = Lap_T u(y) - Lap(Eu)(x): the extension's Laplacian at rho
+       * against the intrinsic one at rho = a */
+      double th, sv, rho;
+      orc_ct_coords(P, x, &th, &sv, &rho);
+      orc_ts_val v = orc_ts_eval(P->f_values, P->f_idx[0], P->f_idx[1], th, sv);
+      return orc_ct_lap(P->p[0], P->p[1], th, v) - orc_ct_lap(P->p[0], rho, th, v);
+    }
   }
   return NAN;
 }
@@ -1040,6 +1218,7 @@ double orc_source(const orc_problem* P, const double* z) {
   if (orc_cp(P, z, y)) return NAN;
   double v = orc_f_omega(P, y);
   if (P->compensation == ORC_COMP_EXACT) v += orc_m_exact(P, z, y);
+  else if (P->compensation == ORC_COMP_SECOND_ORDER) v += orc_m_second_order(P, z, y);
   return v;
 }
 
@@ -1068,7 +1247,7 @@ double orc_radius(const orc_problem* P, const double* y) {
     if (orc_pc_project(P, y, &pc)) return NAN;
   }
   double rg = orc_rho_geo(P, y, &pc);
-  double dg = (P->manifold == ORC_SPHERE_CAP) ? orc_cap_delta(P, y) : INFINITY;
+  double dg = orc_has_boundary(P) ? orc_bdry_delta(P, y) : INFINITY;
   return P->theta * (dg < rg ? dg : rg);
 }
 
@@ -1093,10 +1272,11 @@ static int orc_walk(const orc_ctx* C, const double* y0, uint32_t q, uint32_t w, 
                     int32_t* K_out, int* truncated) {
   const orc_problem* P = C->P;
   int n = P->n;
-  int boundary = (P->manifold == ORC_SPHERE_CAP);
-  double* buf = (double*)malloc(sizeof(double) * 6 * (size_t)n);
+  int boundary = orc_has_boundary(P);
+  double* buf = (double*)malloc(sizeof(double) * 7 * (size_t)n);
   if (!buf) return ORC_ENOMEM;
   double *Y = buf, *Yn = buf + n, *Th = buf + 2 * n, *Z = buf + 3 * n, *g = buf + 4 * n, *yg = buf + 5 * n;
+  double* ng = buf + 6 * n;
   memcpy(Y, y0, sizeof(double) * (size_t)n);
   double W = 1.0, S = 0.0, comp = 0.0;
   uint32_t k = 0;
@@ -1109,7 +1289,7 @@ static int orc_walk(const orc_ctx* C, const double* y0, uint32_t q, uint32_t w, 
     memcpy(Y, pc_cur.y, sizeof(double) * 3);
   }
   if (boundary && orc_in_layer(P, Y)) {
-    orc_cap_cp_gamma(P, Y, yg);
+    orc_gamma_point(P, Y, yg, ng);
     *S_out = W * orc_g_omega(P, yg);
     *K_out = 0;
     free(buf);
@@ -1118,7 +1298,7 @@ static int orc_walk(const orc_ctx* C, const double* y0, uint32_t q, uint32_t w, 
   for (;;) {
     /* (i) radius */
     double rg = orc_rho_geo(P, Y, &pc_cur);
-    double dg = boundary ? orc_cap_delta(P, Y) : INFINITY;
+    double dg = boundary ? orc_bdry_delta(P, Y) : INFINITY;
     double r = P->theta * (dg < rg ? dg : rg);
     double c = orc_c_sigma_r(n, P->sigma, r);
     double om = orc_omega(n, P->sigma, r);
@@ -1152,7 +1332,7 @@ static int orc_walk(const orc_ctx* C, const double* y0, uint32_t q, uint32_t w, 
     if (P->manifold == ORC_POINT_CLOUD) pc_cur = pc_next;
     k += 1;
     if (boundary && orc_in_layer(P, Y)) {
-      orc_cap_cp_gamma(P, Y, yg);
+      orc_gamma_point(P, Y, yg, ng);
       orc_sum_add(&S, &comp, W * orc_g_omega(P, yg));
       break;
     }
@@ -1211,13 +1391,30 @@ static int orc_check(const orc_problem* P) {
   if (!(P->c_kappa > 0.0)) return ORC_EINVAL;
   if (P->n_v < 1 || P->n_v > 255) return ORC_EINVAL;
   if (P->max_steps < 1) return ORC_EINVAL;
-  if (P->manifold == ORC_SPHERE_CAP) {
+  if (orc_has_boundary(P)) {
     if (!(P->eps > 0.0)) return ORC_EINVAL;
-    if (!(fabs(P->p[1]) < P->p[0])) return ORC_EINVAL;
+    if (P->manifold == ORC_SPHERE_CAP && !(fabs(P->p[1]) < P->p[0])) return ORC_EINVAL;
   } else {
     if (!(P->tau_w > 0.0 && P->tau_w < 1.0)) return ORC_EINVAL;
   }
-  if ((P->manifold == ORC_TORUS || P->manifold == ORC_POINT_CLOUD) && P->n != 3) return ORC_EINVAL;
+  if ((P->manifold == ORC_TORUS || P->manifold == ORC_CUT_TORUS || P->manifold == ORC_POINT_CLOUD) && P->n != 3)
+    return ORC_EINVAL;
+  if (P->manifold == ORC_CUT_TORUS) {
+    if (!(P->p[1] > 0.0 && P->p[1] < P->p[0]) || !isfinite(P->p[2])) return ORC_EINVAL;
+    if (P->radius_rule != ORC_RADIUS_CURVATURE) return ORC_EINVAL;
+    if (P->f_kind != ORC_FN_ZERO && P->f_kind != ORC_FN_CONST && P->f_kind != ORC_FN_TORUS_SINE) return ORC_EINVAL;
+    if (P->g_kind != ORC_FN_ZERO && P->g_kind != ORC_FN_CONST) return ORC_EINVAL;
+    if (P->f_kind == ORC_FN_TORUS_SINE &&
+        (!P->f_values || P->f_idx[0] < 1 || P->f_idx[1] < 0 ||
+         P->f_nvalues != (int64_t)P->f_idx[0] * (2 * P->f_idx[1] + 1)))
+      return ORC_EINVAL;
+    if (P->compensation == ORC_COMP_SECOND_ORDER &&
+        (P->f_kind != ORC_FN_TORUS_SINE || !P->pred_coef || P->pred_ks < 1 || P->pred_kt < 0 ||
+         !(P->h_eta > 0.0 && P->h_eta < 0.5 * P->p[1])))
+      return ORC_EINVAL;
+  } else if (P->f_kind == ORC_FN_TORUS_SINE || P->compensation == ORC_COMP_SECOND_ORDER) {
+    return ORC_EINVAL;
+  }
   if (P->manifold == ORC_POINT_CLOUD && (P->k_nn < 6 || P->k_nn > ORC_MAXK || P->n_points < P->k_nn))
     return ORC_EINVAL;
   /* the nearest point carries no curvature: its radius comes from the spacing or a bound */
@@ -1261,7 +1458,7 @@ static double orc_max_radius(const orc_problem* P) {
     return P->theta * P->c_kappa;
   }
   double kmin = 1.0 / P->p[0];
-  if (P->manifold == ORC_TORUS) kmin = 1.0 / P->p[1];
+  if (P->manifold == ORC_TORUS || P->manifold == ORC_CUT_TORUS) kmin = 1.0 / P->p[1];
   if (P->manifold == ORC_PRODUCT) kmin = orc_kappa(P, NULL);
   return P->theta * P->c_kappa / (1.0 + kmin);
 }

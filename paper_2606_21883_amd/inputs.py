@@ -200,6 +200,10 @@ def exact_u(prob, y):
         rho = np.hypot(y[:, 0], y[:, 1])
         psi = np.arctan2(y[:, 2], rho - Rt)
         return f["coef"][0] * np.sin(phi) * np.cos(2.0 * psi)
+    if kind == "torus_sine":
+        ks, kt = f["idx"][:2]
+        th, sv = cut_torus_angles(y, prob["p"][0], prob["p"][2])
+        return torus_sine_u(np.asarray(f["values"]).reshape(ks, 2 * kt + 1), th, sv)
     if kind == "product_modes":
         c = f["coef"]
         a = prob["p"][1]
@@ -337,6 +341,89 @@ def dumbbell_points(nq, n=1001, alpha=0.35, kc=1.2, seed=1, phi_margin=0.1):
     xs = kc * np.cos(t)
     r = dumbbell_profile_radius(xs, alpha, kc)
     return np.concatenate([e * r[:, None], xs[:, None]], axis=1)
+
+
+# ---------------------------------------------------------------------------
+# the torus with a planar cut of Example 1: R = 1, a = 0.45, cut by the plane
+# through the axis at phi_c = 0.35 pi, Omega = {s = phi - phi_c in (0, pi)}
+# ---------------------------------------------------------------------------
+
+# Example 1's solution u = sin(s) A(th) + sin(2s) B(th) + sin(3s) C(th) as a
+# Fourier-sine series: per k = 1..3 the row (c_0, c_1, d_1, c_2, d_2, c_3, d_3)
+# of T_k(th) = c_0 + sum_j c_j cos(j th) + d_j sin(j th).
+#   A = 1 + 0.90 cos th + 0.60 sin 2th + 0.35 cos 3th,  B = 0.45 cos 2th,
+#   C = 0.30 (0.5 + sin th)
+EX1_COEF = np.array([
+    [1.0, 0.90, 0.0, 0.0, 0.60, 0.35, 0.0],
+    [0.0, 0.0, 0.0, 0.45, 0.0, 0.0, 0.0],
+    [0.15, 0.0, 0.30, 0.0, 0.0, 0.0, 0.0],
+])
+
+
+def cut_torus_point(th, s, R=1.0, a=0.45, phi_c=0.35 * math.pi):
+    """X(th, phi) of the paper's parametrization with phi = phi_c + s."""
+    return torus_point(R, a, np.asarray(s) + phi_c, np.asarray(th))
+
+
+def cut_torus_points(nq, R=1.0, a=0.45, phi_c=0.35 * math.pi, seed=1, s_margin=0.0):
+    """Area-uniform random points of Omega (s in (s_margin, pi - s_margin))."""
+    rng = np.random.default_rng(seed)
+    ths = []
+    cnt = 0
+    while cnt < nq:
+        m = 2 * (nq - cnt) + 16
+        th = rng.uniform(0.0, 2.0 * np.pi, m)
+        th = th[rng.uniform(0.0, R + a, m) < R + a * np.cos(th)]
+        ths.append(th)
+        cnt += th.size
+    th = np.concatenate(ths)[:nq]
+    s = rng.uniform(s_margin, np.pi - s_margin, nq)
+    return cut_torus_point(th, s, R, a, phi_c)
+
+
+def cut_torus_nodes(nt, ns, R=1.0, a=0.45, phi_c=0.35 * math.pi):
+    """Predictor nodes th_i = 2 pi i / nt, s_j = pi j / ns (0 < j < ns), th-major."""
+    th = 2.0 * np.pi * np.arange(nt) / nt
+    s = np.pi * np.arange(1, ns) / ns
+    T, S = np.meshgrid(th, s, indexing="ij")
+    return cut_torus_point(T.ravel(), S.ravel(), R, a, phi_c)
+
+
+def torus_sine_u(coef, th, s):
+    """The series sum_k sin(k s) T_k(th) (coef: ks rows of 2 kt + 1)."""
+    coef = np.asarray(coef, dtype=np.float64)
+    ks = coef.shape[0]
+    kt = (coef.shape[1] - 1) // 2
+    th = np.asarray(th)
+    s = np.asarray(s)
+    out = np.zeros(np.broadcast(th, s).shape)
+    for k in range(1, ks + 1):
+        T = coef[k - 1, 0] * np.ones_like(th)
+        for j in range(1, kt + 1):
+            T = T + coef[k - 1, 2 * j - 1] * np.cos(j * th) + coef[k - 1, 2 * j] * np.sin(j * th)
+        out = out + np.sin(k * s) * T
+    return out
+
+
+def cut_torus_angles(y, R=1.0, phi_c=0.35 * math.pi):
+    """(th, s) of points near the torus; s wrapped to (-pi, pi]."""
+    y = np.asarray(y, dtype=np.float64)
+    rho = np.hypot(y[:, 0], y[:, 1])
+    th = np.arctan2(y[:, 2], rho - R)
+    s = np.arctan2(y[:, 1], y[:, 0]) - phi_c
+    s = (s + np.pi) % (2.0 * np.pi) - np.pi
+    s[s == -np.pi] = np.pi
+    return th, s
+
+
+def cut_torus_problem(R=1.0, a=0.45, phi_c=0.35 * math.pi, sigma=4.0, eps=1e-5, n_v=50, coef=None,
+                      compensation="none"):
+    """Example 1: screened Poisson (sigma = 4) on the cut torus with the
+    paper's u (zero on both cut circles), boundary layer eps = 1e-5, N_V = 50."""
+    c = EX1_COEF if coef is None else np.asarray(coef, dtype=np.float64)
+    return problem(manifold="cut_torus", n=3, p=[R, a, phi_c], sigma=sigma, eps=eps, n_v=n_v,
+                   f=dict(kind="torus_sine", idx=[c.shape[0], (c.shape[1] - 1) // 2], values=c.ravel().copy()),
+                   g=dict(kind="zero"), compensation=compensation)
 
 
 # ---------------------------------------------------------------------------
