@@ -64,11 +64,16 @@ typedef enum {
                                 profile parameter; n in [4, 4096]; takes the CURVATURE_BOUND rule
                                 (kappa_bound >= its largest principal curvature) and no
                                 compensation */
-  MPWOS_PRODUCT = 5          /* product manifold of Sec. 4, Example 3: S^1_Fourier(R) x S^2(a) in R^9,
+  MPWOS_PRODUCT = 5,         /* product manifold of Sec. 4, Example 3: S^1_Fourier(R) x S^2(a) in R^9,
                                 X(phi, w) = (R C(phi), a w), C = (cos phi, sin phi, cos 2phi/2,
                                 sin 2phi/2, cos 3phi/3, sin 3phi/3); R = p[0], a = p[1]; n = 9;
                                 cp by Newton on the curve and normalisation; curvature indicator
                                 max(sqrt(14)/(3R), 1/a); no compensation */
+  MPWOS_CUT_TORUS = 6        /* torus with a planar cut of Sec. 4, Example 1: the torus of radii
+                                R = p[0], a = p[1] (0 < a <= R/2) cut by the plane through its axis at
+                                angle phi_c = p[2]; Omega = {0 < phi - phi_c < pi} (phi the angle about
+                                the x_3 axis), Gamma the two tube circles of the cut (boundary case;
+                                delta_Gamma of eq. delta_Gamma_general with ell = rho_geo); n = 3 */
 } mpwos_kind;
 
 /* Source and boundary-data families.  For f the family describes f_Omega;
@@ -90,13 +95,28 @@ typedef enum {
   MPWOS_FN_DUMBBELL_POLY = 7, /* dumbbell, f: u = coef[0] x_n + coef[1] x_n^2 + coef[2] (sum x_h)/sqrt(n-1)
                                 + coef[3] sum_i values[i] x_i^2 (n_values = n - 1, host memory),
                                 f = -Lap_M u + sigma u (Example 2's family; A = diag(values)) */
-  MPWOS_FN_PRODUCT_MODES = 8 /* product manifold, f: u = coef[0] cos(phi) w1 + coef[1] sin(2 phi) w2
+  MPWOS_FN_PRODUCT_MODES = 8, /* product manifold, f: u = coef[0] cos(phi) w1 + coef[1] sin(2 phi) w2
                                 + coef[2] cos(3 phi) (w1^2 - w2^2), f = -Lap_M u + sigma u
                                 (Example 3's family) */
+  MPWOS_FN_TORUS_SINE = 9    /* cut torus, f: u(th, s) = sum_{k=1..K} sin(k s) T_k(th), s = phi - phi_c,
+                                th the tube angle, T_k(th) = c_k0 + sum_{j=1..J} (c_kj cos j th +
+                                d_kj sin j th); K = idx[0] in [1, 64], J = idx[1] in [0, 64]; values
+                                holds the rows (c_k0, c_k1, d_k1, .., c_kJ, d_kJ), k = 1..K (host
+                                memory); f = -Lap_T u + sigma u (Example 1's family; u = 0 on Gamma).
+                                With COMP_SECOND_ORDER the predictor u_* follows as idx[2] >= 1 more
+                                rows of the same width, and coef[0] = h_eta in (0, a/2) is the normal
+                                difference step; n_values = (idx[0] + idx[2]) (2 idx[1] + 1) */
 } mpwos_fn_kind;
 
 typedef enum { MPWOS_FP64_PLAIN = 0, MPWOS_FP32_MIXED = 1 } mpwos_precision;
-typedef enum { MPWOS_COMP_NONE = 0, MPWOS_COMP_EXACT = 1 } mpwos_compensation;
+/* Compensation m (eq. mismatch_definition) added to the source of each Green sample:
+ *   NONE: m_* = 0 (the baseline variant);
+ *   EXACT: m from the family's closed-form u;
+ *   SECOND_ORDER: m_*(x) = eta m1(cp x) + eta^2 m2(cp x) / 2 from a predictor u_* (the
+ *     subsection on approximating the compensation term): R_*(s; y) = -Lap(E u_*)(y + s n(y))
+ *     + sigma u_*(y) - f_Omega(y), m1 and m2 its central differences at s = 0, +-h_eta, eta the
+ *     signed normal distance of x; TORUS_SINE on CUT_TORUS only (see mpwos_predictor_fit). */
+typedef enum { MPWOS_COMP_NONE = 0, MPWOS_COMP_EXACT = 1, MPWOS_COMP_SECOND_ORDER = 2 } mpwos_compensation;
 typedef enum {
   MPWOS_RADIUS_CURVATURE = 0,     /* rho_geo = c_kappa/(1 + kappa(y)) (eq. rho_geo_curvature) */
   MPWOS_RADIUS_SPACING = 1,       /* rho_geo = c_h h(y), h = mean kNN distance (eq. rho_geo_spacing) */
@@ -206,6 +226,24 @@ mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_fn* f, cons
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* mpwos_last_error(void);
+
+/* Coarse predictor u_* for COMP_SECOND_ORDER on a CUT_TORUS (the subsection on
+ * approximating the compensation term, where u_* comes from a coarse Monte
+ * Carlo solve): the baseline solve (compensation forced to NONE, the other
+ * options as given) with n_walks paths at the nt x (ns - 1) interior nodes of
+ * the grid th_i = 2 pi i / nt, s_j = pi j / ns (0 < j < ns), then the discrete
+ * orthogonal projection of the node estimates onto the Fourier-sine series of
+ * MPWOS_FN_TORUS_SINE with ks rows of 2 kt + 1 coefficients (DFT in th, DST
+ * in s; exact for a series with ks < ns and 2 kt < nt).  Every step runs on
+ * the device.
+ *   f, g, c, eps, seed, opt: as for mpwos_solve (opt->device_io is ignored).
+ *   nt >= 1, ns >= 2, 1 <= ks < ns, 0 <= kt, 2 kt < nt; nt (ns - 1) <= 2^20.
+ *   coef_out: ks (2 kt + 1) doubles (host), the rows (c_k0, c_k1, d_k1, ...).
+ *   stats (nullable): the baseline solve's statistics.
+ * EINVAL for another manifold or an out-of-range grid. */
+mpwos_status mpwos_predictor_fit(const mpwos_manifold* manifold, const mpwos_fn* f, const mpwos_fn* g, double c,
+                                 double eps, uint64_t seed, const mpwos_options* opt, int32_t nt, int32_t ns,
+                                 int64_t n_walks, int32_t ks, int32_t kt, double* coef_out, mpwos_stats* stats);
 
 /* ---- graph-captured solves -----------------------------------------------
  * A plan captures the device work of one solve shape (manifold, f, g, c,
@@ -338,6 +376,11 @@ mpwos_status mpwos_debug_cloud_info(const mpwos_manifold* m, int64_t* knn_fallba
  * radial law of eq. Z_sampling_density, in the given precision. */
 mpwos_status mpwos_debug_radial_inv(int32_t n, double X, const double* u, int64_t count,
                                     int32_t precision, double* s);
+
+/* The device fit of mpwos_predictor_fit alone: node values U (nt x (ns - 1)
+ * doubles, host, th-major) to ks (2 kt + 1) series coefficients (host), under
+ * the same limits. */
+mpwos_status mpwos_debug_ts_fit(const double* U, int32_t nt, int32_t ns, int32_t ks, int32_t kt, double* coef_out);
 
 /* `count` Philox4x32-10 blocks for counters (c0 + i, c1, c2, c3), key
  * (seed_lo, seed_hi), written as 4 x count words (host). */

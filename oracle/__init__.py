@@ -157,7 +157,7 @@ class Problem:
             self._keep.append(pc)
             s.pred_coef = pc.ctypes.data
             s.pred_ks, s.pred_kt = (int(v) for v in d["predictor"]["idx"])
-        s.h_eta = float(d.get("h_eta", 1e-3))
+        s.h_eta = float(d.get("h_eta", 1e-2))
         self.s = s
 
     @property

@@ -13,7 +13,9 @@ struct CloudState;
 
 mpwos_status fail(mpwos_status st, const std::string& msg);
 // Families whose host `values` array is copied to the device with the solve.
-inline bool fn_has_values(int kind) { return kind == MPWOS_FN_TABLE_S1 || kind == MPWOS_FN_DUMBBELL_POLY; }
+inline bool fn_has_values(int kind) {
+  return kind == MPWOS_FN_TABLE_S1 || kind == MPWOS_FN_DUMBBELL_POLY || kind == MPWOS_FN_TORUS_SINE;
+}
 mpwos_status hip_fail(hipError_t e, const char* what);
 int device_cu_count();
 void manifold_ref(const mpwos_manifold* m, int d);
@@ -50,6 +52,9 @@ hipError_t launch_valu_probe(int op, uint32_t seed, int32_t iters, uint32_t* out
 mpwos_status launch_group_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue);
 void group_shape(int n, int lanes_req, int& L, int& mb, int& nblk, int& rblk, int& rword);
 hipError_t launch_cp_group(const WalkArgs& a, const double* x, double* y, int64_t m, hipStream_t s);
+hipError_t launch_ct_nodes(double R, double a, double cut_c, double cut_s, int nt, int ns, double* out,
+                           hipStream_t s);
+hipError_t launch_ts_fit(const double* U, int nt, int ns, int kt, int ks, double* coef, hipStream_t s);
 // Bytes of the state record of one time-sliced walk (0 for an unsupported shape).
 int64_t group_record_bytes(int n, int lanes_req, bool fp64);
 

@@ -8,18 +8,21 @@ namespace mpwos {
 constexpr int kMaxJ = 32;       // series terms kept for the radial law
 constexpr int kMaxK = 32;       // point-cloud neighbours
 
-enum Kind : int32_t { kSphere = 0, kCap = 1, kTorus = 2, kCloud = 3, kDumbbell = 4, kProduct = 5 };
+enum Kind : int32_t { kSphere = 0, kCap = 1, kTorus = 2, kCloud = 3, kDumbbell = 4, kProduct = 5, kCutTorus = 6 };
 enum FnKind : int32_t {
   kFnZero = 0, kFnConst = 1, kFnSphPair = 2, kFnCircle = 3, kFnLegendre = 4, kFnTorus = 5, kFnTableS1 = 6,
-  kFnDumbbell = 7, kFnProduct = 8
+  kFnDumbbell = 7, kFnProduct = 8, kFnTorusSine = 9
 };
+// compensation modes (WalkArgs::comp)
+enum Comp : int32_t { kCompNone = 0, kCompExact = 1, kCompSecondOrder = 2 };
 
 // A source / boundary family as the device sees it.
 struct FnDev {
   int32_t kind;
   int32_t idx[3];
   double coef[8];
-  const double* values;   // device copy of a TABLE_S1 table (2M doubles) or the dumbbell diagonal (n-1)
+  const double* values;   // device copy of a TABLE_S1 table (2M doubles), the dumbbell diagonal (n-1),
+                          // or a TORUS_SINE series (idx[0] rows of 2 idx[1] + 1, then idx[2] predictor rows)
   int64_t m;              // M (table length of one half); n - 1 for the dumbbell diagonal
   double lam;             // eigenvalue of the family (sphere families); trace of the dumbbell diagonal
   double u_scale;         // u = u_scale * f for eigen families
@@ -134,6 +137,7 @@ struct WalkArgs {
   double inv_sigma;            // 1 / sigma
   double rho_geo;              // c_kappa / (1 + kappa) with the manifold's constant curvature bound
   double cap_rg;               // sphere cap: radius sqrt(R^2 - h^2) of the boundary circle
+  double cut_c, cut_s;         // cut torus: cos and sin of the cut angle phi_c
   int64_t max_steps;
   FnDev f, g;
   // constant-radius data (closed analytic manifolds)

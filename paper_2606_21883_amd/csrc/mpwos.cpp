@@ -333,6 +333,12 @@ static mpwos_status check_manifold_desc(const mpwos_manifold_desc* d) {
       if (!(d->p[1] > 0 && d->p[1] <= 0.5 * d->p[0]))
         return fail(MPWOS_EINVAL, "torus: need 0 < a <= R/2 (constant curvature indicator 1/a)");
       return MPWOS_OK;
+    case MPWOS_CUT_TORUS:
+      if (d->n != 3) return fail(MPWOS_EINVAL, "cut torus: n must be 3");
+      if (!(d->p[1] > 0 && d->p[1] <= 0.5 * d->p[0]))
+        return fail(MPWOS_EINVAL, "cut torus: need 0 < a <= R/2 (constant curvature indicator 1/a)");
+      if (!std::isfinite(d->p[2])) return fail(MPWOS_EINVAL, "cut torus: the cut angle p[2] must be finite");
+      return MPWOS_OK;
     case MPWOS_PRODUCT:
       if (d->n != 9) return fail(MPWOS_EINVAL, "product manifold: n must be 9");
       if (!(d->p[0] > 0.0) || !(d->p[1] > 0.0) || !std::isfinite(d->p[0]) || !std::isfinite(d->p[1]))
@@ -361,7 +367,8 @@ static double const_kappa(const mpwos_manifold_desc& d) {
   switch (d.kind) {
     case MPWOS_SPHERE:
     case MPWOS_SPHERE_CAP: return 1.0 / d.p[0];
-    case MPWOS_TORUS_IMPLICIT: return 1.0 / d.p[1];
+    case MPWOS_TORUS_IMPLICIT:
+    case MPWOS_CUT_TORUS: return 1.0 / d.p[1];
     // the Fourier curve's curvature (|C''|^2 = 14, speed sqrt 3) and the sphere's
     case MPWOS_PRODUCT: return std::max(std::sqrt(14.0) / (3.0 * d.p[0]), 1.0 / d.p[1]);
   }
@@ -402,6 +409,15 @@ static mpwos_status check_fn(const mpwos_fn* f, const mpwos_manifold_desc& d, bo
     case MPWOS_FN_DUMBBELL_POLY:
       if (d.kind != MPWOS_DUMBBELL || is_g) return bad("DUMBBELL_POLY is a source on the dumbbell");
       if (!f->values || f->n_values != d.n - 1) return bad("DUMBBELL_POLY needs n - 1 values");
+      return MPWOS_OK;
+    case MPWOS_FN_TORUS_SINE:
+      if (d.kind != MPWOS_CUT_TORUS || is_g) return bad("TORUS_SINE is a source on the cut torus");
+      if (f->idx[0] < 1 || f->idx[0] > 64 || f->idx[1] < 0 || f->idx[1] > 64 || f->idx[2] < 0 || f->idx[2] > 64)
+        return bad("TORUS_SINE: idx[0] in [1, 64], idx[1] and idx[2] in [0, 64]");
+      if (!f->values || f->n_values != (int64_t)(f->idx[0] + f->idx[2]) * (2 * f->idx[1] + 1))
+        return bad("TORUS_SINE needs (idx[0] + idx[2]) (2 idx[1] + 1) values");
+      for (int64_t i = 0; i < f->n_values; ++i)
+        if (!std::isfinite(f->values[i])) return bad("TORUS_SINE: non-finite coefficient");
       return MPWOS_OK;
   }
   return bad("unknown function kind");
@@ -478,6 +494,12 @@ static bool query_on_manifold(const mpwos_manifold_desc& d, const double* y) {
       const double rho = std::hypot(y[0], y[1]);
       const double dc = std::hypot(rho - d.p[0], y[2]);
       return std::fabs(dc - d.p[1]) <= tol;
+    }
+    case MPWOS_CUT_TORUS: {
+      // on the torus and on the open half 0 < phi - phi_c < pi
+      const double rho = std::hypot(y[0], y[1]);
+      const double dc = std::hypot(rho - d.p[0], y[2]);
+      return std::fabs(dc - d.p[1]) <= tol && y[1] * std::cos(d.p[2]) - y[0] * std::sin(d.p[2]) > 0.0;
     }
     case MPWOS_PRODUCT: {
       // nearest point of the Fourier curve: maximise x_c . C(phi) (fine grid, Newton)
@@ -603,7 +625,7 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(MPWOS_EINVAL, "c (sigma) must be finite and > 0");
   if (nq < 1 || nq > 0xFFFFFFFFll) return fail(MPWOS_EINVAL, "n_queries must be in [1, 2^32)");
   if (nw < 1 || nw > 0xFFFFFFFFll) return fail(MPWOS_EINVAL, "n_walks must be in [1, 2^32)");
-  const bool boundary = d.kind == MPWOS_SPHERE_CAP;
+  const bool boundary = d.kind == MPWOS_SPHERE_CAP || d.kind == MPWOS_CUT_TORUS;
   if (boundary && !g) return fail(MPWOS_EINVAL, "g is required on a manifold with boundary");
   if (!boundary && g) return fail(MPWOS_EINVAL, "g must be NULL on a closed manifold");
   if (boundary && !(eps > 0.0 && std::isfinite(eps))) return fail(MPWOS_EINVAL, "eps must be > 0");
@@ -616,8 +638,22 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
   if (o.max_steps < 1) return fail(MPWOS_EINVAL, "max_steps must be >= 1");
   if (o.precision != MPWOS_FP64_PLAIN && o.precision != MPWOS_FP32_MIXED)
     return fail(MPWOS_EINVAL, "unknown precision");
-  if (o.compensation != MPWOS_COMP_NONE && o.compensation != MPWOS_COMP_EXACT)
+  if (o.compensation != MPWOS_COMP_NONE && o.compensation != MPWOS_COMP_EXACT &&
+      o.compensation != MPWOS_COMP_SECOND_ORDER)
     return fail(MPWOS_EINVAL, "unknown compensation");
+  if (o.compensation == MPWOS_COMP_SECOND_ORDER) {
+    if (d.kind != MPWOS_CUT_TORUS || f->kind != MPWOS_FN_TORUS_SINE)
+      return fail(MPWOS_EINVAL, "the second-order compensation takes a TORUS_SINE source on the cut torus");
+    if (f->idx[2] < 1) return fail(MPWOS_EINVAL, "the second-order compensation needs predictor rows (idx[2] >= 1)");
+    if (!(f->coef[0] > 0.0 && f->coef[0] < 0.5 * d.p[1]))
+      return fail(MPWOS_EINVAL, "the second-order compensation needs h_eta = coef[0] in (0, a/2)");
+  }
+  if (d.kind == MPWOS_CUT_TORUS) {
+    if (f->kind != MPWOS_FN_ZERO && f->kind != MPWOS_FN_CONST && f->kind != MPWOS_FN_TORUS_SINE)
+      return fail(MPWOS_EINVAL, "f: the cut torus takes ZERO, CONST or TORUS_SINE");
+    if (g && g->kind != MPWOS_FN_ZERO && g->kind != MPWOS_FN_CONST)
+      return fail(MPWOS_EINVAL, "g: the cut torus takes ZERO or CONST boundary data");
+  }
   if (o.radius_rule < MPWOS_RADIUS_CURVATURE || o.radius_rule > MPWOS_RADIUS_CURVATURE_BOUND)
     return fail(MPWOS_EINVAL, "unknown radius_rule");
   if (d.kind == MPWOS_PRODUCT && o.compensation != MPWOS_COMP_NONE)
@@ -662,6 +698,10 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
   a.inv_sigma = 1.0 / sigma;
   a.rho_geo = o.c_kappa / (1.0 + const_kappa(d));
   if (d.kind == MPWOS_SPHERE_CAP) a.cap_rg = std::sqrt(d.p[0] * d.p[0] - d.p[1] * d.p[1]);
+  if (d.kind == MPWOS_CUT_TORUS) {
+    a.cut_c = std::cos(d.p[2]);
+    a.cut_s = std::sin(d.p[2]);
+  }
   a.eps = eps;
   a.theta = o.theta;
   a.c_kappa = o.c_kappa;
@@ -932,6 +972,90 @@ extern "C" mpwos_status mpwos_debug_cp(const mpwos_manifold* m, const double* x,
   hipError_t e = a.n >= 4 ? launch_cp_group(a, dx, dy, n_points, s) : launch_cp_points(a, dx, dy, n_points, s);
   if (e != hipSuccess) return hip_fail(e, "cp kernel");
   HIP_TRY(hipMemcpyAsync(y, dy, bytes, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MPWOS_OK;
+}
+
+// grid limits shared by the predictor fit and its inspection entry point
+static mpwos_status check_fit_grid(int32_t nt, int32_t ns, int32_t ks, int32_t kt) {
+  if (nt < 1 || ns < 2 || (int64_t)nt * (ns - 1) > ((int64_t)1 << 20))
+    return fail(MPWOS_EINVAL, "predictor grid: nt >= 1, ns >= 2 and nt (ns - 1) <= 2^20");
+  if (ks < 1 || ks >= ns || kt < 0 || 2 * kt >= nt || ks > 64 || kt > 64)
+    return fail(MPWOS_EINVAL, "predictor series: 1 <= ks < ns, 0 <= kt, 2 kt < nt, both <= 64");
+  return MPWOS_OK;
+}
+
+extern "C" mpwos_status mpwos_predictor_fit(const mpwos_manifold* manifold, const mpwos_fn* f, const mpwos_fn* g,
+                                            double c, double eps, uint64_t seed, const mpwos_options* opt, int32_t nt,
+                                            int32_t ns, int64_t n_walks, int32_t ks, int32_t kt, double* coef_out,
+                                            mpwos_stats* stats) {
+  g_last_error.clear();
+  if (!manifold || !coef_out) return fail(MPWOS_EINVAL, "manifold and coef_out must not be NULL");
+  const mpwos_manifold_desc& d = manifold->desc;
+  if (d.kind != MPWOS_CUT_TORUS) return fail(MPWOS_EINVAL, "the predictor fit is defined on the cut torus");
+  mpwos_status st = check_fit_grid(nt, ns, ks, kt);
+  if (st) return st;
+  mpwos_options o;
+  if (opt) o = *opt;
+  else mpwos_options_default(&o);
+  o.compensation = MPWOS_COMP_NONE;
+  o.device_io = 1;
+  o.walk_S = nullptr;
+  o.walk_K = nullptr;
+  hipStream_t s = (hipStream_t)o.stream;
+  hipStream_t own = nullptr;
+  if (!s) {
+    HIP_TRY(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+    s = own;
+  }
+  o.stream = s;
+  const int64_t m = (int64_t)nt * (ns - 1);
+  const int64_t nc = (int64_t)ks * (2 * kt + 1);
+  double* buf = nullptr;
+  hipError_t e = hipMalloc((void**)&buf, (size_t)(4 * m + nc) * sizeof(double));
+  if (e != hipSuccess) {
+    if (own) (void)hipStreamDestroy(own);
+    return hip_fail(e, "predictor buffers");
+  }
+  double *nodes = buf, *u = buf + 3 * m, *coef = buf + 4 * m;
+  e = launch_ct_nodes(d.p[0], d.p[1], std::cos(d.p[2]), std::sin(d.p[2]), nt, ns, nodes, s);
+  if (e != hipSuccess) st = hip_fail(e, "predictor nodes");
+  // the coarse solve: every node is a query of the baseline estimator
+  if (!st) st = mpwos_solve(manifold, f, g, c, nodes, m, n_walks, eps, seed, &o, u, nullptr, stats);
+  if (st >= 0) {
+    const mpwos_status solve_st = st;
+    e = launch_ts_fit(u, nt, ns, kt, ks, coef, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(coef_out, coef, (size_t)nc * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    st = e == hipSuccess ? solve_st : hip_fail(e, "predictor fit");
+  } else {
+    (void)hipStreamSynchronize(s);
+  }
+  (void)hipFree(buf);
+  if (own) (void)hipStreamDestroy(own);
+  return st;
+}
+
+extern "C" mpwos_status mpwos_debug_ts_fit(const double* U, int32_t nt, int32_t ns, int32_t ks, int32_t kt,
+                                           double* coef_out) {
+  g_last_error.clear();
+  if (!U || !coef_out) return fail(MPWOS_EINVAL, "bad arguments");
+  mpwos_status st = check_fit_grid(nt, ns, ks, kt);
+  if (st) return st;
+  std::lock_guard<std::mutex> guard(g_ctx.lock);
+  st = context_init(g_ctx);
+  if (st) return st;
+  const int64_t m = (int64_t)nt * (ns - 1);
+  const int64_t nc = (int64_t)ks * (2 * kt + 1);
+  st = ensure(g_ctx.tmp, (size_t)(m + nc) * sizeof(double));
+  if (st) return st;
+  hipStream_t s = g_ctx.stream;
+  double* du = (double*)g_ctx.tmp.p;
+  double* dc = du + m;
+  HIP_TRY(hipMemcpyAsync(du, U, (size_t)m * sizeof(double), hipMemcpyHostToDevice, s));
+  hipError_t e = launch_ts_fit(du, nt, ns, kt, ks, dc, s);
+  if (e != hipSuccess) return hip_fail(e, "fit kernel");
+  HIP_TRY(hipMemcpyAsync(coef_out, dc, (size_t)nc * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return MPWOS_OK;
 }

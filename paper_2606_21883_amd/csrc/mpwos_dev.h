@@ -569,6 +569,94 @@ __device__ __forceinline__ T torus_neg_lap(T R, T tube, T sphi, T cpsi, T spsi) 
   return over_((T)4 * u, tube * tube) + over_(u, rt * rt) - over_((T)2 * sphi * spsi * s2, tube * rt);
 }
 
+// ---- Fourier-sine series over the cut torus (Example 1's family) ---------
+// u(th, s) = sum_{k=1..ks} sin(k s) [c_k0 + sum_{j=1..kt} (c_kj cos j th + d_kj sin j th)],
+// rows of 2 kt + 1 coefficients (c_k0, c_k1, d_k1, ...).  Evaluated from the
+// unit vectors (cos th, sin th) and (cos s, sin s) by angle addition, j
+// outermost: A_j = sum_k c_kj sin(k s), B_j = sum_k d_kj sin(k s) (and the
+// same with -k^2 for u_ss), so no per-k array is kept.  FP64 throughout.
+struct TsVal {
+  double u, ut, utt, uss;
+};
+
+__device__ __forceinline__ TsVal ts_eval(const double* c, int ks, int kt, double ct, double st, double cs,
+                                         double ss) {
+  TsVal v{0.0, 0.0, 0.0, 0.0};
+  const int w = 2 * kt + 1;
+  double cj = 1.0, sj = 0.0;  // cos(j th), sin(j th)
+  for (int j = 0; j <= kt; ++j) {
+    double A = 0.0, B = 0.0, A2 = 0.0, B2 = 0.0;
+    double sk = ss, ck = cs;  // sin(k s), cos(k s) from k = 1
+    for (int k = 1; k <= ks; ++k) {
+      const double* row = c + (size_t)(k - 1) * w;
+      const double ca = j == 0 ? row[0] : row[2 * j - 1];
+      const double cb = j == 0 ? 0.0 : row[2 * j];
+      const double kk = (double)(k * k);
+      A = fma(ca, sk, A);
+      B = fma(cb, sk, B);
+      A2 = fma(-kk * ca, sk, A2);
+      B2 = fma(-kk * cb, sk, B2);
+      const double sn = sk * cs + ck * ss;
+      ck = ck * cs - sk * ss;
+      sk = sn;
+    }
+    const double jj = (double)j;
+    v.u += cj * A + sj * B;
+    v.ut += jj * (cj * B - sj * A);
+    v.utt -= jj * jj * (cj * A + sj * B);
+    v.uss += cj * A2 + sj * B2;
+    const double cn = cj * ct - sj * st;
+    sj = sj * ct + cj * st;
+    cj = cn;
+  }
+  return v;
+}
+
+// Ambient Laplacian of the closest-point extension at distance rho from the
+// core circle (the extension does not depend on rho in toroidal
+// coordinates); at rho = a, the torus's Laplace-Beltrami operator.
+__device__ __forceinline__ double ct_lap(double R, double rho, double ct, double st, const TsVal& v) {
+  const double q = R + rho * ct;
+  return v.utt / (rho * rho) - st * v.ut / (rho * q) + v.uss / (q * q);
+}
+
+// f_Omega(y) + m(z) for the series family on the cut torus.  The angles come
+// from y (those of z are the same: cp keeps them); z contributes its
+// distance rho_z from the core circle.
+//   exact m: Lap_T u(y) - Lap(Eu)(z);
+//   second order (predictor u_* in the rows after u's, normal step h_eta =
+//   coef[0]): R_*(s) = -Lap(Eu_*)(y + s n) + sigma u_*(y) - f_Omega(y) at
+//   s = 0, +-h, central differences m1, m2, and m_* = eta m1 + eta^2 m2 / 2
+//   with eta = rho_z - a.
+__device__ __forceinline__ double torus_sine_source(const WalkArgs& a, const double* z, const double* y) {
+  const FnDev& f = a.f;
+  const double R = a.p[0], tube = a.p[1];
+  const double rxy = sqrt(y[0] * y[0] + y[1] * y[1]);
+  const double dr = rxy - R;
+  const double dt = sqrt(dr * dr + y[2] * y[2]);
+  const double ct = dr / dt, st = y[2] / dt;
+  const double cp = y[0] / rxy, sp = y[1] / rxy;
+  const double cs = cp * a.cut_c + sp * a.cut_s, ss = sp * a.cut_c - cp * a.cut_s;
+  const int ks = f.idx[0], kt = f.idx[1];
+  const TsVal v = ts_eval(f.values, ks, kt, ct, st, cs, ss);
+  const double lap_t = ct_lap(R, tube, ct, st, v);
+  const double fv = -lap_t + a.sigma * v.u;
+  if (a.comp == kCompNone) return fv;
+  const double rz = sqrt(z[0] * z[0] + z[1] * z[1]);
+  const double rho = sqrt((rz - R) * (rz - R) + z[2] * z[2]);
+  if (a.comp == kCompExact) return fv + (lap_t - ct_lap(R, rho, ct, st, v));
+  const double h = f.coef[0];
+  const TsVal w = ts_eval(f.values + (size_t)ks * (2 * kt + 1), f.idx[2], kt, ct, st, cs, ss);
+  const double base = a.sigma * w.u - fv;
+  const double Rp = -ct_lap(R, tube + h, ct, st, w) + base;
+  const double R0 = -ct_lap(R, tube, ct, st, w) + base;
+  const double Rm = -ct_lap(R, tube - h, ct, st, w) + base;
+  const double m1 = (Rp - Rm) / (2.0 * h);
+  const double m2 = (Rp - 2.0 * R0 + Rm) / (h * h);
+  const double eta = rho - tube;
+  return fv + (eta * m1 + 0.5 * eta * eta * m2);
+}
+
 // f_Omega(y) + m(z) for a point z of the ball and y = cp(z): the families
 // with more state (circle modes, Legendre sums, tabulated S^1 data).
 template <class T>
@@ -616,6 +704,11 @@ __device__ T source_rich(const WalkArgs& a, const T* z, const T* y, int n) {
       const double us = (1.0 - fr) * f.values[f.m + i0] + fr * f.values[f.m + i1];
       const T zz = z[0] * z[0] + z[1] * z[1];
       return (T)fv + (T)(fv - a.sigma * us) * (over_(R * R, zz) - (T)1);
+    }
+    case kFnTorusSine: {
+      const double zd[3] = {(double)z[0], (double)z[1], (double)z[2]};
+      const double yd[3] = {(double)y[0], (double)y[1], (double)y[2]};
+      return (T)torus_sine_source(a, zd, yd);
     }
   }
   return (T)0;

@@ -70,10 +70,77 @@ __device__ __forceinline__ bool cap_in_layer(const WalkArgs& a, const T* y, doub
   return dg < a.eps;
 }
 
+// ---- geometry of the torus with a planar cut --------------------------------
+// Omega = {0 < s < pi}, s = phi - phi_c; Gamma is the two tube circles s = 0
+// and s = pi.  y_Gamma is the nearer of the two circles' nearest points; the
+// torus normal there is the unit vector from the circle's centre.  FP64 in
+// both precisions (a handful of operations per step).
+__device__ __forceinline__ void ct_gamma_point(const WalkArgs& a, const double* y, double* yg, double* ng) {
+  const double R = a.p[0], tube = a.p[1];
+  double best = 0.0;
+  for (int b = 0; b < 2; ++b) {
+    const double ex = b ? -a.cut_c : a.cut_c, ey = b ? -a.cut_s : a.cut_s;
+    const double pe = y[0] * ex + y[1] * ey - R, pz = y[2];
+    const double d = sqrt(pe * pe + pz * pz);
+    const double n0 = ex * pe / d, n1 = ey * pe / d, n2 = pz / d;
+    const double q0 = R * ex + tube * n0, q1 = R * ey + tube * n1, q2 = tube * n2;
+    const double dd = (q0 - y[0]) * (q0 - y[0]) + (q1 - y[1]) * (q1 - y[1]) + (q2 - y[2]) * (q2 - y[2]);
+    if (b == 0 || dd < best) {
+      best = dd;
+      yg[0] = q0; yg[1] = q1; yg[2] = q2;
+      ng[0] = n0; ng[1] = n1; ng[2] = n2;
+    }
+  }
+}
+
+// effective distance to the normal segment of half-length ell = rho_geo(y_Gamma)
+// (the manifold's constant curvature indicator 1/a)
+__device__ __forceinline__ double ct_delta(const WalkArgs& a, const double* y) {
+  double yg[3], ng[3];
+  ct_gamma_point(a, y, yg, ng);
+  const double r0 = yg[0] - y[0], r1 = yg[1] - y[1], r2 = yg[2] - y[2];
+  const double rn = r0 * ng[0] + r1 * ng[1] + r2 * ng[2];
+  const double t0 = r0 - rn * ng[0], t1 = r1 - rn * ng[1], t2 = r2 - rn * ng[2];
+  double tn = fabs(rn) - a.rho_geo;
+  tn = tn > 0.0 ? tn : 0.0;
+  return sqrt(t0 * t0 + t1 * t1 + t2 * t2 + tn * tn);
+}
+
+// Membership of the boundary layer; the far side of the cut (sin s <= 0)
+// counts as inside.  dg receives delta_Gamma(y) otherwise.
+template <class T>
+__device__ __forceinline__ bool ct_in_layer(const WalkArgs& a, const T* y, double& dg) {
+  const double yd[3] = {(double)y[0], (double)y[1], (double)y[2]};
+  if (!(yd[1] * a.cut_c - yd[0] * a.cut_s > 0.0)) return true;
+  dg = ct_delta(a, yd);
+  return dg < a.eps;
+}
+
+// boundary layer test and boundary datum, by manifold
+template <class T, int N, int KIND>
+__device__ __forceinline__ bool in_layer(const WalkArgs& a, const T* y, double& dg) {
+  if constexpr (KIND == kCutTorus) return ct_in_layer<T>(a, y, dg);
+  else return cap_in_layer<T, N>(a, y, dg);
+}
+
+template <class T, int N, int KIND>
+__device__ __forceinline__ double layer_value(const WalkArgs& a, const T* y) {
+  T yg[N];
+  if constexpr (KIND == kCutTorus) {
+    const double yd[3] = {(double)y[0], (double)y[1], (double)y[2]};
+    double gd[3], nd[3];
+    ct_gamma_point(a, yd, gd, nd);
+    for (int i = 0; i < 3; ++i) yg[i] = (T)gd[i];
+  } else {
+    cap_gamma_point<T, N>(a, y, yg);
+  }
+  return boundary_value<T>(a, yg, N);
+}
+
 // ---- closest point ----------------------------------------------------------
 template <class T, int N, int KIND>
 __device__ __forceinline__ void closest_point(const WalkArgs& a, const T* x, T* y) {
-  if constexpr (KIND == kTorus) {
+  if constexpr (KIND == kTorus || KIND == kCutTorus) {
     // FP64 in both modes: the quartic cancels to a few bits in FP32 near the
     // surface, which the Newton solve cannot recover
     double xd[3] = {(double)x[0], (double)x[1], (double)x[2]}, yd[3];
@@ -113,11 +180,9 @@ __device__ __forceinline__ bool walk_init(const WalkArgs& a, const double* queri
     for (int i = 0; i < N; ++i) st.Y[i] = p.y[i];
     if (!a.const_r) st.rg = cloud_rho_geo(a, p);
   }
-  if constexpr (KIND == kCap) {
-    if (cap_in_layer<T, N>(a, st.Y, st.rg)) {
-      T yg[N];
-      cap_gamma_point<T, N>(a, st.Y, yg);
-      st.S = boundary_value<T>(a, yg, N);
+  if constexpr (KIND == kCap || KIND == kCutTorus) {
+    if (in_layer<T, N, KIND>(a, st.Y, st.rg)) {
+      st.S = layer_value<T, N, KIND>(a, st.Y);
       return true;
     }
   }
@@ -152,7 +217,7 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
   const Stream rs{st.q, st.w, (uint32_t)seed, (uint32_t)(seed >> 32)};
   // (i) radius r(Y) = theta min(delta_Gamma, rho_geo) and the weights
   double r, c, om, X2, norm = 0.0;
-  if constexpr (KIND == kCap) {
+  if constexpr (KIND == kCap || KIND == kCutTorus) {
     // delta_Gamma(Y) from the previous step's stop test (or the start)
     const double dg = st.rg;
     const double rg = a.rho_geo;
@@ -206,11 +271,9 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
   for (int i = 0; i < N; ++i) st.Y[i] = Yn[i];
   if constexpr (KIND == kCloud) st.rg = rg_next;
   st.k += 1;
-  if constexpr (KIND == kCap) {
-    if (cap_in_layer<T, N>(a, st.Y, st.rg)) {
-      T yg[N];
-      cap_gamma_point<T, N>(a, st.Y, yg);
-      kahan_add(st.S, st.C, st.W * boundary_value<T>(a, yg, N));
+  if constexpr (KIND == kCap || KIND == kCutTorus) {
+    if (in_layer<T, N, KIND>(a, st.Y, st.rg)) {
+      kahan_add(st.S, st.C, st.W * layer_value<T, N, KIND>(a, st.Y));
       return true;
     }
   } else {
@@ -625,6 +688,7 @@ hipError_t launch_valu_probe(int op, uint32_t seed, int32_t iters, uint32_t* out
       if (kind == kCap && n == 2) return FN<double, 2, kCap>(__VA_ARGS__);           \
       if (kind == kTorus && n == 3) return FN<double, 3, kTorus>(__VA_ARGS__);       \
       if (kind == kCloud && n == 3) return FN<double, 3, kCloud>(__VA_ARGS__);       \
+      if (kind == kCutTorus && n == 3) return FN<double, 3, kCutTorus>(__VA_ARGS__); \
     } else {                                                                         \
       if (kind == kSphere && n == 2) return FN<float, 2, kSphere>(__VA_ARGS__);      \
       if (kind == kSphere && n == 3) return FN<float, 3, kSphere>(__VA_ARGS__);      \
@@ -632,6 +696,7 @@ hipError_t launch_valu_probe(int op, uint32_t seed, int32_t iters, uint32_t* out
       if (kind == kCap && n == 2) return FN<float, 2, kCap>(__VA_ARGS__);            \
       if (kind == kTorus && n == 3) return FN<float, 3, kTorus>(__VA_ARGS__);        \
       if (kind == kCloud && n == 3) return FN<float, 3, kCloud>(__VA_ARGS__);        \
+      if (kind == kCutTorus && n == 3) return FN<float, 3, kCutTorus>(__VA_ARGS__);  \
     }                                                                                \
   } while (0)
 
@@ -718,7 +783,8 @@ int lane_occupancy(const WalkArgs& a, int block) {
 }
 
 bool lane_supported(int kind, int n) {
-  return (n == 2 || n == 3) && (kind == kSphere || kind == kCap || ((kind == kTorus || kind == kCloud) && n == 3));
+  return (n == 2 || n == 3) &&
+         (kind == kSphere || kind == kCap || ((kind == kTorus || kind == kCloud || kind == kCutTorus) && n == 3));
 }
 
 hipError_t launch_reduce(const double* walk_S, const int32_t* walk_K, int64_t nq, int64_t nw, int64_t max_steps,

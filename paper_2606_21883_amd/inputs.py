@@ -467,6 +467,14 @@ def config(name, scale=1.0, seed=1):
         # Example 4: 8000 points on S^2, queries on the sphere
         prob = sphere_cloud_problem(sphere_point_cloud(8000, seed))
         return prob, sphere_uniform(sz(1024), 3, seed + 7), sz(1024)
+    if name == "cut_torus":
+        # Example 1: N_s = 100 random points of the cut torus, N_V = 50,
+        # eps = 1e-5, second-order compensation from a coarse predictor (the
+        # baseline solve with 256 paths at 32 x 15 nodes, fitted by a 4 x 9
+        # Fourier-sine series), h_eta = 1e-2
+        prob = dict(cut_torus_problem(compensation="second_order"), h_eta=1e-2,
+                    predictor_grid=dict(nt=32, ns=16, n_walks=sz(256), ks=4, kt=4))
+        return prob, cut_torus_points(sz(100), seed=seed), sz(10000)
     if name == "dumbbell":
         # Table 1's setting: 20 points of the 1000-dimensional dumbbell, N = 1000
         # paths each, N_V = 50 Green samples per step, tau_W = 1e-8

@@ -15,12 +15,13 @@ LIBPATH = os.path.join(_HERE, "libmpwos.so")
 OK, EINVAL, EOFFMANIFOLD, ENOMEM, EDEVICE, EBUSY, WTRUNC = 0, -1, -2, -3, -4, -5, 1
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EOFFMANIFOLD", -3: "ENOMEM", -4: "EDEVICE", -5: "EBUSY",
                 1: "WTRUNC"}
-KINDS = {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3, "dumbbell": 4, "product": 5}
+KINDS = {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3, "dumbbell": 4, "product": 5,
+         "cut_torus": 6}
 FN_KINDS = {"zero": 0, "const": 1, "sph_pair": 2, "circle_mode": 3, "legendre": 4, "torus_mode": 5,
-            "table_s1": 6, "dumbbell_poly": 7, "product_modes": 8}
+            "table_s1": 6, "dumbbell_poly": 7, "product_modes": 8, "torus_sine": 9}
 PRECISION = {"fp64": 0, "fp32": 1}
 RECONSTRUCTIONS = {"patch": 0, "nearest": 1}
-COMP = {"none": 0, "exact": 1}
+COMP = {"none": 0, "exact": 1, "second_order": 2}
 RADIUS_RULES = {"curvature": 0, "spacing": 1, "curvature_fit": 2, "curvature_bound": 3}
 
 
@@ -77,7 +78,8 @@ EXPORTS = ["mpwos_options_default", "mpwos_manifold_create", "mpwos_manifold_des
            "mpwos_server_stats_get", "mpwos_server_destroy", "mpwos_debug_cp", "mpwos_debug_cloud_info",
            "mpwos_debug_radial_inv",
            "mpwos_debug_philox", "mpwos_copy_probe", "mpwos_valu_probe", "mpwos_version",
-           "mpwos_plan_create", "mpwos_plan_execute", "mpwos_plan_stats", "mpwos_plan_destroy", "mpwos_autotune"]
+           "mpwos_plan_create", "mpwos_plan_execute", "mpwos_plan_stats", "mpwos_plan_destroy", "mpwos_autotune",
+           "mpwos_predictor_fit", "mpwos_debug_ts_fit"]
 
 _lib = None
 
@@ -122,6 +124,8 @@ def lib():
         L.mpwos_plan_stats.argtypes = [vp, vp, vp]
         L.mpwos_plan_destroy.argtypes = [vp]
         L.mpwos_autotune.argtypes = [vp, vp, vp, d, vp, i64, i64, d, vp, vp, vp]
+        L.mpwos_predictor_fit.argtypes = [vp, vp, vp, d, d, ctypes.c_uint64, vp, i32, i32, i64, i32, i32, vp, vp]
+        L.mpwos_debug_ts_fit.argtypes = [vp, i32, i32, i32, i32, vp]
         for nm in EXPORTS:
             if nm not in ("mpwos_options_default", "mpwos_last_error", "mpwos_version"):
                 getattr(L, nm).restype = ctypes.c_int
@@ -173,6 +177,27 @@ def make_options(prob=None, **kw):
     if "stream" in src and src["stream"] is not None:
         o.stream = ctypes.c_void_p(int(src["stream"]))
     return o
+
+
+def has_boundary(prob):
+    return prob["manifold"] in ("sphere_cap", "cut_torus")
+
+
+def source_fn(prob):
+    """The f record of a problem dict.  A TORUS_SINE source under the
+    second-order compensation carries the predictor's rows after u's (both
+    padded to one th width) and h_eta in coef[0]."""
+    f = prob.get("f", {"kind": "zero"})
+    if f["kind"] != "torus_sine" or prob.get("compensation") != "second_order" or "predictor" not in prob:
+        return f
+    ks, kt = (int(v) for v in f["idx"][:2])
+    pk, pt = (int(v) for v in prob["predictor"]["idx"][:2])
+    w = 2 * max(kt, pt) + 1
+    rows = np.zeros((ks + pk, w))
+    rows[:ks, :2 * kt + 1] = np.asarray(f["values"], dtype=np.float64).reshape(ks, 2 * kt + 1)
+    rows[ks:, :2 * pt + 1] = np.asarray(prob["predictor"]["values"], dtype=np.float64).reshape(pk, 2 * pt + 1)
+    return {"kind": "torus_sine", "idx": [ks, max(kt, pt), pk], "coef": [float(prob.get("h_eta", 1e-2))],
+            "values": rows.ravel()}
 
 
 def make_fn(d, keep):
@@ -241,8 +266,8 @@ def solve(prob, queries, n_walks, seed, manifold=None, walk_outputs=False, **opt
     keep = []
     Q = np.ascontiguousarray(queries, dtype=np.float64)
     nq = Q.shape[0]
-    f = make_fn(prob.get("f", {"kind": "zero"}), keep)
-    g = make_fn(prob.get("g"), keep) if prob["manifold"] == "sphere_cap" else None
+    f = make_fn(source_fn(prob), keep)
+    g = make_fn(prob.get("g"), keep) if has_boundary(prob) else None
     o = make_options(prob, **optkw)
     u = np.zeros(nq)
     se = np.zeros(nq)
@@ -268,8 +293,8 @@ def solve(prob, queries, n_walks, seed, manifold=None, walk_outputs=False, **opt
 def solve_device(manifold, prob, queries_ptr, nq, n_walks, seed, u_ptr, se_ptr, stream=None, **optkw):
     """mpwos_solve with device-resident queries and outputs (raw device pointers)."""
     keep = []
-    f = make_fn(prob.get("f", {"kind": "zero"}), keep)
-    g = make_fn(prob.get("g"), keep) if prob["manifold"] == "sphere_cap" else None
+    f = make_fn(source_fn(prob), keep)
+    g = make_fn(prob.get("g"), keep) if has_boundary(prob) else None
     o = make_options(prob, device_io=1, stream=stream, **optkw)
     st = Stats()
     rc = lib().mpwos_solve(manifold.handle, ctypes.byref(f), ctypes.byref(g) if g is not None else None,
@@ -336,8 +361,8 @@ class Plan:
 
     def __init__(self, manifold, prob, n_queries, n_walks, **optkw):
         self._keep = []
-        f = make_fn(prob.get("f", {"kind": "zero"}), self._keep)
-        g = make_fn(prob.get("g"), self._keep) if prob["manifold"] == "sphere_cap" else None
+        f = make_fn(source_fn(prob), self._keep)
+        g = make_fn(prob.get("g"), self._keep) if has_boundary(prob) else None
         o = make_options(prob, **optkw)
         self.handle = ctypes.c_void_p()
         _check(lib().mpwos_plan_create(manifold.handle, ctypes.byref(f), ctypes.byref(g) if g is not None else None,
@@ -367,8 +392,8 @@ def autotune(prob, queries, n_walks, manifold=None, **optkw):
     m = Manifold(prob) if own else manifold
     keep = []
     Q = np.ascontiguousarray(queries, dtype=np.float64)
-    f = make_fn(prob.get("f", {"kind": "zero"}), keep)
-    g = make_fn(prob.get("g"), keep) if prob["manifold"] == "sphere_cap" else None
+    f = make_fn(source_fn(prob), keep)
+    g = make_fn(prob.get("g"), keep) if has_boundary(prob) else None
     o = make_options(prob, **optkw)
     best = Options()
     ms = ctypes.c_double()
@@ -398,8 +423,8 @@ class Server:
         Q = np.ascontiguousarray(queries, dtype=np.float64)
         req = Request()
         req.manifold = manifold.handle
-        req.f = make_fn(prob.get("f", {"kind": "zero"}), keep)
-        if prob["manifold"] == "sphere_cap":
+        req.f = make_fn(source_fn(prob), keep)
+        if has_boundary(prob):
             req.g = make_fn(prob["g"], keep)
             req.has_g = 1
         req.c = float(prob["sigma"])
@@ -451,3 +476,31 @@ class Server:
 
 def server_create(hbm_budget_bytes, slice_walk_steps=0):
     return Server(hbm_budget_bytes, slice_walk_steps)
+
+
+def predictor_fit(prob, nt, ns, n_walks, seed, ks, kt, manifold=None, **optkw):
+    """mpwos_predictor_fit: coarse baseline solve at the (th, s) nodes and the
+    Fourier-sine fit; returns (coef (ks, 2 kt + 1), stats)."""
+    own = manifold is None
+    m = Manifold(prob) if own else manifold
+    keep = []
+    f = make_fn(prob.get("f", {"kind": "zero"}), keep)
+    g = make_fn(prob.get("g"), keep)
+    o = make_options(prob, **optkw)
+    coef = np.zeros(ks * (2 * kt + 1))
+    st = Stats()
+    rc = lib().mpwos_predictor_fit(m.handle, ctypes.byref(f), ctypes.byref(g), float(prob["sigma"]),
+                                   float(prob.get("eps", 1e-3)), int(seed), ctypes.byref(o), int(nt), int(ns),
+                                   int(n_walks), int(ks), int(kt), _ptr(coef), ctypes.byref(st))
+    if own:
+        m.close()
+    _check(rc)
+    return coef.reshape(ks, 2 * kt + 1), {k: getattr(st, k) for k, _ in Stats._fields_}
+
+
+def debug_ts_fit(U, ks, kt):
+    """The device fit alone: node values U (nt, ns - 1) to (ks, 2 kt + 1) coefficients."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    coef = np.zeros(ks * (2 * kt + 1))
+    _check(lib().mpwos_debug_ts_fit(_ptr(U), U.shape[0], U.shape[1] + 1, int(ks), int(kt), _ptr(coef)))
+    return coef.reshape(ks, 2 * kt + 1)

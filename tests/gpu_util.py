@@ -20,7 +20,7 @@ def score_scale(prob):
         s = 1.0 + abs(f["coef"][0]) * 2 * fmax / prob["sigma"]
     if "values" in prob.get("f", {}):
         s += float(np.max(np.abs(prob["f"]["values"]))) * 2 / prob["sigma"]
-    if prob["manifold"] == "sphere_cap":
+    if prob["manifold"] in ("sphere_cap", "cut_torus"):
         s += sum(abs(c) for c in prob.get("g", {}).get("coef", [0.0]))
     return s
 

@@ -89,9 +89,13 @@ def test_enum_values_match_header():
     for name, val in [("MPWOS_SPHERE", 0), ("MPWOS_SPHERE_CAP", 1), ("MPWOS_TORUS_IMPLICIT", 2),
                       ("MPWOS_POINT_CLOUD", 3), ("MPWOS_DUMBBELL", 4), ("MPWOS_FN_SPH_PAIR", 2),
                       ("MPWOS_FN_TABLE_S1", 6), ("MPWOS_FN_DUMBBELL_POLY", 7),
-                      ("MPWOS_FP32_MIXED", 1), ("MPWOS_EOFFMANIFOLD", -2), ("MPWOS_WTRUNC", 1)]:
+                      ("MPWOS_FP32_MIXED", 1), ("MPWOS_EOFFMANIFOLD", -2), ("MPWOS_WTRUNC", 1),
+                      ("MPWOS_PRODUCT", 5), ("MPWOS_CUT_TORUS", 6), ("MPWOS_FN_TORUS_SINE", 9),
+                      ("MPWOS_COMP_SECOND_ORDER", 2)]:
         assert re.search(rf"\b{name}\s*=\s*{val}\b", txt), name
-    assert mpwos.KINDS == {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3, "dumbbell": 4, "product": 5}
+    assert mpwos.KINDS == {"sphere": 0, "sphere_cap": 1, "torus": 2, "point_cloud": 3, "dumbbell": 4, "product": 5,
+                           "cut_torus": 6}
+    assert mpwos.FN_KINDS["torus_sine"] == 9 and mpwos.COMP["second_order"] == 2
     assert mpwos.FN_KINDS["table_s1"] == 6 and mpwos.FN_KINDS["torus_mode"] == 5
     assert mpwos.FN_KINDS["dumbbell_poly"] == 7 and mpwos.FN_KINDS["product_modes"] == 8
 
