@@ -140,7 +140,18 @@ __device__ __forceinline__ double layer_value(const WalkArgs& a, const T* y) {
 // ---- closest point ----------------------------------------------------------
 template <class T, int N, int KIND>
 __device__ __forceinline__ void closest_point(const WalkArgs& a, const T* x, T* y) {
-  if constexpr (KIND == kTorus || KIND == kCutTorus) {
+  if constexpr (KIND == kCutTorus) {
+    // the parametrized torus of the cut example: the nearest point of the
+    // core circle, then the tube radius along the offset (closed form)
+    const T R = (T)a.p[0], tube = (T)a.p[1];
+    const T f = R * rsqrt_(x[0] * x[0] + x[1] * x[1]);
+    const T c0 = x[0] * f, c1 = x[1] * f;
+    const T d0 = x[0] - c0, d1 = x[1] - c1, d2 = x[2];
+    const T g = tube * rsqrt_(d0 * d0 + d1 * d1 + d2 * d2);
+    y[0] = c0 + g * d0;
+    y[1] = c1 + g * d1;
+    y[2] = g * d2;
+  } else if constexpr (KIND == kTorus) {
     // FP64 in both modes: the quartic cancels to a few bits in FP32 near the
     // surface, which the Newton solve cannot recover
     double xd[3] = {(double)x[0], (double)x[1], (double)x[2]}, yd[3];
