@@ -574,38 +574,39 @@ __device__ __forceinline__ T torus_neg_lap(T R, T tube, T sphi, T cpsi, T spsi) 
 // rows of 2 kt + 1 coefficients (c_k0, c_k1, d_k1, ...).  Evaluated from the
 // unit vectors (cos th, sin th) and (cos s, sin s) by angle addition, j
 // outermost: A_j = sum_k c_kj sin(k s), B_j = sum_k d_kj sin(k s) (and the
-// same with -k^2 for u_ss), so no per-k array is kept.  FP64 throughout.
+// same with -k^2 for u_ss), so no per-k array is kept.
+template <class T>
 struct TsVal {
-  double u, ut, utt, uss;
+  T u, ut, utt, uss;
 };
 
-__device__ __forceinline__ TsVal ts_eval(const double* c, int ks, int kt, double ct, double st, double cs,
-                                         double ss) {
-  TsVal v{0.0, 0.0, 0.0, 0.0};
+template <class T>
+__device__ __forceinline__ TsVal<T> ts_eval(const double* c, int ks, int kt, T ct, T st, T cs, T ss) {
+  TsVal<T> v{(T)0, (T)0, (T)0, (T)0};
   const int w = 2 * kt + 1;
-  double cj = 1.0, sj = 0.0;  // cos(j th), sin(j th)
+  T cj = (T)1, sj = (T)0;  // cos(j th), sin(j th)
   for (int j = 0; j <= kt; ++j) {
-    double A = 0.0, B = 0.0, A2 = 0.0, B2 = 0.0;
-    double sk = ss, ck = cs;  // sin(k s), cos(k s) from k = 1
+    T A = (T)0, B = (T)0, A2 = (T)0, B2 = (T)0;
+    T sk = ss, ck = cs;  // sin(k s), cos(k s) from k = 1
     for (int k = 1; k <= ks; ++k) {
       const double* row = c + (size_t)(k - 1) * w;
-      const double ca = j == 0 ? row[0] : row[2 * j - 1];
-      const double cb = j == 0 ? 0.0 : row[2 * j];
-      const double kk = (double)(k * k);
+      const T ca = (T)(j == 0 ? row[0] : row[2 * j - 1]);
+      const T cb = (T)(j == 0 ? 0.0 : row[2 * j]);
+      const T kk = (T)(k * k);
       A = fma(ca, sk, A);
       B = fma(cb, sk, B);
       A2 = fma(-kk * ca, sk, A2);
       B2 = fma(-kk * cb, sk, B2);
-      const double sn = sk * cs + ck * ss;
+      const T sn = sk * cs + ck * ss;
       ck = ck * cs - sk * ss;
       sk = sn;
     }
-    const double jj = (double)j;
+    const T jj = (T)j;
     v.u += cj * A + sj * B;
     v.ut += jj * (cj * B - sj * A);
     v.utt -= jj * jj * (cj * A + sj * B);
     v.uss += cj * A2 + sj * B2;
-    const double cn = cj * ct - sj * st;
+    const T cn = cj * ct - sj * st;
     sj = sj * ct + cj * st;
     cj = cn;
   }
@@ -614,47 +615,72 @@ __device__ __forceinline__ TsVal ts_eval(const double* c, int ks, int kt, double
 
 // Ambient Laplacian of the closest-point extension at distance rho from the
 // core circle (the extension does not depend on rho in toroidal
-// coordinates); at rho = a, the torus's Laplace-Beltrami operator.
-__device__ __forceinline__ double ct_lap(double R, double rho, double ct, double st, const TsVal& v) {
-  const double q = R + rho * ct;
-  return v.utt / (rho * rho) - st * v.ut / (rho * q) + v.uss / (q * q);
+// coordinates); at rho = a, the torus's Laplace-Beltrami operator:
+//   L(rho) = u_thth / rho^2 - sin(th) u_th / (rho q) + u_ss / q^2,  q = R + rho cos(th).
+template <class T>
+__device__ __forceinline__ T ct_lap(T R, T rho, T ct, T st, const TsVal<T>& v) {
+  const T q = R + rho * ct;
+  return over_(v.utt, rho * rho) - over_(st * v.ut, rho * q) + over_(v.uss, q * q);
 }
 
 // f_Omega(y) + m(z) for the series family on the cut torus.  The angles come
 // from y (those of z are the same: cp keeps them); z contributes its
 // distance rho_z from the core circle.
 //   exact m: Lap_T u(y) - Lap(Eu)(z);
-//   second order (predictor u_* in the rows after u's, normal step h_eta =
-//   coef[0]): R_*(s) = -Lap(Eu_*)(y + s n) + sigma u_*(y) - f_Omega(y) at
-//   s = 0, +-h, central differences m1, m2, and m_* = eta m1 + eta^2 m2 / 2
-//   with eta = rho_z - a.
-__device__ __forceinline__ double torus_sine_source(const WalkArgs& a, const double* z, const double* y) {
+//   second order (predictor u_* in the rows after u's, normal step h =
+//   coef[0]): with R_*(s) = -L_*(a + s) + sigma u_*(y) - f_Omega(y),
+//   m1 = (R_*(h) - R_*(-h)) / (2h), m2 = (R_*(h) - 2 R_*(0) + R_*(-h)) / h^2
+//   and m_* = eta m1 + eta^2 m2 / 2, eta = rho_z - a.
+// The differences are taken in closed form: L is linear in (u_thth, u_th,
+// u_ss) with coefficients 1/rho^2, -sin(th)/(rho q), 1/q^2, and the central
+// differences of those at a +- h are rational in a, h and q0 = R + a cos(th):
+//   D1[1/rho^2] = -2a / (a^2 - h^2)^2,        D2[1/rho^2] = (6a^2 - 2h^2) / (a^2 (a^2 - h^2)^2),
+//   D1[1/q^2]   = -2 q0 c / (q0^2 - h^2c^2)^2, D2[1/q^2]   = (6 q0^2 - 2h^2c^2) c^2 / (q0^2 (q0^2 - h^2c^2)^2),
+//   1/(rho q) = (1/rho - c/q) / R with D1[1/rho] = -1/(a^2 - h^2), D2[1/rho] = 2 / (a (a^2 - h^2)),
+//   D1[1/q] = -c / (q0^2 - h^2c^2), D2[1/q] = 2c^2 / (q0 (q0^2 - h^2c^2))   (c = cos th).
+// These equal the difference quotients exactly but do not cancel, so the
+// walk's own precision suffices (the quotients themselves lose
+// log10(1/h^2) digits to rounding).
+template <class T>
+__device__ __forceinline__ T torus_sine_source(const WalkArgs& a, const T* z, const T* y) {
   const FnDev& f = a.f;
-  const double R = a.p[0], tube = a.p[1];
-  const double rxy = sqrt(y[0] * y[0] + y[1] * y[1]);
-  const double dr = rxy - R;
-  const double dt = sqrt(dr * dr + y[2] * y[2]);
-  const double ct = dr / dt, st = y[2] / dt;
-  const double cp = y[0] / rxy, sp = y[1] / rxy;
-  const double cs = cp * a.cut_c + sp * a.cut_s, ss = sp * a.cut_c - cp * a.cut_s;
+  const T R = (T)a.p[0], tube = (T)a.p[1];
+  const T rxy = sqrt_(y[0] * y[0] + y[1] * y[1]);
+  const T dr = rxy - R;
+  const T idt = rsqrt_(dr * dr + y[2] * y[2]);
+  const T ct = dr * idt, st = y[2] * idt;
+  const T irxy = rcp_(rxy);
+  const T cp = y[0] * irxy, sp = y[1] * irxy;
+  const T cc = (T)a.cut_c, sc = (T)a.cut_s;
+  const T cs = cp * cc + sp * sc, ss = sp * cc - cp * sc;
   const int ks = f.idx[0], kt = f.idx[1];
-  const TsVal v = ts_eval(f.values, ks, kt, ct, st, cs, ss);
-  const double lap_t = ct_lap(R, tube, ct, st, v);
-  const double fv = -lap_t + a.sigma * v.u;
+  const TsVal<T> v = ts_eval<T>(f.values, ks, kt, ct, st, cs, ss);
+  const T lap_t = ct_lap<T>(R, tube, ct, st, v);
+  const T fv = -lap_t + (T)a.sigma * v.u;
   if (a.comp == kCompNone) return fv;
-  const double rz = sqrt(z[0] * z[0] + z[1] * z[1]);
-  const double rho = sqrt((rz - R) * (rz - R) + z[2] * z[2]);
-  if (a.comp == kCompExact) return fv + (lap_t - ct_lap(R, rho, ct, st, v));
-  const double h = f.coef[0];
-  const TsVal w = ts_eval(f.values + (size_t)ks * (2 * kt + 1), f.idx[2], kt, ct, st, cs, ss);
-  const double base = a.sigma * w.u - fv;
-  const double Rp = -ct_lap(R, tube + h, ct, st, w) + base;
-  const double R0 = -ct_lap(R, tube, ct, st, w) + base;
-  const double Rm = -ct_lap(R, tube - h, ct, st, w) + base;
-  const double m1 = (Rp - Rm) / (2.0 * h);
-  const double m2 = (Rp - 2.0 * R0 + Rm) / (h * h);
-  const double eta = rho - tube;
-  return fv + (eta * m1 + 0.5 * eta * eta * m2);
+  const T rz = sqrt_(z[0] * z[0] + z[1] * z[1]);
+  const T rho = sqrt_((rz - R) * (rz - R) + z[2] * z[2]);
+  if (a.comp == kCompExact) return fv + (lap_t - ct_lap<T>(R, rho, ct, st, v));
+  const T h = (T)f.coef[0];
+  const TsVal<T> w = ts_eval<T>(f.values + (size_t)ks * (2 * kt + 1), f.idx[2], kt, ct, st, cs, ss);
+  const T h2 = h * h;
+  const T e = tube * tube - h2;                      // a^2 - h^2
+  const T q0 = R + tube * ct;
+  const T hc2 = h2 * ct * ct;
+  const T g = q0 * q0 - hc2;                         // q0^2 - h^2 c^2
+  const T ie = rcp_(e), ig = rcp_(g);
+  const T d1_r2 = -(T)2 * tube * ie * ie;
+  const T d2_r2 = ((T)6 * tube * tube - (T)2 * h2) * ie * ie * rcp_(tube * tube);
+  const T d1_q2 = -(T)2 * q0 * ct * ig * ig;
+  const T d2_q2 = ((T)6 * q0 * q0 - (T)2 * hc2) * ct * ct * ig * ig * rcp_(q0 * q0);
+  const T iR = rcp_(R);
+  const T d1_rq = (-ie + ct * ct * ig) * iR;
+  const T d2_rq = ((T)2 * ie * rcp_(tube) - (T)2 * ct * ct * ct * ig * rcp_(q0)) * iR;
+  const T B = -st * w.ut;
+  const T m1 = -(w.utt * d1_r2 + B * d1_rq + w.uss * d1_q2);
+  const T m2 = -(w.utt * d2_r2 + B * d2_rq + w.uss * d2_q2);
+  const T eta = rho - tube;
+  return fv + (eta * m1 + (T)0.5 * eta * eta * m2);
 }
 
 // f_Omega(y) + m(z) for a point z of the ball and y = cp(z): the families
@@ -705,11 +731,7 @@ __device__ T source_rich(const WalkArgs& a, const T* z, const T* y, int n) {
       const T zz = z[0] * z[0] + z[1] * z[1];
       return (T)fv + (T)(fv - a.sigma * us) * (over_(R * R, zz) - (T)1);
     }
-    case kFnTorusSine: {
-      const double zd[3] = {(double)z[0], (double)z[1], (double)z[2]};
-      const double yd[3] = {(double)y[0], (double)y[1], (double)y[2]};
-      return (T)torus_sine_source(a, zd, yd);
-    }
+    case kFnTorusSine: return torus_sine_source<T>(a, z, y);
   }
   return (T)0;
 }
