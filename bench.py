@@ -48,8 +48,8 @@ PEAK_SLOTS = 256 * 128 * 2.4e9
 # WRITE_SIZE all of them).  Valid only for the kernel sources they were taken
 # on (their SHA-256 below); any change to those sources makes traffic null.
 TRAFFIC = {
-    "kernel_sha256": "c623a0348897d2ae65ada04e3dc2e7ecd87a8985850b9042d0b8ca2641fe9d9b",
-    "fetch_kib": 464.0, "fetch_factor": 2.0,
+    "kernel_sha256": "4bd856f27341eaa4b6e6b03196432ebfe34c9ef57433bd2e850d3de1ecda590f",
+    "fetch_kib": 459.875, "fetch_factor": 2.0,
     "write_kib": 196608.0, "write_factor": 1.0,
 }
 KERNEL_SOURCES = ["walk_lane.hip", "mpwos_dev.h", "kernel_args.h", "cloud_dev.h"]
@@ -68,7 +68,8 @@ def step_ops(kind, n, n_v=1):
     per walk), by issue class.  Counts what the method as specified must do:
       - Philox4x32-10 blocks: one for the direction and one per Green sample
         (direction words and the radius word); 10 rounds of two 32x32->64
-        multiplies and four xors per block (the key schedule is scalar);
+        multiplies and two three-way xors per block (one v_bitop3_b32 each;
+        the key schedule is scalar);
       - two operations per uniform; per direction cos and sin of the angle,
         and on S^2 the axis coordinate and its radius (one square root, three
         multiply-adds, two multiplies);
@@ -82,7 +83,7 @@ def step_ops(kind, n, n_v=1):
         stop test.
     """
     sets = 1 + n_v                        # the direction of Theta and each Green sample
-    ops = {"mad_u64_u32": 20 * sets, "xor_b32": 40 * sets, "f32": 0, "trans": 0, "f64": 13}
+    ops = {"mad_u64_u32": 20 * sets, "bitop3_b32": 20 * sets, "f32": 0, "trans": 0, "f64": 13}
     words = (n - 1) + n_v * n             # direction words, plus the radius word per sample
     ops["f32"] += 2 * words
     ops["trans"] += sets * (3 if n == 3 else 2)
@@ -111,7 +112,7 @@ def valu_weights():
     def mixed(name):
         return max(0.0, (4.0 / r[name] - 3.0 / base) * base)
 
-    w = {"f32": 1.0, "xor_b32": base / r["xor_b32"], "f64": base / r["fma_f64"],
+    w = {"f32": 1.0, "bitop3_b32": base / r["bitop3_b32"], "f64": base / r["fma_f64"],
          "trans": mixed("sin_f32+3fma"), "mad_u64_u32": mixed("mad_u64_u32+3fma")}
     return w, r
 

@@ -397,7 +397,8 @@ mpwos_status mpwos_copy_probe(int64_t bytes, int32_t reps, double* ms);
  * multiply-add), 3 mul_hi_u32, 4 log_f32, 5 sin_f32, 6 sqrt_f32, 7 rsq_f32,
  * 8 rcp_f32, 9 xor_b32, 10 add_f64; mixed streams (each step one operation
  * beside three independent fma_f32, all four counted): 11 sin_f32,
- * 12 mad_u64_u32.  Used to weight the operations of the walk-step cost model.
+ * 12 mad_u64_u32; 13 bitop3_b32 (three-input bitwise operation, here a
+ * three-way xor).  Used to weight the operations of the walk-step cost model.
  * EINVAL for another op. */
 mpwos_status mpwos_valu_probe(int32_t op, double* lane_ops_per_s);
 

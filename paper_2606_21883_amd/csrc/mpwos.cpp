@@ -1142,7 +1142,7 @@ extern "C" mpwos_status mpwos_copy_probe(int64_t bytes, int32_t reps, double* ms
 
 extern "C" mpwos_status mpwos_valu_probe(int32_t op, double* lane_ops_per_s) {
   g_last_error.clear();
-  if (op < 0 || op > 12 || !lane_ops_per_s) return fail(MPWOS_EINVAL, "bad arguments");
+  if (op < 0 || op > 13 || !lane_ops_per_s) return fail(MPWOS_EINVAL, "bad arguments");
   std::lock_guard<std::mutex> guard(g_ctx.lock);
   mpwos_status st = context_init(g_ctx);
   if (st) return st;
@@ -1164,8 +1164,8 @@ extern "C" mpwos_status mpwos_valu_probe(int32_t op, double* lane_ops_per_s) {
   }
   if (out) (void)hipFree(out);
   if (e != hipSuccess) return hip_fail(e, "valu probe");
-  // operations per chain step: the xor chain issues two, the mixed streams four
-  const double per_chain = (op == 9) ? 2.0 : (op >= 11 ? 4.0 : 1.0);
+  // operations per chain step: the xor and bitop3 chains issue two, the mixed streams four
+  const double per_chain = (op == 9 || op == 13) ? 2.0 : (op == 11 || op == 12 ? 4.0 : 1.0);
   *lane_ops_per_s = (double)blocks * 256.0 * 8.0 * per_chain * (double)iters / (best * 1e-3);
   return MPWOS_OK;
 }

@@ -16,17 +16,23 @@ namespace mpwos {
 // Philox4x32-10 (Salmon et al., SC'11): each round multiplies words 0 and 2
 // by the two Philox constants (full 64-bit products), mixes the high halves
 // with the other words and the round key; the key advances by the Weyl
-// increments between rounds.
+// increments between rounds.  Each three-way xor is one gfx950 v_bitop3_b32
+// (truth table 0x96: the parity of the three input bits), so a round costs
+// two 32x32->64 multiply-adds and two bitwise operations.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t xor3_(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t m0 = (uint64_t)c0 * 0xD2511F53ull;
     const uint64_t m1 = (uint64_t)c2 * 0xCD9E8D57ull;
-    const uint32_t a = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+    const uint32_t a = xor3_((uint32_t)(m1 >> 32), c1, k0);
     const uint32_t b = (uint32_t)m1;
-    const uint32_t c = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+    const uint32_t c = xor3_((uint32_t)(m0 >> 32), c3, k1);
     const uint32_t d = (uint32_t)m0;
     c0 = a; c1 = b; c2 = c; c3 = d;
     k0 += 0x9E3779B9u;

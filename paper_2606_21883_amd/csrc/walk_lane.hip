@@ -669,6 +669,10 @@ __global__ __launch_bounds__(256) void valu_probe_kernel(uint32_t seed, int32_t 
           x[i] = x[i] ^ y[(i + 1) & 7];
           y[i] = y[i] ^ x[(i + 3) & 7];
         }
+        if constexpr (OP == 13) {
+          x[i] = __builtin_amdgcn_bitop3_b32(x[i], y[(i + 1) & 7], m, 0x96);
+          y[i] = __builtin_amdgcn_bitop3_b32(y[i], x[(i + 3) & 7], m, 0x96);
+        }
       }
     }
 #pragma unroll
@@ -683,7 +687,7 @@ hipError_t launch_valu_probe(int op, uint32_t seed, int32_t iters, uint32_t* out
   case K: hipLaunchKernelGGL(valu_probe_kernel<K>, dim3(blocks), dim3(256), 0, s, seed, iters, out); break;
     MPWOS_PROBE_CASE(0) MPWOS_PROBE_CASE(1) MPWOS_PROBE_CASE(2) MPWOS_PROBE_CASE(3) MPWOS_PROBE_CASE(4)
     MPWOS_PROBE_CASE(5) MPWOS_PROBE_CASE(6) MPWOS_PROBE_CASE(7) MPWOS_PROBE_CASE(8) MPWOS_PROBE_CASE(9)
-    MPWOS_PROBE_CASE(10) MPWOS_PROBE_CASE(11) MPWOS_PROBE_CASE(12)
+    MPWOS_PROBE_CASE(10) MPWOS_PROBE_CASE(11) MPWOS_PROBE_CASE(12) MPWOS_PROBE_CASE(13)
 #undef MPWOS_PROBE_CASE
     default: return hipErrorInvalidValue;
   }

@@ -341,7 +341,7 @@ def copy_probe(nbytes, reps):
 
 VALU_OPS = ["fma_f32", "fma_f64", "mad_u64_u32", "mul_hi_u32", "log_f32", "sin_f32", "sqrt_f32", "rsq_f32",
             "rcp_f32", "xor_b32", "add_f64",
-            "sin_f32+3fma", "mad_u64_u32+3fma"]
+            "sin_f32+3fma", "mad_u64_u32+3fma", "bitop3_b32"]
 
 
 def valu_probe(op):
