@@ -135,6 +135,7 @@ struct WalkArgs {
   int32_t n_v, comp, precision, persistent;
   double inv_R;                // 1 / p[0] (the radius the source families scale by)
   double inv_sigma;            // 1 / sigma
+  double inv_nv;               // 1 / N_V (the mean over the Green samples of a step)
   double rho_geo;              // c_kappa / (1 + kappa) with the manifold's constant curvature bound
   double cap_rg;               // sphere cap: radius sqrt(R^2 - h^2) of the boundary circle
   double cut_c, cut_s;         // cut torus: cos and sin of the cut angle phi_c

@@ -696,6 +696,7 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
   a.inv_R = 1.0 / d.p[0];
   a.lam_sqrt = std::sqrt(sigma);
   a.inv_sigma = 1.0 / sigma;
+  a.inv_nv = 1.0 / (double)o.n_v;
   a.rho_geo = o.c_kappa / (1.0 + const_kappa(d));
   if (d.kind == MPWOS_SPHERE_CAP) a.cap_rg = std::sqrt(d.p[0] * d.p[0] - d.p[1] * d.p[1]);
   if (d.kind == MPWOS_CUT_TORUS) {

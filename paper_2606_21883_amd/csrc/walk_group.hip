@@ -442,8 +442,9 @@ __device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB
     }
     Fsum += v;
   }
-  const double F = a.n_v == 1 ? (double)Fsum : (double)Fsum / (double)a.n_v;
-  kahan_add(st.S, st.C, (st.W * a.om0) * F);
+  const double F = (double)Fsum * a.inv_nv;
+  if constexpr (sizeof(T) == 8) kahan_add(st.S, st.C, (st.W * a.om0) * F);
+  else st.S += (st.W * a.om0) * F;
   st.W = st.W * a.c0;
 #pragma unroll
   for (int i = 0; i < 4 * MB; ++i) st.Y[i] = Yn[i];

@@ -200,6 +200,15 @@ __device__ __forceinline__ bool walk_init(const WalkArgs& a, const double* queri
   return false;
 }
 
+// S += x in FP64: with Neumaier compensation in the FP64 mode (the oracle's
+// summation); a plain FP64 sum in the FP32 mode, whose rounding (K eps
+// relative) is far below the FP32 walk arithmetic's.
+template <class T, class St>
+__device__ __forceinline__ void score_add(St& st, double x) {
+  if constexpr (sizeof(T) == 8) kahan_add(st.S, st.C, x);
+  else st.S += x;
+}
+
 template <class T, int N>
 __device__ __forceinline__ void walk_store(double* walk_S, int32_t* walk_K, const LaneState<T, N>& st) {
   walk_S[st.idx] = st.S + st.C;
@@ -276,15 +285,17 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
     const uint4 b = rs.block(st.k, (uint32_t)l, 0);
     Fsum += green_sample<T, N, KIND, RICH>(a, st.Y, b, b.w, rT, X2, norm);
   }
-  const double F = a.n_v == 1 ? (double)Fsum : (double)Fsum / (double)a.n_v;
-  kahan_add(st.S, st.C, (st.W * om) * F);
+  // the mean over the N_V samples (times 1/N_V: exact for N_V = 1 and powers
+  // of two, within an ulp of the quotient otherwise)
+  const double F = (double)Fsum * a.inv_nv;
+  score_add<T>(st, (st.W * om) * F);
   st.W = st.W * c;
   for (int i = 0; i < N; ++i) st.Y[i] = Yn[i];
   if constexpr (KIND == kCloud) st.rg = rg_next;
   st.k += 1;
   if constexpr (KIND == kCap || KIND == kCutTorus) {
     if (in_layer<T, N, KIND>(a, st.Y, st.rg)) {
-      kahan_add(st.S, st.C, st.W * layer_value<T, N, KIND>(a, st.Y));
+      score_add<T>(st, st.W * layer_value<T, N, KIND>(a, st.Y));
       return true;
     }
   } else {

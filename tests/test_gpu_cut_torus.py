@@ -131,3 +131,32 @@ def test_compensated_estimate_against_the_closed_form():
     e_none = np.sqrt(np.mean((out["none"]["u"] - ex["u"]) ** 2))
     e_so = np.sqrt(np.mean((out["second_order"]["u"] - ex["u"]) ** 2))
     assert e_so < 0.6 * e_none, (e_none, e_so)
+
+
+def test_served_and_planned_second_order_equal_solo():
+    """The compensated cut-torus solve through the server and as a captured
+    plan: the same bits as the solo solve (the predictor rows travel with
+    the source family's values)."""
+    import torch
+    prob = inputs.cut_torus_problem(n_v=2, compensation="second_order")
+    prob.update(h_eta=1e-2, predictor=_predictor(3))
+    Q = inputs.cut_torus_points(12, seed=9)
+    m = mpwos.Manifold(prob)
+    announce("cut torus served + plan 12x256")
+    solo = mpwos.solve(prob, Q, 256, 4, manifold=m, precision="fp32", persistent=1)
+    srv = mpwos.Server(1 << 30)
+    out = srv.wait(srv.submit(m, prob, Q, 256, 4, precision="fp32", persistent=1), 60_000)
+    srv.close()
+    assert np.array_equal(solo["u"], out["u"]) and np.array_equal(solo["stderr"], out["stderr"])
+    plan = mpwos.Plan(m, prob, len(Q), 256, precision="fp32", persistent=1)
+    stream = torch.cuda.current_stream().cuda_stream
+    dq = torch.from_numpy(np.ascontiguousarray(Q)).to("cuda")
+    u = torch.zeros(len(Q), dtype=torch.float64, device="cuda")
+    se = torch.zeros(len(Q), dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        plan.execute(dq.data_ptr(), u.data_ptr(), se.data_ptr(), 4, stream)
+        torch.cuda.synchronize()
+        assert np.array_equal(u.cpu().numpy(), solo["u"])
+        torch.ones(1 << 16, device="cuda").sum().item()
+    plan.close()
+    m.close()
