@@ -48,8 +48,8 @@ PEAK_SLOTS = 256 * 128 * 2.4e9
 # WRITE_SIZE all of them).  Valid only for the kernel sources they were taken
 # on (their SHA-256 below); any change to those sources makes traffic null.
 TRAFFIC = {
-    "kernel_sha256": "192bed310c44beac57352e5045a3351f0939aa847d21ae5f0f23436a6b2c18fa",
-    "fetch_kib": 462.4375, "fetch_factor": 2.0,
+    "kernel_sha256": "bbe45cdbd77f3782f7710d4bb3d939972a120c3d07cf0281d4d8b7b5669e99c0",
+    "fetch_kib": 462.5625, "fetch_factor": 2.0,
     "write_kib": 196608.0, "write_factor": 1.0,
 }
 KERNEL_SOURCES = ["walk_lane.hip", "mpwos_dev.h", "kernel_args.h", "cloud_dev.h"]
@@ -72,7 +72,8 @@ def step_ops(kind, n, n_v=1):
         the key schedule is scalar);
       - two operations per uniform; per direction cos and sin of the angle,
         and on S^2 the axis coordinate and its radius (one square root, three
-        multiply-adds, two multiplies);
+        multiply-adds, two multiplies; the kernel folds the step's scale into
+        the radius, which the count does not credit);
       - per n-vector update Y + r zeta (n) and projection: a squared norm (n),
         a reciprocal square root and the scaling (n + 1), for Theta and for
         each Green point Z;

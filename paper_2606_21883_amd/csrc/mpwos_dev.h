@@ -52,9 +52,10 @@ struct Stream {
 // bits, (x>>9 + 1/2) 2^-23, exact in binary32.
 __device__ __forceinline__ double u01_64(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
 // FP32 form built from the bits: 1 + m 2^-23 (m = x >> 9) minus (1 - 2^-24)
-// is (m + 1/2) 2^-23 exactly, in two operations.
+// is (m + 1/2) 2^-23 exactly.  The exponent bits and the shifted word come
+// from one funnel shift: ({0x7F, x} >> 9) = 0x3F800000 | (x >> 9).
 __device__ __forceinline__ float u01_32(uint32_t x) {
-  return __uint_as_float((x >> 9) | 0x3F800000u) - 0x1.fffffep-1f;
+  return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, x, 9u)) - 0x1.fffffep-1f;
 }
 
 template <class T> __device__ __forceinline__ T u01(uint32_t x);
@@ -112,6 +113,34 @@ __device__ __forceinline__ void lane_direction(uint32_t x0, uint32_t x1, float* 
     z[0] = rho * __builtin_amdgcn_cosf(t);
     z[1] = rho * __builtin_amdgcn_sinf(t);
     z[2] = fmaf(-2.0f, u, 1.0f);
+  }
+}
+
+// The point Y + s zeta for the direction zeta of lane_direction.  FP64: the
+// direction, then the update.  FP32: the same point with the scale folded
+// into the hat-box radius, (2s) sqrt(u (1 - u)), and the axis coordinate as
+// (Y_3 + s) - 2s u, which saves the separate multiplies by the radius and by
+// s (rounding differs from the two-stage form by an ulp or so).
+template <int N>
+__device__ __forceinline__ void lane_point(uint32_t x0, uint32_t x1, double s, const double* Y, double* out) {
+  double zeta[N];
+  lane_direction<N>(x0, x1, zeta);
+  for (int i = 0; i < N; ++i) out[i] = Y[i] + s * zeta[i];
+}
+template <int N>
+__device__ __forceinline__ void lane_point(uint32_t x0, uint32_t x1, float s, const float* Y, float* out) {
+  if constexpr (N == 2) {
+    const float t = u01_32(x0);
+    out[0] = fmaf(s, __builtin_amdgcn_cosf(t), Y[0]);
+    out[1] = fmaf(s, __builtin_amdgcn_sinf(t), Y[1]);
+  } else {
+    const float u = u01_32(x0);
+    const float t = u01_32(x1);
+    const float s2 = 2.0f * s;
+    const float sr = s2 * __builtin_amdgcn_sqrtf(fmaf(-u, u, u));
+    out[0] = fmaf(sr, __builtin_amdgcn_cosf(t), Y[0]);
+    out[1] = fmaf(sr, __builtin_amdgcn_sinf(t), Y[1]);
+    out[2] = fmaf(-s2, u, Y[2] + s);
   }
 }
 

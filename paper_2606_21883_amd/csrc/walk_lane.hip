@@ -220,14 +220,12 @@ __device__ __forceinline__ void walk_store(double* walk_S, int32_t* walk_K, cons
 template <class T, int N, int KIND, bool RICH>
 __device__ __forceinline__ T green_sample(const WalkArgs& a, const T* Y, uint4 b, uint32_t ux, T rT, double X2,
                                           double norm) {
-  T zeta[N];
-  lane_direction<N>(b.x, b.y, zeta);
   T s;
   if constexpr (sizeof(T) == 8) s = radial_inv64(a, u01_64(ux), X2, norm);
   else s = radial_inv32(a, u01_32(ux), (float)X2);
   const T t = rT * s;
   T Z[N], Zc[N];
-  for (int i = 0; i < N; ++i) Z[i] = Y[i] + t * zeta[i];
+  lane_point<N>(b.x, b.y, t, Y, Z);
   closest_point<T, N, KIND>(a, Z, Zc);
   return source<T, RICH>(a, Z, Zc, N);
 }
@@ -267,10 +265,8 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
   T Yn[N];
   double rg_next = 0.0;
   {
-    T zeta[N];
-    lane_direction<N>(bd.x, bd.y, zeta);
     T Th[N];
-    for (int i = 0; i < N; ++i) Th[i] = st.Y[i] + rT * zeta[i];
+    lane_point<N>(bd.x, bd.y, rT, st.Y, Th);
     if constexpr (KIND == kCloud) {
       const CloudProj<T> p = cloud_cp<T>(a.cloud, Th);
       for (int i = 0; i < N; ++i) Yn[i] = p.y[i];
