@@ -220,24 +220,25 @@ __device__ __forceinline__ T db_source(const WalkArgs& a, const T* z, const T* A
   zl = group_sum<L>(zl);
   const T rho = sqrt_(s2);
   const T phi = db_phi<T, L>((T)a.p[0], (T)a.p[1], rho, zl, gl);
-  // the scalar tail in FP64 in both precisions
-  const double kc = a.p[1];
-  const DbProfile<double> p = db_profile<double>(a.p[0], kc, (double)phi);
-  const double Lp = sqrt(p.r1 * p.r1 + p.z1 * p.z1);
-  const double Nr = -p.z1 / Lp, Nz = p.r1 / Lp;
-  const double k1 = (p.z1 * p.r2 - p.r1 * p.z2) / (Lp * Lp * Lp);
-  const double k2 = kc / (p.g * Lp);
-  const double ir = rho > (T)0 ? 1.0 / (double)rho : 0.0;
-  const double e1 = (double)s1 * ir, ea = (double)sa * ir * ir;
-  const double isq = 1.0 / sqrt((double)(a.n - 1));
-  const double* c = f.coef;
-  const double zz = p.z, rr = p.r;
-  const double U = c[0] * zz + c[1] * zz * zz + c[2] * rr * e1 * isq + c[3] * rr * rr * ea;
-  const double lapU = 2.0 * c[1] + 2.0 * c[3] * f.lam;
-  const double hess = 2.0 * c[1] * Nz * Nz + 2.0 * c[3] * Nr * Nr * ea;
-  const double dnu = Nz * (c[0] + 2.0 * c[1] * zz) + Nr * (c[2] * e1 * isq + 2.0 * c[3] * rr * ea);
-  const double H = k1 + (double)(a.n - 2) * k2;
-  return (T)(-(lapU - hess - H * dnu) + a.sigma * U);
+  // the scalar tail in the walk's precision (no cancellation: sigma U and the
+  // curvature terms add with their own signs)
+  const T kc = (T)a.p[1];
+  const DbProfile<T> p = db_profile<T>((T)a.p[0], kc, phi);
+  const T iLp = rsqrt_(p.r1 * p.r1 + p.z1 * p.z1);
+  const T Nr = -p.z1 * iLp, Nz = p.r1 * iLp;
+  const T k1 = (p.z1 * p.r2 - p.r1 * p.z2) * (iLp * iLp * iLp);
+  const T k2 = over_(kc * iLp, p.g);
+  const T ir = rho > (T)0 ? rcp_(rho) : (T)0;
+  const T e1 = s1 * ir, ea = sa * ir * ir;
+  const T isq = (T)(1.0 / sqrt((double)(a.n - 1)));
+  const T c0 = (T)f.coef[0], c1 = (T)f.coef[1], c2 = (T)f.coef[2], c3 = (T)f.coef[3];
+  const T zz = p.z, rr = p.r;
+  const T U = c0 * zz + c1 * zz * zz + c2 * rr * e1 * isq + c3 * rr * rr * ea;
+  const T lapU = (T)2 * c1 + (T)2 * c3 * (T)f.lam;
+  const T hess = (T)2 * c1 * Nz * Nz + (T)2 * c3 * Nr * Nr * ea;
+  const T dnu = Nz * (c0 + (T)2 * c1 * zz) + Nr * (c2 * e1 * isq + (T)2 * c3 * rr * ea);
+  const T H = k1 + (T)(a.n - 2) * k2;
+  return -(lapU - hess - H * dnu) + (T)a.sigma * U;
 }
 
 template <class T, int L, int MB>
@@ -355,13 +356,20 @@ __device__ __forceinline__ T pr_source(const WalkArgs& a, const T* z, int gl) {
   T v[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) v[i] = coord_of<T, L, MB>(z, i, gl);
-  const double phi = (double)pr_phi<T, L>(v, gl);
-  const double ns = sqrt((double)v[6] * v[6] + (double)v[7] * v[7] + (double)v[8] * v[8]);
-  const double w1 = (double)v[6] / ns, w2 = (double)v[7] / ns;
-  const double R = a.p[0], q = 1.0 / (3.0 * R * R), s2 = 1.0 / (a.p[1] * a.p[1]), sg = a.sigma;
-  const double* c = f.coef;
-  return (T)(c[0] * (sg + q + 2.0 * s2) * cos(phi) * w1 + c[1] * (sg + 4.0 * q + 2.0 * s2) * sin(2.0 * phi) * w2 +
-             c[2] * (sg + 9.0 * q + 6.0 * s2) * cos(3.0 * phi) * (w1 * w1 - w2 * w2));
+  // in the walk's precision: cos phi, sin 2phi and cos 3phi from one sincos
+  // by the angle-addition formulas
+  const T phi = pr_phi<T, L>(v, gl);
+  const T ins = rsqrt_(v[6] * v[6] + v[7] * v[7] + v[8] * v[8]);
+  const T w1 = v[6] * ins, w2 = v[7] * ins;
+  T sn1, cs1;
+  sincos_(phi, sn1, cs1);
+  const T sn2 = (T)2 * sn1 * cs1, cs2 = cs1 * cs1 - sn1 * sn1;
+  const T cs3 = cs2 * cs1 - sn2 * sn1;
+  const double R = a.p[0];
+  const T q = (T)(1.0 / (3.0 * R * R)), sa = (T)(1.0 / (a.p[1] * a.p[1])), sg = (T)a.sigma;
+  const T k0 = (T)f.coef[0], k1 = (T)f.coef[1], k2 = (T)f.coef[2];
+  return k0 * (sg + q + (T)2 * sa) * cs1 * w1 + k1 * (sg + (T)4 * q + (T)2 * sa) * sn2 * w2 +
+         k2 * (sg + (T)9 * q + (T)6 * sa) * cs3 * (w1 * w1 - w2 * w2);
 }
 
 template <class T, int L, int MB, int KIND>
