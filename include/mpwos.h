@@ -237,7 +237,8 @@ const char* mpwos_last_error(void);
  * in s; exact for a series with ks < ns and 2 kt < nt).  Every step runs on
  * the device.
  *   f, g, c, eps, seed, opt: as for mpwos_solve (opt->device_io is ignored).
- *   nt >= 1, ns >= 2, 1 <= ks < ns, 0 <= kt, 2 kt < nt; nt (ns - 1) <= 2^20.
+ *   nt >= 1, ns >= 2, 1 <= ks < ns, 0 <= kt, 2 kt < nt, ks and kt <= 64;
+ *   nt (ns - 1) <= 2^20.
  *   coef_out: ks (2 kt + 1) doubles (host), the rows (c_k0, c_k1, d_k1, ...).
  *   stats (nullable): the baseline solve's statistics.
  * EINVAL for another manifold or an out-of-range grid. */
