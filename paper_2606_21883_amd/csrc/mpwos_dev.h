@@ -648,6 +648,77 @@ __device__ __forceinline__ TsVal<T> ts_eval(const double* c, int ks, int kt, T c
   return v;
 }
 
+// The same series from a float table staged in LDS by the walk kernel: entry
+// (row, j) = (c_rj, d_rj, -k^2 c_rj, -k^2 d_rj) at row (kt + 1) + j, with the
+// sines sin(k s), k <= ks <= kTsMaxK, computed once per evaluation and held in
+// registers.  FP32 only (the FP64 mode reads the double coefficients).
+constexpr int kTsMaxK = 8;
+constexpr int kTsLds = 512;
+
+__device__ __forceinline__ TsVal<float> ts_eval_tab(const float4* tab, int ks, int kt, float ct, float st, float cs,
+                                                    float ss) {
+  float sk[kTsMaxK];
+  {
+    float sv = ss, cv = cs;
+#pragma unroll
+    for (int k = 0; k < kTsMaxK; ++k) {
+      sk[k] = sv;
+      const float sn = sv * cs + cv * ss;
+      cv = cv * cs - sv * ss;
+      sv = sn;
+    }
+  }
+  TsVal<float> v{0.f, 0.f, 0.f, 0.f};
+  const int w = kt + 1;
+  float cj = 1.f, sj = 0.f;
+  for (int j = 0; j <= kt; ++j) {
+    float A = 0.f, B = 0.f, A2 = 0.f, B2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < kTsMaxK; ++k) {
+      if (k < ks) {
+        const float4 q = tab[k * w + j];
+        A = fmaf(q.x, sk[k], A);
+        B = fmaf(q.y, sk[k], B);
+        A2 = fmaf(q.z, sk[k], A2);
+        B2 = fmaf(q.w, sk[k], B2);
+      }
+    }
+    const float jj = (float)j;
+    v.u += cj * A + sj * B;
+    v.ut += jj * (cj * B - sj * A);
+    v.utt -= jj * jj * (cj * A + sj * B);
+    v.uss += cj * A2 + sj * B2;
+    const float cn = cj * ct - sj * st;
+    sj = sj * ct + cj * st;
+    cj = cn;
+  }
+  return v;
+}
+
+// Stages the series of u (and of the predictor, second order) into `tab`.
+// Called by every thread of the workgroup; returns whether the table is used
+// (uniform: FP32 mode, series family, at most kTsMaxK rows per series and
+// kTsLds entries in all).
+__device__ __forceinline__ bool ts_stage(const WalkArgs& a, float4* tab) {
+  const FnDev& f = a.f;
+  if (f.kind != kFnTorusSine) return false;
+  const int ks = f.idx[0], kt = f.idx[1], kp = a.comp == kCompSecondOrder ? f.idx[2] : 0;
+  const int w = kt + 1, rows = ks + kp;
+  if (ks > kTsMaxK || kp > kTsMaxK || rows * w > kTsLds) return false;
+  const int stride = 2 * kt + 1;
+  for (int e = threadIdx.x; e < rows * w; e += blockDim.x) {
+    const int row = e / w, j = e - row * w;
+    const int k = row < ks ? row + 1 : row - ks + 1;
+    const double* rc = f.values + (size_t)row * stride;
+    const float ca = (float)(j == 0 ? rc[0] : rc[2 * j - 1]);
+    const float cb = j == 0 ? 0.f : (float)rc[2 * j];
+    const float kk = (float)(k * k);
+    tab[e] = make_float4(ca, cb, -kk * ca, -kk * cb);
+  }
+  __syncthreads();
+  return true;
+}
+
 // Ambient Laplacian of the closest-point extension at distance rho from the
 // core circle (the extension does not depend on rho in toroidal
 // coordinates); at rho = a, the torus's Laplace-Beltrami operator:
@@ -677,7 +748,8 @@ __device__ __forceinline__ T ct_lap(T R, T rho, T ct, T st, const TsVal<T>& v) {
 // walk's own precision suffices (the quotients themselves lose
 // log10(1/h^2) digits to rounding).
 template <class T>
-__device__ __forceinline__ T torus_sine_source(const WalkArgs& a, const T* z, const T* y) {
+__device__ __forceinline__ T torus_sine_source(const WalkArgs& a, const T* z, const T* y,
+                                               const float4* tab = nullptr) {
   const FnDev& f = a.f;
   const T R = (T)a.p[0], tube = (T)a.p[1];
   const T rxy = sqrt_(y[0] * y[0] + y[1] * y[1]);
@@ -689,7 +761,13 @@ __device__ __forceinline__ T torus_sine_source(const WalkArgs& a, const T* z, co
   const T cc = (T)a.cut_c, sc = (T)a.cut_s;
   const T cs = cp * cc + sp * sc, ss = sp * cc - cp * sc;
   const int ks = f.idx[0], kt = f.idx[1];
-  const TsVal<T> v = ts_eval<T>(f.values, ks, kt, ct, st, cs, ss);
+  TsVal<T> v;
+  if constexpr (sizeof(T) == 4) {
+    if (tab) v = ts_eval_tab(tab, ks, kt, ct, st, cs, ss);
+    else v = ts_eval<T>(f.values, ks, kt, ct, st, cs, ss);
+  } else {
+    v = ts_eval<T>(f.values, ks, kt, ct, st, cs, ss);
+  }
   const T lap_t = ct_lap<T>(R, tube, ct, st, v);
   const T fv = -lap_t + (T)a.sigma * v.u;
   if (a.comp == kCompNone) return fv;
@@ -697,7 +775,13 @@ __device__ __forceinline__ T torus_sine_source(const WalkArgs& a, const T* z, co
   const T rho = sqrt_((rz - R) * (rz - R) + z[2] * z[2]);
   if (a.comp == kCompExact) return fv + (lap_t - ct_lap<T>(R, rho, ct, st, v));
   const T h = (T)f.coef[0];
-  const TsVal<T> w = ts_eval<T>(f.values + (size_t)ks * (2 * kt + 1), f.idx[2], kt, ct, st, cs, ss);
+  TsVal<T> w;
+  if constexpr (sizeof(T) == 4) {
+    if (tab) w = ts_eval_tab(tab + ks * (kt + 1), f.idx[2], kt, ct, st, cs, ss);
+    else w = ts_eval<T>(f.values + (size_t)ks * (2 * kt + 1), f.idx[2], kt, ct, st, cs, ss);
+  } else {
+    w = ts_eval<T>(f.values + (size_t)ks * (2 * kt + 1), f.idx[2], kt, ct, st, cs, ss);
+  }
   const T h2 = h * h;
   const T e = tube * tube - h2;                      // a^2 - h^2
   const T q0 = R + tube * ct;

@@ -219,7 +219,7 @@ __device__ __forceinline__ void walk_store(double* walk_S, int32_t* walk_K, cons
 // uniform word ux, zeta' from words x, y of block b) and (f + m)(Z).
 template <class T, int N, int KIND, bool RICH>
 __device__ __forceinline__ T green_sample(const WalkArgs& a, const T* Y, uint4 b, uint32_t ux, T rT, double X2,
-                                          double norm) {
+                                          double norm, const float4* tab) {
   T s;
   if constexpr (sizeof(T) == 8) s = radial_inv64(a, u01_64(ux), X2, norm);
   else s = radial_inv32(a, u01_32(ux), (float)X2);
@@ -227,11 +227,20 @@ __device__ __forceinline__ T green_sample(const WalkArgs& a, const T* Y, uint4 b
   T Z[N], Zc[N];
   lane_point<N>(b.x, b.y, t, Y, Z);
   closest_point<T, N, KIND>(a, Z, Zc);
+  if constexpr (KIND == kCutTorus) {
+    // the cut torus takes the series family (from the workgroup's staged
+    // table when there is one) or ZERO / CONST: no other family is compiled in
+    if constexpr (RICH) {
+      if (a.f.kind == kFnTorusSine) return torus_sine_source<T>(a, Z, Zc, tab);
+    }
+    return source<T, false>(a, Z, Zc, N);
+  }
   return source<T, RICH>(a, Z, Zc, N);
 }
 
 template <class T, int N, int KIND, bool RICH>
-__device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st, uint64_t seed) {
+__device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st, uint64_t seed,
+                                          const float4* tab = nullptr) {
   const Stream rs{st.q, st.w, (uint32_t)seed, (uint32_t)(seed >> 32)};
   // (i) radius r(Y) = theta min(delta_Gamma, rho_geo) and the weights
   double r, c, om, X2, norm = 0.0;
@@ -279,7 +288,7 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
   T Fsum = (T)0;
   for (int l = 1; l <= a.n_v; ++l) {
     const uint4 b = rs.block(st.k, (uint32_t)l, 0);
-    Fsum += green_sample<T, N, KIND, RICH>(a, st.Y, b, b.w, rT, X2, norm);
+    Fsum += green_sample<T, N, KIND, RICH>(a, st.Y, b, b.w, rT, X2, norm, tab);
   }
   // the mean over the N_V samples (times 1/N_V: exact for N_V = 1 and powers
   // of two, within an ulp of the quotient otherwise)
@@ -310,6 +319,13 @@ __global__ __launch_bounds__(256) void walk_lane_kernel(WalkArgs a) {
   const int64_t total = a.count;
   const uint64_t seed = a.seed_dev ? *a.seed_dev : a.seed;
   LaneState<T, N> st;
+  // cut torus, FP32: the source series staged in LDS once per workgroup
+  // (before any lane leaves)
+  const float4* tab = nullptr;
+  if constexpr (KIND == kCutTorus && RICH && sizeof(T) == 4) {
+    __shared__ float4 ts_tab[kTsLds];
+    if (ts_stage(a, ts_tab)) tab = ts_tab;
+  }
   if constexpr (!PERSIST) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
@@ -317,7 +333,7 @@ __global__ __launch_bounds__(256) void walk_lane_kernel(WalkArgs a) {
       walk_store(a.walk_S, a.walk_K, st);
       return;
     }
-    while (!walk_step<T, N, KIND, RICH>(a, st, seed)) {
+    while (!walk_step<T, N, KIND, RICH>(a, st, seed, tab)) {
     }
     walk_store(a.walk_S, a.walk_K, st);
     return;
@@ -358,7 +374,7 @@ __global__ __launch_bounds__(256) void walk_lane_kernel(WalkArgs a) {
       }
       if (__ballot(active) == 0) break;
       if (active) {
-        if (walk_step<T, N, KIND, RICH>(a, st, seed)) {
+        if (walk_step<T, N, KIND, RICH>(a, st, seed, tab)) {
           walk_store(a.walk_S, a.walk_K, st);
           active = false;
         }
@@ -382,6 +398,11 @@ __global__ __launch_bounds__(256) void walk_lane_batch_kernel(WalkArgs a) {
   const uint32_t lane = lane_id();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   LaneState<T, N> st;
+  const float4* tab = nullptr;
+  if constexpr (KIND == kCutTorus && RICH && sizeof(T) == 4) {
+    __shared__ float4 ts_tab[kTsLds];
+    if (ts_stage(a, ts_tab)) tab = ts_tab;
+  }
   bool active = false;
   bool exhausted = false;
   int cur = -1;                // entry of the walks the wave runs
@@ -450,7 +471,7 @@ __global__ __launch_bounds__(256) void walk_lane_batch_kernel(WalkArgs a) {
       continue;
     }
     if (active) {
-      if (walk_step<T, N, KIND, RICH>(a, st, e_seed)) {
+      if (walk_step<T, N, KIND, RICH>(a, st, e_seed, tab)) {
         walk_store(e_S, e_K, st);
         active = false;
       }

@@ -489,7 +489,8 @@ def predictor_fit(prob, nt, ns, n_walks, seed, ks, kt, manifold=None, **optkw):
     o = make_options(prob, **optkw)
     coef = np.zeros(ks * (2 * kt + 1))
     st = Stats()
-    rc = lib().mpwos_predictor_fit(m.handle, ctypes.byref(f), ctypes.byref(g), float(prob["sigma"]),
+    rc = lib().mpwos_predictor_fit(m.handle, ctypes.byref(f), ctypes.byref(g) if g is not None else None,
+                                   float(prob["sigma"]),
                                    float(prob.get("eps", 1e-3)), int(seed), ctypes.byref(o), int(nt), int(ns),
                                    int(n_walks), int(ks), int(kt), _ptr(coef), ctypes.byref(st))
     if own:

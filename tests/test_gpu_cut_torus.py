@@ -160,3 +160,24 @@ def test_served_and_planned_second_order_equal_solo():
         torch.ones(1 << 16, device="cuda").sum().item()
     plan.close()
     m.close()
+
+
+def test_predictor_fit_rejects_bad_grids():
+    prob = inputs.cut_torus_problem(n_v=1)
+    m = mpwos.Manifold(prob)
+    announce("predictor fit argument checks")
+    for nt, ns, ks, kt in [(8, 6, 6, 1), (8, 6, 2, 4), (0, 6, 2, 1), (8, 1, 1, 0), (2048, 1024, 2, 1)]:
+        with pytest.raises(mpwos.MpwosError):
+            mpwos.predictor_fit(prob, nt, ns, 4, 1, ks, kt, manifold=m)
+    m.close()
+    # the fit is defined on the cut torus only
+    sph = inputs.sphere_problem()
+    with pytest.raises(mpwos.MpwosError):
+        mpwos.predictor_fit(dict(sph, f=prob["f"]), 8, 6, 4, 1, 2, 1)
+    # a second-order solve without predictor rows, or with h_eta out of range
+    Q = inputs.cut_torus_points(2, seed=1)
+    with pytest.raises(mpwos.MpwosError):
+        mpwos.solve(dict(prob, compensation="second_order"), Q, 4, 1)
+    with pytest.raises(mpwos.MpwosError):
+        mpwos.solve(dict(prob, compensation="second_order", h_eta=0.3,
+                         predictor=dict(idx=[1, 0], values=[0.0])), Q, 4, 1)
