@@ -1152,9 +1152,10 @@ extern "C" mpwos_status mpwos_valu_probe(int32_t op, double* lane_ops_per_s) {
   uint32_t* out = nullptr;
   hipStream_t s = g_ctx.stream;
   hipError_t e = hipMalloc((void**)&out, (size_t)blocks * 256 * sizeof(uint32_t));
-  if (e == hipSuccess) e = launch_valu_probe(op, 1u, iters, out, blocks, s);
+  // warm-up launches (clocks settle), then the best of seven timed ones
+  for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_valu_probe(op, 1u, iters, out, blocks, s);
   float best = 1e30f;
-  for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+  for (int r = 0; r < 7 && e == hipSuccess; ++r) {
     e = hipEventRecord(g_ctx.ev[0], s);
     if (e == hipSuccess) e = launch_valu_probe(op, (uint32_t)(r + 2), iters, out, blocks, s);
     if (e == hipSuccess) e = hipEventRecord(g_ctx.ev[1], s);
