@@ -275,6 +275,35 @@ def compensation_legs(it, stream):
     return out
 
 
+def compensation_sweep(walks):
+    """Example 1's comparison as a function of the walk count N: the same 100
+    points solved with m_* = 0, with the second-order m_* from one device
+    predictor fit, and with the exact m, each scored against the closed-form
+    u (the three share their random numbers at each N)."""
+    from paper_2606_21883_amd import inputs, mpwos
+    prob, Q, _ = inputs.config("cut_torus")
+    g = prob["predictor_grid"]
+    base = {k: v for k, v in prob.items() if k != "predictor_grid"}
+    exact = inputs.exact_u(base, Q)
+    m = mpwos.Manifold(base)
+    coef, _ = mpwos.predictor_fit(base, g["nt"], g["ns"], g["n_walks"], 1, g["ks"], g["kt"], manifold=m,
+                                  precision="fp32", persistent=1)
+    rows = []
+    for nw in walks:
+        row = {"n_walks": nw}
+        for comp in ("none", "second_order", "exact"):
+            pr = dict(base, compensation=comp)
+            if comp == "second_order":
+                pr["predictor"] = dict(idx=[g["ks"], g["kt"]], values=coef.ravel())
+            r = mpwos.solve(pr, Q, nw, 0, manifold=m, precision="fp32", persistent=1)
+            row[comp] = {"rmse": inputs.rmse(r["u"], exact), "mean_stderr": float(np.sqrt(np.mean(r["stderr"] ** 2)))}
+        print(f"[bench] compensation sweep N={nw}: " + ", ".join(f"{k} {row[k]['rmse']:.4g}"
+              for k in ("none", "second_order", "exact")), file=sys.stderr, flush=True)
+        rows.append(row)
+    m.close()
+    return {"workload": "cut torus (Example 1), 100 points, N_V = 50, eps = 1e-5, FP32", "sweep": rows}
+
+
 def cpu_baseline(work):
     """The FP64 oracle on the host cores over a bounded sample of the workload
     (about 10-20 s of CPU work)."""
@@ -529,6 +558,9 @@ def main():
     ap.add_argument("--served-rates", default="100,400,800",
                     help="arrival rates (req/s) of the served sweep besides 200; empty to skip")
     ap.add_argument("--served-only", action="store_true", help="run only the served-mix leg and print it")
+    ap.add_argument("--compensation-sweep", default="", metavar="N1,N2,...",
+                    help="Example 1: RMSE against the closed form of the baseline, second-order and exact "
+                         "compensation at these walk counts (100 points, N_V = 50, FP32), printed and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the walk path runs on a "
@@ -543,6 +575,9 @@ def main():
     if args.valu_probe:
         w, r = valu_weights()
         print(json.dumps({"lane_ops_per_s": r, "weights": w, "peak_lane_ops_per_s": PEAK_SLOTS}), flush=True)
+        return
+    if args.compensation_sweep:
+        print(json.dumps(compensation_sweep([int(v) for v in args.compensation_sweep.split(",")])), flush=True)
         return
     if args.served_only:
         out = served_mix()
