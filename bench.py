@@ -275,6 +275,30 @@ def compensation_legs(it, stream):
     return out
 
 
+def host_io_rate(work, per, steps=3):
+    """The same step through mpwos_solve with host (numpy) queries and outputs:
+    each solve copies its queries in and its estimates out over PCIe inside
+    the call.  Reported beside the device-resident value, never as it."""
+    from paper_2606_21883_amd import mpwos
+    items = []
+    for name, prob, Q, nw in work:
+        m = mpwos.Manifold(prob)
+        opt = {k: v for k, v in per[name]["launch"].items() if k in ("persistent", "block_size", "lanes_per_walk")}
+        items.append((m, prob, np.ascontiguousarray(Q), nw, opt))
+    for m, prob, Q, nw, opt in items:  # warm-up
+        mpwos.solve(prob, Q, nw, 0, manifold=m, precision="fp32", **opt)
+    t0 = time.perf_counter()
+    ws = 0
+    for _ in range(steps):
+        for m, prob, Q, nw, opt in items:
+            ws += mpwos.solve(prob, Q, nw, 0, manifold=m, precision="fp32", **opt)["stats"]["walk_steps"]
+    dt = time.perf_counter() - t0
+    for it in items:
+        it[0].close()
+    return {"value": ws / dt, "unit": "walk-steps/s", "ms_per_step": 1e3 * dt / steps,
+            "form": "mpwos_solve per solve with host buffers (PCIe copies and the host query check inside)"}
+
+
 def compensation_sweep(walks):
     """Example 1's comparison as a function of the walk count N: the same 100
     points solved with m_* = 0, with the second-order m_* from one device
@@ -637,6 +661,8 @@ def main():
     n0 = prob0["n"]
     if not args.no_roofline and n0 <= 3 and prob0["manifold"] == "sphere":
         out["roofline"] = roofline(fast, first[0], "sphere", n0, prob0.get("n_v", 1), prec)
+    if headline and args.only is None:
+        out["host_io"] = host_io_rate(work, fast["per"])
     if slow is not None:
         v64 = slow["walk_steps_per_step"] * slow["steps"] / slow["seconds"]
         out["fp64_plain"] = {"value": v64, "ms_per_step": 1e3 * slow["seconds"] / slow["steps"],
