@@ -145,6 +145,11 @@ struct WalkArgs {
   int32_t const_r;
   double r0, c0, om0, X0;
   RadialLaw law;
+  // FP32 walks whose radius varies per step: the screening series'
+  // coefficients alpha_j in float (wcoef[0] unused) and the number of terms
+  // that can exceed 1e-10 over the solve's radii
+  float wcoef[kMaxJ];
+  int32_t wjs;
   RadialFixed fixed;
   InvTable tab;
   CloudDev cloud;

@@ -735,6 +735,15 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
     return fail(MPWOS_EINVAL, "sqrt(sigma) r_max = " + std::to_string(std::sqrt(x2max)) +
                                   " is beyond the range of the series radial law for this n");
   fill_law(h, js, jd, a.law);
+  // FP32 screening series for per-step radii: alpha_j in float, the terms
+  // whose alpha_j X^2j can reach 1e-10 (far below FP32 rounding of
+  // c = 1/(1+s1)); never more than the FP64 series keeps
+  a.wjs = js;
+  for (int j = 1; j < js; ++j) {
+    if (h.alpha[j] * std::pow(x2max, j) < 1e-10) { a.wjs = j; break; }
+  }
+  memset(a.wcoef, 0, sizeof(a.wcoef));
+  for (int j = 1; j < a.wjs; ++j) a.wcoef[j] = (float)h.alpha[j];
   a.const_r = (d.kind == MPWOS_SPHERE || d.kind == MPWOS_TORUS_IMPLICIT || d.kind == MPWOS_DUMBBELL ||
                d.kind == MPWOS_PRODUCT || cloud_bound)
                   ? 1 : 0;

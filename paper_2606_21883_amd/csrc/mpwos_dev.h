@@ -194,6 +194,32 @@ __device__ __forceinline__ void weights(const WalkArgs& a, double r, double& c, 
   om = s1 * c * a.inv_sigma;
 }
 
+// The same weights in FP32 (mixed mode): Horner in z = sigma r^2 over the
+// float coefficients and c from the hardware reciprocal (1 ulp).  All terms
+// are positive, so the float sum is accurate to a few ulps at any size.  W and
+// S stay FP64.
+__device__ __forceinline__ void weights32(const WalkArgs& a, float r, float& c, float& om) {
+  const float z = (float)a.sigma * r * r;
+  float t = 0.0f;
+  for (int j = a.wjs - 1; j >= 1; --j) t = fmaf(t, z, a.wcoef[j]);
+  const float s1 = t * z;
+  c = __builtin_amdgcn_rcpf(1.0f + s1);
+  om = s1 * c * (float)a.inv_sigma;
+}
+
+// Weights for a per-step radius in the walk's precision.
+template <class T, int N>
+__device__ __forceinline__ void step_weights(const WalkArgs& a, double r, double& c, double& om) {
+  if constexpr (sizeof(T) == 4) {
+    float cf, omf;
+    weights32(a, (float)r, cf, omf);
+    c = (double)cf;
+    om = (double)omf;
+  } else {
+    weights(a, r, c, om);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Radial law of the normalised Green density, in s = t/r, with X = sqrt(sigma) r:
 //   F(s) = norm [ t1/(1+t1) + X^2 s^2 S_{nu+1}(Xs)/(2(nu+1)) D(s) ],  t1 = S_nu(Xs) - 1

@@ -249,12 +249,12 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
     const double dg = st.rg;
     const double rg = a.rho_geo;
     r = a.theta * (dg < rg ? dg : rg);
-    weights(a, r, c, om);
+    step_weights<T, N>(a, r, c, om);
     X2 = a.sigma * r * r;
     if constexpr (sizeof(T) == 8) norm = radial_norm(a.law, X2);
   } else if (KIND == kCloud && !a.const_r) {
     r = a.theta * st.rg;
-    weights(a, r, c, om);
+    step_weights<T, N>(a, r, c, om);
     X2 = a.sigma * r * r;
     if constexpr (sizeof(T) == 8) norm = radial_norm(a.law, X2);
   } else {

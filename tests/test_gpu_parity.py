@@ -33,6 +33,18 @@ CASES = {
     "circle_R": (inputs.problem(manifold="sphere", n=2, p=[1.7], sigma=1.3,
                                 f=dict(kind="circle_mode", idx=[2], coef=[0.4, -1.1])),
                  1.7 * inputs.circle_queries(24), 45),
+    # a wide boundary layer (eps = 0.2) on a cap whose solution x1 x3 has a
+    # nonzero normal derivative at Gamma: short walks, some queries inside
+    # the layer (K = 0)
+    "cap_wide_layer": (inputs.problem(manifold="sphere_cap", n=3, p=[1.0, 0.0], sigma=0.5, eps=0.2,
+                                      f=dict(kind="sph_pair", idx=[0, 2], coef=[6.5]),
+                                      g=dict(kind="sph_pair", idx=[0, 2], coef=[1.0])),
+                       np.concatenate([[[math.cos(0.15), 0.0, math.sin(0.15)]],
+                                       inputs.cap_uniform(30, 3, 0.0, seed=5)]), 45),
+    # a large truncation threshold (tau_W = 0.3: K = 12) on the degree-1 mode
+    "sphere_tau_w": (inputs.problem(manifold="sphere", n=3, p=[1.0], sigma=2.0, tau_w=0.3,
+                                    f=dict(kind="legendre", coef=[0.0, 4.0])),
+                     inputs.sphere_uniform(20, 3, seed=6), 50),
 }
 
 
