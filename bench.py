@@ -650,7 +650,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": desc,
-                   "precision": "f32 walk arithmetic, f64 weights/scores/per-query sums" if prec == "fp32"
+                   "precision": "f32 walk arithmetic, f64 path weight/scores/per-query sums" if prec == "fp32"
                    else "f64",
                    "form": fast["form"] if prec == "fp32" else "plain one launch per solve",
                    "n_v": prob0.get("n_v", 1), "tau_w": prob0.get("tau_w"), "theta": prob0.get("theta"),
@@ -661,7 +661,9 @@ def main():
     n0 = prob0["n"]
     if not args.no_roofline and n0 <= 3 and prob0["manifold"] == "sphere":
         out["roofline"] = roofline(fast, first[0], "sphere", n0, prob0.get("n_v", 1), prec)
-    if headline and args.only is None:
+    # the host-buffer rate of the headline step (the unit-sphere workload only:
+    # the others' pipelines, such as the cut torus predictor, are not single solves)
+    if headline and args.only is None and args.workload == "sphere":
         out["host_io"] = host_io_rate(work, fast["per"])
     if slow is not None:
         v64 = slow["walk_steps_per_step"] * slow["steps"] / slow["seconds"]

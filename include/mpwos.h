@@ -108,6 +108,11 @@ typedef enum {
                                 difference step; n_values = (idx[0] + idx[2]) (2 idx[1] + 1) */
 } mpwos_fn_kind;
 
+/* FP64_PLAIN: every operation of the walk in FP64 (the oracle's arithmetic).
+ * FP32_MIXED: uniforms, normals, direction, projection (except the implicit
+ * torus), radial inverse (table), source and the step factors c and omega of
+ * a per-step radius in FP32; the path weight W, the score and the per-query
+ * sums in FP64. */
 typedef enum { MPWOS_FP64_PLAIN = 0, MPWOS_FP32_MIXED = 1 } mpwos_precision;
 /* Compensation m (eq. mismatch_definition) added to the source of each Green sample:
  *   NONE: m_* = 0 (the baseline variant);
