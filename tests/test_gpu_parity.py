@@ -196,6 +196,29 @@ def test_full_size_sampled_walks_match_oracle():
         assert bad == 0
 
 
+@pytest.mark.parametrize("name,persistent", [("sphere", 0), ("cap", 1)])
+def test_full_size_fp32_benchmark_form_sampled_walks_track_oracle(name, persistent):
+    # the form the benchmark times (FP32, block 256; plain on the closed
+    # sphere, queue refill on the cap) at the full size: sampled walks against
+    # the oracle's FP64 walks on the same Philox stream
+    prob, Q, nw = inputs.config(name)
+    announce(f"full-size fp32 sampled tracking {name} persistent={persistent}")
+    g = mpwos.solve(prob, Q, nw, 0, walk_outputs=True, precision="fp32", persistent=persistent,
+                    block_size=256)
+    rng = np.random.default_rng(1)
+    P = oracle.Problem(prob)
+    picks = [(int(rng.integers(len(Q))), int(rng.integers(nw))) for _ in range(48)]
+    picks += [(len(Q) - 1, nw - 1), (0, 0)]
+    same, rel = 0, []
+    for q, w in picks:
+        S, K, _ = oracle.walk(P, Q[q], q, w, 0)
+        if K == g["walk_K"][q, w]:
+            same += 1
+            rel.append(abs(S - g["walk_S"][q, w]) / (1.0 + abs(S)))
+    assert same >= len(picks) - 2, same
+    assert np.median(rel) < 1e-4 and max(rel) < 1e-2, (np.median(rel), max(rel))
+
+
 def test_edge_sizes():
     prob = inputs.sphere_problem()
     Q = inputs.sphere_uniform(1, 3, seed=1)
