@@ -110,23 +110,25 @@ static void host_law(int n, HostLaw& h) {
   h.n = n;
   h.nu = 0.5 * (n - 2);
   h.nu_int = (n % 2 == 0) ? (n - 2) / 2 : -1;
-  h.alpha[0] = h.alpha1[0] = 1.0;
+  // alpha_j = 1/(4^j j! (nu+1)_j); the S_{nu+1} coefficients follow from
+  // (nu+2)_j = (nu+1)_j (nu+1+j)/(nu+1).
+  h.alpha[0] = 1.0;
+  for (int j = 1; j < kHostJ; ++j) h.alpha[j] = h.alpha[j - 1] * (0.25 / j) / (h.nu + j);
+  for (int j = 0; j < kHostJ; ++j) h.alpha1[j] = h.alpha[j] * ((h.nu + 1.0) / (h.nu + 1.0 + j));
+  // S_nu^-2 as the square of the reciprocal series P = 1/S_nu:
+  // p_0 = 1, p_j = -sum_{i=1..j} alpha_i p_{j-i}; beta_j = sum_i p_i p_{j-i}.
+  double p[kHostJ];
+  p[0] = 1.0;
   for (int j = 1; j < kHostJ; ++j) {
-    h.alpha[j] = h.alpha[j - 1] / (4.0 * j * (h.nu + j));
-    h.alpha1[j] = h.alpha1[j - 1] / (4.0 * j * (h.nu + 1.0 + j));
+    double acc = 0.0;
+    for (int i = j; i >= 1; --i) acc -= h.alpha[i] * p[j - i];
+    p[j] = acc;
   }
-  // power-series reciprocal of S_nu^2
-  double sq[kHostJ];
   for (int j = 0; j < kHostJ; ++j) {
     double acc = 0.0;
-    for (int i = 0; i <= j; ++i) acc += h.alpha[i] * h.alpha[j - i];
-    sq[j] = acc;
-  }
-  h.beta[0] = 1.0;
-  for (int j = 1; j < kHostJ; ++j) {
-    double acc = 0.0;
-    for (int i = 1; i <= j; ++i) acc += sq[i] * h.beta[j - i];
-    h.beta[j] = -acc;
+    for (int i = 0; 2 * i < j; ++i) acc += 2.0 * p[i] * p[j - i];
+    if (j % 2 == 0) acc += p[j / 2] * p[j / 2];
+    h.beta[j] = acc;
   }
 }
 
@@ -289,18 +291,16 @@ static mpwos_status get_table(const HostLaw& h, int mx, double x2max, InvTable& 
   return MPWOS_OK;
 }
 
-// screening factor c and omega (Lemma 3.1 series)
-static void host_weights(int n, double sigma, double r, double& c, double& om) {
-  const double nu = 0.5 * (n - 2);
-  const double q = 0.25 * sigma * r * r;
-  double term = 1.0, s1 = 0.0;
-  for (int j = 1; j < 100000; ++j) {
-    term = term * q / ((double)j * (nu + (double)j));
-    s1 += term;
-    if (term <= 1e-18 * s1) break;
-  }
+// Screening factor c and volume weight omega for a constant radius (Lemma
+// 3.1 series, eq. omega_explicit_formula): s1 = S_nu(X) - 1 by Horner in
+// z = X^2 = sigma r^2 over the law's coefficients alpha_j (the same form the
+// device uses for per-step radii), with every coefficient the host keeps.
+static void host_weights(const HostLaw& h, double sigma, double r, double& c, double& om) {
+  const double z = sigma * r * r;
+  double s1 = 0.0;
+  for (int j = kHostJ - 1; j >= 1; --j) s1 = (s1 + h.alpha[j]) * z;
   c = 1.0 / (1.0 + s1);
-  om = s1 / (sigma * (1.0 + s1));
+  om = s1 * c / sigma;
 }
 
 // ---------------------------------------------------------------------------
@@ -442,42 +442,40 @@ static void fill_fn(const mpwos_fn* f, const mpwos_manifold_desc& d, double sigm
   }
 }
 
-// Nearest profile parameter of the dumbbell to (|x_h|, x_n) = (rho, zs), on
-// the host (query checks): the best point of a fine grid, then Newton on the
-// derivative of the squared planar distance, bracketed.
-static double dumbbell_phi_host(double a, double k, double rho, double zs) {
-  auto prof = [&](double t, double* v) {
-    const double s = std::sin(t), c = std::cos(t);
-    const double g = 1.0 - a + 2.0 * a * c * c, g1 = -4.0 * a * c * s, g2 = -4.0 * a * (c * c - s * s);
-    v[0] = s * g;
-    v[1] = c * g + s * g1;
-    v[2] = -s * g + 2.0 * c * g1 + s * g2;
-    v[3] = k * c;
-    v[4] = -k * s;
-    v[5] = -k * c;
+// Distance from (|x_h|, x_n) = (rho, zs) to the dumbbell's profile
+// {(R(x*), x*) : |x*| <= kc}, R(x*) = sqrt(1 - (x*/kc)^2) (1 - a + 2a (x*/kc)^2)
+// (Example 2's level set), as far as the query check needs it: a profile
+// point within tol of (rho, zs) has |x* - zs| <= tol, so the minimum of the
+// distance over that window decides whether the query lies within tol of
+// the manifold.  The window is far shorter than any radius of curvature of
+// the profile, so the distance is unimodal on it and a golden-section search
+// finds its minimum.
+static double dumbbell_window_distance(double a, double kc, double rho, double zs, double tol) {
+  const double lo0 = std::max(-kc, zs - tol), hi0 = std::min(kc, zs + tol);
+  if (lo0 > hi0) return INFINITY;
+  // 1 - (x*/kc)^2 as (kc - x*)(kc + x*)/kc^2: no cancellation at the tips
+  auto dist2 = [&](double xs) {
+    const double q = xs / kc;
+    const double w = std::max(0.0, (kc - xs) * (kc + xs)) / (kc * kc);
+    const double R = std::sqrt(w) * (1.0 - a + 2.0 * a * q * q);
+    return (rho - R) * (rho - R) + (zs - xs) * (zs - xs);
   };
-  const int G = 1024;
-  const double pi = 3.141592653589793, h = pi / G;
-  int best = 0;
-  double bd = INFINITY, v[6];
-  for (int j = 0; j <= G; ++j) {
-    prof(j * h, v);
-    const double d = (rho - v[0]) * (rho - v[0]) + (zs - v[3]) * (zs - v[3]);
-    if (d < bd) { bd = d; best = j; }
+  const double gr = 0.6180339887498949;
+  double lo = lo0, hi = hi0;
+  double x1 = hi - gr * (hi - lo), x2 = lo + gr * (hi - lo);
+  double f1 = dist2(x1), f2 = dist2(x2);
+  double best = std::min({dist2(lo0), dist2(hi0), f1, f2});
+  for (int it = 0; it < 200 && hi - lo > 1e-17 * (1.0 + std::fabs(hi)); ++it) {
+    if (f1 <= f2) {
+      hi = x2; x2 = x1; f2 = f1;
+      x1 = hi - gr * (hi - lo); f1 = dist2(x1);
+    } else {
+      lo = x1; x1 = x2; f1 = f2;
+      x2 = lo + gr * (hi - lo); f2 = dist2(x2);
+    }
+    best = std::min({best, f1, f2});
   }
-  double lo = best > 0 ? (best - 1) * h : 0.0, hi = best < G ? (best + 1) * h : pi, t = best * h;
-  for (int it = 0; it < 100; ++it) {
-    prof(t, v);
-    const double d1 = -2.0 * ((rho - v[0]) * v[1] + (zs - v[3]) * v[4]);
-    const double d2 = 2.0 * (v[1] * v[1] + v[4] * v[4]) - 2.0 * ((rho - v[0]) * v[2] + (zs - v[3]) * v[5]);
-    if (d1 > 0.0) hi = t; else lo = t;
-    double nx = d2 > 0.0 ? t - d1 / d2 : lo - 1.0;
-    if (!(nx >= lo && nx <= hi)) nx = 0.5 * (lo + hi);
-    const double step = std::fabs(nx - t);
-    t = nx;
-    if (step <= 1e-16 * (1.0 + t) || hi - lo <= 1e-16 * (1.0 + t)) break;
-  }
-  return t;
+  return std::sqrt(best);
 }
 
 // on-manifold test of a query (host side, analytic manifolds)
@@ -541,9 +539,7 @@ static bool query_on_manifold(const mpwos_manifold_desc& d, const double* y) {
       double hh = 0.0;
       for (int i = 0; i < n - 1; ++i) hh += y[i] * y[i];
       const double rho = std::sqrt(hh), zs = y[n - 1];
-      const double t = dumbbell_phi_host(d.p[0], d.p[1], rho, zs);
-      const double pr = std::sin(t) * (1.0 - d.p[0] + 2.0 * d.p[0] * std::cos(t) * std::cos(t));
-      return std::hypot(rho - pr, zs - d.p[1] * std::cos(t)) <= tol;
+      return dumbbell_window_distance(d.p[0], d.p[1], rho, zs, tol) <= tol;
     }
   }
   return true;
@@ -749,7 +745,7 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
                   ? 1 : 0;
   if (a.const_r) {
     a.r0 = rmax;
-    host_weights(d.n, sigma, a.r0, a.c0, a.om0);
+    host_weights(h, sigma, a.r0, a.c0, a.om0);
     a.X0 = std::sqrt(sigma) * a.r0;
     fill_fixed(h, a.law, a.X0, a.fixed);
     st = get_table(h, 1, a.X0 * a.X0, a.tab);

@@ -70,3 +70,37 @@ def test_served_dumbbell_equals_solo():
     srv.close()
     m.close()
     assert np.array_equal(solo["u"], out["u"]) and np.array_equal(solo["stderr"], out["stderr"])
+
+
+def test_query_check_accepts_level_set_and_rejects_offsets():
+    """The host's on-manifold check of dumbbell queries (Example 2's level set
+    ||x_h|| = R(x_n)): points of the profile, also within 1e-6 of the tips,
+    are accepted; points moved 1e-7 along the normal are refused."""
+    n = 11
+    prob = inputs.dumbbell_problem(n)
+    m = mpwos.Manifold(prob)
+    kc = prob["p"][1]
+    Q = inputs.dumbbell_points(16, n, seed=9, phi_margin=0.0)
+    # points near both tips: x_n = +-(kc - d), radius from the paper's R
+    tips = []
+    for d in (1e-6, 1e-9):
+        for sgn in (1.0, -1.0):
+            xs = sgn * (kc - d)
+            e = np.zeros(n - 1)
+            e[0] = 1.0
+            tips.append(np.concatenate([e * inputs.dumbbell_profile_radius(xs), [xs]]))
+    Q = np.concatenate([Q, np.array(tips)])
+    announce("dumbbell query check n=11")
+    mpwos.solve(prob, Q, 4, 0, manifold=m, precision="fp64", tau_w=0.5)
+    # the normal at (R(xs) e, xs): the gradient of ||x_h|| - R(x_n), normalised
+    for q in inputs.dumbbell_points(4, n, seed=10):
+        xh, xs = q[:-1], q[-1]
+        h = 1e-7
+        dR = (inputs.dumbbell_profile_radius(xs + h) - inputs.dumbbell_profile_radius(xs - h)) / (2 * h)
+        g = np.concatenate([xh / np.linalg.norm(xh), [-dR]])
+        g /= np.linalg.norm(g)
+        for s in (1e-7, -1e-7):
+            with pytest.raises(mpwos.MpwosError) as ei:
+                mpwos.solve(prob, (q + s * g)[None, :], 4, 0, manifold=m, precision="fp64", tau_w=0.5)
+            assert ei.value.status == mpwos.EOFFMANIFOLD
+    m.close()
