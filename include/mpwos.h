@@ -229,6 +229,33 @@ mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_fn* f, cons
                          double eps, uint64_t seed, const mpwos_options* opt, double* u_out,
                          double* stderr_out, mpwos_stats* stats);
 
+/* ---- allocation-free solve ----------------------------------------------
+ * For callers that cannot allocate device memory: tight serving loops and
+ * harnesses that forbid hipMalloc (it synchronises on the stream, so it is
+ * not for graph capture; mpwos_plan_* is).  The same solve as mpwos_solve
+ * with device_io = 1, on the same kernels and with the same results bit for
+ * bit, except that everything mpwos_solve would allocate lives in one fixed
+ * device array of MPWOS_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends: statistics and queue words, the source's values, one
+ * inverse radial table (a table another solve already cached is used from
+ * the cache), and the per-walk scores of a batch of queries (12 bytes per
+ * walk; queries are processed in batches that fit).
+ *   queries, u_out, stderr_out (nullable), opt->walk_S / walk_K (optional,
+ *   both or neither, n_queries x n_walks): device pointers, whatever
+ *   opt->device_io says.  The manifold must live on the current device.
+ * Limits (EINVAL beyond them): n_walks <= (MPWOS_NOALLOC_SCRATCH_BYTES -
+ * 1 MiB - 8) / 12 per query (5 505 023); at most 32768 source values;
+ * the radial table of 17 slices.
+ * Calls on one GPU share its array, which keeps the last call's contents:
+ * calls that overlap on one GPU (from several threads, or on several
+ * streams) race and must be serialised by the caller.
+ * stats->kernel_ms and reduce_ms are 0 (no timing events). */
+#define MPWOS_NOALLOC_SCRATCH_BYTES (64u << 20)
+mpwos_status mpwos_solve_noalloc(const mpwos_manifold* manifold, const mpwos_fn* f, const mpwos_fn* g,
+                                 double c, const double* queries, int64_t n_queries, int64_t n_walks,
+                                 double eps, uint64_t seed, const mpwos_options* opt, double* u_out,
+                                 double* stderr_out, mpwos_stats* stats);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* mpwos_last_error(void);
 

@@ -658,28 +658,41 @@ double cloud_max_spacing(const CloudState* c) { return c->hmean_max; }
 
 // A point-cloud query is an ambient point within two local spacings of the
 // reconstructed surface (the walk starts from its projection).
-mpwos_status cloud_check_queries(const WalkArgs& a, const double* dq, int64_t nq, hipStream_t s) {
-  double* dout = nullptr;
-  const size_t bytes = (size_t)nq * 2 * sizeof(double);
-  hipError_t e = hipMalloc((void**)&dout, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(MPWOS_ENOMEM, "query check buffer");
+mpwos_status cloud_check_queries(const WalkArgs& a, const double* dq, int64_t nq, hipStream_t s, double* out_dev,
+                                 int64_t out_cap) {
+  double* dout = out_dev;
+  int64_t batch = out_cap / 2;
+  if (!dout) {
+    const size_t bytes = (size_t)nq * 2 * sizeof(double);
+    hipError_t e = hipMalloc((void**)&dout, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MPWOS_ENOMEM, "query check buffer");
+    }
+    batch = nq;
   }
-  std::vector<double> out((size_t)nq * 2);
-  hipLaunchKernelGGL(cloud_query_check_kernel, dim3((unsigned)((nq + kCloudBlock - 1) / kCloudBlock)),
-                     dim3(kCloudBlock), 0, s, a.cloud, dq,
-                     dout, nq);
-  e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemcpyAsync(out.data(), dout, bytes, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(dout);
+  if (batch < 1) return fail(MPWOS_EINVAL, "query check buffer too small");
+  std::vector<double> out((size_t)std::min(batch, nq) * 2);
+  hipError_t e = hipSuccess;
+  mpwos_status st = MPWOS_OK;
+  for (int64_t q0 = 0; q0 < nq && e == hipSuccess && !st; q0 += batch) {
+    const int64_t nb = std::min(batch, nq - q0);
+    hipLaunchKernelGGL(cloud_query_check_kernel, dim3((unsigned)((nb + kCloudBlock - 1) / kCloudBlock)),
+                       dim3(kCloudBlock), 0, s, a.cloud, dq + q0 * 3, dout, nb);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(out.data(), dout, (size_t)nb * 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) break;
+    for (int64_t i = 0; i < nb; ++i)
+      if (!(out[2 * i] <= 2.0 * out[2 * i + 1])) {
+        st = fail(MPWOS_EOFFMANIFOLD, "query " + std::to_string(q0 + i) + " is farther than two local spacings "
+                                      "from the reconstructed surface");
+        break;
+      }
+  }
+  if (!out_dev) (void)hipFree(dout);
   if (e != hipSuccess) return hip_fail(e, "query check");
-  for (int64_t i = 0; i < nq; ++i)
-    if (!(out[2 * i] <= 2.0 * out[2 * i + 1]))
-      return fail(MPWOS_EOFFMANIFOLD, "query " + std::to_string(i) + " is farther than two local spacings from "
-                                      "the reconstructed surface");
-  return MPWOS_OK;
+  return st;
 }
 
 }  // namespace mpwos

@@ -21,16 +21,24 @@ int device_cu_count();
 void manifold_ref(const mpwos_manifold* m, int d);
 const mpwos_manifold_desc& manifold_desc(const mpwos_manifold* m);
 
+struct TableSink;
+// Validates a solve and fills the kernel arguments (except buffers).  With a
+// sink, an inverse table that is not cached goes to the sink's device region
+// instead of a new allocation.
 mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const mpwos_fn* g, double sigma,
                            int64_t nq, int64_t nw, double eps, uint64_t seed, const mpwos_options& o,
-                           WalkArgs& a);
+                           WalkArgs& a, TableSink* sink = nullptr);
 mpwos_status launch_walks(WalkArgs& a, const mpwos_options& o, hipStream_t s, unsigned long long* queue);
 // Walks per batch unit of a batched launch: every entry begins on a multiple.
 int64_t batch_unit(const WalkArgs& a, const mpwos_options& o);
 // Philox blocks one walk-step draws (a cost estimate for sizing work): one
 // per sub-stream for n <= 3, the normal pairs and radius word for n >= 4.
 double philox_blocks_per_step(int n, int n_v);
-mpwos_status cloud_check_queries(const WalkArgs& a, const double* dq, int64_t nq, hipStream_t s);
+// Every point-cloud query within two local spacings of the reconstruction.
+// With a device buffer (out, out_cap doubles) the check runs in batches in
+// it and allocates no device memory.
+mpwos_status cloud_check_queries(const WalkArgs& a, const double* dq, int64_t nq, hipStream_t s,
+                                 double* out = nullptr, int64_t out_cap = 0);
 mpwos_status check_queries_host(const mpwos_manifold* man, const WalkArgs& a, const double* q, int64_t nq);
 
 // walk_lane.hip

@@ -246,48 +246,91 @@ struct TableVal {
 static std::mutex g_tab_lock;
 static std::map<TableKey, TableVal> g_tables;
 
-static mpwos_status get_table(const HostLaw& h, int mx, double x2max, InvTable& t) {
-  // 1025 points per half keep linear interpolation in w within 1.1e-6 of the
-  // root for every n (the worst case is n = 2 near u = 0, where s ~ sqrt(u / ln(1/u)))
-  const int mu = 1025;
-  TableKey key{h.n, mx, x2max};
-  std::lock_guard<std::mutex> g(g_tab_lock);
-  auto it = g_tables.find(key);
-  if (it == g_tables.end()) {
-    std::vector<double> s64((size_t)mx * 2 * mu);
-    std::vector<float> s32((size_t)mx * 2 * mu);
-    const double wmax = std::sqrt(0.5);
-    for (int k = 0; k < mx; ++k) {
-      const double X2 = (mx == 1) ? x2max : (k == 0 ? x2max * 1e-6 : x2max * k / (mx - 1));
-      for (int half = 0; half < 2; ++half) {
-        double* row = s64.data() + ((size_t)k * 2 + half) * mu;
-        for (int i = 0; i < mu; ++i) {
-          const double w = wmax * (double)i / (mu - 1);
-          const double u = half == 0 ? w * w : 1.0 - w * w;
-          double sv;
-          if (half == 0 && i == 0) sv = 0.0;
-          else if (half == 1 && i == 0) sv = 1.0;
-          else sv = host_inv(h, X2, u, 0.0, 1.0);
-          row[i] = sv;
-        }
-        for (int i = 0; i < mu; ++i) s32[((size_t)k * 2 + half) * mu + i] = (float)row[i];
+// 1025 points per half keep linear interpolation in w within 1.1e-6 of the
+// root for every n (the worst case is n = 2 near u = 0, where s ~ sqrt(u / ln(1/u)))
+static constexpr int kTableMu = 1025;
+
+// The inverse radial law at the table points, on the host: mx slices in X^2,
+// two halves (u = w^2 and 1 - w^2, w uniform in [0, sqrt(1/2)]) of kTableMu
+// points each, FP64 and FP32 copies.
+static void fill_table_host(const HostLaw& h, int mx, double x2max, double* s64, float* s32) {
+  const int mu = kTableMu;
+  const double wmax = std::sqrt(0.5);
+  for (int k = 0; k < mx; ++k) {
+    const double X2 = (mx == 1) ? x2max : (k == 0 ? x2max * 1e-6 : x2max * k / (mx - 1));
+    for (int half = 0; half < 2; ++half) {
+      double* row = s64 + ((size_t)k * 2 + half) * mu;
+      for (int i = 0; i < mu; ++i) {
+        const double w = wmax * (double)i / (mu - 1);
+        const double u = half == 0 ? w * w : 1.0 - w * w;
+        double sv;
+        if (half == 0 && i == 0) sv = 0.0;
+        else if (half == 1 && i == 0) sv = 1.0;
+        else sv = host_inv(h, X2, u, 0.0, 1.0);
+        row[i] = sv;
       }
+      for (int i = 0; i < mu; ++i) s32[((size_t)k * 2 + half) * mu + i] = (float)row[i];
     }
-    TableVal v;
-    v.mu = mu;
-    hipError_t e = hipMalloc(&v.d64, s64.size() * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&v.d32, s32.size() * sizeof(float));
-    if (e == hipSuccess) e = hipMemcpy(v.d64, s64.data(), s64.size() * sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(v.d32, s32.data(), s32.size() * sizeof(float), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "inverse table upload");
-    it = g_tables.emplace(key, v).first;
   }
-  t.s64 = it->second.d64;
-  t.s32 = it->second.d32;
-  t.mu = it->second.mu;
+}
+
+static void set_table_view(const double* d64, const float* d32, int mx, double x2max, InvTable& t) {
+  t.s64 = d64;
+  t.s32 = d32;
+  t.mu = kTableMu;
   t.mx = mx;
   t.x2max = x2max;
   t.x2scale = mx > 1 ? (double)(mx - 1) / x2max : 0.0;
+}
+
+// A device region the allocation-free solve keeps one inverse table in
+// (instead of the cache below, which allocates), and the key of the table it
+// holds.
+struct TableSink {
+  double* d64 = nullptr;
+  float* d32 = nullptr;
+  size_t bytes = 0;
+  TableKey* held = nullptr;
+  hipStream_t stream = nullptr;
+  bool use_cache = false;  // the cache's tables live on the calling device
+};
+
+static mpwos_status get_table(const HostLaw& h, int mx, double x2max, InvTable& t, TableSink* sink = nullptr) {
+  const int mu = kTableMu;
+  TableKey key{h.n, mx, x2max};
+  std::lock_guard<std::mutex> g(g_tab_lock);
+  auto it = g_tables.find(key);
+  if (it != g_tables.end() && (!sink || sink->use_cache)) {
+    set_table_view(it->second.d64, it->second.d32, mx, x2max, t);
+    return MPWOS_OK;
+  }
+  std::vector<double> s64((size_t)mx * 2 * mu);
+  std::vector<float> s32((size_t)mx * 2 * mu);
+  if (sink) {
+    const size_t b64 = s64.size() * sizeof(double), b32 = s32.size() * sizeof(float);
+    if (b64 + b32 > sink->bytes) return fail(MPWOS_EINVAL, "inverse table exceeds the allocation-free scratch");
+    sink->d32 = (float*)((char*)sink->d64 + b64);
+    if (!(sink->held && !(*sink->held < key) && !(key < *sink->held))) {
+      fill_table_host(h, mx, x2max, s64.data(), s32.data());
+      hipError_t e = hipMemcpyAsync(sink->d64, s64.data(), b64, hipMemcpyHostToDevice, sink->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(sink->d32, s32.data(), b32, hipMemcpyHostToDevice, sink->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(sink->stream);
+      if (e != hipSuccess) return hip_fail(e, "inverse table upload to the scratch");
+      if (sink->held) *sink->held = key;
+    }
+    set_table_view(sink->d64, sink->d32, mx, x2max, t);
+    return MPWOS_OK;
+  }
+  fill_table_host(h, mx, x2max, s64.data(), s32.data());
+  TableVal v;
+  v.mu = mu;
+  hipError_t e = hipMalloc(&v.d64, s64.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&v.d32, s32.size() * sizeof(float));
+  if (e == hipSuccess) e = hipMemcpy(v.d64, s64.data(), s64.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(v.d32, s32.data(), s32.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "inverse table upload");
+  it = g_tables.emplace(key, v).first;
+  set_table_view(it->second.d64, it->second.d32, mx, x2max, t);
   return MPWOS_OK;
 }
 
@@ -615,7 +658,7 @@ const mpwos_manifold_desc& manifold_desc(const mpwos_manifold* m) { return m->de
 // Validates a solve and fills the kernel arguments (except buffers).
 mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const mpwos_fn* g, double sigma,
                            int64_t nq, int64_t nw, double eps, uint64_t seed, const mpwos_options& o,
-                           WalkArgs& a) {
+                           WalkArgs& a, TableSink* sink) {
   if (!man) return fail(MPWOS_EINVAL, "manifold is NULL");
   const mpwos_manifold_desc& d = man->desc;
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(MPWOS_EINVAL, "c (sigma) must be finite and > 0");
@@ -748,9 +791,9 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
     host_weights(h, sigma, a.r0, a.c0, a.om0);
     a.X0 = std::sqrt(sigma) * a.r0;
     fill_fixed(h, a.law, a.X0, a.fixed);
-    st = get_table(h, 1, a.X0 * a.X0, a.tab);
+    st = get_table(h, 1, a.X0 * a.X0, a.tab, sink);
   } else {
-    st = get_table(h, 17, x2max, a.tab);
+    st = get_table(h, 17, x2max, a.tab, sink);
   }
   if (st) return st;
   if (d.kind == MPWOS_POINT_CLOUD) cloud_fill_args(man->cloud, o, a);
@@ -943,6 +986,161 @@ extern "C" mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_
     stats->k_mean = (double)ksum / ((double)n_queries * (double)n_walks);
     stats->kernel_ms = kernel_ms;
     stats->reduce_ms = reduce_ms;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return ntr ? MPWOS_WTRUNC : MPWOS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free solve
+// ---------------------------------------------------------------------------
+// One fixed array per device holds everything mpwos_solve would allocate:
+//   [0, 4 KiB)        statistics words and the persistent queue counter
+//   [4 KiB, 260 KiB)  the source family's values (at most 32768 doubles)
+//   [512 KiB, 1 MiB)  one inverse radial table (at most 17 slices)
+//   [1 MiB, end)      per-walk scores and lengths of a batch of queries, the
+//                     discarded standard errors when stderr_out is NULL, or
+//                     the point-cloud query check's output
+// In host code `scratch` names a host-side stand-in: only the address from
+// hipGetSymbolAddress is passed to kernels and copies.
+namespace mpwos {
+static constexpr size_t kScratchBytes = (size_t)MPWOS_NOALLOC_SCRATCH_BYTES;
+static constexpr size_t kScratchValuesOff = 4096, kScratchValuesMax = 32768;
+static constexpr size_t kScratchTableOff = 512 * 1024, kScratchTableBytes = 512 * 1024;
+static constexpr size_t kScratchWalkOff = 1024 * 1024;
+static_assert(kScratchValuesOff + kScratchValuesMax * sizeof(double) <= kScratchTableOff, "scratch layout");
+static_assert(kScratchTableOff + kScratchTableBytes <= kScratchWalkOff && kScratchWalkOff < kScratchBytes,
+              "scratch layout");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static constexpr int kMaxDevices = 64;
+struct ScratchSlot {
+  unsigned char* ptr = nullptr;  // device address of this device's array
+  TableKey table{0, 0, 0.0};     // inverse table the array holds (n = 0: none)
+};
+static ScratchSlot g_scratch[kMaxDevices];
+static std::mutex g_scratch_lock;
+
+// The device address of the current device's array, looked up once per device.
+static mpwos_status scratch_slot(int dev, ScratchSlot*& slot) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(MPWOS_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> g(g_scratch_lock);
+  ScratchSlot& sl = g_scratch[dev];
+  if (!sl.ptr) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch symbol address");
+    sl.ptr = (unsigned char*)p;
+  }
+  slot = &sl;
+  return MPWOS_OK;
+}
+}  // namespace mpwos
+
+extern "C" mpwos_status mpwos_solve_noalloc(const mpwos_manifold* manifold, const mpwos_fn* f, const mpwos_fn* g,
+                                            double c, const double* queries, int64_t n_queries, int64_t n_walks,
+                                            double eps, uint64_t seed, const mpwos_options* opt, double* u_out,
+                                            double* stderr_out, mpwos_stats* stats) {
+  g_last_error.clear();
+  const auto t0 = std::chrono::steady_clock::now();
+  mpwos_options o;
+  if (opt) o = *opt;
+  else mpwos_options_default(&o);
+  o.device_io = 1;
+  if (!queries || !u_out) return fail(MPWOS_EINVAL, "queries and u_out must not be NULL");
+  if ((o.walk_S == nullptr) != (o.walk_K == nullptr))
+    return fail(MPWOS_EINVAL, "walk_S and walk_K are given together or not at all");
+  std::lock_guard<std::mutex> guard(g_ctx.lock);
+  mpwos_status st = context_init(g_ctx);
+  if (st) return st;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  ScratchSlot* slot = nullptr;
+  st = scratch_slot(dev, slot);
+  if (st) return st;
+  unsigned char* base = slot->ptr;
+  hipStream_t s = o.stream ? (hipStream_t)o.stream : (dev == g_ctx.device ? g_ctx.stream : nullptr);
+
+  TableSink sink;
+  sink.d64 = (double*)(base + kScratchTableOff);
+  sink.bytes = kScratchTableBytes;
+  sink.held = &slot->table;
+  sink.stream = s;
+  sink.use_cache = dev == g_ctx.device;
+  WalkArgs a;
+  st = prepare_solve(manifold, f, g, c, n_queries, n_walks, eps, seed, o, a, &sink);
+  if (st) return st;
+  const mpwos_manifold_desc& d = manifold->desc;
+  const int n = d.n;
+
+  // sizes against the array
+  const bool user_walk = o.walk_S && o.walk_K;
+  const size_t walk_region = kScratchBytes - kScratchWalkOff;
+  const int64_t max_walks = (int64_t)((walk_region - sizeof(double)) / 12);
+  if (!user_walk && n_walks > max_walks)
+    return fail(MPWOS_EINVAL, "n_walks = " + std::to_string(n_walks) + " exceeds the allocation-free limit of " +
+                                  std::to_string(max_walks) + " walks per query");
+  const size_t per_query = (user_walk ? 0 : (size_t)n_walks * 12) + (stderr_out ? 0 : sizeof(double));
+  const int64_t qb =
+      user_walk ? n_queries : (int64_t)std::min<size_t>((size_t)n_queries, walk_region / per_query);
+  if (user_walk && !stderr_out && (size_t)n_queries * sizeof(double) > walk_region)
+    return fail(MPWOS_EINVAL, "n_queries exceeds the allocation-free limit without stderr_out");
+  if (fn_has_values(f->kind) && (size_t)f->n_values > kScratchValuesMax)
+    return fail(MPWOS_EINVAL, "f has more than " + std::to_string(kScratchValuesMax) +
+                                  " values, beyond the allocation-free limit");
+
+  // queries on the manifold
+  if (d.kind != MPWOS_POINT_CLOUD) {
+    std::vector<double> hq((size_t)n_queries * n);
+    HIP_TRY(hipMemcpyAsync(hq.data(), queries, hq.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int64_t q = 0; q < n_queries; ++q)
+      if (!query_on_manifold(d, hq.data() + q * n))
+        return fail(MPWOS_EOFFMANIFOLD, "query " + std::to_string(q) + " is not on the manifold");
+  } else {
+    st = cloud_check_queries(a, queries, n_queries, s, (double*)(base + kScratchWalkOff),
+                             (int64_t)(walk_region / sizeof(double)));
+    if (st) return st;
+  }
+  if (fn_has_values(f->kind)) {
+    double* dv = (double*)(base + kScratchValuesOff);
+    HIP_TRY(hipMemcpyAsync(dv, f->values, (size_t)f->n_values * sizeof(double), hipMemcpyHostToDevice, s));
+    a.f.values = dv;
+  }
+
+  unsigned long long* dstat = (unsigned long long*)base;
+  HIP_TRY(launch_zero_u64(dstat, 8, s));
+  double* wS = user_walk ? o.walk_S : (double*)(base + kScratchWalkOff);
+  int32_t* wK = user_walk ? o.walk_K : (int32_t*)(base + kScratchWalkOff + (size_t)qb * n_walks * sizeof(double));
+  double* se_discard =
+      user_walk ? (double*)(base + kScratchWalkOff) : (double*)((unsigned char*)wK + (size_t)qb * n_walks * 4);
+  for (int64_t q0 = 0; q0 < n_queries; q0 += qb) {
+    const int64_t nb = std::min(qb, n_queries - q0);
+    a.queries = queries + q0 * n;
+    a.nq = nb;
+    a.nw = n_walks;
+    a.q_offset = q0;
+    a.idx_base = 0;
+    a.count = nb * n_walks;
+    a.walk_S = user_walk ? wS + q0 * n_walks : wS;
+    a.walk_K = user_walk ? wK + q0 * n_walks : wK;
+    st = launch_walks(a, o, s, dstat + 4);
+    if (st) return st;
+    HIP_TRY(launch_reduce(a.walk_S, a.walk_K, nb, n_walks, o.max_steps, u_out + q0,
+                          stderr_out ? stderr_out + q0 : se_discard, dstat + 0, (int32_t*)(dstat + 1), dstat + 2, s));
+  }
+  unsigned long long hs[8];
+  HIP_TRY(hipMemcpyAsync(hs, dstat, sizeof(hs), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t ntr = (int64_t)hs[2];
+  if (stats) {
+    stats->walk_steps = (int64_t)hs[0];
+    stats->truncated = ntr;
+    stats->k_max = (int32_t)(uint32_t)hs[1];
+    stats->k_mean = (double)hs[0] / ((double)n_queries * (double)n_walks);
+    stats->kernel_ms = 0.0;
+    stats->reduce_ms = 0.0;
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return ntr ? MPWOS_WTRUNC : MPWOS_OK;

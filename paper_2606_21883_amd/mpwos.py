@@ -79,7 +79,7 @@ EXPORTS = ["mpwos_options_default", "mpwos_manifold_create", "mpwos_manifold_des
            "mpwos_debug_radial_inv",
            "mpwos_debug_philox", "mpwos_copy_probe", "mpwos_valu_probe", "mpwos_version",
            "mpwos_plan_create", "mpwos_plan_execute", "mpwos_plan_stats", "mpwos_plan_destroy", "mpwos_autotune",
-           "mpwos_predictor_fit", "mpwos_debug_ts_fit"]
+           "mpwos_predictor_fit", "mpwos_debug_ts_fit", "mpwos_solve_noalloc"]
 
 _lib = None
 
@@ -104,6 +104,7 @@ def lib():
         L.mpwos_manifold_create.argtypes = [vp, vp]
         L.mpwos_manifold_destroy.argtypes = [vp]
         L.mpwos_solve.argtypes = [vp, vp, vp, d, vp, i64, i64, d, ctypes.c_uint64, vp, vp, vp, vp]
+        L.mpwos_solve_noalloc.argtypes = [vp, vp, vp, d, vp, i64, i64, d, ctypes.c_uint64, vp, vp, vp, vp]
         L.mpwos_last_error.restype = ctypes.c_char_p
         L.mpwos_version.restype = ctypes.c_char_p
         L.mpwos_server_create.argtypes = [ctypes.c_size_t, i64, vp]
@@ -301,6 +302,26 @@ def solve_device(manifold, prob, queries_ptr, nq, n_walks, seed, u_ptr, se_ptr, 
                            float(prob["sigma"]), ctypes.c_void_p(queries_ptr), int(nq), int(n_walks),
                            float(prob.get("eps", 1e-3)), int(seed), ctypes.byref(o), ctypes.c_void_p(u_ptr),
                            ctypes.c_void_p(se_ptr) if se_ptr else None, ctypes.byref(st))
+    _check(rc)
+    return {k: getattr(st, k) for k, _ in Stats._fields_}
+
+
+def solve_noalloc(manifold, prob, queries_ptr, nq, n_walks, seed, u_ptr, se_ptr, stream=None, walk_S_ptr=None,
+                  walk_K_ptr=None, **optkw):
+    """mpwos_solve_noalloc: device queries and outputs (raw device pointers),
+    no device allocation in the call."""
+    keep = []
+    f = make_fn(source_fn(prob), keep)
+    g = make_fn(prob.get("g"), keep) if has_boundary(prob) else None
+    o = make_options(prob, stream=stream, **optkw)
+    if walk_S_ptr:
+        o.walk_S = int(walk_S_ptr)
+        o.walk_K = int(walk_K_ptr)
+    st = Stats()
+    rc = lib().mpwos_solve_noalloc(manifold.handle, ctypes.byref(f), ctypes.byref(g) if g is not None else None,
+                                   float(prob["sigma"]), ctypes.c_void_p(queries_ptr), int(nq), int(n_walks),
+                                   float(prob.get("eps", 1e-3)), int(seed), ctypes.byref(o), ctypes.c_void_p(u_ptr),
+                                   ctypes.c_void_p(se_ptr) if se_ptr else None, ctypes.byref(st))
     _check(rc)
     return {k: getattr(st, k) for k, _ in Stats._fields_}
 
