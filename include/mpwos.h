@@ -139,12 +139,17 @@ typedef struct {
                                (the torus the source families refer to) */
   const float* points;      /* POINT_CLOUD: n_points x 3 FP32 */
   int64_t n_points;         /* POINT_CLOUD: k_nn .. 2^27 */
-  int32_t k_nn;             /* POINT_CLOUD: neighbours of the local fit, 6..32 (default 16) */
+  int32_t k_nn;             /* POINT_CLOUD: neighbours of the local fit and the spacing, 6..32 (default 16) */
   int32_t points_on_device; /* 1: `points` is a device pointer */
   int32_t reconstruction;   /* POINT_CLOUD: 0 = local quadratic patch of the k_nn points (default);
                                1 = the nearest cloud point itself (the pure nearest-neighbour
                                projection of Sec. 4, Example 4), with rho_geo from the spacing or a
                                curvature bound */
+  double fit_scale;         /* POINT_CLOUD, patch: the patch of a cloud point p is fitted to the cloud
+                               points within fit_scale r_k of p, r_k the distance to its k_nn-th nearest
+                               point; 0 or 1 = the k_nn nearest points themselves (default); at most 16.
+                               A wider fit resolves the curvature of a noisy cloud whose k_nn-point
+                               patches span the noise level */
 } mpwos_manifold_desc;
 
 typedef struct {

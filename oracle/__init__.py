@@ -49,7 +49,7 @@ class _Problem(ctypes.Structure):
         ("k_spacing", ctypes.c_int32), ("newton_iters", ctypes.c_int32),
         ("kappa_bound", ctypes.c_double), ("reconstruction", ctypes.c_int32),
         ("pred_coef", ctypes.c_void_p), ("pred_ks", ctypes.c_int32), ("pred_kt", ctypes.c_int32),
-        ("h_eta", ctypes.c_double),
+        ("h_eta", ctypes.c_double), ("fit_scale", ctypes.c_double), ("grid", ctypes.c_void_p),
     ]
 
 
@@ -85,6 +85,10 @@ def lib():
             getattr(L, nm).restype = d
         L.orc_radial_xmax.argtypes = [ctypes.c_int]; L.orc_radial_xmax.restype = d
         L.orc_knn.argtypes = [vp, i64, vp, ctypes.c_int, vp, vp]; L.orc_knn.restype = ctypes.c_int
+        L.orc_grid_build.argtypes = [vp, i64]; L.orc_grid_build.restype = vp
+        L.orc_grid_free.argtypes = [vp]; L.orc_grid_free.restype = None
+        L.orc_grid_knn.argtypes = [vp, vp, ctypes.c_int, vp, vp]; L.orc_grid_knn.restype = ctypes.c_int
+        L.orc_grid_ball.argtypes = [vp, vp, d, vp, i64]; L.orc_grid_ball.restype = i64
         L.orc_cp.argtypes = [vp, vp, vp]; L.orc_cp.restype = ctypes.c_int
         L.orc_delta_gamma.argtypes = [vp, vp]; L.orc_delta_gamma.restype = d
         L.orc_source.argtypes = [vp, vp]; L.orc_source.restype = d
@@ -104,6 +108,47 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+GRID_MIN_POINTS = 100_000
+
+
+class Grid:
+    """Exact uniform-grid index of a point cloud (orc_grid_*)."""
+
+    def __init__(self, pts):
+        self.pts = np.ascontiguousarray(pts, dtype=np.float64)
+        self.handle = lib().orc_grid_build(_ptr(self.pts), self.pts.shape[0])
+        if not self.handle:
+            raise MemoryError("orc_grid_build")
+
+    def knn(self, x, k):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        idx = np.zeros(k, dtype=np.int64)
+        d2 = np.zeros(k)
+        st = lib().orc_grid_knn(self.handle, _ptr(x), k, _ptr(idx), _ptr(d2))
+        if st:
+            raise ValueError(st)
+        return idx, d2
+
+    def ball(self, x, rho2):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        cap = 64
+        while True:
+            out = np.zeros(cap, dtype=np.int64)
+            cnt = lib().orc_grid_ball(self.handle, _ptr(x), float(rho2), _ptr(out), cap)
+            if cnt < 0:
+                raise ValueError(cnt)
+            if cnt <= cap:
+                return out[:cnt]
+            cap = cnt
+
+    def __del__(self):
+        try:
+            if self.handle and _lib is not None:
+                _lib.orc_grid_free(self.handle)
+        except Exception:
+            pass
+
+
 class Problem:
     """Marshals a problem dict into the oracle's struct; keeps arrays alive."""
 
@@ -115,11 +160,17 @@ class Problem:
         for i, v in enumerate(d.get("p", [1.0])):
             s.p[i] = float(v)
         self._keep = []
+        self._grid = None
         if d["manifold"] == "point_cloud":
             pts = np.ascontiguousarray(d["points"], dtype=np.float64)
             self._keep.append(pts)
             s.points = pts.ctypes.data
             s.n_points = pts.shape[0]
+            # large clouds are searched on an exact grid (equal to brute force)
+            if pts.shape[0] >= GRID_MIN_POINTS:
+                self._grid = Grid(pts)
+                s.grid = self._grid.handle
+        s.fit_scale = float(d.get("fit_scale", 1.0))
         s.k_nn = int(d.get("k_nn", 16))
         s.radius_rule = RADIUS_RULES[d.get("radius_rule", "curvature")]
         f = d.get("f", {"kind": "zero"})

@@ -68,6 +68,11 @@ typedef struct {
   /* second-order compensation: coefficients of the predictor u_* as a
    * Fourier-sine series (layout of ORC_FN_TORUS_SINE), and the normal step */
   const double* pred_coef; int32_t pred_ks, pred_kt; double h_eta;
+  /* point cloud: the patch of a cloud point p is fitted to the cloud points
+   * within fit_scale r_k of p, r_k the distance to its k_nn-th nearest
+   * point; fit_scale <= 1 fits the k_nn nearest points themselves */
+  double fit_scale;
+  const struct orc_grid* grid;  /* optional exact grid index of the points (orc_grid_build) */
 } orc_problem;
 
 /* ------------------------------------------------------------------------- */
@@ -384,6 +389,228 @@ int orc_knn(const double* pts, int64_t np, const double* x, int k, int64_t* idx_
   return ORC_OK;
 }
 
+/* Exact search on a uniform grid of cubic cells of side h: point i lies in
+ * cell floor((p_i - lo) / h) (clamped to the grid), the cells' point lists in
+ * ascending index.  A k-nearest search visits the cells in shells of growing
+ * Chebyshev distance L from the cell of x; every point outside the shells
+ * visited so far lies beyond the slab faces of the visited block, so the search
+ * stops once the k-th distance is below the nearest face (less a rounding
+ * allowance for the binning).  The results equal orc_knn's brute force. */
+typedef struct orc_grid {
+  const double* pts;
+  int64_t np;
+  double lo[3], h, slack;
+  int64_t nc[3];
+  int64_t* start;  /* ncell + 1 offsets into idx */
+  int64_t* idx;    /* point indices by cell */
+} orc_grid;
+
+static int64_t orc_grid_axis(const orc_grid* G, int d, double v) {
+  double c = floor((v - G->lo[d]) / G->h);
+  if (!(c >= 0.0)) return 0;
+  if (c > (double)(G->nc[d] - 1)) return G->nc[d] - 1;
+  return (int64_t)c;
+}
+
+orc_grid* orc_grid_build(const double* pts, int64_t np) {
+  if (!pts || np < 1) return NULL;
+  orc_grid* G = (orc_grid*)calloc(1, sizeof(orc_grid));
+  if (!G) return NULL;
+  G->pts = pts;
+  G->np = np;
+  double hi[3];
+  for (int d = 0; d < 3; ++d) { G->lo[d] = pts[d]; hi[d] = pts[d]; }
+  for (int64_t i = 0; i < np; ++i)
+    for (int d = 0; d < 3; ++d) {
+      G->lo[d] = fmin(G->lo[d], pts[3 * i + d]);
+      hi[d] = fmax(hi[d], pts[3 * i + d]);
+    }
+  double vol = 1.0, amax = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    vol *= fmax(hi[d] - G->lo[d], 1e-12);
+    amax = fmax(amax, fmax(fabs(G->lo[d]), fabs(hi[d])));
+  }
+  /* about one cell per point of the bounding box, coarsened until at most
+   * 2^24 cells */
+  G->h = 1.5 * cbrt(vol / (double)np);
+  for (;;) {
+    double cells = 1.0;
+    for (int d = 0; d < 3; ++d) cells *= floor((hi[d] - G->lo[d]) / G->h) + 1.0;
+    if (cells <= 16777216.0) break;
+    G->h *= 1.25;
+  }
+  for (int d = 0; d < 3; ++d) G->nc[d] = (int64_t)floor((hi[d] - G->lo[d]) / G->h) + 1;
+  G->slack = 1e-13 * (amax + G->h);
+  int64_t ncell = G->nc[0] * G->nc[1] * G->nc[2];
+  G->start = (int64_t*)calloc((size_t)ncell + 1, sizeof(int64_t));
+  G->idx = (int64_t*)malloc(sizeof(int64_t) * (size_t)np);
+  int64_t* cell = (int64_t*)malloc(sizeof(int64_t) * (size_t)np);
+  if (!G->start || !G->idx || !cell) {
+    free(cell);
+    free(G->start);
+    free(G->idx);
+    free(G);
+    return NULL;
+  }
+  for (int64_t i = 0; i < np; ++i) {
+    const double* q = pts + 3 * i;
+    cell[i] = (orc_grid_axis(G, 2, q[2]) * G->nc[1] + orc_grid_axis(G, 1, q[1])) * G->nc[0] + orc_grid_axis(G, 0, q[0]);
+    G->start[cell[i] + 1] += 1;
+  }
+  for (int64_t c = 0; c < ncell; ++c) G->start[c + 1] += G->start[c];
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)ncell);
+  if (!fill) {
+    free(cell);
+    free(G->start);
+    free(G->idx);
+    free(G);
+    return NULL;
+  }
+  memcpy(fill, G->start, sizeof(int64_t) * (size_t)ncell);
+  for (int64_t i = 0; i < np; ++i) G->idx[fill[cell[i]]++] = i;
+  free(fill);
+  free(cell);
+  return G;
+}
+
+void orc_grid_free(orc_grid* G) {
+  if (!G) return;
+  free(G->start);
+  free(G->idx);
+  free(G);
+}
+
+/* k nearest points of x on the grid, sorted by (distance^2, index). */
+int orc_grid_knn(const orc_grid* G, const double* x, int k, int64_t* idx_out, double* d2_out) {
+  if (!G || k > ORC_MAXK || k > G->np || k < 1) return ORC_EINVAL;
+  orc_nb best[ORC_MAXK];
+  int cnt = 0;
+  int64_t c[3];
+  for (int d = 0; d < 3; ++d) c[d] = orc_grid_axis(G, d, x[d]);
+  int64_t Lmax = 0;
+  for (int d = 0; d < 3; ++d) {
+    if (c[d] > Lmax) Lmax = c[d];
+    if (G->nc[d] - 1 - c[d] > Lmax) Lmax = G->nc[d] - 1 - c[d];
+  }
+  for (int64_t L = 0; L <= Lmax; ++L) {
+    for (int64_t kz = c[2] - L; kz <= c[2] + L; ++kz) {
+      if (kz < 0 || kz >= G->nc[2]) continue;
+      for (int64_t ky = c[1] - L; ky <= c[1] + L; ++ky) {
+        if (ky < 0 || ky >= G->nc[1]) continue;
+        for (int64_t kx = c[0] - L; kx <= c[0] + L; ++kx) {
+          if (kx < 0 || kx >= G->nc[0]) continue;
+          int64_t cheb = llabs(kx - c[0]);
+          if (llabs(ky - c[1]) > cheb) cheb = llabs(ky - c[1]);
+          if (llabs(kz - c[2]) > cheb) cheb = llabs(kz - c[2]);
+          if (cheb != L) continue;
+          int64_t cc = (kz * G->nc[1] + ky) * G->nc[0] + kx;
+          for (int64_t t = G->start[cc]; t < G->start[cc + 1]; ++t) {
+            int64_t i = G->idx[t];
+            const double* q = G->pts + 3 * i;
+            double dx = q[0] - x[0], dy = q[1] - x[1], dz = q[2] - x[2];
+            orc_nb cand = {dx * dx + dy * dy + dz * dz, i};
+            if (cnt < k) {
+              int j = cnt++;
+              while (j > 0 && orc_nb_less(&cand, &best[j - 1])) { best[j] = best[j - 1]; --j; }
+              best[j] = cand;
+            } else if (orc_nb_less(&cand, &best[k - 1])) {
+              int j = k - 1;
+              while (j > 0 && orc_nb_less(&cand, &best[j - 1])) { best[j] = best[j - 1]; --j; }
+              best[j] = cand;
+            }
+          }
+        }
+      }
+    }
+    if (cnt == k) {
+      /* distance from x to the nearest face of the visited block of cells
+       * that has cells beyond it */
+      double face = INFINITY;
+      for (int d = 0; d < 3; ++d) {
+        if (c[d] - L > 0) face = fmin(face, x[d] - (G->lo[d] + (double)(c[d] - L) * G->h));
+        if (c[d] + L < G->nc[d] - 1) face = fmin(face, (G->lo[d] + (double)(c[d] + L + 1) * G->h) - x[d]);
+      }
+      face -= G->slack;
+      if (face > 0.0 && best[k - 1].d2 < face * face) break;
+    }
+  }
+  for (int j = 0; j < k; ++j) { idx_out[j] = best[j].idx; d2_out[j] = best[j].d2; }
+  return ORC_OK;
+}
+
+/* Every point within distance^2 <= rho2 of x (ascending index within cells),
+ * up to cap of them; returns the count (which may exceed cap), or -1. */
+int64_t orc_grid_ball(const orc_grid* G, const double* x, double rho2, int64_t* idx_out, int64_t cap) {
+  if (!G || !(rho2 >= 0.0)) return -1;
+  double rho = sqrt(rho2) + G->slack;
+  int64_t a[3], b[3];
+  for (int d = 0; d < 3; ++d) {
+    a[d] = orc_grid_axis(G, d, x[d] - rho) - 1;
+    b[d] = orc_grid_axis(G, d, x[d] + rho) + 1;
+    if (a[d] < 0) a[d] = 0;
+    if (b[d] > G->nc[d] - 1) b[d] = G->nc[d] - 1;
+  }
+  int64_t cnt = 0;
+  for (int64_t kz = a[2]; kz <= b[2]; ++kz)
+    for (int64_t ky = a[1]; ky <= b[1]; ++ky)
+      for (int64_t kx = a[0]; kx <= b[0]; ++kx) {
+        int64_t cc = (kz * G->nc[1] + ky) * G->nc[0] + kx;
+        for (int64_t t = G->start[cc]; t < G->start[cc + 1]; ++t) {
+          int64_t i = G->idx[t];
+          const double* q = G->pts + 3 * i;
+          double dx = q[0] - x[0], dy = q[1] - x[1], dz = q[2] - x[2];
+          if (dx * dx + dy * dy + dz * dz <= rho2) {
+            if (cnt < cap) idx_out[cnt] = i;
+            ++cnt;
+          }
+        }
+      }
+  return cnt;
+}
+
+/* The problem's k nearest search: on its grid when it has one. */
+static int orc_pc_knn(const orc_problem* P, const double* x, int k, int64_t* idx, double* d2) {
+  if (P->grid) return orc_grid_knn(P->grid, x, k, idx, d2);
+  return orc_knn(P->points, P->n_points, x, k, idx, d2);
+}
+
+static int orc_cmp_i64(const void* a, const void* b) {
+  int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+  return (x > y) - (x < y);
+}
+
+/* The cloud points within distance^2 <= rho2 of x, in ascending index order
+ * (so that a fit over them is summed in the same order with or without the
+ * grid), in a buffer the caller frees; returns the count or -1. */
+static int64_t orc_pc_ball(const orc_problem* P, const double* x, double rho2, int64_t** out) {
+  int64_t cap = 512;
+  for (;;) {
+    int64_t* buf = (int64_t*)malloc(sizeof(int64_t) * (size_t)cap);
+    if (!buf) return -1;
+    int64_t cnt;
+    if (P->grid) {
+      cnt = orc_grid_ball(P->grid, x, rho2, buf, cap);
+    } else {
+      cnt = 0;
+      for (int64_t i = 0; i < P->n_points; ++i) {
+        const double* q = P->points + 3 * i;
+        double dx = q[0] - x[0], dy = q[1] - x[1], dz = q[2] - x[2];
+        if (dx * dx + dy * dy + dz * dz <= rho2) {
+          if (cnt < cap) buf[cnt] = i;
+          ++cnt;
+        }
+      }
+    }
+    if (cnt < 0 || cnt <= cap) {
+      if (cnt > 1) qsort(buf, (size_t)cnt, sizeof(int64_t), orc_cmp_i64);
+      *out = buf;
+      return cnt;
+    }
+    free(buf);
+    cap = cnt;
+  }
+}
+
 /* Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations (textbook).
  * Eigenvalues ascending in w, eigenvectors as columns of V. */
 static void orc_jacobi3(const double A_in[9], double w[3], double V[9]) {
@@ -472,12 +699,12 @@ int orc_pc_project(const orc_problem* P, const double* x, orc_pc_result* res) {
   int k = P->k_nn;
   int64_t inn;
   double nn_d2;
-  int st = orc_knn(P->points, P->n_points, x, 1, &inn, &nn_d2);
+  int st = orc_pc_knn(P, x, 1, &inn, &nn_d2);
   if (st) return st;
   const double* pn = P->points + 3 * inn;
   int64_t idx[ORC_MAXK];
   double d2[ORC_MAXK];
-  st = orc_knn(P->points, P->n_points, pn, k, idx, d2);
+  st = orc_pc_knn(P, pn, k, idx, d2);
   if (st) return st;
   /* local spacing: mean distance from p to its k-1 other neighbours */
   double hsum = 0.0;
@@ -489,14 +716,25 @@ int orc_pc_project(const orc_problem* P, const double* x, orc_pc_result* res) {
     res->kappa = 0.0;
     return ORC_OK;
   }
+  /* the points the patch is fitted to: the k nearest, or the ball of radius
+   * fit_scale r_k around p */
+  const int64_t* fit = idx;
+  int64_t nfit = k;
+  int64_t* ball = NULL;
+  if (P->fit_scale > 1.0) {
+    double rho2 = P->fit_scale * P->fit_scale * d2[k - 1];
+    nfit = orc_pc_ball(P, pn, rho2, &ball);
+    if (nfit < 6) { free(ball); return ORC_EINVAL; }
+    fit = ball;
+  }
   double cen[3] = {0, 0, 0};
-  for (int j = 0; j < k; ++j)
-    for (int c = 0; c < 3; ++c) cen[c] += P->points[3 * idx[j] + c];
-  for (int c = 0; c < 3; ++c) cen[c] /= (double)k;
+  for (int64_t j = 0; j < nfit; ++j)
+    for (int c = 0; c < 3; ++c) cen[c] += P->points[3 * fit[j] + c];
+  for (int c = 0; c < 3; ++c) cen[c] /= (double)nfit;
   double C[9] = {0};
-  for (int j = 0; j < k; ++j) {
+  for (int64_t j = 0; j < nfit; ++j) {
     double d[3];
-    for (int c = 0; c < 3; ++c) d[c] = P->points[3 * idx[j] + c] - cen[c];
+    for (int c = 0; c < 3; ++c) d[c] = P->points[3 * fit[j] + c] - cen[c];
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) C[3 * r + c] += d[r] * d[c];
   }
@@ -508,9 +746,9 @@ int orc_pc_project(const orc_problem* P, const double* x, orc_pc_result* res) {
   /* least-squares height field h = a0 + a1 a + a2 b + a3 a^2 + a4 a b + a5 b^2 */
   double M[36] = {0}, rhs[6] = {0}, coef[6];
   double ext = 0.0; /* support of the patch: largest |a| or |b| of its points */
-  for (int j = 0; j < k; ++j) {
+  for (int64_t j = 0; j < nfit; ++j) {
     double d[3];
-    for (int c = 0; c < 3; ++c) d[c] = P->points[3 * idx[j] + c] - cen[c];
+    for (int c = 0; c < 3; ++c) d[c] = P->points[3 * fit[j] + c] - cen[c];
     double a = orc_dot(d, e1, 3), b = orc_dot(d, e2, 3), h = orc_dot(d, nn, 3);
     ext = fmax(ext, fmax(fabs(a), fabs(b)));
     double phi[6] = {1.0, a, b, a * a, a * b, b * b};
@@ -519,6 +757,7 @@ int orc_pc_project(const orc_problem* P, const double* x, orc_pc_result* res) {
       for (int c = 0; c < 6; ++c) M[6 * r + c] += phi[r] * phi[c];
     }
   }
+  free(ball);
   st = orc_solve6(M, rhs, coef);
   if (st) return st;
   double dx[3];
@@ -1417,6 +1656,7 @@ static int orc_check(const orc_problem* P) {
   }
   if (P->manifold == ORC_POINT_CLOUD && (P->k_nn < 6 || P->k_nn > ORC_MAXK || P->n_points < P->k_nn))
     return ORC_EINVAL;
+  if (P->manifold == ORC_POINT_CLOUD && !(P->fit_scale >= 0.0 && P->fit_scale <= 16.0)) return ORC_EINVAL;
   /* the nearest point carries no curvature: its radius comes from the spacing or a bound */
   if (P->manifold == ORC_POINT_CLOUD && P->reconstruction == 1 && P->radius_rule != ORC_RADIUS_SPACING &&
       P->radius_rule != ORC_RADIUS_CURVATURE_BOUND)

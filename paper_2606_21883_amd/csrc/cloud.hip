@@ -312,6 +312,50 @@ __device__ void eig3(double A[3][3], double V[3][3], double w[3]) {
       }
 }
 
+// Height-field coefficients from the normal equations M c = rhs of the scaled
+// basis 1, a/sc, b/sc, (a/sc)^2, ab/sc^2, (b/sc)^2 (Cholesky), then the patch in
+// FP64 and FP32.
+__device__ void finish_patch(const double cen[3], const double e1[3], const double e2[3], const double nn[3],
+                             double M[6][6], double rhs[6], double sc, double ext, double hmean,
+                             Patch<double>& P64, Patch<float>& P32) {
+  double L[6][6];
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c <= r; ++c) {
+      double s = M[r][c];
+      for (int t = 0; t < c; ++t) s -= L[r][t] * L[c][t];
+      L[r][c] = (r == c) ? sqrt(fmax(s, 1e-300)) : s / L[c][c];
+    }
+  double y[6], cf[6];
+  for (int r = 0; r < 6; ++r) {
+    double s = rhs[r];
+    for (int t = 0; t < r; ++t) s -= L[r][t] * y[t];
+    y[r] = s / L[r][r];
+  }
+  for (int r = 5; r >= 0; --r) {
+    double s = y[r];
+    for (int t = r + 1; t < 6; ++t) s -= L[t][r] * cf[t];
+    cf[r] = s / L[r][r];
+  }
+  // undo the scaling of a and b
+  cf[1] /= sc; cf[2] /= sc; cf[3] /= sc * sc; cf[4] /= sc * sc; cf[5] /= sc * sc;
+  Patch<double> P;
+  for (int d = 0; d < 3; ++d) {
+    P.cen[d] = cen[d]; P.e1[d] = e1[d]; P.e2[d] = e2[d]; P.n[d] = nn[d];
+  }
+  for (int t = 0; t < 6; ++t) P.c[t] = cf[t];
+  P.ext = ext;
+  P.hmean = hmean;
+  P64 = P;
+  Patch<float> Q;
+  for (int d = 0; d < 3; ++d) {
+    Q.cen[d] = (float)cen[d]; Q.e1[d] = (float)e1[d]; Q.e2[d] = (float)e2[d]; Q.n[d] = (float)nn[d];
+  }
+  for (int t = 0; t < 6; ++t) Q.c[t] = (float)cf[t];
+  Q.ext = (float)ext;
+  Q.hmean = (float)hmean;
+  P32 = Q;
+}
+
 // Local quadratic patch of every point from its k nearest points: centroid,
 // PCA frame (normal = least-variance direction), height field by least
 // squares on the scaled basis 1, a, b, a^2, a b, b^2 (Cholesky on the normal
@@ -368,43 +412,94 @@ __global__ void fit_kernel(GridArgs g, Patch<double>* P64, Patch<float>* P32) {
       for (int c = 0; c < 6; ++c) M[r][c] += ph[r] * ph[c];
     }
   }
-  // Cholesky M = L L^T
-  double L[6][6];
-  for (int r = 0; r < 6; ++r)
-    for (int c = 0; c <= r; ++c) {
-      double s = M[r][c];
-      for (int t = 0; t < c; ++t) s -= L[r][t] * L[c][t];
-      L[r][c] = (r == c) ? sqrt(fmax(s, 1e-300)) : s / L[c][c];
+  finish_patch(cen, e1, e2, nn, M, rhs, sc, ext, hs / (double)(k - 1), P64[i], P32[i]);
+}
+
+// The patch of every point fitted to the cloud points within fit_scale r_k of
+// it (r_k: the distance to its k-th nearest point; ball membership
+// |p - x_i|^2 <= (fit_scale^2) r_k^2 in exact FP64 products and sums), found
+// on the uniform grid: the cells within the ball's bounding box (one cell of
+// margin for the binning's rounding).  Two passes over the ball: moments about
+// x_i give the centroid and covariance (PCA frame); then the normal
+// equations of the height field on the basis scaled by the ball radius, and
+// the patch support.  The spacing stays the mean distance to the k-1 nearest.
+__global__ void fit_ball_kernel(GridArgs g, double fit_scale, Patch<double>* P64, Patch<float>* P32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  const int k = g.k;
+  const int32_t* nb = g.knn + i * k;
+  const float4 pi = g.orig[i];
+  const double xi[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
+  double hs = 0.0;
+  for (int j = 1; j < k; ++j) {
+    const float4 p = g.orig[nb[j]];
+    hs += sqrt(dist2_exact(xi, p.x, p.y, p.z));
+  }
+  const float4 pk = g.orig[nb[k - 1]];
+  const double rho2 = __dmul_rn(__dmul_rn(fit_scale, fit_scale), dist2_exact(xi, pk.x, pk.y, pk.z));
+  const double rho = sqrt(rho2);
+  const double lo[3] = {(double)g.lox, (double)g.loy, (double)g.loz};
+  const int nc[3] = {g.nx, g.ny, g.nz};
+  int ca[3], cb[3];
+  for (int d = 0; d < 3; ++d) {
+    ca[d] = max(0, (int)floor((xi[d] - rho - lo[d]) / (double)g.h) - 1);
+    cb[d] = min(nc[d] - 1, (int)floor((xi[d] + rho - lo[d]) / (double)g.h) + 1);
+  }
+  // visit(f): f(offset from x_i) for every point of the ball
+  auto visit = [&](auto&& f) {
+    for (int cz = ca[2]; cz <= cb[2]; ++cz)
+      for (int cy = ca[1]; cy <= cb[1]; ++cy) {
+        const int row = (cz * g.ny + cy) * g.nx;
+        const int s0 = g.cell_start[row + ca[0]], s1 = g.cell_start[row + cb[0] + 1];
+        for (int t = s0; t < s1; ++t) {
+          const float4 p = g.pts[t];
+          if (dist2_exact(xi, p.x, p.y, p.z) <= rho2) {
+            const double d[3] = {(double)p.x - xi[0], (double)p.y - xi[1], (double)p.z - xi[2]};
+            f(d);
+          }
+        }
+      }
+  };
+  double cnt = 0.0, m1[3] = {0, 0, 0}, m2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  visit([&](const double* d) {
+    cnt += 1.0;
+    for (int r = 0; r < 3; ++r) {
+      m1[r] += d[r];
+      for (int c = 0; c < 3; ++c) m2[r][c] += d[r] * d[c];
     }
-  double y[6], cf[6];
+  });
+  double mu[3], cen[3], C[3][3];
+  for (int r = 0; r < 3; ++r) {
+    mu[r] = m1[r] / cnt;
+    cen[r] = xi[r] + mu[r];
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) C[r][c] = m2[r][c] - cnt * mu[r] * mu[c];
+  double V[3][3], w[3];
+  eig3(C, V, w);
+  const double e1[3] = {V[0][2], V[1][2], V[2][2]};
+  const double e2[3] = {V[0][1], V[1][1], V[2][1]};
+  const double nn[3] = {V[0][0], V[1][0], V[2][0]};
+  const double sc = rho > 0.0 ? rho : 1.0;
+  double M[6][6], rhs[6], ext = 0.0;
   for (int r = 0; r < 6; ++r) {
-    double s = rhs[r];
-    for (int t = 0; t < r; ++t) s -= L[r][t] * y[t];
-    y[r] = s / L[r][r];
+    rhs[r] = 0.0;
+    for (int c = 0; c < 6; ++c) M[r][c] = 0.0;
   }
-  for (int r = 5; r >= 0; --r) {
-    double s = y[r];
-    for (int t = r + 1; t < 6; ++t) s -= L[t][r] * cf[t];
-    cf[r] = s / L[r][r];
-  }
-  // undo the scaling of a and b
-  cf[1] /= sc; cf[2] /= sc; cf[3] /= sc * sc; cf[4] /= sc * sc; cf[5] /= sc * sc;
-  Patch<double> P;
-  for (int d = 0; d < 3; ++d) {
-    P.cen[d] = cen[d]; P.e1[d] = e1[d]; P.e2[d] = e2[d]; P.n[d] = nn[d];
-  }
-  for (int t = 0; t < 6; ++t) P.c[t] = cf[t];
-  P.ext = ext;
-  P.hmean = hs / (double)(k - 1);
-  P64[i] = P;
-  Patch<float> Q;
-  for (int d = 0; d < 3; ++d) {
-    Q.cen[d] = (float)cen[d]; Q.e1[d] = (float)e1[d]; Q.e2[d] = (float)e2[d]; Q.n[d] = (float)nn[d];
-  }
-  for (int t = 0; t < 6; ++t) Q.c[t] = (float)cf[t];
-  Q.ext = (float)ext;
-  Q.hmean = (float)P.hmean;
-  P32[i] = Q;
+  visit([&](const double* d0) {
+    const double d[3] = {d0[0] - mu[0], d0[1] - mu[1], d0[2] - mu[2]};
+    const double a = d[0] * e1[0] + d[1] * e1[1] + d[2] * e1[2];
+    const double b = d[0] * e2[0] + d[1] * e2[1] + d[2] * e2[2];
+    const double h = d[0] * nn[0] + d[1] * nn[1] + d[2] * nn[2];
+    ext = fmax(ext, fmax(fabs(a), fabs(b)));
+    const double as = a / sc, bs = b / sc;
+    const double ph[6] = {1.0, as, bs, as * as, as * bs, bs * bs};
+    for (int r = 0; r < 6; ++r) {
+      rhs[r] += ph[r] * h;
+      for (int c = 0; c < 6; ++c) M[r][c] += ph[r] * ph[c];
+    }
+  });
+  finish_patch(cen, e1, e2, nn, M, rhs, sc, ext, hs / (double)(k - 1), P64[i], P32[i]);
 }
 
 // Distance from each query to its FP64 projection, and the local spacing there.
@@ -599,7 +694,11 @@ mpwos_status cloud_create(const mpwos_manifold_desc& d, hipStream_t s, CloudStat
                        C->root, C->kd_pts, d_orig, k, d_redo, (int32_t)redo.size(), d_knn);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) {
+  if (e == hipSuccess && d.fit_scale > 1.0 && d.reconstruction == 0) {
+    hipLaunchKernelGGL(fit_ball_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, g, d.fit_scale,
+                       C->patch64, C->patch32);
+    e = hipGetLastError();
+  } else if (e == hipSuccess) {
     hipLaunchKernelGGL(fit_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, g, C->patch64, C->patch32);
     e = hipGetLastError();
   }

@@ -400,6 +400,8 @@ static mpwos_status check_manifold_desc(const mpwos_manifold_desc* d) {
         return fail(MPWOS_EINVAL, "point cloud: n_points must be in [k_nn, 2^27]");
       if (d->reconstruction != 0 && d->reconstruction != 1)
         return fail(MPWOS_EINVAL, "point cloud: reconstruction must be 0 (patch) or 1 (nearest point)");
+      if (!(d->fit_scale >= 0.0 && d->fit_scale <= 16.0))
+        return fail(MPWOS_EINVAL, "point cloud: fit_scale must be in [0, 16]");
       return MPWOS_OK;
   }
   return fail(MPWOS_EINVAL, "unknown manifold kind");

@@ -143,9 +143,9 @@ def torus_problem(R=1.0, a=0.3):
                    f=dict(kind="torus_mode", coef=[1.0]))
 
 
-def point_cloud_problem(points, k_nn=16, radius_rule="curvature_fit", R=1.0, a=0.3, kappa_bound=None):
+def point_cloud_problem(points, k_nn=16, radius_rule="curvature_fit", R=1.0, a=0.3, kappa_bound=None, fit_scale=1.0):
     d = problem(manifold="point_cloud", n=3, p=[R, a], sigma=1.0, points=points, k_nn=k_nn,
-                radius_rule=radius_rule, c_h=2.4, newton_iters=6,
+                radius_rule=radius_rule, c_h=2.4, newton_iters=6, fit_scale=fit_scale,
                 f=dict(kind="torus_mode", coef=[1.0]))
     if kappa_bound is not None:
         d["kappa_bound"] = kappa_bound
@@ -455,10 +455,11 @@ def config(name, scale=1.0, seed=1):
         # 1e6 noisy torus samples (queries: analytic torus points, within the
         # noise and the fit error of the reconstruction)
         # At this density a 16-point patch spans about 0.008, where the quadratic
-        # term (about 1e-4) is at the noise level: the per-point fitted curvature
-        # is noise, so the radius takes the curvature bound of the torus, 1/a.
+        # term (about 1e-4) is at the noise level, so each patch is fitted to the
+        # points within 4 r_16 (about 250 points, span 0.03), which resolves the
+        # torus's curvature; the radius takes the curvature bound 1/a (constant).
         pts = torus_point_cloud(1_000_000, 1.0, 0.3, 1e-4, seed)
-        prob = point_cloud_problem(pts, radius_rule="curvature_bound", kappa_bound=1.0 / 0.3)
+        prob = point_cloud_problem(pts, radius_rule="curvature_bound", kappa_bound=1.0 / 0.3, fit_scale=4.0)
         return prob, torus_area_uniform(sz(8192), 1.0, 0.3, seed + 7), sz(1024)
     if name == "product":
         # Example 3: S^1_Fourier x S^2(0.65) in R^9

@@ -34,7 +34,8 @@ class MpwosError(RuntimeError):
 class ManifoldDesc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32), ("p", ctypes.c_double * 4),
                 ("points", ctypes.c_void_p), ("n_points", ctypes.c_int64), ("k_nn", ctypes.c_int32),
-                ("points_on_device", ctypes.c_int32), ("reconstruction", ctypes.c_int32)]
+                ("points_on_device", ctypes.c_int32), ("reconstruction", ctypes.c_int32),
+                ("fit_scale", ctypes.c_double)]
 
 
 class Fn(ctypes.Structure):
@@ -235,6 +236,7 @@ class Manifold:
             d.n_points = pts.shape[0]
             d.k_nn = int(prob.get("k_nn", 16))
             d.reconstruction = RECONSTRUCTIONS[prob.get("reconstruction", "patch")]
+            d.fit_scale = float(prob.get("fit_scale", 1.0))
         self.handle = ctypes.c_void_p()
         _check(lib().mpwos_manifold_create(ctypes.byref(d), ctypes.byref(self.handle)))
         self._keep = []

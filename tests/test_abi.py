@@ -51,6 +51,7 @@ int main(void) {
   P(mpwos_manifold_desc) P(mpwos_fn) P(mpwos_options) P(mpwos_stats) P(mpwos_request) P(mpwos_server_stats)
   O(mpwos_options, max_steps) O(mpwos_options, stream) O(mpwos_options, walk_S) O(mpwos_options, walk_K)
   O(mpwos_fn, values) O(mpwos_fn, n_values) O(mpwos_manifold_desc, points) O(mpwos_manifold_desc, k_nn)
+  O(mpwos_manifold_desc, fit_scale)
   O(mpwos_request, opt) O(mpwos_request, u_out) O(mpwos_request, seed) O(mpwos_stats, kernel_ms)
   return 0;
 }
@@ -78,6 +79,7 @@ def test_struct_layouts_match_header(tmp_path):
         "mpwos_fn.values": (m.Fn, "values"), "mpwos_fn.n_values": (m.Fn, "n_values"),
         "mpwos_manifold_desc.points": (m.ManifoldDesc, "points"),
         "mpwos_manifold_desc.k_nn": (m.ManifoldDesc, "k_nn"), "mpwos_request.opt": (m.Request, "opt"),
+        "mpwos_manifold_desc.fit_scale": (m.ManifoldDesc, "fit_scale"),
         "mpwos_request.u_out": (m.Request, "u_out"), "mpwos_request.seed": (m.Request, "seed"),
         "mpwos_stats.kernel_ms": (m.Stats, "kernel_ms"),
     }.items():

@@ -2,9 +2,9 @@
 local reconstruction) against the oracle: the FP64 projection cp_h at cloud
 points (which checks every patch, hence the device kNN build, through both the
 MFMA grid-tile path and the KD-tree path) and at points off the surface; the
-FP32 projection; whole FP64 walks on a small cloud, walk by walk; truncated
-walks on the full 1e6-point cloud in the launch form the benchmark times; FP32
-statistics; query validation."""
+FP32 projection; whole FP64 walks on a small cloud and on the full 1e6-point
+cloud (in the launch form the benchmark times), walk by walk; FP32 statistics;
+query validation."""
 import numpy as np
 import pytest
 
@@ -21,12 +21,13 @@ def cloud(npts, seed, k=16, **kw):
     return p
 
 
-@pytest.mark.parametrize("k", [16, 28])
-def test_cp_at_cloud_points_matches_oracle(k):
+@pytest.mark.parametrize("k,fit_scale", [(16, 1.0), (28, 1.0), (16, 4.0)])
+def test_cp_at_cloud_points_matches_oracle(k, fit_scale):
     """cp_h of a cloud point is the Newton foot point on its own patch: every
-    sampled point checks its k nearest neighbours and its fit."""
-    prob = cloud(20000, seed=31, k=k)
-    announce(f"cloud cp at cloud points k={k}")
+    sampled point checks its k nearest neighbours and its fit (over the k
+    nearest, or over the ball of 4 r_k found on the device grid)."""
+    prob = cloud(20000, seed=31, k=k, fit_scale=fit_scale)
+    announce(f"cloud cp at cloud points k={k} fit_scale={fit_scale}")
     m = mpwos.Manifold(prob)
     info = mpwos.debug_cloud_info(m)
     if k <= 24:
@@ -91,34 +92,36 @@ def test_walks_fp64_other_radius_rules(rule):
         assert len(set(gpu["walk_K"].ravel().tolist())) == 1
 
 
-def test_full_cloud_truncated_walks_sampled():
-    """1e6-point cloud at the benchmark's launch form (persistent lanes): a
-    sample of walk prefixes against the oracle.  At this density the 16-point
-    patches fit noise, and a far point beyond a patch's focal distance makes
-    the foot point ill-conditioned: a rounding-level difference between the
-    two implementations of the fit grows by up to 1e5 in one step and keeps
-    growing, so walk-level agreement is checked on the first 5 steps (whole
-    walks are compared on the well-sampled clouds above)."""
+def test_full_cloud_whole_walks_match_oracle():
+    """The 1e6-point noisy torus with patches fitted over 4 r_16, in the
+    launch form the benchmark times (persistent lanes): whole FP64 walks
+    (tau_W = 1e-8, K = 1601) against the oracle walk by walk on 8 queries x 16
+    walks, the per-query means, and FP32 walks of the same stream against
+    them."""
     prob, Q, _ = inputs.config("cloud")
-    prob = dict(prob, max_steps=5)
     announce("cloud 1e6 build")
     m = mpwos.Manifold(prob)
     info = mpwos.debug_cloud_info(m)
     assert info["knn_fallback_points"] < 0.05 * len(prob["points"]), info
     Qs = Q[:8]
-    announce("cloud 1e6 truncated walks fp64 persistent 8x4")
-    gpu = mpwos.solve(prob, Qs, 4, 3, manifold=m, walk_outputs=True, precision="fp64", persistent=1)
-    assert gpu["stats"]["truncated"] == 32
+    announce("cloud 1e6 whole walks fp64 persistent 8x16")
+    gpu = mpwos.solve(prob, Qs, 16, 3, manifold=m, walk_outputs=True, precision="fp64", persistent=1)
+    assert np.all(gpu["walk_K"] == 1601)
     P = oracle.Problem(prob)
-    orc = oracle.solve(P, Qs, 4, 3)
-    compare_walks(gpu, orc, prob, tol=1e-9, min_frac=0.999)
-    announce("cloud 1e6 truncated walks fp32 persistent")
-    g32 = mpwos.solve(prob, Qs, 4, 3, manifold=m, walk_outputs=True, precision="fp32", persistent=1)
-    assert np.all(g32["walk_K"] == 5)
-    # FP32 walks follow the FP64 paths until a near-tie of the nearest-point
-    # search sends one to another patch
-    close = np.abs(g32["walk_S"] - orc["walk_S"]) < 1e-3 * (1 + np.abs(orc["walk_S"]))
-    assert close.mean() >= 0.75, close
+    orc = oracle.solve(P, Qs, 16, 3)
+    assert compare_walks(gpu, orc, prob, tol=1e-12, min_frac=0.999) == 1.0
+    np.testing.assert_allclose(gpu["u"], orc["u"], rtol=1e-10, atol=1e-12)
+    announce("cloud 1e6 whole walks fp32 persistent 8x16")
+    g32 = mpwos.solve(prob, Qs, 16, 3, manifold=m, walk_outputs=True, precision="fp32", persistent=1)
+    assert np.all(g32["walk_K"] == 1601)
+    # FP32 walks follow the FP64 paths; where FP32 rounding moves a sphere
+    # point across the boundary between two cloud points' nearest regions the
+    # projection switches to the neighbouring patch, whose surface differs at
+    # the 1e-5 level, and that walk drifts a little further (measured on
+    # MI355X: median 3e-6, 99th percentile 1.5e-3, largest 3.9e-3)
+    rel = np.abs(g32["walk_S"] - orc["walk_S"]) / (1 + np.abs(orc["walk_S"]))
+    q = np.quantile(rel, [0.5, 0.9, 0.99, 1.0])
+    assert q[0] < 1e-4 and np.mean(rel < 1e-3) >= 0.95 and q[-1] < 2e-2, q
     m.close()
 
 

@@ -177,6 +177,52 @@ def test_fp32_rmse_within_5_percent_of_fp64_full_size(name):
     assert ra < 4 * np.sqrt(np.mean(a["stderr"] ** 2))
 
 
+# The FP32 gate on every configuration at its full query set: the mixed mode's
+# RMSE against the closed form within 5% of the FP64 mode's at the same walk
+# count (reduced here so that the FP64 solves stay short).  Both modes run the
+# same estimator on the same random stream, so the gate isolates what FP32
+# walk arithmetic adds (Theorem 3.9: the MSE is the Monte Carlo, truncation,
+# compensation and projection terms; FP32 rounding enters as projection error).
+RMSE_GATES = {"circle": 1000, "hyper100": 64, "hyper1000": 8, "torus": 128, "cloud": 4}
+
+
+@pytest.mark.parametrize("name", list(RMSE_GATES))
+def test_fp32_rmse_within_5_percent_of_fp64_every_config(name):
+    prob, Q, _ = inputs.config(name)
+    nw = RMSE_GATES[name]
+    m = mpwos.Manifold(prob)
+    if name == "cloud":
+        # the estimate refers to the query's projection on the reconstruction
+        exact = inputs.exact_u(prob, mpwos.debug_cp(m, Q, "fp64"))
+    else:
+        exact = inputs.exact_u(prob, Q)
+    announce(f"rmse gate {name} {len(Q)}x{nw} fp64")
+    a = mpwos.solve(prob, Q, nw, 0, manifold=m, precision="fp64")
+    announce(f"rmse gate {name} {len(Q)}x{nw} fp32 persistent")
+    b = mpwos.solve(prob, Q, nw, 0, manifold=m, precision="fp32", persistent=1)
+    m.close()
+    ra, rb = inputs.rmse(a["u"], exact), inputs.rmse(b["u"], exact)
+    assert rb <= 1.05 * ra, (ra, rb)
+    if name != "cloud":
+        # unbiased to the Monte Carlo error (the cloud adds its reconstruction error)
+        assert ra < 4 * np.sqrt(np.mean(a["stderr"] ** 2)), (ra, np.sqrt(np.mean(a["stderr"] ** 2)))
+
+
+@pytest.mark.parametrize("n,tau_w", [(100, 1e-3), (1000, 1e-3)])
+def test_fp32_wave_per_walk_tracks_fp64_walks(n, tau_w):
+    """The lane-group kernels at n = 100 (16 lanes per walk) and n = 1000 (a
+    whole wavefront per walk, 42520 steps at tau_W = 1e-3): FP32 walks of the
+    same stream keep every walk length and stay close to the FP64 scores."""
+    prob = dict(inputs.hypersphere_problem(n), tau_w=tau_w)
+    Q = inputs.hypersphere_queries(6, n, seed=4)
+    announce(f"fp32 tracking hyper{n}")
+    a = mpwos.solve(prob, Q, 8, 7, walk_outputs=True, precision="fp64")
+    b = mpwos.solve(prob, Q, 8, 7, walk_outputs=True, precision="fp32")
+    assert np.array_equal(a["walk_K"], b["walk_K"])
+    rel = np.abs(a["walk_S"] - b["walk_S"]) / (1 + np.abs(a["walk_S"]).max())
+    assert np.median(rel) < 1e-4 and rel.max() < 1e-2, (np.median(rel), rel.max())
+
+
 def test_full_size_sampled_walks_match_oracle():
     # the launch configuration the benchmark times (FP64 plain, full config),
     # checked on sampled walks that the oracle recomputes one by one

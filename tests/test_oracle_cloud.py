@@ -211,3 +211,74 @@ def test_sphere_cloud_estimator_near_closed_form(orc):
     u = inputs.exact_u(prob, y)
     err = np.abs(res["u"] - u)
     assert np.all(err < 4 * res["stderr"] + 0.05), (err, res["stderr"])
+
+
+# -- the exact grid search and patches fitted over a wider ball ----------------
+
+
+def _d2(pts, x):
+    d = pts - x
+    return (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+
+
+def test_grid_knn_equals_brute_force(orc):
+    """The grid search returns the brute-force neighbours, distances and tie
+    order: points on and off the cloud, outside its box, at duplicated points
+    (exact ties, broken by index), k = 1, 16, 28."""
+    pts = inputs.torus_point_cloud(30000, seed=7)
+    pts = np.concatenate([pts, pts[:50]])
+    G = orc.Grid(pts)
+    rng = np.random.default_rng(3)
+    X = np.concatenate([pts[rng.choice(len(pts), 30)], inputs.torus_near_points(30, 0.25, seed=8),
+                        rng.uniform(-2.0, 2.0, (15, 3)), pts[:8]])
+    for x in X:
+        for k in (1, 16, 28):
+            gi, gd = G.knn(x, k)
+            bi, bd = orc.knn(pts, x, k)
+            assert np.array_equal(gi, bi) and np.array_equal(gd, bd), (x, k)
+
+
+def test_grid_ball_equals_brute_force(orc):
+    pts = inputs.torus_point_cloud(30000, seed=9)
+    G = orc.Grid(pts)
+    rng = np.random.default_rng(4)
+    X = np.concatenate([pts[rng.choice(len(pts), 20)], inputs.torus_near_points(10, 0.1, seed=10)])
+    for x in X:
+        d2 = _d2(pts, x)
+        for rho2 in (1e-4, 1e-3, 4e-3, float(np.sort(d2)[40])):  # the last one on a point: inclusive
+            got = np.sort(G.ball(x, rho2))
+            assert np.array_equal(got, np.nonzero(d2 <= rho2)[0])
+
+
+def test_projection_same_with_and_without_grid(orc):
+    pts = inputs.torus_point_cloud(30000, seed=11)
+    prob = cloud_problem(pts, fit_scale=4.0)
+    brute = orc.Problem(prob)
+    grid = orc.Problem(prob)
+    grid._grid = orc.Grid(pts)
+    grid.s.grid = grid._grid.handle
+    for x in inputs.torus_near_points(40, 0.2, seed=12):
+        assert np.array_equal(orc.cp(brute, x), orc.cp(grid, x))
+
+
+def test_wide_fit_resolves_curvature_on_noisy_million_point_torus(orc):
+    """At 1e6 points with 1e-4 noise a 16-point patch spans about 0.008, where
+    the quadratic term equals the noise: its curvature indicator ranges over
+    an order of magnitude and walk points 0.26 away project up to 1e-2 off.
+    Fitted to the ball of 4 r_16 (about 250 points) the indicator stays within
+    15% of the torus's 1/a and the projection within 5e-4 of the exact one."""
+    pts = inputs.torus_point_cloud(1_000_000, 1.0, 0.3, 1e-4, 1)
+    T = orc.Problem(inputs.torus_problem())
+    x = inputs.torus_near_points(200, 0.26, seed=11)
+    y = np.array([orc.cp(T, xi) for xi in x])
+    out = {}
+    for scale in (1.0, 4.0):
+        P = orc.Problem(cloud_problem(pts, fit_scale=scale))
+        err = np.array([np.linalg.norm(orc.cp(P, xi) - yi) for xi, yi in zip(x, y)])
+        kap = np.array([0.95 * 1.2 / orc.radius(P, yi) - 1.0 for yi in y[:80]])
+        out[scale] = (err, kap)
+    err4, kap4 = out[4.0]
+    assert err4.max() < 5e-4 and np.median(err4) < 1e-4, (err4.max(), np.median(err4))
+    assert np.all(np.abs(kap4 - 1 / 0.3) < 0.15 / 0.3), (kap4.min(), kap4.max())
+    err1, kap1 = out[1.0]
+    assert err1.max() > 10 * err4.max() and kap1.max() > 2 * kap4.max()
