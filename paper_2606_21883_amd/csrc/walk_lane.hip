@@ -152,11 +152,7 @@ __device__ __forceinline__ void closest_point(const WalkArgs& a, const T* x, T* 
     y[1] = c1 + g * d1;
     y[2] = g * d2;
   } else if constexpr (KIND == kTorus) {
-    // FP64 in both modes: the quartic cancels to a few bits in FP32 near the
-    // surface, which the Newton solve cannot recover
-    double xd[3] = {(double)x[0], (double)x[1], (double)x[2]}, yd[3];
-    torus_cp_newton<double>(a.p[0], a.p[1], xd, yd, 16);
-    for (int i = 0; i < 3; ++i) y[i] = (T)yd[i];
+    torus_cp_newton<T>((T)a.p[0], (T)a.p[1], x, y);
   } else if constexpr (KIND == kCloud) {
     const CloudProj<T> p = cloud_cp<T>(a.cloud, x);
     for (int i = 0; i < 3; ++i) y[i] = p.y[i];
