@@ -194,30 +194,44 @@ __device__ __forceinline__ void weights(const WalkArgs& a, double r, double& c, 
   om = s1 * c * a.inv_sigma;
 }
 
-// The same weights in FP32 (mixed mode): Horner in z = sigma r^2 over the
-// float coefficients and c from the hardware reciprocal (1 ulp).  All terms
-// are positive, so the float sum is accurate to a few ulps at any size.  W and
-// S stay FP64.
+// The same weights in FP32 (mixed mode): Horner in z = sigma r^2 and c from
+// the hardware reciprocal (1 ulp).  All terms are positive, so the float sum
+// is accurate to a few ulps at any size.  W and S stay FP64.  For the lane
+// kernels' dimensions (n <= 3) the coefficients are compile-time constants
+// (alpha_j = 1/(4^j j! (nu+1)_j), nu = (n-2)/2) and the first kSeries32 of
+// them are always summed: that covers every solve whose series the host cut
+// at kSeries32 + 1 terms (alpha_j z^j below 1e-10), sigma r^2 up to about 5;
+// wider ones and lane groups take the solve's float coefficients.
+constexpr int kSeries32 = 8;
+
+template <int N>
+struct SeriesCoef {
+  float v[kSeries32 + 1];
+  constexpr SeriesCoef() : v() {
+    const double nu = 0.5 * (N - 2);
+    double al = 1.0;
+    v[0] = 1.0f;
+    for (int j = 1; j <= kSeries32; ++j) {
+      al = al / (4.0 * j * (nu + j));
+      v[j] = (float)al;
+    }
+  }
+};
+
+template <int N>
 __device__ __forceinline__ void weights32(const WalkArgs& a, float r, float& c, float& om) {
   const float z = (float)a.sigma * r * r;
   float t = 0.0f;
-  for (int j = a.wjs - 1; j >= 1; --j) t = fmaf(t, z, a.wcoef[j]);
+  if (N <= 3 && a.wjs <= kSeries32 + 1) {
+    constexpr SeriesCoef<N> K;
+#pragma unroll
+    for (int j = kSeries32; j >= 1; --j) t = fmaf(t, z, K.v[j]);
+  } else {
+    for (int j = a.wjs - 1; j >= 1; --j) t = fmaf(t, z, a.wcoef[j]);
+  }
   const float s1 = t * z;
   c = __builtin_amdgcn_rcpf(1.0f + s1);
   om = s1 * c * (float)a.inv_sigma;
-}
-
-// Weights for a per-step radius in the walk's precision.
-template <class T, int N>
-__device__ __forceinline__ void step_weights(const WalkArgs& a, double r, double& c, double& om) {
-  if constexpr (sizeof(T) == 4) {
-    float cf, omf;
-    weights32(a, (float)r, cf, omf);
-    c = (double)cf;
-    om = (double)omf;
-  } else {
-    weights(a, r, c, om);
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -328,8 +342,9 @@ __device__ __forceinline__ float table_guess32(const InvTable& t, float u, float
   int k = (int)xpos;
   k = k < 0 ? 0 : (k > t.mx - 2 ? t.mx - 2 : k);
   const float fx = xpos - (float)k;
-  const float* ra = t.s32 + ((size_t)k * 2 + (up ? 1 : 0)) * t.mu;
-  const float* rb = ra + 2 * (size_t)t.mu;
+  // at most 17 x 2 x 1025 entries: 32-bit offsets
+  const float* ra = t.s32 + (uint32_t)((k * 2 + (up ? 1 : 0)) * t.mu);
+  const float* rb = ra + (uint32_t)(2 * t.mu);
   const float ga = ra[i] + fr * (ra[i + 1] - ra[i]);
   const float gb = rb[i] + fr * (rb[i + 1] - rb[i]);
   return ga + fx * (gb - ga);
@@ -769,10 +784,17 @@ __device__ __forceinline__ double boundary_value(const WalkArgs& a, const T* y, 
     case kFnZero: return 0.0;
     case kFnConst: return g.coef[0];
     case kFnSphPair: {
-      const double R = a.p[0];
-      return g.coef[0] * ((double)y[g.idx[0]] / R) * ((double)y[g.idx[1]] / R);
+      if constexpr (sizeof(T) == 4) {
+        const float iR = (float)a.inv_R;
+        return (double)((float)g.coef[0] * (y[g.idx[0]] * iR) * (y[g.idx[1]] * iR));
+      } else {
+        const double R = a.p[0];
+        return g.coef[0] * ((double)y[g.idx[0]] / R) * ((double)y[g.idx[1]] / R);
+      }
     }
-    case kFnLegendre: return (double)legendre_sum<T>(g.coef, (T)((double)y[n - 1] / a.p[0]));
+    case kFnLegendre:
+      if constexpr (sizeof(T) == 4) return (double)legendre_sum<T>(g.coef, y[n - 1] * (float)a.inv_R);
+      else return (double)legendre_sum<T>(g.coef, (T)((double)y[n - 1] / a.p[0]));
   }
   return 0.0;
 }

@@ -18,7 +18,7 @@ template <class T, int N>
 struct LaneState {
   T Y[N];
   double W, S, C;
-  double rg;           // point cloud: rho_geo from the reconstruction that produced Y; cap: delta_Gamma(Y)
+  T rg;                // point cloud: rho_geo from the reconstruction that produced Y; cap: delta_Gamma(Y)
   uint32_t k, q, w;
   int64_t idx;
 };
@@ -40,20 +40,20 @@ __device__ __forceinline__ void cap_gamma_point(const WalkArgs& a, const T* y, T
 
 template <class T, int N>
 __device__ __forceinline__ T cap_delta(const WalkArgs& a, const T* y) {
-  T yg[N], rG[N], nr[N];
+  T yg[N];
   cap_gamma_point<T, N>(a, y, yg);
-  const T R = (T)a.p[0];
-  T rn = (T)0;
+  // r = y_Gamma - y splits into rn along the normal y_Gamma / R and the
+  // tangential rest, |r^T|^2 = |r|^2 - rn^2 (rn^2 is the smaller term: no
+  // cancellation)
+  T rr = (T)0, rn = (T)0;
   for (int i = 0; i < N; ++i) {
-    rG[i] = yg[i] - y[i];
-    nr[i] = over_(yg[i], R);
-    rn += rG[i] * nr[i];
+    const T d = yg[i] - y[i];
+    rr += d * d;
+    rn += d * yg[i];
   }
-  T rt2 = (T)0;
-  for (int i = 0; i < N; ++i) {
-    const T v = rG[i] - rn * nr[i];
-    rt2 += v * v;
-  }
+  rn *= (T)a.inv_R;
+  T rt2 = rr - rn * rn;
+  rt2 = rt2 > (T)0 ? rt2 : (T)0;
   // ell = c_kappa / (1 + kappa) with kappa = 1/R, the same as rho_geo
   const T ell = (T)a.rho_geo;
   T tn = abs_(rn) - ell;
@@ -61,13 +61,14 @@ __device__ __forceinline__ T cap_delta(const WalkArgs& a, const T* y) {
   return sqrt_(rt2 + tn * tn);
 }
 
-// Membership of the boundary layer; dg receives delta_Gamma(y) when y is
-// above the cutting plane (the next step's radius reuses it).
+// Membership of the boundary layer, in the walk's precision; dg receives
+// delta_Gamma(y) when y is above the cutting plane (the next step's radius
+// reuses it).
 template <class T, int N>
-__device__ __forceinline__ bool cap_in_layer(const WalkArgs& a, const T* y, double& dg) {
-  if ((double)y[N - 1] <= a.p[1]) return true;
-  dg = (double)cap_delta<T, N>(a, y);
-  return dg < a.eps;
+__device__ __forceinline__ bool cap_in_layer(const WalkArgs& a, const T* y, T& dg) {
+  if (y[N - 1] <= (T)a.p[1]) return true;
+  dg = cap_delta<T, N>(a, y);
+  return dg < (T)a.eps;
 }
 
 // ---- geometry of the torus with a planar cut --------------------------------
@@ -109,16 +110,17 @@ __device__ __forceinline__ double ct_delta(const WalkArgs& a, const double* y) {
 // Membership of the boundary layer; the far side of the cut (sin s <= 0)
 // counts as inside.  dg receives delta_Gamma(y) otherwise.
 template <class T>
-__device__ __forceinline__ bool ct_in_layer(const WalkArgs& a, const T* y, double& dg) {
+__device__ __forceinline__ bool ct_in_layer(const WalkArgs& a, const T* y, T& dg) {
   const double yd[3] = {(double)y[0], (double)y[1], (double)y[2]};
   if (!(yd[1] * a.cut_c - yd[0] * a.cut_s > 0.0)) return true;
-  dg = ct_delta(a, yd);
-  return dg < a.eps;
+  const double d = ct_delta(a, yd);
+  dg = (T)d;
+  return d < a.eps;
 }
 
 // boundary layer test and boundary datum, by manifold
 template <class T, int N, int KIND>
-__device__ __forceinline__ bool in_layer(const WalkArgs& a, const T* y, double& dg) {
+__device__ __forceinline__ bool in_layer(const WalkArgs& a, const T* y, T& dg) {
   if constexpr (KIND == kCutTorus) return ct_in_layer<T>(a, y, dg);
   else return cap_in_layer<T, N>(a, y, dg);
 }
@@ -180,12 +182,12 @@ __device__ __forceinline__ bool walk_init(const WalkArgs& a, const double* queri
   st.S = 0.0;
   st.C = 0.0;
   st.k = 0;
-  st.rg = 0.0;
+  st.rg = (T)0;
   if constexpr (KIND == kCloud) {
     // the walk starts from the query's projection onto the reconstruction
     const CloudProj<T> p = cloud_cp<T>(a.cloud, st.Y);
     for (int i = 0; i < N; ++i) st.Y[i] = p.y[i];
-    if (!a.const_r) st.rg = cloud_rho_geo(a, p);
+    if (!a.const_r) st.rg = (T)cloud_rho_geo(a, p);
   }
   if constexpr (KIND == kCap || KIND == kCutTorus) {
     if (in_layer<T, N, KIND>(a, st.Y, st.rg)) {
@@ -214,11 +216,11 @@ __device__ __forceinline__ void walk_store(double* walk_S, int32_t* walk_K, cons
 // One Green sample Z = Y + t zeta' (t = r s, s from the radial law for the
 // uniform word ux, zeta' from words x, y of block b) and (f + m)(Z).
 template <class T, int N, int KIND, bool RICH>
-__device__ __forceinline__ T green_sample(const WalkArgs& a, const T* Y, uint4 b, uint32_t ux, T rT, double X2,
+__device__ __forceinline__ T green_sample(const WalkArgs& a, const T* Y, uint4 b, uint32_t ux, T rT, T X2,
                                           double norm, const float4* tab) {
   T s;
   if constexpr (sizeof(T) == 8) s = radial_inv64(a, u01_64(ux), X2, norm);
-  else s = radial_inv32(a, u01_32(ux), (float)X2);
+  else s = radial_inv32(a, u01_32(ux), X2);
   const T t = rT * s;
   T Z[N], Zc[N];
   lane_point<N>(b.x, b.y, t, Y, Z);
@@ -238,26 +240,38 @@ template <class T, int N, int KIND, bool RICH>
 __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st, uint64_t seed,
                                           const float4* tab = nullptr) {
   const Stream rs{st.q, st.w, (uint32_t)seed, (uint32_t)(seed >> 32)};
-  // (i) radius r(Y) = theta min(delta_Gamma, rho_geo) and the weights
-  double r, c, om, X2, norm = 0.0;
-  if constexpr (KIND == kCap || KIND == kCutTorus) {
-    // delta_Gamma(Y) from the previous step's stop test (or the start)
-    const double dg = st.rg;
-    const double rg = a.rho_geo;
-    r = a.theta * (dg < rg ? dg : rg);
-    step_weights<T, N>(a, r, c, om);
-    X2 = a.sigma * r * r;
-    if constexpr (sizeof(T) == 8) norm = radial_norm(a.law, X2);
-  } else if (KIND == kCloud && !a.const_r) {
-    r = a.theta * st.rg;
-    step_weights<T, N>(a, r, c, om);
-    X2 = a.sigma * r * r;
-    if constexpr (sizeof(T) == 8) norm = radial_norm(a.law, X2);
+  // (i) radius r(Y) = theta min(delta_Gamma, rho_geo) and the weights; a
+  // per-step radius is computed in the walk's precision (its step factors c
+  // and omega too), the constant one comes from the host in FP64
+  double r, c, om, norm = 0.0;
+  T X2;
+  constexpr bool kStepRadius = KIND == kCap || KIND == kCutTorus || KIND == kCloud;
+  if (kStepRadius && (KIND != kCloud || !a.const_r)) {
+    T rs;
+    if constexpr (KIND == kCloud) {
+      rs = (T)a.theta * st.rg;
+    } else {
+      // delta_Gamma(Y) from the previous step's stop test (or the start)
+      const T rg = (T)a.rho_geo;
+      rs = (T)a.theta * (st.rg < rg ? st.rg : rg);
+    }
+    if constexpr (sizeof(T) == 4) {
+      float cf, omf;
+      weights32<N>(a, rs, cf, omf);
+      c = (double)cf;
+      om = (double)omf;
+      X2 = (float)a.sigma * rs * rs;
+    } else {
+      weights(a, rs, c, om);
+      X2 = a.sigma * rs * rs;
+      norm = radial_norm(a.law, X2);
+    }
+    r = (double)rs;
   } else {
     r = a.r0;
     c = a.c0;
     om = a.om0;
-    X2 = a.X0 * a.X0;
+    X2 = (T)(a.X0 * a.X0);
   }
   const T rT = (T)r;
   // Each Philox block is drawn where it is used.  (Drawing the first Green
@@ -268,14 +282,14 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
   const uint4 bd = rs.block(st.k, 0, 0);
   // (ii) Theta = Y + r zeta and Y' = cp(Theta)
   T Yn[N];
-  double rg_next = 0.0;
+  T rg_next = (T)0;
   {
     T Th[N];
     lane_point<N>(bd.x, bd.y, rT, st.Y, Th);
     if constexpr (KIND == kCloud) {
       const CloudProj<T> p = cloud_cp<T>(a.cloud, Th);
       for (int i = 0; i < N; ++i) Yn[i] = p.y[i];
-      if (!a.const_r) rg_next = cloud_rho_geo(a, p);
+      if (!a.const_r) rg_next = (T)cloud_rho_geo(a, p);
     } else {
       closest_point<T, N, KIND>(a, Th, Yn);
     }
@@ -310,8 +324,11 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// The cap kernel is held to 80 VGPRs (6 waves per SIMD instead of 5): its
+// walks are short, and the refill and stop paths want the latency hiding.
 template <class T, int N, int KIND, bool PERSIST, bool RICH>
-__global__ __launch_bounds__(256) void walk_lane_kernel(WalkArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == kCap && sizeof(T) == 4 ? 6 : 1)))
+void walk_lane_kernel(WalkArgs a) {
   const int64_t total = a.count;
   const uint64_t seed = a.seed_dev ? *a.seed_dev : a.seed;
   LaneState<T, N> st;
@@ -334,14 +351,22 @@ __global__ __launch_bounds__(256) void walk_lane_kernel(WalkArgs a) {
     walk_store(a.walk_S, a.walk_K, st);
     return;
   } else {
-    // persistent form: per-wave chunks of the global queue
+    // persistent form: per-wave chunks of the global queue.  A refill pass
+    // costs the whole wave the issue of a walk's start (and the steps in
+    // between carry its stop), so idle lanes are refilled together once at
+    // least kRefillIdle of them wait (or the wave is empty): with walks of
+    // 28 steps on average (the cap) a wave otherwise refills on almost
+    // every step.
+    constexpr int kRefillIdle = 12;
     const uint32_t lane = lane_id();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     bool active = false;
     bool exhausted = false;
     int64_t next = 0, end = 0;
     for (;;) {
-      for (;;) {
+      const uint64_t idle = __ballot(!active);
+      const bool refill = !exhausted && (__popcll(idle) >= kRefillIdle || idle == ~0ull);
+      for (; refill;) {
         const uint64_t want = __ballot(!active);
         if (want == 0 || exhausted) break;
         if (next >= end) {
