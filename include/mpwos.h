@@ -376,7 +376,11 @@ typedef struct {
 mpwos_status mpwos_server_create(size_t hbm_budget_bytes, int64_t slice_walk_steps, mpwos_server** out);
 
 /* Queues a request (non-blocking); returns its ticket.  EINVAL for bad
- * arguments; ENOMEM when the request alone exceeds the HBM budget. */
+ * arguments; ENOMEM when the request alone exceeds the HBM budget;
+ * EOFFMANIFOLD for a query off an analytic manifold.  Point-cloud queries
+ * are checked on the device at admission (a check at submit would wait for
+ * the device): a request with a query farther than two local spacings from
+ * the reconstruction completes with EOFFMANIFOLD and writes no output. */
 mpwos_status mpwos_submit(mpwos_server* s, const mpwos_request* req, uint64_t* ticket);
 
 /* done = 1 once the request finished; `result` then holds its status. */

@@ -757,6 +757,12 @@ double cloud_max_spacing(const CloudState* c) { return c->hmean_max; }
 
 // A point-cloud query is an ambient point within two local spacings of the
 // reconstructed surface (the walk starts from its projection).
+hipError_t launch_cloud_check(const WalkArgs& a, const double* dq, double* out, int64_t nq, hipStream_t s) {
+  hipLaunchKernelGGL(cloud_query_check_kernel, dim3((unsigned)((nq + kCloudBlock - 1) / kCloudBlock)),
+                     dim3(kCloudBlock), 0, s, a.cloud, dq, out, nq);
+  return hipGetLastError();
+}
+
 mpwos_status cloud_check_queries(const WalkArgs& a, const double* dq, int64_t nq, hipStream_t s, double* out_dev,
                                  int64_t out_cap) {
   double* dout = out_dev;

@@ -40,6 +40,9 @@ double philox_blocks_per_step(int n, int n_v);
 mpwos_status cloud_check_queries(const WalkArgs& a, const double* dq, int64_t nq, hipStream_t s,
                                  double* out = nullptr, int64_t out_cap = 0);
 mpwos_status check_queries_host(const mpwos_manifold* man, const WalkArgs& a, const double* q, int64_t nq);
+// The point-cloud query check on a stream, without waiting: per query the
+// distance to its FP64 projection and the local spacing there (2 doubles).
+hipError_t launch_cloud_check(const WalkArgs& a, const double* dq, double* out, int64_t nq, hipStream_t s);
 
 // walk_lane.hip
 hipError_t launch_walk_lane(const WalkArgs& a, int grid, int block, hipStream_t s);

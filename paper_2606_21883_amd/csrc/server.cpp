@@ -176,8 +176,11 @@ static double since(const mpwos_server* s) {
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-static size_t request_bytes(const mpwos_request& r, int n) {
+// Device bytes of a request; a point-cloud request also holds its query
+// check (distance to the reconstruction and local spacing per query).
+static size_t request_bytes(const mpwos_request& r, int n, bool cloud) {
   size_t b = 0;
+  if (cloud) b += align256((size_t)r.n_queries * 2 * sizeof(double));
   b += align256((size_t)r.n_queries * n * sizeof(double));
   b += align256((size_t)r.n_queries * r.n_walks * sizeof(double));
   b += align256((size_t)r.n_queries * r.n_walks * sizeof(int32_t));
@@ -198,11 +201,27 @@ static hipEvent_t take_event(mpwos_server* s) {
   return e;
 }
 
-// Staging bytes of R: queries and table in; u, stderr and 8 counters out.
+static bool is_cloud(const SrvReq* R) { return R->args.kind == kCloud; }
+
+// Staging bytes of R: queries and table in; u, stderr and 8 counters out;
+// for a point cloud, the query check out.
 static size_t staging_bytes(const SrvReq* R) {
   return HostArena::round((size_t)R->r.n_queries * R->args.n * sizeof(double)) +
          HostArena::round(R->table.size() * sizeof(double)) +
-         HostArena::round((size_t)R->r.n_queries * 2 * sizeof(double)) + 8 * sizeof(unsigned long long);
+         HostArena::round((size_t)R->r.n_queries * 2 * sizeof(double)) + 8 * sizeof(unsigned long long) +
+         (is_cloud(R) ? (size_t)R->r.n_queries * 2 * sizeof(double) : 0);
+}
+
+// Staging of R: queries, table, then u, stderr and the counters out.
+static double* staging_out(const SrvReq* R) {
+  return (double*)(R->h_io + HostArena::round((size_t)R->r.n_queries * R->args.n * sizeof(double)) +
+                   HostArena::round(R->table.size() * sizeof(double)));
+}
+
+// After u, stderr and the counters: the point-cloud query check.
+static double* check_out(const SrvReq* R) {
+  return (double*)((char*)staging_out(R) + HostArena::round((size_t)R->r.n_queries * 2 * sizeof(double)) +
+                   8 * sizeof(unsigned long long));
 }
 
 // Admission without waiting: device memory from the stream-ordered allocator
@@ -248,6 +267,7 @@ static mpwos_status admit(mpwos_server* s, SrvReq* R) {
   R->d_stats = (unsigned long long*)take(8 * sizeof(unsigned long long));
   if (!R->table.empty()) R->d_table = (double*)take(R->table.size() * sizeof(double));
   if (R->rec_bytes) R->d_state = take((size_t)R->total * R->rec_bytes);
+  double* d_check = is_cloud(R) ? (double*)take((size_t)R->r.n_queries * 2 * sizeof(double)) : nullptr;
   const size_t qb = (size_t)R->r.n_queries * n * sizeof(double);
   std::memcpy(R->h_io, R->r.queries, qb);
   char* ht = R->h_io + HostArena::round(qb);
@@ -256,6 +276,15 @@ static mpwos_status admit(mpwos_server* s, SrvReq* R) {
   if (e == hipSuccess && R->d_table)
     e = hipMemcpyAsync(R->d_table, ht, R->table.size() * sizeof(double), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = launch_zero_u64(R->d_stats, 8, st);
+  // a point-cloud request's queries are checked here, on the completion
+  // stream (a check at submit would wait for the device): the verdict is
+  // read when the request completes
+  if (e == hipSuccess && d_check) {
+    e = launch_cloud_check(R->args, R->d_queries, d_check, R->r.n_queries, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(check_out(R), d_check, (size_t)R->r.n_queries * 2 * sizeof(double), hipMemcpyDeviceToHost,
+                         st);
+  }
   if (e == hipSuccess) e = hipEventRecord(R->ready_ev, st);
   if (e != hipSuccess) return hip_fail(e, "server: admission copies");
   WalkArgs& a = R->args;
@@ -287,11 +316,6 @@ static mpwos_status admit(mpwos_server* s, SrvReq* R) {
   return MPWOS_OK;
 }
 
-static double* staging_out(const SrvReq* R) {
-  return (double*)(R->h_io + HostArena::round((size_t)R->r.n_queries * R->args.n * sizeof(double)) +
-                   HostArena::round(R->table.size() * sizeof(double)));
-}
-
 // Every launch holding walks of R has completed (their events were
 // observed): the reduction and the copies out are enqueued on the completion
 // stream, followed by R's done event; nothing waits here.
@@ -311,10 +335,21 @@ static mpwos_status begin_finish(mpwos_server* s, SrvReq* R) {
   return MPWOS_OK;
 }
 
-// R's done event completed: results to the caller's buffers.
+// R's done event completed: results to the caller's buffers, unless a
+// point-cloud query lies farther than two local spacings from the
+// reconstruction (then the request fails with EOFFMANIFOLD and its outputs
+// stay untouched).
 static void end_finish(SrvReq* R) {
   const double* out = staging_out(R);
   const size_t nq = (size_t)R->r.n_queries;
+  if (is_cloud(R)) {
+    const double* chk = check_out(R);
+    for (size_t i = 0; i < nq; ++i)
+      if (!(chk[2 * i] <= 2.0 * chk[2 * i + 1])) {
+        R->status = MPWOS_EOFFMANIFOLD;
+        return;
+      }
+  }
   std::memcpy(R->r.u_out, out, nq * sizeof(double));
   if (R->r.stderr_out) std::memcpy(R->r.stderr_out, out + nq, nq * sizeof(double));
   unsigned long long hs[8];
@@ -699,7 +734,10 @@ mpwos_status mpwos_submit(mpwos_server* s, const mpwos_request* req, uint64_t* t
     R->table.assign(req->f.values, req->f.values + req->f.n_values);
   mpwos_status st = prepare_solve(req->manifold, &R->r.f, g, req->c, req->n_queries, req->n_walks, req->eps,
                                   req->seed, R->opt, R->args);
-  if (!st) st = check_queries_host(req->manifold, R->args, req->queries, req->n_queries);
+  // analytic manifolds: the host check; point clouds are checked on the
+  // device at admission (see admit)
+  if (!st && manifold_desc(req->manifold).kind != MPWOS_POINT_CLOUD)
+    st = check_queries_host(req->manifold, R->args, req->queries, req->n_queries);
   if (st) {
     delete R;
     std::lock_guard<std::mutex> lk(s->mu);
@@ -708,7 +746,7 @@ mpwos_status mpwos_submit(mpwos_server* s, const mpwos_request* req, uint64_t* t
   }
   const int n = R->args.n;
   R->total = req->n_queries * req->n_walks;
-  R->bytes = request_bytes(*req, n);
+  R->bytes = request_bytes(*req, n, R->args.kind == kCloud);
   if (R->bytes > s->budget) {
     delete R;
     std::lock_guard<std::mutex> lk(s->mu);

@@ -1,6 +1,6 @@
 """The benchmark's cost model and contract pieces that need no GPU: the
 algorithmic operation counts of a walk-step (the roofline's numerator), the
-traffic gate on the kernel sources' hash, and the single-GPU exit."""
+counter gate on the kernel sources' hash, and the single-GPU exit."""
 import subprocess
 import sys
 
@@ -17,31 +17,48 @@ def test_sphere_step_counts():
     # every extra Green sample adds a block and its sample work
     ops2 = bench.step_ops("sphere", 3, 2)
     assert ops2["mad_u64_u32"] == 60 and ops2["bitop3_b32"] == 60 and ops2["f32"] > ops["f32"]
-    # the cap adds the boundary distance, two-slice table and the per-step weights
+    # the cap adds the boundary distance, two-slice table, the weight series and the radius
     cap = bench.step_ops("cap", 3, 1)
-    assert cap["f64"] > ops["f64"] and cap["f32"] > ops["f32"]
+    assert cap["f32"] == ops["f32"] + 40 and cap["trans"] == ops["trans"] + 3
+    # the torus replaces the sphere's projection by the level-set Newton steps
+    tor = bench.step_ops("torus", 3, 1)
+    assert tor["f32"] > ops["f32"] and tor["mad_u64_u32"] == 40
 
 
-def test_traffic_constants_follow_the_kernel_sources():
-    # the counters are used only for the sources they were taken on
-    assert len(bench.kernel_sha256()) == 64
-    fake = {"sphere": {"walk_steps": 4096 * 4096 * 174, "kernel_ms": 10.0, "launch": {"persistent": 0}}}
-    saved = dict(bench.TRAFFIC)
+def test_high_dimension_step_counts():
+    # n = 1000, N_V = 1: 250 blocks of normals for the direction, 251 for the
+    # Green sample (its normals and the radius word); 1000 Box-Muller pairs
+    ops = bench.step_ops("sphere", 1000, 1)
+    assert ops["mad_u64_u32"] == 20 * 501 and ops["bitop3_b32"] == 20 * 501
+    assert ops["trans"] == 4 * 1000 + 4 + 2
+    assert ops["f32"] == 2 * 2001 + 3 * 1000 + 7 * 1000 + 18
+    # n = 100: 25 + 26 blocks
+    assert bench.step_ops("sphere", 100, 1)["mad_u64_u32"] == 20 * 51
+
+
+def test_roofline_objects_and_counter_gate():
+    r = bench.roofline_alu("sphere", "sphere", 3, 1, 2_919_235_584, 10.0, {"persistent": 0})
+    assert r["bound"] == "alu" and r["frac"] == pytest.approx(r["achieved"] / r["peak"])
+    slots = sum(bench.step_ops("sphere", 3, 1)[k] * bench.SLOT_WEIGHTS[k] for k in bench.SLOT_WEIGHTS)
+    assert r["achieved"] == pytest.approx(slots * 2_919_235_584 / 0.010 / 1e12)
+    assert 0 < r["fp32_flop_frac"] < r["frac"]
+    c = bench.roofline_cloud("cloud", 8192, 1024, 8192 * 1024 * 16, 1000.0, {"persistent": 1})
+    assert c["bound"] == "hbm" and c["unit"] == "GB/s" and c["frac"] == pytest.approx(c["achieved"] * 1e9 / 8e12)
+    # counter figures apply only to the kernel sources they were taken on
+    saved = {k: v for k, v in bench.PROFILED.items()}
     try:
-        bench.TRAFFIC["kernel_sha256"] = "0" * 64
-        bench.valu_weights = lambda: ({k: 1.0 for k in ("f32", "bitop3_b32", "f64", "trans", "mad_u64_u32")}, {})
-        r = bench.roofline({"per": fake, "form": "graph replay"}, "sphere", "sphere", 3, 1, "fp32")
-        assert r["traffic"] is None and r["bound"] == "alu"
-        assert r["frac"] == pytest.approx(r["achieved"] / r["peak"])
-        bench.TRAFFIC["kernel_sha256"] = bench.kernel_sha256()
-        r = bench.roofline({"per": fake, "form": "graph replay"}, "sphere", "sphere", 3, 1, "fp32")
-        assert r["traffic"] == pytest.approx(1024 * (saved["fetch_kib"] * saved["fetch_factor"] +
-                                                     saved["write_kib"] * saved["write_factor"]))
+        bench.PROFILED["kernel_sha256"] = "0" * 64
+        bench.PROFILED["kernels"] = {"sphere": {"valu_per_walk_step": 161.0, "walk_steps": 2_919_235_584,
+                                                "fetch_kib": 456.0, "write_kib": 196608.0}}
+        r = bench.roofline_alu("sphere", "sphere", 3, 1, 2_919_235_584, 10.0, {"persistent": 0})
+        assert r["traffic"] is None and "valu_issue_frac" not in r
+        bench.PROFILED["kernel_sha256"] = bench.kernel_sha256()
+        r = bench.roofline_alu("sphere", "sphere", 3, 1, 2_919_235_584, 10.0, {"persistent": 0})
+        assert r["traffic"] == pytest.approx(1024 * (456.0 * 2.0 + 196608.0))
+        assert r["valu_issue_frac"] == pytest.approx(161.0 * 2_919_235_584 / 0.010 / bench.PEAK_SLOTS)
     finally:
-        bench.TRAFFIC.clear()
-        bench.TRAFFIC.update(saved)
-        import importlib
-        importlib.reload(bench)
+        bench.PROFILED.clear()
+        bench.PROFILED.update(saved)
 
 
 def test_more_than_one_gpu_exits_with_a_message():

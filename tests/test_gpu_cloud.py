@@ -166,6 +166,30 @@ def test_server_serves_cloud_requests():
     m.close()
 
 
+def test_server_checks_cloud_queries_at_admission():
+    """A served point-cloud request is checked on the device when it is
+    admitted (submit does not wait for the device): one with a query far
+    from the cloud completes with EOFFMANIFOLD, a good one beside it is
+    served as solved alone."""
+    prob = cloud(12000, seed=43, tau_w=1e-3)
+    Q = inputs.torus_area_uniform(6, seed=44)
+    bad = Q.copy()
+    bad[2] *= 1.3
+    m = mpwos.Manifold(prob)
+    announce("cloud served: query check at admission")
+    solo = mpwos.solve(prob, Q, 64, 5, manifold=m, precision="fp32", persistent=1)
+    srv = mpwos.Server(4 << 30)
+    t_bad = srv.submit(m, prob, bad, 64, 5, precision="fp32", persistent=1)
+    t_good = srv.submit(m, prob, Q, 64, 5, precision="fp32", persistent=1)
+    out = srv.wait(t_good, 120_000)
+    with pytest.raises(mpwos.MpwosError) as e:
+        srv.wait(t_bad, 120_000)
+    assert e.value.status == mpwos.EOFFMANIFOLD
+    srv.close()
+    m.close()
+    assert np.array_equal(out["u"], solo["u"])
+
+
 # -- the pure nearest-neighbour projection of Example 4 -----------------------
 
 
