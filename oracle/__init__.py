@@ -85,6 +85,7 @@ def lib():
             getattr(L, nm).restype = d
         L.orc_radial_xmax.argtypes = [ctypes.c_int]; L.orc_radial_xmax.restype = d
         L.orc_knn.argtypes = [vp, i64, vp, ctypes.c_int, vp, vp]; L.orc_knn.restype = ctypes.c_int
+        L.orc_pc_project_from.argtypes = [vp, vp, i64, vp]; L.orc_pc_project_from.restype = ctypes.c_int
         L.orc_grid_build.argtypes = [vp, i64]; L.orc_grid_build.restype = vp
         L.orc_grid_free.argtypes = [vp]; L.orc_grid_free.restype = None
         L.orc_grid_knn.argtypes = [vp, vp, ctypes.c_int, vp, vp]; L.orc_grid_knn.restype = ctypes.c_int
@@ -311,6 +312,23 @@ def cp(problem, x):
     if st:
         raise ValueError(STATUS.get(st, st))
     return y
+
+
+class _PcResult(ctypes.Structure):
+    _fields_ = [("y", ctypes.c_double * 3), ("kappa", ctypes.c_double), ("h_mean", ctypes.c_double),
+                ("patch", ctypes.c_int64)]
+
+
+def pc_project(problem, x, start=-1):
+    """Point-cloud projection from a start patch (-1: from the cloud point
+    nearest to x): (y, kappa, h_mean, patch)."""
+    P = problem if isinstance(problem, Problem) else Problem(problem)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    r = _PcResult()
+    st = lib().orc_pc_project_from(P.ref, _ptr(xx), int(start), ctypes.byref(r))
+    if st:
+        raise ValueError(STATUS.get(st, st))
+    return np.array(r.y[:]), r.kappa, r.h_mean, r.patch
 
 
 def delta_gamma(problem, y):

@@ -688,36 +688,30 @@ static int orc_solve6(double M[36], double b[6], double a[6]) {
 typedef struct {
   double y[3];        /* projected point cp_h(x) */
   double kappa;       /* max |principal curvature| of the fitted patch at the foot */
-  double h_mean;      /* mean distance from the nearest cloud point to its k-1 neighbours */
+  double h_mean;      /* mean distance from the patch's cloud point to its k-1 neighbours */
+  int64_t patch;      /* index of the cloud point whose patch holds y */
 } orc_pc_result;
 
-/* Local reconstruction and projection of x onto a point cloud: the nearest
- * cloud point p of x, the k nearest cloud points of p (p included), their
- * centroid and PCA frame, the least-squares quadratic height field over the
- * tangent plane, and the foot point of x on that patch by Newton. */
-int orc_pc_project(const orc_problem* P, const double* x, orc_pc_result* res) {
+/* The local reconstruction at cloud point i: its k nearest cloud points (i
+ * included) or, with fit_scale > 1, the cloud points within fit_scale r_k of
+ * it; their centroid and PCA frame; the least-squares quadratic height field
+ * h = c0 + c1 a + c2 b + c3 a^2 + c4 a b + c5 b^2 over the tangent plane; the
+ * support (largest |a| or |b| of its points); the mean distance from i to its
+ * k-1 other neighbours. */
+typedef struct {
+  double cen[3], e1[3], e2[3], nn[3], coef[6], ext, h_mean;
+} orc_patch;
+
+static int orc_pc_fit(const orc_problem* P, int64_t i, orc_patch* pt) {
   int k = P->k_nn;
-  int64_t inn;
-  double nn_d2;
-  int st = orc_pc_knn(P, x, 1, &inn, &nn_d2);
-  if (st) return st;
-  const double* pn = P->points + 3 * inn;
+  const double* pn = P->points + 3 * i;
   int64_t idx[ORC_MAXK];
   double d2[ORC_MAXK];
-  st = orc_pc_knn(P, pn, k, idx, d2);
+  int st = orc_pc_knn(P, pn, k, idx, d2);
   if (st) return st;
-  /* local spacing: mean distance from p to its k-1 other neighbours */
   double hsum = 0.0;
   for (int j = 1; j < k; ++j) hsum += sqrt(d2[j]);
-  res->h_mean = hsum / (double)(k - 1);
-  if (P->reconstruction == 1) {
-    /* the pure nearest-neighbour projection (Sec. 4, Example 4) */
-    for (int c = 0; c < 3; ++c) res->y[c] = pn[c];
-    res->kappa = 0.0;
-    return ORC_OK;
-  }
-  /* the points the patch is fitted to: the k nearest, or the ball of radius
-   * fit_scale r_k around p */
+  pt->h_mean = hsum / (double)(k - 1);
   const int64_t* fit = idx;
   int64_t nfit = k;
   int64_t* ball = NULL;
@@ -740,16 +734,18 @@ int orc_pc_project(const orc_problem* P, const double* x, orc_pc_result* res) {
   }
   double w[3], V[9];
   orc_jacobi3(C, w, V);
-  double e1[3] = {V[0 * 3 + 2], V[1 * 3 + 2], V[2 * 3 + 2]};
-  double e2[3] = {V[0 * 3 + 1], V[1 * 3 + 1], V[2 * 3 + 1]};
-  double nn[3] = {V[0 * 3 + 0], V[1 * 3 + 0], V[2 * 3 + 0]};
-  /* least-squares height field h = a0 + a1 a + a2 b + a3 a^2 + a4 a b + a5 b^2 */
-  double M[36] = {0}, rhs[6] = {0}, coef[6];
-  double ext = 0.0; /* support of the patch: largest |a| or |b| of its points */
+  for (int c = 0; c < 3; ++c) {
+    pt->cen[c] = cen[c];
+    pt->e1[c] = V[c * 3 + 2];
+    pt->e2[c] = V[c * 3 + 1];
+    pt->nn[c] = V[c * 3 + 0];
+  }
+  double M[36] = {0}, rhs[6] = {0};
+  double ext = 0.0;
   for (int64_t j = 0; j < nfit; ++j) {
     double d[3];
     for (int c = 0; c < 3; ++c) d[c] = P->points[3 * fit[j] + c] - cen[c];
-    double a = orc_dot(d, e1, 3), b = orc_dot(d, e2, 3), h = orc_dot(d, nn, 3);
+    double a = orc_dot(d, pt->e1, 3), b = orc_dot(d, pt->e2, 3), h = orc_dot(d, pt->nn, 3);
     ext = fmax(ext, fmax(fabs(a), fabs(b)));
     double phi[6] = {1.0, a, b, a * a, a * b, b * b};
     for (int r = 0; r < 6; ++r) {
@@ -758,16 +754,26 @@ int orc_pc_project(const orc_problem* P, const double* x, orc_pc_result* res) {
     }
   }
   free(ball);
-  st = orc_solve6(M, rhs, coef);
-  if (st) return st;
+  pt->ext = ext;
+  return orc_solve6(M, rhs, pt->coef);
+}
+
+/* Foot point of x on patch pt: minimise E(a,b) = (a-ax)^2 + (b-bx)^2 +
+ * (h(a,b)-hx)^2 over the support square |a|, |b| <= ext (unbounded when
+ * clamp is 0: the patch's whole quadratic), from (ax,bx) clamped to it, by
+ * newton_iters Newton steps; where the Newton Hessian is not positive
+ * definite (x beyond the focal distance of the quadratic) the Gauss-Newton
+ * matrix I + J^T J replaces it; every iterate is clamped to the square.
+ * Then the curvature indicator there: the largest |eigenvalue| of the shape
+ * operator I^-1 II of the graph, I = [[1+ha^2, ha hb],[ha hb, 1+hb^2]],
+ * II = Hess(h)/sqrt(1+ha^2+hb^2). */
+static void orc_patch_foot(const orc_problem* P, const orc_patch* pt, const double* x, int clamp, double* y,
+                           double* kappa) {
+  const double* coef = pt->coef;
   double dx[3];
-  for (int c = 0; c < 3; ++c) dx[c] = x[c] - cen[c];
-  double ax = orc_dot(dx, e1, 3), bx = orc_dot(dx, e2, 3), hx = orc_dot(dx, nn, 3);
-  /* Foot point: minimise E(a,b) = (a-ax)^2 + (b-bx)^2 + (h(a,b)-hx)^2 over
-   * the patch's support square |a|, |b| <= ext, from (ax,bx) clamped to it.
-   * Newton steps; where the Newton Hessian is not positive definite (x beyond
-   * the focal distance of the fitted quadratic) the Gauss-Newton matrix
-   * I + J^T J replaces it; every iterate is clamped to the square. */
+  for (int c = 0; c < 3; ++c) dx[c] = x[c] - pt->cen[c];
+  double ax = orc_dot(dx, pt->e1, 3), bx = orc_dot(dx, pt->e2, 3), hx = orc_dot(dx, pt->nn, 3);
+  double ext = clamp ? pt->ext : 3.0e38;
   double a = fmin(fmax(ax, -ext), ext), b = fmin(fmax(bx, -ext), ext);
   for (int it = 0; it < P->newton_iters; ++it) {
     double h = coef[0] + coef[1] * a + coef[2] * b + coef[3] * a * a + coef[4] * a * b + coef[5] * b * b;
@@ -793,29 +799,85 @@ int orc_pc_project(const orc_problem* P, const double* x, orc_pc_result* res) {
     b = fmin(fmax(b - db, -ext), ext);
   }
   double h = coef[0] + coef[1] * a + coef[2] * b + coef[3] * a * a + coef[4] * a * b + coef[5] * b * b;
-  for (int c = 0; c < 3; ++c) res->y[c] = cen[c] + a * e1[c] + b * e2[c] + h * nn[c];
-  /* curvature indicator: largest |eigenvalue| of the shape operator of the
-   * graph at the foot, I^-1 II with I = [[1+ha^2, ha hb],[ha hb, 1+hb^2]],
-   * II = Hess(h)/sqrt(1+ha^2+hb^2). */
-  {
-    double ha = coef[1] + 2.0 * coef[3] * a + coef[4] * b;
-    double hb = coef[2] + coef[4] * a + 2.0 * coef[5] * b;
-    double gfac = sqrt(1.0 + ha * ha + hb * hb);
-    double I11 = 1.0 + ha * ha, I12 = ha * hb, I22 = 1.0 + hb * hb;
-    double II11 = 2.0 * coef[3] / gfac, II12 = coef[4] / gfac, II22 = 2.0 * coef[5] / gfac;
-    double detI = I11 * I22 - I12 * I12;
-    /* S = I^-1 II */
-    double S11 = (I22 * II11 - I12 * II12) / detI;
-    double S12 = (I22 * II12 - I12 * II22) / detI;
-    double S21 = (I11 * II12 - I12 * II11) / detI;
-    double S22 = (I11 * II22 - I12 * II12) / detI;
-    double tr = S11 + S22, det = S11 * S22 - S12 * S21;
-    double disc = tr * tr / 4.0 - det;
-    if (disc < 0.0) disc = 0.0;
-    double l1 = tr / 2.0 + sqrt(disc), l2 = tr / 2.0 - sqrt(disc);
-    res->kappa = fmax(fabs(l1), fabs(l2));
+  for (int c = 0; c < 3; ++c) y[c] = pt->cen[c] + a * pt->e1[c] + b * pt->e2[c] + h * pt->nn[c];
+  double ha = coef[1] + 2.0 * coef[3] * a + coef[4] * b;
+  double hb = coef[2] + coef[4] * a + 2.0 * coef[5] * b;
+  double gfac = sqrt(1.0 + ha * ha + hb * hb);
+  double I11 = 1.0 + ha * ha, I12 = ha * hb, I22 = 1.0 + hb * hb;
+  double II11 = 2.0 * coef[3] / gfac, II12 = coef[4] / gfac, II22 = 2.0 * coef[5] / gfac;
+  double detI = I11 * I22 - I12 * I12;
+  double S11 = (I22 * II11 - I12 * II12) / detI;
+  double S12 = (I22 * II12 - I12 * II22) / detI;
+  double S21 = (I11 * II12 - I12 * II11) / detI;
+  double S22 = (I11 * II22 - I12 * II12) / detI;
+  double tr = S11 + S22, dt = S11 * S22 - S12 * S21;
+  double disc = tr * tr / 4.0 - dt;
+  if (disc < 0.0) disc = 0.0;
+  double l1 = tr / 2.0 + sqrt(disc), l2 = tr / 2.0 - sqrt(disc);
+  *kappa = fmax(fabs(l1), fabs(l2));
+}
+
+#define ORC_PC_ROUNDS 4
+
+/* Local reconstruction and projection of x onto a point cloud (Sec. 2.3.2,
+ * "nearest-neighbour search with local reconstruction"): cp_h(x) is the
+ * foot point of x on the patch of the cloud point nearest to that foot
+ * point.  It is found from a start patch by alternating the foot point on
+ * the current patch and the nearest cloud point of the foot, until the
+ * nearest point is the current one, in at most ORC_PC_ROUNDS foot points.
+ * Start (start < 0): the cloud point nearest to x.  Otherwise the walker's
+ * patch `start`: the cloud point nearest to the foot point of x on that
+ * patch's whole quadratic.  The pure nearest-neighbour projection of
+ * Example 4 (reconstruction 1) is the cloud point nearest to x. */
+int orc_pc_project_from(const orc_problem* P, const double* x, int64_t start, orc_pc_result* res) {
+  int64_t p;
+  double d2;
+  orc_patch pt;
+  int st;
+  if (P->reconstruction == 1) {
+    st = orc_pc_knn(P, x, 1, &p, &d2);
+    if (st) return st;
+    int64_t idx[ORC_MAXK];
+    double dk[ORC_MAXK];
+    st = orc_pc_knn(P, P->points + 3 * p, P->k_nn, idx, dk);
+    if (st) return st;
+    double hsum = 0.0;
+    for (int j = 1; j < P->k_nn; ++j) hsum += sqrt(dk[j]);
+    for (int c = 0; c < 3; ++c) res->y[c] = P->points[3 * p + c];
+    res->kappa = 0.0;
+    res->h_mean = hsum / (double)(P->k_nn - 1);
+    res->patch = p;
+    return ORC_OK;
   }
+  if (start < 0) {
+    st = orc_pc_knn(P, x, 1, &p, &d2);
+    if (st) return st;
+  } else {
+    double y0[3], kap;
+    st = orc_pc_fit(P, start, &pt);
+    if (st) return st;
+    orc_patch_foot(P, &pt, x, 0, y0, &kap);
+    st = orc_pc_knn(P, y0, 1, &p, &d2);
+    if (st) return st;
+  }
+  for (int j = 0; j < ORC_PC_ROUNDS; ++j) {
+    st = orc_pc_fit(P, p, &pt);
+    if (st) return st;
+    orc_patch_foot(P, &pt, x, 1, res->y, &res->kappa);
+    res->h_mean = pt.h_mean;
+    if (j == ORC_PC_ROUNDS - 1) break;
+    int64_t q;
+    st = orc_pc_knn(P, res->y, 1, &q, &d2);
+    if (st) return st;
+    if (q == p) break;
+    p = q;
+  }
+  res->patch = p;
   return ORC_OK;
+}
+
+int orc_pc_project(const orc_problem* P, const double* x, orc_pc_result* res) {
+  return orc_pc_project_from(P, x, -1, res);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -1439,8 +1501,10 @@ static double orc_g_omega(const orc_problem* P, const double* y) {
   return NAN;
 }
 
-/* Source term of one Green sample at ambient point z: f(z) + m(z). */
-double orc_source(const orc_problem* P, const double* z) {
+/* Source term of one Green sample at ambient point z: f(z) + m(z).  On a
+ * point cloud the projection of z starts from patch `start` (the walker's;
+ * -1: from the cloud point nearest to z). */
+static double orc_source_from(const orc_problem* P, const double* z, int64_t start) {
   double y[ORC_MAXN];
   if (P->manifold == ORC_DUMBBELL) {
     double phi;
@@ -1454,12 +1518,20 @@ double orc_source(const orc_problem* P, const double* z) {
     if (P->f_kind == ORC_FN_PRODUCT_MODES) return orc_pr_f(P, y, phi);
     return orc_f_omega(P, y);
   }
-  if (orc_cp(P, z, y)) return NAN;
+  if (P->manifold == ORC_POINT_CLOUD) {
+    orc_pc_result pc;
+    if (orc_pc_project_from(P, z, start, &pc)) return NAN;
+    for (int i = 0; i < 3; ++i) y[i] = pc.y[i];
+  } else if (orc_cp(P, z, y)) {
+    return NAN;
+  }
   double v = orc_f_omega(P, y);
   if (P->compensation == ORC_COMP_EXACT) v += orc_m_exact(P, z, y);
   else if (P->compensation == ORC_COMP_SECOND_ORDER) v += orc_m_second_order(P, z, y);
   return v;
 }
+
+double orc_source(const orc_problem* P, const double* z) { return orc_source_from(P, z, -1); }
 
 /* ------------------------------------------------------------------------- */
 /* Radius rule r(y) = theta min{delta_Gamma(y), rho_geo(y)}                   */
@@ -1548,7 +1620,7 @@ static int orc_walk(const orc_ctx* C, const double* y0, uint32_t q, uint32_t w, 
     orc_direction(C->seed, q, w, k, 0, n, g);
     for (int i = 0; i < n; ++i) Th[i] = Y[i] + r * g[i];
     if (P->manifold == ORC_POINT_CLOUD) {
-      if (orc_pc_project(P, Th, &pc_next)) { free(buf); return ORC_EINVAL; }
+      if (orc_pc_project_from(P, Th, pc_cur.patch, &pc_next)) { free(buf); return ORC_EINVAL; }
       for (int i = 0; i < 3; ++i) Yn[i] = pc_next.y[i];
     } else if (orc_cp(P, Th, Yn)) {
       free(buf);
@@ -1562,7 +1634,7 @@ static int orc_walk(const orc_ctx* C, const double* y0, uint32_t q, uint32_t w, 
       double s = orc_radial_inv_r(&C->rad, X, u);
       orc_direction(C->seed, q, w, k, (uint32_t)l, n, g);
       for (int i = 0; i < n; ++i) Z[i] = Y[i] + (r * s) * g[i];
-      F += orc_source(P, Z);
+      F += orc_source_from(P, Z, P->manifold == ORC_POINT_CLOUD ? pc_cur.patch : -1);
     }
     F = F / (double)P->n_v;
     orc_sum_add(&S, &comp, (W * om) * F);

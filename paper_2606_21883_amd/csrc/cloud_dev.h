@@ -1,8 +1,16 @@
 // Device side of the point-cloud closest-point map (Sec. 2.3.2: nearest-
-// neighbour search with local reconstruction).  cp_h(x): the nearest cloud
-// point p of x (KD-tree search, ties to the lower original index), then the
-// Newton foot point of x on p's local quadratic patch (built once per
-// manifold from p's k nearest cloud points).
+// neighbour search with local reconstruction).  cp_h(x) is the Newton foot
+// point of x on the local quadratic patch (built once per manifold) of the
+// cloud point nearest to that foot point: a fixed point found from a start
+// patch by alternating the foot point on the current patch and the nearest
+// cloud point of the foot (KD-tree search, ties to the lower original index),
+// at most kCloudRounds times.  The start patch is that of the cloud point
+// nearest to x for a query, and for a walk point x near the walker's Y the
+// one nearest to x's foot on the osculating quadratic of Y's patch (not
+// clamped to its support).  Every search is then of a point near the
+// surface; a search from x itself, up to a walk radius away, has to visit
+// the boxes of every sample nearly as close as the nearest when x lies near
+// a focal point of the surface.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -120,7 +128,12 @@ struct CloudProj {
   T y[3];
   T kappa;   // largest |principal curvature| of the patch at the foot point
   T hmean;   // local spacing of the nearest cloud point
+  int32_t patch;  // original index of the cloud point whose patch holds y
 };
+
+// Rounds of the fixed-point search for the patch (foot point, then nearest
+// cloud point of the foot).
+constexpr int kCloudRounds = 4;
 
 // Foot point of x on patch P: minimise E = (a - ax)^2 + (b - bx)^2 +
 // (h(a,b) - hx)^2 over the support square |a|, |b| <= ext from (ax, bx)
@@ -128,14 +141,16 @@ struct CloudProj {
 // I + J^T J where the Newton Hessian is not positive definite (x beyond the
 // focal distance of the fitted quadratic), each iterate clamped; then the
 // curvature of the patch there (eigenvalues of the shape operator I^-1 II).
+// Without `clamp` the support square is unbounded: the foot point on the
+// patch's whole quadratic (its osculating extension).
 template <class T>
-__device__ __forceinline__ CloudProj<T> patch_project(const Patch<T>& P, const T* x, int iters) {
+__device__ __forceinline__ CloudProj<T> patch_project(const Patch<T>& P, const T* x, int iters, bool clamp = true) {
   const T d0 = x[0] - P.cen[0], d1 = x[1] - P.cen[1], d2 = x[2] - P.cen[2];
   const T ax = d0 * P.e1[0] + d1 * P.e1[1] + d2 * P.e1[2];
   const T bx = d0 * P.e2[0] + d1 * P.e2[1] + d2 * P.e2[2];
   const T hx = d0 * P.n[0] + d1 * P.n[1] + d2 * P.n[2];
   const T* c = P.c;
-  const T ext = P.ext;
+  const T ext = clamp ? P.ext : (T)3.0e38;
   T a = fmin(fmax(ax, -ext), ext), b = fmin(fmax(bx, -ext), ext);
   for (int it = 0; it < iters; ++it) {
     const T h = c[0] + c[1] * a + c[2] * b + c[3] * a * a + c[4] * a * b + c[5] * b * b;
@@ -185,11 +200,12 @@ __device__ __forceinline__ const Patch<double>& patch_of<double>(const CloudDev&
 template <>
 __device__ __forceinline__ const Patch<float>& patch_of<float>(const CloudDev& c, int32_t i) { return c.patch32[i]; }
 
+// cp_h(x) from a start patch (start < 0: the cloud point nearest to x).
 template <class T>
-__device__ __forceinline__ CloudProj<T> cloud_cp(const CloudDev& c, const T* x) {
-  const int32_t nn = kd_nearest<T>(c, x);
+__device__ __forceinline__ CloudProj<T> cloud_cp(const CloudDev& c, const T* x, int32_t start = -1) {
   if (c.nn_only) {
     // the nearest cloud point itself; its patch supplies only the spacing
+    const int32_t nn = kd_nearest<T>(c, x);
     const float4 p = c.pts[nn];
     CloudProj<T> r;
     r.y[0] = (T)p.x;
@@ -197,10 +213,26 @@ __device__ __forceinline__ CloudProj<T> cloud_cp(const CloudDev& c, const T* x) 
     r.y[2] = (T)p.z;
     r.kappa = (T)0;
     r.hmean = patch_of<T>(c, nn).hmean;
+    r.patch = nn;
     return r;
   }
-  const Patch<T> P = patch_of<T>(c, nn);
-  return patch_project<T>(P, x, c.newton_iters);
+  int32_t p;
+  if (start < 0) {
+    p = kd_nearest<T>(c, x);
+  } else {
+    const CloudProj<T> y0 = patch_project<T>(patch_of<T>(c, start), x, c.newton_iters, false);
+    p = kd_nearest<T>(c, y0.y);
+  }
+  CloudProj<T> r;
+  for (int j = 0; j < kCloudRounds; ++j) {
+    r = patch_project<T>(patch_of<T>(c, p), x, c.newton_iters);
+    if (j == kCloudRounds - 1) break;
+    const int32_t q = kd_nearest<T>(c, r.y);
+    if (q == p) break;
+    p = q;
+  }
+  r.patch = p;
+  return r;
 }
 
 // rho_geo of a projected point: curvature rule on the fitted patch, or c_h h.

@@ -19,6 +19,7 @@ struct LaneState {
   T Y[N];
   double W, S, C;
   T rg;                // point cloud: rho_geo from the reconstruction that produced Y; cap: delta_Gamma(Y)
+  int32_t pidx;        // point cloud: the patch that holds Y (start of the next projections)
   uint32_t k, q, w;
   int64_t idx;
 };
@@ -140,8 +141,10 @@ __device__ __forceinline__ double layer_value(const WalkArgs& a, const T* y) {
 }
 
 // ---- closest point ----------------------------------------------------------
+// (point clouds: `start` is the patch the search for x's patch starts from,
+// the walker's, or -1 for the cloud point nearest to x)
 template <class T, int N, int KIND>
-__device__ __forceinline__ void closest_point(const WalkArgs& a, const T* x, T* y) {
+__device__ __forceinline__ void closest_point(const WalkArgs& a, const T* x, T* y, int32_t start = -1) {
   if constexpr (KIND == kCutTorus) {
     // the parametrized torus of the cut example: the nearest point of the
     // core circle, then the tube radius along the offset (closed form)
@@ -156,7 +159,7 @@ __device__ __forceinline__ void closest_point(const WalkArgs& a, const T* x, T* 
   } else if constexpr (KIND == kTorus) {
     torus_cp_newton<T>((T)a.p[0], (T)a.p[1], x, y);
   } else if constexpr (KIND == kCloud) {
-    const CloudProj<T> p = cloud_cp<T>(a.cloud, x);
+    const CloudProj<T> p = cloud_cp<T>(a.cloud, x, start);
     for (int i = 0; i < 3; ++i) y[i] = p.y[i];
   } else {
     T s = (T)0;
@@ -183,10 +186,12 @@ __device__ __forceinline__ bool walk_init(const WalkArgs& a, const double* queri
   st.C = 0.0;
   st.k = 0;
   st.rg = (T)0;
+  st.pidx = -1;
   if constexpr (KIND == kCloud) {
     // the walk starts from the query's projection onto the reconstruction
     const CloudProj<T> p = cloud_cp<T>(a.cloud, st.Y);
     for (int i = 0; i < N; ++i) st.Y[i] = p.y[i];
+    st.pidx = p.patch;
     if (!a.const_r) st.rg = (T)cloud_rho_geo(a, p);
   }
   if constexpr (KIND == kCap || KIND == kCutTorus) {
@@ -217,14 +222,14 @@ __device__ __forceinline__ void walk_store(double* walk_S, int32_t* walk_K, cons
 // uniform word ux, zeta' from words x, y of block b) and (f + m)(Z).
 template <class T, int N, int KIND, bool RICH>
 __device__ __forceinline__ T green_sample(const WalkArgs& a, const T* Y, uint4 b, uint32_t ux, T rT, T X2,
-                                          double norm, const float4* tab) {
+                                          double norm, const float4* tab, int32_t pidx) {
   T s;
   if constexpr (sizeof(T) == 8) s = radial_inv64(a, u01_64(ux), X2, norm);
   else s = radial_inv32(a, u01_32(ux), X2);
   const T t = rT * s;
   T Z[N], Zc[N];
   lane_point<N>(b.x, b.y, t, Y, Z);
-  closest_point<T, N, KIND>(a, Z, Zc);
+  closest_point<T, N, KIND>(a, Z, Zc, pidx);
   if constexpr (KIND == kCutTorus) {
     // the cut torus takes the series family (from the workgroup's staged
     // table when there is one) or ZERO / CONST: no other family is compiled in
@@ -283,12 +288,14 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
   // (ii) Theta = Y + r zeta and Y' = cp(Theta)
   T Yn[N];
   T rg_next = (T)0;
+  int32_t pidx_next = -1;
   {
     T Th[N];
     lane_point<N>(bd.x, bd.y, rT, st.Y, Th);
     if constexpr (KIND == kCloud) {
-      const CloudProj<T> p = cloud_cp<T>(a.cloud, Th);
+      const CloudProj<T> p = cloud_cp<T>(a.cloud, Th, st.pidx);
       for (int i = 0; i < N; ++i) Yn[i] = p.y[i];
+      pidx_next = p.patch;
       if (!a.const_r) rg_next = (T)cloud_rho_geo(a, p);
     } else {
       closest_point<T, N, KIND>(a, Th, Yn);
@@ -298,7 +305,7 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
   T Fsum = (T)0;
   for (int l = 1; l <= a.n_v; ++l) {
     const uint4 b = rs.block(st.k, (uint32_t)l, 0);
-    Fsum += green_sample<T, N, KIND, RICH>(a, st.Y, b, b.w, rT, X2, norm, tab);
+    Fsum += green_sample<T, N, KIND, RICH>(a, st.Y, b, b.w, rT, X2, norm, tab, st.pidx);
   }
   // the mean over the N_V samples (times 1/N_V: exact for N_V = 1 and powers
   // of two, within an ulp of the quotient otherwise)
@@ -306,7 +313,10 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
   score_add<T>(st, (st.W * om) * F);
   st.W = st.W * c;
   for (int i = 0; i < N; ++i) st.Y[i] = Yn[i];
-  if constexpr (KIND == kCloud) st.rg = rg_next;
+  if constexpr (KIND == kCloud) {
+    st.rg = rg_next;
+    st.pidx = pidx_next;
+  }
   st.k += 1;
   if constexpr (KIND == kCap || KIND == kCutTorus) {
     if (in_layer<T, N, KIND>(a, st.Y, st.rg)) {

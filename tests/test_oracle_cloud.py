@@ -282,3 +282,37 @@ def test_wide_fit_resolves_curvature_on_noisy_million_point_torus(orc):
     assert np.all(np.abs(kap4 - 1 / 0.3) < 0.15 / 0.3), (kap4.min(), kap4.max())
     err1, kap1 = out[1.0]
     assert err1.max() > 10 * err4.max() and kap1.max() > 2 * kap4.max()
+
+
+def test_patch_is_that_of_the_foot_points_nearest_cloud_point(orc):
+    """The reading of the reconstruction for far points: cp_h(x) is the foot
+    point of x on the patch of the cloud point nearest to that foot point (a
+    fixed point of foot point and nearest cloud point, found in at most four
+    rounds).  On the 1e6-point noisy torus with the wide fit, for walk points
+    0.26 from the surface, from the point's own nearest cloud point and from
+    a walker's patch 0.26 away: the fixed point is reached for 95% of them
+    (the returned patch is the foot's nearest cloud point), both starts give
+    the same patch or a neighbour's (their feet within 1e-4), and the projection lies
+    within 1e-3 of the exact torus projection (median 1e-4)."""
+    pts = inputs.torus_point_cloud(1_000_000, 1.0, 0.3, 1e-4, 1)
+    P = orc.Problem(cloud_problem(pts, fit_scale=4.0))
+    T = orc.Problem(inputs.torus_problem())
+    rng = np.random.default_rng(12)
+    Y = inputs.torus_area_uniform(120, seed=13)
+    z = rng.standard_normal((120, 3))
+    z /= np.linalg.norm(z, axis=1, keepdims=True)
+    X = Y + 0.26 * z
+    fixed, agree, err = 0, 0, []
+    for y0, x in zip(Y, X):
+        _, _, _, p0 = orc.pc_project(P, y0)        # the walker's patch
+        ya, _, _, pa = orc.pc_project(P, x)        # from x's nearest cloud point
+        yb, _, _, pb = orc.pc_project(P, x, p0)    # from the walker's patch
+        idx, _ = orc.knn(pts, yb, 1)
+        fixed += int(idx[0] == pb)
+        agree += int(np.linalg.norm(ya - yb) < 1e-4)
+        err.append(np.linalg.norm(yb - orc.cp(T, x)))
+    # at a seam two neighbouring patches can hand the foot back and forth
+    # (each foot nearer to the other's cloud point, the feet ~1e-5 apart):
+    # then the fourth round's foot is returned
+    assert fixed >= 114 and agree >= 114, (fixed, agree)
+    assert max(err) < 1e-3 and np.median(err) < 1e-4, (max(err), np.median(err))
