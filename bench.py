@@ -429,7 +429,7 @@ CONFIGS = {
     "hyper100": ("sphere", 1000, 100, 11340),
     "hyper1000": ("sphere", 200, 20, 113393),
     "torus": ("torus", None, None, 1601),
-    "cloud": ("cloud", 16, 4, 1601),
+    "cloud": ("cloud", 64, 16, 1601),
 }
 
 
@@ -558,7 +558,7 @@ def cpu_baseline(work, per_config=True):
 # (round figures from the configurations section), which turns a request's
 # drawn GPU time into its size.
 SERVED_KINDS = {"circle": (232, 5e10), "sphere": (174, 2e11), "cap": (29, 1e11), "torus": (1601, 5e10),
-                "hyper100": (11340, 5e9), "hyper1000": (113393, 7e8), "cloud": (1601, 4e7),
+                "hyper100": (11340, 5e9), "hyper1000": (113393, 7e8), "cloud": (1601, 3e8),
                 "dumbbell": (220, 1e7)}
 
 
