@@ -41,6 +41,12 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# The server runs its launches on GPU_MAX_HW_QUEUES - 2 streams (two at
+# least); the runtime reads the variable when it starts, so it is set before
+# anything touches the device.  Eight hardware queues give the served mix three
+# streams for its long classes and three for the rest; one-stream legs are
+# unaffected.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
 
 METRIC = "walk-steps/s and queries/s at fixed RMSE vs FP64 oracle; served p50/p99 ms"
 # Full-rate VALU lane-operations per second: 256 CUs x 128 FP32 FMA lanes per
@@ -681,6 +687,8 @@ def served_mix(rate=200.0, window=30.0, seed=2, ms_range=(0.02, 20.0), q_range=(
            "drain_s": max(0.0, wall - window), "backlog_growth": backlog_growth(reqs, lat),
            "walk_steps": int(st["walk_steps"]),
            "walk_steps_per_s": st["walk_steps"] / wall, "launches": st["rounds"],
+           "slots_busy_s": st["busy_seconds"], "wall_s": wall,
+           "gpu_max_hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
            "closed_form_check": {"queries": nqs, "within_4se_plus_bias": ok / max(1, nqs),
                                  "median_abs_z": float(np.median(zs)) if zs else None},
            "by_manifold": {}}

@@ -368,8 +368,12 @@ typedef struct {
  * shared by the requests of its class, in three-dimensional walk-steps (0 =
  * about 9e7); a launch holds at least the walks that fill the device, or all
  * that its class has left, and at least one wavefront's walks per request.
- * The library allocates 8 launch tables of 512 entries and 64 MiB of pinned
- * staging at creation; admission, uploads, reductions and copies out are
+ * Launches run on max(2, min(8, GPU_MAX_HW_QUEUES - 2)) streams (the
+ * variable as read at creation, default 4), one hardware queue each when the
+ * runtime has them; classes whose launches take above 20 ms of device time
+ * run on half of them, and no launch is queued behind such a launch.  The
+ * library allocates two launch tables of 512 entries per stream and 64 MiB of
+ * pinned staging at creation; admission, uploads, reductions and copies out are
  * asynchronous (events), so the scheduling thread never waits for the
  * device.  A request whose staging does not fit waits for completions to
  * free it; one above 16 MiB takes pinned memory of its own. */

@@ -3,7 +3,11 @@
 // Requests are validated and costed at submit time and queued.  A worker
 // thread admits queued requests in arrival order while their device
 // footprint fits the HBM budget and keeps a fixed number of batched launches
-// in flight: two per stream on a few streams of default priority.  Admitted
+// in flight: two per stream on a few streams of default priority.  Classes
+// whose launches run long (walks whose every step is costly: point clouds,
+// the dumbbell's profile projection) are served on half of the streams, and
+// no launch is queued behind a long one, so short requests never wait for a
+// long launch to drain its stream.  Admitted
 // requests that run the same kernel with the same problem data (manifold, f,
 // g, sigma, eps, options) form a class; one launch carries slices of every
 // request of a class, each request with its own queries, seed and outputs
@@ -24,6 +28,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -40,10 +45,11 @@ namespace mpwos {
 
 namespace {
 
-constexpr int kStreams = 4;
+constexpr int kMaxStreams = 8;            // walk streams at most
 constexpr int kDepth = 2;                  // launches in flight per stream
-constexpr int kSlots = kStreams * kDepth;
+constexpr int kSlots = kMaxStreams * kDepth;
 constexpr int kMaxBatch = 512;             // requests per launch
+constexpr double kLongMs = 20.0;           // launches of a long class take longer (device time, moving average)
 
 struct SrvReq {
   uint64_t ticket = 0;
@@ -130,13 +136,16 @@ constexpr double kSliceBlocks = 1e6;       // Philox blocks per time-sliced walk
 struct ClassInfo {
   int inflight = 0;
   double last = -1.0;
+  double ms = -1.0;            // device time of its launches, moving average (-1: none completed yet)
 };
 
 struct Slot {
   std::vector<SrvReq*> members;
   std::string cls;             // class of the launch in flight
   double issued = 0.0;         // when it was enqueued
-  hipEvent_t ev = nullptr;
+  bool is_long = false;        // launch of a long class
+  hipEvent_t t0 = nullptr;     // before the kernel (timing)
+  hipEvent_t ev = nullptr;     // after the kernel and the table copy back (timing)
   BatchEntry* h_tab = nullptr;
   BatchEntry* d_tab = nullptr;
   unsigned long long* d_queue = nullptr;
@@ -159,7 +168,9 @@ struct mpwos_server {
   std::unordered_map<uint64_t, mpwos::SrvReq*> reqs;
   uint64_t next_ticket = 1;
   size_t in_flight = 0;
-  hipStream_t streams[mpwos::kStreams] = {};
+  int n_streams = 2;           // walk streams in use; slot j runs on stream j % n_streams
+  int n_long = 1;              // streams [0, n_long) take the long classes
+  hipStream_t streams[mpwos::kMaxStreams] = {};
   hipStream_t done_stream = nullptr;   // per-query reductions and copies out
   mpwos::Slot slots[mpwos::kSlots];
   mpwos::HostArena arena;
@@ -466,6 +477,7 @@ static mpwos_status launch_batch(mpwos_server* s, Slot& sl, const std::vector<Sr
     if (!R->ready && e == hipSuccess) e = hipStreamWaitEvent(st, R->ready_ev, 0);
   if (e == hipSuccess)
     e = hipMemcpyAsync(sl.d_tab, sl.h_tab, (size_t)nb * sizeof(BatchEntry), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventRecord(sl.t0, st);
   if (e != hipSuccess) return hip_fail(e, "server: batch table upload");
   mpwos_status ls = launch_walks(a, cls.front()->opt, st, sl.d_queue);
   if (ls) return ls;
@@ -479,12 +491,13 @@ static mpwos_status launch_batch(mpwos_server* s, Slot& sl, const std::vector<Sr
 static void worker_main(mpwos_server* s) {
   (void)hipSetDevice(s->device);
   Slot* slots = s->slots;
-  std::map<std::string, ClassInfo> cinfo;   // per class: launches in flight, last launch time
+  const int n_slots = s->n_streams * kDepth;
+  std::map<std::string, ClassInfo> cinfo;   // per class: launches in flight, last launch time, launch duration
   auto last = std::chrono::steady_clock::now();
   for (;;) {
     std::vector<SrvReq*> active;
     bool busy_slot = false;
-    for (int k = 0; k < kSlots; ++k) busy_slot = busy_slot || !slots[k].members.empty();
+    for (int k = 0; k < n_slots; ++k) busy_slot = busy_slot || !slots[k].members.empty();
     {
       const auto now = std::chrono::steady_clock::now();
       if (busy_slot) {
@@ -520,12 +533,15 @@ static void worker_main(mpwos_server* s) {
       s->st.in_flight_bytes = (int64_t)s->in_flight;
     }
     // completed launches free their slots
-    for (int k = 0; k < kSlots; ++k) {
+    for (int k = 0; k < n_slots; ++k) {
       Slot& sl = slots[k];
       if (sl.members.empty()) continue;
       const hipError_t q = hipEventQuery(sl.ev);
       if (q == hipErrorNotReady) continue;
       auto ci = cinfo.find(sl.cls);
+      float ms = 0.f;
+      if (ci != cinfo.end() && q == hipSuccess && hipEventElapsedTime(&ms, sl.t0, sl.ev) == hipSuccess)
+        ci->second.ms = ci->second.ms < 0 ? ms : 0.7 * ci->second.ms + 0.3 * ms;
       if (ci != cinfo.end() && --ci->second.inflight <= 0 && ci->second.last < since(s) - 60.0) cinfo.erase(ci);
       for (size_t i = 0; i < sl.members.size(); ++i) {
         SrvReq* R = sl.members[i];
@@ -576,15 +592,18 @@ static void worker_main(mpwos_server* s) {
     }
     // Free slots go to the classes least recently served: those with fewer
     // launches in flight first, then the one whose last launch is oldest.  A
-    // launch prefers a stream with nothing in flight; otherwise it queues
-    // behind the stream's launch that was issued first.  Time slicing keeps
-    // launches short, so no class holds a stream for long.
+    // long class (launches above kLongMs) runs on the long streams only; a
+    // short one on the other streams, or on an idle long stream, never behind
+    // a long launch.  Among the streams allowed, an idle one first (for a
+    // short class an idle short stream before an idle long one), then the one
+    // whose launch in flight was issued first.
+    std::vector<char> skip(classes.size(), 0);
     for (;;) {
       int best = -1;
       for (size_t t = 0; t < classes.size(); ++t) {
         auto& c = classes[t];
         c.erase(std::remove_if(c.begin(), c.end(), [](SrvReq* R) { return walks_left(R) == 0; }), c.end());
-        if (c.empty()) continue;
+        if (c.empty() || skip[t]) continue;
         if (best < 0) {
           best = (int)t;
           continue;
@@ -594,24 +613,40 @@ static void worker_main(mpwos_server* s) {
         if (a.inflight < b.inflight || (a.inflight == b.inflight && a.last < b.last)) best = (int)t;
       }
       if (best < 0) break;
-      int k = -1;
-      double oldest = 1e300;
-      for (int j = 0; j < kSlots; ++j) {
-        if (!slots[j].members.empty()) continue;
-        const Slot& partner = slots[(j + kStreams) % kSlots];
-        if (partner.members.empty()) {
-          k = j;
-          break;
+      auto& c = classes[best];
+      const bool want_long = cinfo[c.front()->cls].ms > kLongMs;
+      int k = -1, best_rank = 3;
+      double best_issued = 1e300;
+      for (int sx = 0; sx < s->n_streams; ++sx) {
+        int free_slot = -1, busy = 0;
+        bool has_long = false;
+        double issued = 1e300;
+        for (int d = 0; d < kDepth; ++d) {
+          const Slot& sl = slots[sx + d * s->n_streams];
+          if (sl.members.empty()) {
+            if (free_slot < 0) free_slot = sx + d * s->n_streams;
+            continue;
+          }
+          busy += 1;
+          has_long = has_long || sl.is_long;
+          issued = std::min(issued, sl.issued);
         }
-        if (partner.issued < oldest) {
-          oldest = partner.issued;
-          k = j;
+        const bool long_stream = sx < s->n_long;
+        if (free_slot < 0 || (want_long && !long_stream) || (!want_long && (has_long || (long_stream && busy))))
+          continue;
+        const int rank = busy ? 2 : (long_stream == want_long ? 0 : 1);
+        if (rank < best_rank || (rank == best_rank && issued < best_issued)) {
+          best_rank = rank;
+          best_issued = issued;
+          k = free_slot;
         }
       }
-      if (k < 0) break;
-      auto& c = classes[best];
+      if (k < 0) {
+        skip[best] = 1;
+        continue;
+      }
       Slot& sl = slots[k];
-      mpwos_status ls = launch_batch(s, sl, c, s->streams[k % kStreams]);
+      mpwos_status ls = launch_batch(s, sl, c, s->streams[k % s->n_streams]);
       ClassInfo& ci = cinfo[c.front()->cls];
       ci.last = since(s);
       if (ls) {
@@ -626,6 +661,7 @@ static void worker_main(mpwos_server* s) {
       }
       sl.cls = c.front()->cls;
       sl.issued = ci.last;
+      sl.is_long = want_long;
       ci.inflight += 1;
       progress = true;
       std::lock_guard<std::mutex> lk(s->mu);
@@ -666,6 +702,7 @@ static void free_server(mpwos_server* s) {
   if (s->done_stream) (void)hipStreamSynchronize(s->done_stream);
   for (int k = 0; k < kSlots; ++k) {
     Slot& sl = s->slots[k];
+    if (sl.t0) (void)hipEventDestroy(sl.t0);
     if (sl.ev) (void)hipEventDestroy(sl.ev);
     if (sl.h_tab) (void)hipHostFree(sl.h_tab);
     if (sl.d_tab) (void)hipFree(sl.d_tab);
@@ -692,11 +729,22 @@ mpwos_status mpwos_server_create(size_t hbm_budget_bytes, int64_t slice_walk_ste
   hipError_t e = hipGetDevice(&s->device);
   hipDeviceProp_t prop;
   if (e == hipSuccess) e = hipGetDeviceProperties(&prop, s->device);
-  for (int i = 0; e == hipSuccess && i < kStreams; ++i) e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
+  // The runtime shares hardware queues between streams beyond
+  // GPU_MAX_HW_QUEUES (default 4), and kernels of streams that share a queue
+  // run one after another: the walk streams take what the null stream and
+  // the completion stream leave, two at least.
+  int hwq = 4;
+  if (const char* v = std::getenv("GPU_MAX_HW_QUEUES"))
+    if (std::atoi(v) > 0) hwq = std::atoi(v);
+  s->n_streams = std::max(2, std::min(kMaxStreams, hwq - 2));
+  s->n_long = std::max(1, s->n_streams / 2);
+  for (int i = 0; e == hipSuccess && i < s->n_streams; ++i)
+    e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->done_stream, hipStreamNonBlocking);
-  for (int k = 0; e == hipSuccess && k < kSlots; ++k) {
+  for (int k = 0; e == hipSuccess && k < s->n_streams * kDepth; ++k) {
     Slot& sl = s->slots[k];
-    e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+    e = hipEventCreateWithFlags(&sl.t0, hipEventDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_tab, kMaxBatch * sizeof(BatchEntry), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void**)&sl.d_tab, kMaxBatch * sizeof(BatchEntry));
     if (e == hipSuccess) e = hipMalloc((void**)&sl.d_queue, 256);
