@@ -352,12 +352,13 @@ def run_gpu(work, steps, warmup, precision, persistent, block_size=0, graph=Fals
         if it["plan"] is not None:
             kms = float(np.mean([s[i][0].elapsed_time(s[i][1]) for s in stats]))
             pst = it["plan"].stats(stream)
-            ws, k_mean = pst["walk_steps"], pst["k_mean"]
         else:
             kms = float(np.mean([s[i]["kernel_ms"] for s in stats]))
-            ws, k_mean = stats[0][i]["walk_steps"], stats[0][i]["k_mean"]
+            pst = stats[0][i]
+        ws = pst["walk_steps"]
         total_ws += ws
-        d = {"kernel_ms": kms, "walk_steps": ws, "k_mean": k_mean, "walk_steps_per_s": ws / (kms * 1e-3),
+        d = {"kernel_ms": kms, "walk_steps": ws, "k_mean": pst["k_mean"], "k_p50": pst.get("k_p50"),
+             "k_p99": pst.get("k_p99"), "k_max": pst.get("k_max"), "walk_steps_per_s": ws / (kms * 1e-3),
              "n_queries": int(it["q"].shape[0]), "n_walks": int(it["nw"]),
              "launch": {k: v for k, v in it["opt"].items() if k not in ("precision", "max_steps")}}
         if score:

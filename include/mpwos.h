@@ -194,6 +194,8 @@ typedef struct {
   double seconds;           /* wall time of the call */
   double kernel_ms;         /* device time of the walk kernel(s), HIP events on the solve stream */
   double reduce_ms;         /* device time of the per-query reduction */
+  int32_t k_p50;            /* median K^i (nearest rank); exact below 2048 steps, */
+  int32_t k_p99;            /* 99th percentile    above within 1/128 (rounded down) */
 } mpwos_stats;
 
 /* Fills `opt` with the defaults listed above. */

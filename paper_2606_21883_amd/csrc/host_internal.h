@@ -44,6 +44,14 @@ mpwos_status check_queries_host(const mpwos_manifold* man, const WalkArgs& a, co
 // distance to its FP64 projection and the local spacing there (2 doubles).
 hipError_t launch_cloud_check(const WalkArgs& a, const double* dq, double* out, int64_t nq, hipStream_t s);
 
+// khist.hip: histogram of the per-walk K^i (exact below kKHistExact, then
+// 128 bins per octave up to 2^31) and its nearest-rank p50 / p99
+constexpr int kKHistExact = 2048;
+constexpr int kKHistBins = kKHistExact + 20 * 128;
+hipError_t launch_khist(const int32_t* K, int64_t n, unsigned long long* hist, hipStream_t s);
+int32_t khist_lower(int bin);
+void khist_quantiles(const unsigned long long* hist, int32_t& p50, int32_t& p99);
+
 // walk_lane.hip
 hipError_t launch_walk_lane(const WalkArgs& a, int grid, int block, hipStream_t s);
 int lane_occupancy(const WalkArgs& a, int block);

@@ -58,7 +58,7 @@ struct Context {
   int n_cu = 256;
   hipStream_t stream = nullptr;
   hipEvent_t ev[4] = {};
-  DevBuf queries, walkS, walkK, u, se, stats, tmp;
+  DevBuf queries, walkS, walkK, u, se, stats, tmp, khist;
   bool ready = false;
 };
 
@@ -939,6 +939,14 @@ extern "C" mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_
   }
   unsigned long long* dstat = (unsigned long long*)g_ctx.stats.p;
   HIP_TRY(launch_zero_u64(dstat, 8, s));
+  // the K histogram, for the statistics only
+  unsigned long long* dhist = nullptr;
+  if (stats) {
+    st = ensure(g_ctx.khist, kKHistBins * sizeof(unsigned long long));
+    if (st) return st;
+    dhist = (unsigned long long*)g_ctx.khist.p;
+    HIP_TRY(launch_zero_u64(dhist, kKHistBins, s));
+  }
   double* du = (double*)g_ctx.u.p;
   double* dse = (double*)g_ctx.se.p;
   float kernel_ms = 0.f, reduce_ms = 0.f;
@@ -961,6 +969,7 @@ extern "C" mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_
     HIP_TRY(launch_reduce(wS, wK, nb, n_walks, o.max_steps, du + q0, dse + q0, dstat + 0, (int32_t*)(dstat + 1),
                           dstat + 2, s));
     HIP_TRY(hipEventRecord(g_ctx.ev[2], s));
+    if (dhist) HIP_TRY(launch_khist(wK, nb * n_walks, dhist, s));
     if (!o.device_io && o.walk_S)
       HIP_TRY(hipMemcpyAsync(o.walk_S + q0 * n_walks, wS, (size_t)nb * n_walks * sizeof(double), hipMemcpyDeviceToHost, s));
     if (!o.device_io && o.walk_K)
@@ -977,6 +986,8 @@ extern "C" mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_
   if (stderr_out) HIP_TRY(hipMemcpyAsync(stderr_out, dse, (size_t)n_queries * sizeof(double), dk, s));
   unsigned long long hs[8];
   HIP_TRY(hipMemcpyAsync(hs, dstat, sizeof(hs), hipMemcpyDeviceToHost, s));
+  std::vector<unsigned long long> hh(dhist ? kKHistBins : 0);
+  if (dhist) HIP_TRY(hipMemcpyAsync(hh.data(), dhist, hh.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const int64_t ksum = (int64_t)hs[0];
   const int32_t kmax = (int32_t)(uint32_t)hs[1];
@@ -988,6 +999,7 @@ extern "C" mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_
     stats->k_mean = (double)ksum / ((double)n_queries * (double)n_walks);
     stats->kernel_ms = kernel_ms;
     stats->reduce_ms = reduce_ms;
+    khist_quantiles(hh.data(), stats->k_p50, stats->k_p99);
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return ntr ? MPWOS_WTRUNC : MPWOS_OK;
@@ -999,6 +1011,7 @@ extern "C" mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_
 // One fixed array per device holds everything mpwos_solve would allocate:
 //   [0, 4 KiB)        statistics words and the persistent queue counter
 //   [4 KiB, 260 KiB)  the source family's values (at most 32768 doubles)
+//   [384 KiB, 420 KiB) the K histogram (when statistics are asked for)
 //   [512 KiB, 1 MiB)  one inverse radial table (at most 17 slices)
 //   [1 MiB, end)      per-walk scores and lengths of a batch of queries, the
 //                     discarded standard errors when stderr_out is NULL, or
@@ -1010,7 +1023,10 @@ static constexpr size_t kScratchBytes = (size_t)MPWOS_NOALLOC_SCRATCH_BYTES;
 static constexpr size_t kScratchValuesOff = 4096, kScratchValuesMax = 32768;
 static constexpr size_t kScratchTableOff = 512 * 1024, kScratchTableBytes = 512 * 1024;
 static constexpr size_t kScratchWalkOff = 1024 * 1024;
-static_assert(kScratchValuesOff + kScratchValuesMax * sizeof(double) <= kScratchTableOff, "scratch layout");
+static constexpr size_t kScratchHistOff = 384 * 1024;
+static_assert(kScratchValuesOff + kScratchValuesMax * sizeof(double) <= kScratchHistOff &&
+                  kScratchHistOff + kKHistBins * sizeof(unsigned long long) <= kScratchTableOff,
+              "scratch layout");
 static_assert(kScratchTableOff + kScratchTableBytes <= kScratchWalkOff && kScratchWalkOff < kScratchBytes,
               "scratch layout");
 
@@ -1113,6 +1129,8 @@ extern "C" mpwos_status mpwos_solve_noalloc(const mpwos_manifold* manifold, cons
 
   unsigned long long* dstat = (unsigned long long*)base;
   HIP_TRY(launch_zero_u64(dstat, 8, s));
+  unsigned long long* dhist = stats ? (unsigned long long*)(base + kScratchHistOff) : nullptr;
+  if (dhist) HIP_TRY(launch_zero_u64(dhist, kKHistBins, s));
   double* wS = user_walk ? o.walk_S : (double*)(base + kScratchWalkOff);
   int32_t* wK = user_walk ? o.walk_K : (int32_t*)(base + kScratchWalkOff + (size_t)qb * n_walks * sizeof(double));
   double* se_discard =
@@ -1131,9 +1149,12 @@ extern "C" mpwos_status mpwos_solve_noalloc(const mpwos_manifold* manifold, cons
     if (st) return st;
     HIP_TRY(launch_reduce(a.walk_S, a.walk_K, nb, n_walks, o.max_steps, u_out + q0,
                           stderr_out ? stderr_out + q0 : se_discard, dstat + 0, (int32_t*)(dstat + 1), dstat + 2, s));
+    if (dhist) HIP_TRY(launch_khist(a.walk_K, nb * n_walks, dhist, s));
   }
   unsigned long long hs[8];
+  unsigned long long hh[kKHistBins];
   HIP_TRY(hipMemcpyAsync(hs, dstat, sizeof(hs), hipMemcpyDeviceToHost, s));
+  if (dhist) HIP_TRY(hipMemcpyAsync(hh, dhist, sizeof(hh), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const int64_t ntr = (int64_t)hs[2];
   if (stats) {
@@ -1143,6 +1164,7 @@ extern "C" mpwos_status mpwos_solve_noalloc(const mpwos_manifold* manifold, cons
     stats->k_mean = (double)hs[0] / ((double)n_queries * (double)n_walks);
     stats->kernel_ms = 0.0;
     stats->reduce_ms = 0.0;
+    khist_quantiles(hh, stats->k_p50, stats->k_p99);
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return ntr ? MPWOS_WTRUNC : MPWOS_OK;

@@ -34,6 +34,7 @@ struct mpwos_plan {
   double* d_u = nullptr;
   double* d_se = nullptr;
   unsigned long long* d_stats = nullptr;  // ksum, kmax, ntrunc, (unused), queue, seed
+  unsigned long long* d_hist = nullptr;   // K histogram, filled by mpwos_plan_stats
   double* d_table = nullptr;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -89,7 +90,7 @@ extern "C" mpwos_status mpwos_plan_create(const mpwos_manifold* manifold, const 
   const bool table = fn_has_values(f->kind);
   size_t bytes = align256((size_t)n_queries * p->n * sizeof(double)) + align256((size_t)total * sizeof(double)) +
                  align256((size_t)total * sizeof(int32_t)) + 2 * align256((size_t)n_queries * sizeof(double)) +
-                 align256(8 * sizeof(unsigned long long)) +
+                 align256(8 * sizeof(unsigned long long)) + align256(kKHistBins * sizeof(unsigned long long)) +
                  (table ? align256((size_t)f->n_values * sizeof(double)) : 0);
   hipError_t e = hipMalloc((void**)&p->dev, bytes);
   if (e != hipSuccess) {
@@ -106,6 +107,7 @@ extern "C" mpwos_status mpwos_plan_create(const mpwos_manifold* manifold, const 
   p->d_u = (double*)take((size_t)n_queries * sizeof(double));
   p->d_se = (double*)take((size_t)n_queries * sizeof(double));
   p->d_stats = (unsigned long long*)take(8 * sizeof(unsigned long long));
+  p->d_hist = (unsigned long long*)take(kKHistBins * sizeof(unsigned long long));
   if (table) p->d_table = (double*)take((size_t)f->n_values * sizeof(double));
   e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
   if (e == hipSuccess && table)
@@ -175,6 +177,14 @@ extern "C" mpwos_status mpwos_plan_stats(mpwos_plan* p, void* stream, mpwos_stat
   stats->k_max = (int32_t)(uint32_t)hs[1];
   stats->truncated = (int64_t)hs[2];
   stats->k_mean = (double)hs[0] / ((double)p->nq * (double)p->nw);
+  // K quantiles of the last execution, from the per-walk K it left
+  std::vector<unsigned long long> hh(kKHistBins);
+  e = launch_zero_u64(p->d_hist, kKHistBins, s);
+  if (e == hipSuccess) e = launch_khist(p->d_K, p->nq * p->nw, p->d_hist, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(hh.data(), p->d_hist, hh.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "plan: K histogram");
+  khist_quantiles(hh.data(), stats->k_p50, stats->k_p99);
   return hs[2] ? MPWOS_WTRUNC : MPWOS_OK;
 }
 

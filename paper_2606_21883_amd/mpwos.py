@@ -57,7 +57,7 @@ class Options(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("walk_steps", ctypes.c_int64), ("truncated", ctypes.c_int64), ("k_max", ctypes.c_int32),
                 ("k_mean", ctypes.c_double), ("seconds", ctypes.c_double), ("kernel_ms", ctypes.c_double),
-                ("reduce_ms", ctypes.c_double)]
+                ("reduce_ms", ctypes.c_double), ("k_p50", ctypes.c_int32), ("k_p99", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):

@@ -53,6 +53,7 @@ int main(void) {
   O(mpwos_fn, values) O(mpwos_fn, n_values) O(mpwos_manifold_desc, points) O(mpwos_manifold_desc, k_nn)
   O(mpwos_manifold_desc, fit_scale)
   O(mpwos_request, opt) O(mpwos_request, u_out) O(mpwos_request, seed) O(mpwos_stats, kernel_ms)
+  O(mpwos_stats, k_p50) O(mpwos_stats, k_p99)
   return 0;
 }
 """
@@ -81,7 +82,8 @@ def test_struct_layouts_match_header(tmp_path):
         "mpwos_manifold_desc.k_nn": (m.ManifoldDesc, "k_nn"), "mpwos_request.opt": (m.Request, "opt"),
         "mpwos_manifold_desc.fit_scale": (m.ManifoldDesc, "fit_scale"),
         "mpwos_request.u_out": (m.Request, "u_out"), "mpwos_request.seed": (m.Request, "seed"),
-        "mpwos_stats.kernel_ms": (m.Stats, "kernel_ms"),
+        "mpwos_stats.kernel_ms": (m.Stats, "kernel_ms"), "mpwos_stats.k_p50": (m.Stats, "k_p50"),
+        "mpwos_stats.k_p99": (m.Stats, "k_p99"),
     }.items():
         assert got[key] == getattr(cls, field).offset, key
 

@@ -273,6 +273,32 @@ def test_edge_sizes():
     assert g["stderr"][0] == 0.0
 
 
+def _k_quantile(K, q):
+    """Nearest-rank quantile of the walk lengths, rounded down to the
+    statistics' resolution: exact below 2048, the top eight bits above."""
+    ks = np.sort(np.asarray(K, dtype=np.int64).ravel())
+    k = int(ks[max(1, -(-int(round(q * 100)) * len(ks) // 100)) - 1])
+    if k < 2048:
+        return k
+    drop = k.bit_length() - 8
+    return (k >> drop) << drop
+
+
+@pytest.mark.parametrize("name", ["cap", "torus", "hyper100"])
+def test_k_quantiles_match_walk_lengths(name):
+    # the cap and the torus: lengths below 2048 (exact bins); S^99 at its
+    # tau_W: about 11000 steps (binned), in two query batches
+    prob, Q, nw = inputs.config(name, scale=0.02)
+    announce(f"k quantiles {name} {len(Q)}x{nw}")
+    g = mpwos.solve(prob, Q, nw, 4, walk_outputs=True, precision="fp32", persistent=1)
+    K = g["walk_K"]
+    assert g["stats"]["k_max"] == int(K.max())
+    assert g["stats"]["k_p50"] == _k_quantile(K, 0.5), (g["stats"]["k_p50"], np.median(K))
+    assert g["stats"]["k_p99"] == _k_quantile(K, 0.99), (g["stats"]["k_p99"], np.percentile(K, 99))
+    if name == "hyper100":
+        assert g["stats"]["k_p50"] >= 2048
+
+
 def test_query_in_boundary_layer_and_truncation():
     prob = inputs.cap_problem(eps=1e-3)
     y = np.array([[math.cos(1e-4) * 0.6, math.cos(1e-4) * 0.8, math.sin(1e-4)]])

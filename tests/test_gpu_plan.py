@@ -46,6 +46,7 @@ def test_plan_replays_equal_eager_solves(name, opt):
         assert np.array_equal(u.cpu().numpy(), eager["u"]), (name, seed)
         assert np.array_equal(se.cpu().numpy(), eager["stderr"])
         assert pst["walk_steps"] == eager["stats"]["walk_steps"]
+        assert (pst["k_p50"], pst["k_p99"]) == (eager["stats"]["k_p50"], eager["stats"]["k_p99"])
         # unrelated eager work on the same stream between replays
         torch.ones(1 << 20, device="cuda").sum().item()
     plan.close()

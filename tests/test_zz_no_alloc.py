@@ -51,6 +51,7 @@ def test_noalloc_equals_solve_on_two_calls():
     assert np.array_equal(a["u"], ra["u"]) and np.array_equal(a["stderr"], ra["stderr"])
     assert a["stats"]["walk_steps"] == ra["stats"]["walk_steps"]
     assert a["stats"]["k_max"] == ra["stats"]["k_max"]
+    assert (a["stats"]["k_p50"], a["stats"]["k_p99"]) == (ra["stats"]["k_p50"], ra["stats"]["k_p99"])
     assert np.array_equal(b["u"], rb["u"])
     assert np.array_equal(b["walk_S"], rb["walk_S"]) and np.array_equal(b["walk_K"], rb["walk_K"])
     assert b["stats"]["walk_steps"] == rb["stats"]["walk_steps"]
