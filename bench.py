@@ -67,12 +67,25 @@ SLOT_WEIGHTS = {"f32": 1.0, "bitop3_b32": 1.53, "f64": 1.72, "trans": 3.06, "mad
 KERNEL_SOURCES = ["walk_lane.hip", "walk_group.hip", "walk_group_dev.h", "walk_group_sphere.hip", "mpwos_dev.h",
                   "kernel_args.h", "cloud_dev.h", "cloud.hip"]
 
-# Per-kernel figures from rocprofv3 counters (profiles/walk_kernels_counters.txt),
-# per walk-step of the benchmark's launches: VALU and SALU lane-instructions
-# (wave instructions x 64 / walk-steps) and the HBM bytes per launch from
-# FETCH_SIZE x 2 + WRITE_SIZE x 1 (KiB), the factors read off a plain copy
-# kernel of known size (profiles/copy_kernel_hbm_probe.txt).
-PROFILED = {"kernel_sha256": None, "kernels": {}}
+# Per-kernel figures from rocprofv3 counters (profiles/walk_kernels_all_configs_counters.txt),
+# per walk-step of the benchmark's launches in the launch shape given: VALU and
+# SALU lane-instructions (wave instructions x 64 / walk-steps) and the counted
+# FETCH_SIZE and WRITE_SIZE (KiB per launch); HBM bytes = FETCH_SIZE x 2 +
+# WRITE_SIZE x 1, the factors read off a plain copy kernel of known size
+# (profiles/copy_kernel_hbm_probe.txt).  They apply to a run only when the
+# kernel sources hash to kernel_sha256 and the launch shape is the same.
+PROFILED = {
+    "kernel_sha256": "41e3bf265e5d588a712853fbb658501d721dade0c9534a12320b06dab0eef354",
+    "kernels": {
+        "sphere": {"valu_per_walk_step": 161.45, "salu_per_walk_step": 31.28, "walk_steps": 2919235584, "fetch_kib": 468.5, "write_kib": 196608.0, "launch": {"persistent": 0, "block_size": 256}},
+        "cap": {"valu_per_walk_step": 320.68, "salu_per_walk_step": 115.64, "walk_steps": 478364826, "fetch_kib": 985.0, "write_kib": 287678.7, "launch": {"persistent": 1, "block_size": 256}},
+        "circle": {"valu_per_walk_step": 157.28, "salu_per_walk_step": 30.34, "walk_steps": 14848000, "fetch_kib": 91.2, "write_kib": 750.0, "launch": {"persistent": 0, "block_size": 0}},
+        "hyper100": {"valu_per_walk_step": 6915.67, "salu_per_walk_step": 897.24, "walk_steps": 2097152000, "fetch_kib": 3350.0, "write_kib": 24576.0, "launch": {"persistent": 0, "block_size": 0}},
+        "hyper1000": {"valu_per_walk_step": 56219.84, "salu_per_walk_step": 7217.6, "walk_steps": 419430400, "fetch_kib": 32156.2, "write_kib": 32768.0, "launch": {"persistent": 0, "block_size": 0}},
+        "torus": {"valu_per_walk_step": 520.53, "salu_per_walk_step": 68.97, "walk_steps": 13430161408, "fetch_kib": 843.8, "write_kib": 98304.0, "launch": {"persistent": 0, "block_size": 0}},
+        "cloud": {"valu_per_walk_step": 24487.33, "salu_per_walk_step": 26661.57, "walk_steps": 536870912, "fetch_kib": 1411424000.1, "write_kib": 99219.2, "launch": {"persistent": 1, "block_size": 0}},
+    },
+}
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
@@ -180,7 +193,7 @@ def roofline_alu(name, kind, n, n_v, walk_steps, kernel_ms, launch, precision="f
            "launch_walk_steps": int(walk_steps), "launch_ms": kernel_ms,
            "ops_per_walk_step": ops, "slots_per_walk_step": slots, "slot_weights": SLOT_WEIGHTS,
            "fp32_flop_frac": fp32_flops(ops) * walk_steps / secs / PEAK_FP32_FLOPS}
-    prof = profiled(name)
+    prof = profiled(name, launch)
     if prof:
         out["valu_issue_frac"] = prof["valu_per_walk_step"] * walk_steps / secs / PEAK_SLOTS
         out["valu_per_walk_step_counted"] = prof["valu_per_walk_step"]
@@ -206,17 +219,21 @@ def roofline_cloud(name, n_queries, n_walks, walk_steps, kernel_ms, launch):
            "algorithmic_bytes_per_walk_step": per_step, "launch_walk_steps": int(walk_steps),
            "launch_ms": kernel_ms,
            "note": "latency-bound: each projection is a depth-first KD-tree nearest-point search"}
-    prof = profiled(name)
+    prof = profiled(name, launch)
     if prof and prof.get("walk_steps") == walk_steps and "fetch_kib" in prof:
         out["traffic"] = 1024 * (prof["fetch_kib"] * FETCH_FACTOR + prof["write_kib"] * WRITE_FACTOR)
         out["traffic_unit"] = "HBM bytes per launch"
     return out
 
 
-def profiled(name):
+def profiled(name, launch=None):
     if PROFILED.get("kernel_sha256") != kernel_sha256():
         return None
-    return PROFILED["kernels"].get(name)
+    prof = PROFILED["kernels"].get(name)
+    if prof is None or launch is None:
+        return prof
+    shape = {k: launch.get(k, 0) for k in ("persistent", "block_size")}
+    return prof if shape == prof["launch"] else None
 
 
 def valu_weights_live():

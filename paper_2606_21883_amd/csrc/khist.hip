@@ -24,14 +24,45 @@ __device__ __forceinline__ int khist_bin(int32_t k) {
   return kKHistExact + (e - 11) * 128 + sub;
 }
 
+// Each lane counts a run of equal bins in registers and adds it to LDS when
+// the bin changes: walk lengths are often concentrated (a constant-radius
+// walk stopped by tau_W has one length), and one LDS address taking every
+// lane's atomic would serialise the pass.
 __global__ void __launch_bounds__(kHistBlock) khist_kernel(const int32_t* __restrict__ K, int64_t n,
                                                             unsigned long long* __restrict__ hist) {
   __shared__ uint32_t h[kKHistBins];
   for (int i = threadIdx.x; i < kKHistBins; i += kHistBlock) h[i] = 0u;
   __syncthreads();
+  int bin = 0;
+  uint32_t run = 0;
+  auto put = [&](int32_t k) {
+    const int b = khist_bin(k);
+    if (b == bin) {
+      ++run;
+    } else {
+      if (run) atomicAdd(&h[bin], run);
+      bin = b;
+      run = 1;
+    }
+  };
   const int64_t stride = (int64_t)gridDim.x * kHistBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kHistBlock + threadIdx.x; i < n; i += stride)
-    atomicAdd(&h[khist_bin(K[i])], 1u);
+  const int64_t t0 = (int64_t)blockIdx.x * kHistBlock + threadIdx.x;
+  if (((uintptr_t)K & 15) == 0) {
+    // four lengths per 16-byte load, then the tail
+    const int4* K4 = (const int4*)K;
+    const int64_t n4 = n / 4;
+    for (int64_t i = t0; i < n4; i += stride) {
+      const int4 v = K4[i];
+      put(v.x);
+      put(v.y);
+      put(v.z);
+      put(v.w);
+    }
+    for (int64_t i = n4 * 4 + t0; i < n; i += stride) put(K[i]);
+  } else {
+    for (int64_t i = t0; i < n; i += stride) put(K[i]);
+  }
+  if (run) atomicAdd(&h[bin], run);
   __syncthreads();
   for (int i = threadIdx.x; i < kKHistBins; i += kHistBlock)
     if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);

@@ -49,13 +49,18 @@ def test_roofline_objects_and_counter_gate():
     try:
         bench.PROFILED["kernel_sha256"] = "0" * 64
         bench.PROFILED["kernels"] = {"sphere": {"valu_per_walk_step": 161.0, "walk_steps": 2_919_235_584,
-                                                "fetch_kib": 456.0, "write_kib": 196608.0}}
-        r = bench.roofline_alu("sphere", "sphere", 3, 1, 2_919_235_584, 10.0, {"persistent": 0})
+                                                "fetch_kib": 456.0, "write_kib": 196608.0,
+                                                "launch": {"persistent": 0, "block_size": 256}}}
+        plain = {"persistent": 0, "block_size": 256, "lanes_per_walk": 1}
+        r = bench.roofline_alu("sphere", "sphere", 3, 1, 2_919_235_584, 10.0, plain)
         assert r["traffic"] is None and "valu_issue_frac" not in r
         bench.PROFILED["kernel_sha256"] = bench.kernel_sha256()
-        r = bench.roofline_alu("sphere", "sphere", 3, 1, 2_919_235_584, 10.0, {"persistent": 0})
+        r = bench.roofline_alu("sphere", "sphere", 3, 1, 2_919_235_584, 10.0, plain)
         assert r["traffic"] == pytest.approx(1024 * (456.0 * 2.0 + 196608.0))
         assert r["valu_issue_frac"] == pytest.approx(161.0 * 2_919_235_584 / 0.010 / bench.PEAK_SLOTS)
+        # ... and to the launch shape they were taken in
+        r = bench.roofline_alu("sphere", "sphere", 3, 1, 2_919_235_584, 10.0, {"persistent": 1, "block_size": 256})
+        assert r["traffic"] is None and "valu_issue_frac" not in r
     finally:
         bench.PROFILED.clear()
         bench.PROFILED.update(saved)
