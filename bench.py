@@ -42,11 +42,14 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 # The server runs its launches on GPU_MAX_HW_QUEUES - 2 streams (two at
-# least); the runtime reads the variable when it starts, so it is set before
-# anything touches the device.  Eight hardware queues give the served mix three
-# streams for its long classes and three for the rest; one-stream legs are
-# unaffected.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# least); the runtime reads the variable when it starts, so it is raised here,
+# before anything touches the device, to eight when it is lower (HIP's default
+# is four).  Eight hardware queues give the served mix three streams for its
+# long classes (point cloud, dumbbell, S^99) and three for the rest; with four,
+# the long classes share one stream and queue behind each other.  One-stream
+# legs are unaffected.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 METRIC = "walk-steps/s and queries/s at fixed RMSE vs FP64 oracle; served p50/p99 ms"
 # Full-rate VALU lane-operations per second: 256 CUs x 128 FP32 FMA lanes per
@@ -73,7 +76,7 @@ KERNEL_SOURCES = ["walk_lane.hip", "walk_group.hip", "walk_group_dev.h", "walk_g
 # FETCH_SIZE and WRITE_SIZE (KiB per launch); HBM bytes = FETCH_SIZE x 2 +
 # WRITE_SIZE x 1, the factors read off a plain copy kernel of known size
 # (profiles/copy_kernel_hbm_probe.txt).  They apply to a run only when the
-# kernel sources hash to kernel_sha256 and the launch shape is the same.
+# kernel sources hash to kernel_sha256 and the launch has the same form.
 PROFILED = {
     "kernel_sha256": "41e3bf265e5d588a712853fbb658501d721dade0c9534a12320b06dab0eef354",
     "kernels": {
@@ -195,6 +198,7 @@ def roofline_alu(name, kind, n, n_v, walk_steps, kernel_ms, launch, precision="f
            "fp32_flop_frac": fp32_flops(ops) * walk_steps / secs / PEAK_FP32_FLOPS}
     prof = profiled(name, launch)
     if prof:
+        out["counted_launch"] = prof["launch"]
         out["valu_issue_frac"] = prof["valu_per_walk_step"] * walk_steps / secs / PEAK_SLOTS
         out["valu_per_walk_step_counted"] = prof["valu_per_walk_step"]
         if prof.get("walk_steps") == walk_steps and "fetch_kib" in prof:
@@ -232,8 +236,9 @@ def profiled(name, launch=None):
     prof = PROFILED["kernels"].get(name)
     if prof is None or launch is None:
         return prof
-    shape = {k: launch.get(k, 0) for k in ("persistent", "block_size")}
-    return prof if shape == prof["launch"] else None
+    # the same form (plain or persistent); the workgroup size the autotuner
+    # picks moves the counts per walk-step by little
+    return prof if launch.get("persistent", 0) == prof["launch"]["persistent"] else None
 
 
 def valu_weights_live():
@@ -690,6 +695,7 @@ def served_mix(rate=200.0, window=30.0, seed=2, ms_range=(0.02, 20.0), q_range=(
     # (the cloud against u at the query's projection, with 0.02 for the
     # reconstruction; the dumbbell, whose m = 0 leaves a bias, is not scored)
     ok, nqs, zs = 0, 0, []
+    rmses = {}
     for (ta, name, Q, nw, sd), o in zip(reqs, outs):
         if name == "dumbbell":
             continue
@@ -700,6 +706,7 @@ def served_mix(rate=200.0, window=30.0, seed=2, ms_range=(0.02, 20.0), q_range=(
         ok += int(np.sum(err <= tol))
         nqs += len(Q)
         zs.extend((err / np.maximum(o["stderr"], 1e-300)).tolist())
+        rmses.setdefault(name, []).append(float(np.sqrt(np.mean(err ** 2))))
     res = {"rate_req_per_s": rate, "window_s": window, "requests": len(reqs),
            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
            "drain_s": max(0.0, wall - window), "backlog_growth": backlog_growth(reqs, lat),
@@ -708,7 +715,10 @@ def served_mix(rate=200.0, window=30.0, seed=2, ms_range=(0.02, 20.0), q_range=(
            "slots_busy_s": st["busy_seconds"], "wall_s": wall,
            "gpu_max_hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
            "closed_form_check": {"queries": nqs, "within_4se_plus_bias": ok / max(1, nqs),
-                                 "median_abs_z": float(np.median(zs)) if zs else None},
+                                 "median_abs_z": float(np.median(zs)) if zs else None,
+                                 "request_rmse": {k: {"median": float(np.median(v)), "max": float(np.max(v)),
+                                                      "within_1e-2": float(np.mean(np.array(v) <= 1e-2))}
+                                                  for k, v in rmses.items()}},
            "by_manifold": {}}
     phases = {"admit": (0, 1), "start": (1, 2), "walks": (2, 3), "deliver": (3, 4)}
     for name in kinds:
@@ -783,7 +793,7 @@ def backlog_growth(reqs, lat):
     return worst
 
 
-def served_sweep(rates, window=10.0):
+def served_sweep(rates, window=20.0):
     """The served mix at several arrival rates (no per-solve runs).  A rate is
     stable when no manifold's median latency grows by more than a fifth from
     the first third of the arrivals to the last (backlog_growth <= 1.2) and
@@ -878,8 +888,8 @@ def main():
     ap.add_argument("--valu-probe", action="store_true", help="print the VALU operation rates and exit")
     ap.add_argument("--no-served", action="store_true", help="skip the served-mix leg")
     ap.add_argument("--served-window", type=float, default=30.0, help="seconds of arrivals at 200 req/s")
-    ap.add_argument("--served-rates", default="100,400",
-                    help="arrival rates (req/s) of the served sweep besides 200; empty to skip")
+    ap.add_argument("--served-rates", default="100,200,300,400",
+                    help="arrival rates (req/s) of the served sweep, 20 s windows; empty to skip")
     ap.add_argument("--served-only", action="store_true", help="run only the served-mix leg and print it")
     ap.add_argument("--compensation-sweep", default="", metavar="N1,N2,...",
                     help="Example 1: RMSE against the closed form of the baseline, second-order and exact "

@@ -71,6 +71,25 @@ def test_fp64_hypersphere_n1000_matches_oracle():
     compare_walks(g, o, prob)
 
 
+def test_fp64_hypersphere_n100_full_threshold_matches_oracle():
+    # the S^99 configuration's own tau_W = 1e-8: 11340 steps per walk
+    prob = inputs.hypersphere_problem(100)
+    Q = inputs.hypersphere_queries(4, 100, seed=2)
+    g, o = run_both(prob, Q, 4, seed=3)
+    assert int(o["walk_K"].min()) == 11340
+    compare_walks(g, o, prob)
+
+
+def test_fp64_hypersphere_n1000_long_walks_match_oracle():
+    # tau_W = 1e-2: 28349 steps per walk at n = 1000 (the oracle takes about
+    # 8 s per walk here)
+    prob = dict(inputs.hypersphere_problem(1000), tau_w=1e-2)
+    Q = inputs.hypersphere_queries(2, 1000, seed=2)
+    g, o = run_both(prob, Q, 2, seed=3)
+    assert int(o["walk_K"].min()) == 28349
+    compare_walks(g, o, prob)
+
+
 def test_fp64_odd_dimension_and_lane_groups():
     prob = dict(inputs.hypersphere_problem(7), tau_w=1e-4)
     Q = inputs.sphere_uniform(9, 7, seed=5)
