@@ -43,6 +43,12 @@ struct CloudState {
   int64_t fallback_points = 0;
   int32_t nn_only = 0;
   float4* pts = nullptr;       // nn_only: the points by original index (kept from the build)
+  // the walk grid (patch reconstruction only)
+  int32_t* g_start = nullptr;
+  float4* g_pts = nullptr;
+  int32_t g_n[3] = {0, 0, 0};
+  double g_lo[3] = {0, 0, 0};
+  double g_h = 0.0, g_slack = 0.0;
 };
 
 struct GridArgs {
@@ -660,6 +666,39 @@ mpwos_status cloud_create(const mpwos_manifold_desc& d, hipStream_t s, CloudStat
   int4* d_tiles = upload(tiles, e);
   C->nodes = upload(kd.nodes, e);
   C->kd_pts = upload(kdp, e);
+  // The walk grid of the patch reconstruction: cells with about three points
+  // each where the surface crosses them (the build grid's cells hold about
+  // k), so a near-surface lookup scans a few dozen points; at most 2^25
+  // cells.  Points are binned in FP64 as the device locates a query.
+  if (e == hipSuccess && d.reconstruction == 0) {
+    double hw = h * std::min(1.0, std::sqrt(3.0 / (double)std::max(k, 1)));
+    auto wcells = [&](int c) { return std::floor(((double)hi[c] - (double)lo[c]) / hw) + 1.0; };
+    while (wcells(0) * wcells(1) * wcells(2) > (double)(1 << 25)) hw *= 1.25;
+    const int wn[3] = {(int)wcells(0), (int)wcells(1), (int)wcells(2)};
+    const int64_t ncw = (int64_t)wn[0] * wn[1] * wn[2];
+    std::vector<int32_t> wcell((size_t)n), wstart((size_t)ncw + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+      int64_t cc[3];
+      for (int c = 0; c < 3; ++c)
+        cc[c] = std::min<int64_t>(wn[c] - 1, (int64_t)(((double)P[3 * i + c] - (double)lo[c]) / hw));
+      wcell[i] = (int32_t)((cc[2] * wn[1] + cc[1]) * wn[0] + cc[0]);
+      wstart[wcell[i] + 1] += 1;
+    }
+    for (int64_t c = 0; c < ncw; ++c) wstart[c + 1] += wstart[c];
+    std::vector<int32_t> fill(wstart.begin(), wstart.end() - 1);
+    std::vector<float4> wpts((size_t)n);
+    for (int64_t i = 0; i < n; ++i) wpts[fill[wcell[i]]++] = orig[i];
+    C->g_start = upload(wstart, e);
+    C->g_pts = upload(wpts, e);
+    double amax = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      C->g_n[c] = wn[c];
+      C->g_lo[c] = (double)lo[c];
+      amax = std::max({amax, std::fabs((double)lo[c]), std::fabs((double)hi[c])});
+    }
+    C->g_h = hw;
+    C->g_slack = 1e-6 * hw + 1e-12 * amax;
+  }
   int32_t* d_knn = nullptr;
   uint8_t* d_flag = nullptr;
   if (e == hipSuccess) e = hipMalloc((void**)&d_knn, (size_t)n * k * sizeof(int32_t));
@@ -728,7 +767,8 @@ mpwos_status cloud_create(const mpwos_manifold_desc& d, hipStream_t s, CloudStat
 
 void cloud_destroy(CloudState* c) {
   if (!c) return;
-  for (void* p : {(void*)c->nodes, (void*)c->kd_pts, (void*)c->patch64, (void*)c->patch32, (void*)c->pts})
+  for (void* p : {(void*)c->nodes, (void*)c->kd_pts, (void*)c->patch64, (void*)c->patch32, (void*)c->pts,
+                  (void*)c->g_start, (void*)c->g_pts})
     if (p) (void)hipFree(p);
   delete c;
 }
@@ -748,6 +788,15 @@ void cloud_fill_args(const CloudState* c, const mpwos_options& o, WalkArgs& a) {
   a.cloud.radius_rule = o.radius_rule == MPWOS_RADIUS_SPACING ? 1 : 0;
   a.cloud.nn_only = c->nn_only;
   a.cloud.pts = c->pts;
+  a.cloud.g_start = c->g_start;
+  a.cloud.g_pts = c->g_pts;
+  for (int d = 0; d < 3; ++d) {
+    a.cloud.g_n[d] = c->g_n[d];
+    a.cloud.g_lo[d] = c->g_lo[d];
+  }
+  a.cloud.g_h = c->g_h;
+  a.cloud.g_inv = c->g_h > 0.0 ? 1.0 / c->g_h : 0.0;
+  a.cloud.g_slack = c->g_slack;
 }
 
 int cloud_nn_only(const CloudState* c) { return c->nn_only; }

@@ -3,7 +3,8 @@
 // point of x on the local quadratic patch (built once per manifold) of the
 // cloud point nearest to that foot point: a fixed point found from a start
 // patch by alternating the foot point on the current patch and the nearest
-// cloud point of the foot (KD-tree search, ties to the lower original index),
+// cloud point of the foot (ties to the lower original index; a grid of small
+// cells answers when it can show the answer exact, else a KD-tree search),
 // at most kCloudRounds times.  The start patch is that of the cloud point
 // nearest to x for a query, and for a walk point x near the walker's Y the
 // one nearest to x's foot on the osculating quadratic of Y's patch (not
@@ -123,6 +124,84 @@ __device__ __forceinline__ int32_t kd_nearest(const CloudDev& c, const T* x) {
   return (uint32_t)bidx < (uint32_t)c.n_points ? bidx : 0;
 }
 
+// Nearest cloud point of x from the walk grid, or -1 when the grid cannot
+// show its answer exact.  The 3x3x3 block of cells around x's cell is
+// scanned plane by plane: three rows of three cells, each row one contiguous
+// run of points whose six bounds are loaded before any point, the points
+// eight at a time (independent loads, one latency per batch).  The answer (ties to the lower original index) is accepted when its
+// distance lies below the distance from x to the block's boundary less the
+// binning allowance, with a relative margin far above the rounding of a
+// squared distance: every point outside the block is then farther, so the
+// block's minimum is the global one, the KD-tree's answer.  A side of the
+// block at the grid's edge has no points beyond it.
+template <class T>
+__device__ __forceinline__ int32_t grid_nearest(const CloudDev& c, const T* x) {
+  constexpr int W = 8;         // points loaded together
+  if (!c.g_start) return -1;
+  double g[3];
+  int ic[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    g[d] = ((double)x[d] - c.g_lo[d]) * c.g_inv;
+    // outside the grid, or not finite
+    if (!(g[d] >= 0.0 && g[d] < (double)c.g_n[d])) return -1;
+    ic[d] = (int)g[d];
+  }
+  const int nx = c.g_n[0], ny = c.g_n[1], nz = c.g_n[2];
+  const int x0 = ic[0] > 0 ? ic[0] - 1 : 0, x1 = ic[0] + 1 < nx ? ic[0] + 1 : nx - 1;
+  T best = (T)3.0e38;
+  int32_t bidx = 0x7fffffff;
+#pragma unroll
+  for (int pz = 0; pz < 3; ++pz) {
+    int32_t rs[3], re[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int yy = ic[1] + r - 1, zz = ic[2] + pz - 1;
+      const bool in = yy >= 0 && yy < ny && zz >= 0 && zz < nz;
+      const int64_t row = ((int64_t)(in ? zz : 0) * ny + (in ? yy : 0)) * nx;
+      const int32_t a = c.g_start[row + x0], b = c.g_start[row + x1 + 1];
+      rs[r] = in ? a : 0;
+      re[r] = in ? b : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int32_t e = re[r];
+      for (int32_t i = rs[r]; i < e; i += W) {
+        float4 q[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) q[j] = c.g_pts[i + j < e ? i + j : e - 1];
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+          const T d2 = dist2_exact(x, q[j].x, q[j].y, q[j].z);
+          const int32_t id = __float_as_int(q[j].w);
+          if (d2 < best || (d2 == best && id < bidx)) {
+            best = d2;
+            bidx = id;
+          }
+        }
+      }
+    }
+  }
+  if (bidx == 0x7fffffff) return -1;
+  double m = 3.0e300;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (ic[d] >= 1) m = fmin(m, (g[d] - (double)(ic[d] - 1)) * c.g_h);
+    if (ic[d] + 2 <= c.g_n[d]) m = fmin(m, ((double)(ic[d] + 2) - g[d]) * c.g_h);
+  }
+  m -= c.g_slack;
+  if (m > 0.0 && (double)best < m * m * (1.0 - 1e-5)) return bidx;
+  return -1;
+}
+
+// Nearest cloud point of a point near the surface: the walk grid, else the
+// KD-tree (the same answer either way).
+template <class T>
+__device__ __forceinline__ int32_t near_surface_nearest(const CloudDev& c, const T* x) {
+  const int32_t g = grid_nearest<T>(c, x);
+  return g >= 0 ? g : kd_nearest<T>(c, x);
+}
+
 template <class T>
 struct CloudProj {
   T y[3];
@@ -218,16 +297,16 @@ __device__ __forceinline__ CloudProj<T> cloud_cp(const CloudDev& c, const T* x, 
   }
   int32_t p;
   if (start < 0) {
-    p = kd_nearest<T>(c, x);
+    p = near_surface_nearest<T>(c, x);
   } else {
     const CloudProj<T> y0 = patch_project<T>(patch_of<T>(c, start), x, c.newton_iters, false);
-    p = kd_nearest<T>(c, y0.y);
+    p = near_surface_nearest<T>(c, y0.y);
   }
   CloudProj<T> r;
   for (int j = 0; j < kCloudRounds; ++j) {
     r = patch_project<T>(patch_of<T>(c, p), x, c.newton_iters);
     if (j == kCloudRounds - 1) break;
-    const int32_t q = kd_nearest<T>(c, r.y);
+    const int32_t q = near_surface_nearest<T>(c, r.y);
     if (q == p) break;
     p = q;
   }

@@ -102,6 +102,16 @@ struct CloudDev {
   int32_t radius_rule;         // 1 = spacing, otherwise curvature of the fitted patch
   int32_t nn_only;             // 1: cp is the nearest cloud point itself (no patch)
   const float4* pts;           // nn_only: the points by original index
+  // The walk's nearest-point lookups of points near the surface: a uniform
+  // grid of cells holding a few points each (null: the KD-tree only).  Cell
+  // (i, j, l) = (l g_n[1] + j) g_n[0] + i holds g_pts[g_start[c] ..
+  // g_start[c + 1]); a point sits in the cell floor((p - g_lo) / g_h).
+  const int32_t* g_start;
+  const float4* g_pts;         // x, y, z, original index bits, sorted by cell
+  int32_t g_n[3];
+  double g_lo[3];
+  double g_h, g_inv;
+  double g_slack;              // bound on the host's cell-binning rounding (ambient units)
 };
 
 // One request of a batched launch (serving).  Launch walks [begin, begin +

@@ -30,8 +30,9 @@ def test_cp_matches_oracle(n):
     np.testing.assert_allclose(y32, yo, rtol=0, atol=5e-6)
 
 
+# the last case is Table 1's setting: n = 1001, N_V = 50, tau_W = 1e-8 (K = 220)
 @pytest.mark.parametrize("n,nq,nw,n_v,tau_w", [(11, 4, 32, 1, 1e-8), (11, 4, 16, 2, 1e-8), (1001, 2, 8, 1, 1e-3),
-                                               (1001, 2, 8, 2, 1e-3)])
+                                               (1001, 2, 8, 2, 1e-3), (1001, 2, 4, 50, 1e-8)])
 def test_walks_fp64_match_oracle(n, nq, nw, n_v, tau_w):
     prob = dict(inputs.dumbbell_problem(n, n_v=n_v), tau_w=tau_w)
     Q = inputs.dumbbell_points(nq, n, seed=5)
