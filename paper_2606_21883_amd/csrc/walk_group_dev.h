@@ -547,12 +547,13 @@ __device__ __forceinline__ void group_load(const char* rec, int64_t idx, int64_t
 // so the groups of a wavefront always share one request (its seed stays
 // uniform); launch walks past an entry's count are padding.
 // The FP32 hypersphere kernels with four blocks per lane (S^99, S^999) are
-// held to 128 VGPRs, four waves per SIMD instead of three: the spilled
-// registers cost less than the latency the fourth wave hides (S^999 runs
-// 10% faster, S^99 5%).
+// held to 128 VGPRs, four waves per SIMD instead of three, and the FP32
+// dumbbell kernels to 168 VGPRs, three waves instead of two: the spilled
+// registers cost less than the latency the extra wave hides (S^999 runs 10%
+// faster, S^99 5%, the 1001-dimensional dumbbell 28%).
 template <class T, int L, int MB, int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    sizeof(T) == 4 && MB == 4 && KIND == kSphere ? 4 : 1))) void walk_group_kernel(WalkArgs a) {
+    sizeof(T) == 4 && MB == 4 && KIND == kSphere ? 4 : (sizeof(T) == 4 && KIND == kDumbbell ? 3 : 1)))) void walk_group_kernel(WalkArgs a) {
   const int64_t total = a.count;
   const int gl = threadIdx.x % L;
   const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / L;
