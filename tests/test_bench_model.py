@@ -4,6 +4,7 @@ counter gate on the kernel sources' hash, and the single-GPU exit."""
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 import bench
@@ -69,3 +70,17 @@ def test_roofline_objects_and_counter_gate():
 def test_more_than_one_gpu_exits_with_a_message():
     p = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True, text=True)
     assert p.returncode != 0 and "one GPU" in p.stderr
+
+
+def test_backlog_growth_reads_a_growing_queue():
+    # per manifold: median latency of the last third of the arrivals over the
+    # first third, the worst manifold; steady latencies read 1, a queue whose
+    # latency grows with time reads the growth
+    t = [i * 0.01 for i in range(300)]
+    reqs = [(ti, "sphere" if i % 2 else "cap", None, 0, 0) for i, ti in enumerate(t)]
+    steady = [0.05] * 300
+    assert bench.backlog_growth(reqs, np.array(steady)) == pytest.approx(1.0)
+    growing = [0.05 + (ti if r[1] == "cap" else 0.0) for ti, r in zip(t, reqs)]
+    g = bench.backlog_growth(reqs, np.array(growing))
+    # cap: median of the first third about 0.05 + 0.5, of the last about 0.05 + 2.5
+    assert 4.0 < g < 6.0
