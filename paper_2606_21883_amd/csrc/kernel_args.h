@@ -120,11 +120,13 @@ struct CloudDev {
 // whole batch unit (64 walks for lane kernels, the walks of one wavefront for
 // group kernels): a wavefront then never holds walks of two requests at once.
 //
-// Time slicing (lane-group kernels): with a state buffer, a walk runs at most
-// step_budget steps per launch; an unfinished walk saves its state (one
-// record per request walk) and counts itself in `pending`, and a later launch
-// of the same range with `resume` set continues it (finished walks of the
-// range are marked in their records and skipped).
+// Time slicing: with a state buffer, a walk runs at most step_budget steps
+// per launch; an unfinished walk saves its state (one record per request
+// walk: kLaneRecordBytes for lane kernels, the group record for lane-group
+// kernels) and counts itself in `pending`, and a later launch of the same
+// range with `resume` set continues it (finished walks of the range are
+// marked in their records and skipped).
+constexpr int64_t kLaneRecordBytes = 80;
 struct BatchEntry {
   int64_t begin, count, idx0, nw;
   const double* queries;       // the request's queries (device)

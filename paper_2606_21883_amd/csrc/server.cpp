@@ -130,6 +130,8 @@ struct HostArena {
 
 constexpr size_t kArenaBytes = (size_t)64 << 20;
 constexpr double kSliceBlocks = 1e6;       // Philox blocks per time-sliced walk and launch
+constexpr int32_t kCloudSliceSteps = 256;  // steps per time-sliced point-cloud walk and launch
+constexpr double kCloudWholeSteps = 4096;  // point-cloud walks known to be shorter run whole
 
 // One slot of in-flight work: a batched launch on a stream, with its entry
 // table (pinned host staging and device copy) and work counter.
@@ -805,8 +807,15 @@ mpwos_status mpwos_submit(mpwos_server* s, const mpwos_request* req, uint64_t* t
   R->step_cost = philox_blocks_per_step(n, R->opt.n_v);
   // Long lane-group walks are time-sliced: a launch runs each for at most
   // kSliceBlocks Philox blocks of work, so that no launch holds a stream (and
-  // whatever shares its hardware queue) for long.  The state records must fit
-  // an eighth of the budget; otherwise the walks run to the end in one launch.
+  // whatever shares its hardware queue) for long.  Point-cloud lane walks
+  // (every step is nearest-point lookups: a walk of 1601 steps holds a launch
+  // for about half a second) run kCloudSliceSteps steps per launch when their
+  // length is not known to stay below kCloudWholeSteps: a radius that varies
+  // per step (the spacing rule gives walks of about 1e6 steps on a dense
+  // cloud), or a constant one with longer walks.  Shorter cloud walks run
+  // whole: slicing them only adds launches between the slices.  The state
+  // records must fit an eighth of the budget; otherwise the walks run to the
+  // end in one launch.
   if (n >= 4) {
     const double budget = std::max(256.0, kSliceBlocks / R->step_cost);
     const int64_t rec = group_record_bytes(n, R->opt.lanes_per_walk, R->args.precision == 0);
@@ -815,6 +824,11 @@ mpwos_status mpwos_submit(mpwos_server* s, const mpwos_request* req, uint64_t* t
       R->rec_bytes = rec;
       R->bytes += align256((size_t)R->total * rec);
     }
+  } else if (R->args.kind == kCloud && (!R->args.const_r || R->k_est > kCloudWholeSteps) &&
+             (size_t)(R->total * kLaneRecordBytes) <= s->budget / 8) {
+    R->args.step_budget = kCloudSliceSteps;
+    R->rec_bytes = kLaneRecordBytes;
+    R->bytes += align256((size_t)R->total * kLaneRecordBytes);
   }
   manifold_ref(req->manifold, +1);
   {

@@ -218,6 +218,51 @@ __device__ __forceinline__ void walk_store(double* walk_S, int32_t* walk_K, cons
   walk_K[st.idx] = (int32_t)st.k;
 }
 
+// Record of a time-sliced lane walk (serving), kLaneRecord bytes per request
+// walk: W, S, C; k and the finished flag; the patch index; Y and rg in the
+// walk's precision (kLaneRecordBytes in all).  The step sequence continues
+// unchanged from a record, so a sliced walk ends with the bits of an
+// unsliced one.
+constexpr int64_t kLaneRecord = kLaneRecordBytes;
+static_assert(40 + 3 * 8 <= 64 && 64 + 8 <= kLaneRecord, "lane record layout");
+
+template <class T, int N>
+__device__ __forceinline__ void lane_save(char* rec, const LaneState<T, N>& st, uint32_t finished) {
+  double* d = (double*)rec;
+  uint32_t* u = (uint32_t*)(rec + 24);
+  u[1] = finished;
+  if (finished) return;
+  d[0] = st.W;
+  d[1] = st.S;
+  d[2] = st.C;
+  u[0] = st.k;
+  ((int32_t*)(rec + 32))[0] = st.pidx;
+  T* y = (T*)(rec + 40);
+  for (int i = 0; i < N; ++i) y[i] = st.Y[i];
+  *(T*)(rec + 64) = st.rg;
+}
+
+// false when the walk finished in an earlier launch
+template <class T, int N>
+__device__ __forceinline__ bool lane_load(const char* rec, int64_t nw, int64_t idx, LaneState<T, N>& st) {
+  const uint32_t* u = (const uint32_t*)(rec + 24);
+  if (u[1]) return false;
+  st.idx = idx;
+  const int64_t ql = idx / nw;
+  st.q = (uint32_t)ql;
+  st.w = (uint32_t)(idx - ql * nw);
+  const double* d = (const double*)rec;
+  st.W = d[0];
+  st.S = d[1];
+  st.C = d[2];
+  st.k = u[0];
+  st.pidx = ((const int32_t*)(rec + 32))[0];
+  const T* y = (const T*)(rec + 40);
+  for (int i = 0; i < N; ++i) st.Y[i] = y[i];
+  st.rg = *(const T*)(rec + 64);
+  return true;
+}
+
 // One Green sample Z = Y + t zeta' (t = r s, s from the radial law for the
 // uniform word ux, zeta' from words x, y of block b) and (f + m)(Z).
 template <class T, int N, int KIND, bool RICH>
@@ -445,6 +490,10 @@ __global__ __launch_bounds__(256) void walk_lane_batch_kernel(WalkArgs a) {
   double* e_S = nullptr;
   int32_t* e_K = nullptr;
   uint64_t e_seed = 0;
+  char* e_rec = nullptr;       // time slicing: the entry's walk records (null: walks run to the end)
+  bool e_resume = false;
+  unsigned long long* e_pending = nullptr;
+  int32_t steps = 0;           // steps of the lane's walk in this launch
   auto enter = [&](int64_t c) {
     cur = batch_entry(a, c * kChunk);
     const BatchEntry& E = a.batch[cur];
@@ -456,6 +505,9 @@ __global__ __launch_bounds__(256) void walk_lane_batch_kernel(WalkArgs a) {
     e_K = E.walk_K;
     e_seed = E.seed;
     e_end = E.begin + E.count;
+    e_rec = (E.state && a.step_budget > 0) ? E.state : nullptr;
+    e_resume = e_rec && E.resume != 0;
+    e_pending = const_cast<unsigned long long*>(&a.batch[cur].pending);
     next = c * kChunk;
     end = next + kChunk < e_end ? next + kChunk : e_end;
   };
@@ -490,8 +542,17 @@ __global__ __launch_bounds__(256) void walk_lane_batch_kernel(WalkArgs a) {
       const int64_t avail = end - next;
       const int64_t cnt = (int64_t)__popcll(want) < avail ? (int64_t)__popcll(want) : avail;
       if (!active && rank < cnt) {
-        if (walk_init<T, N, KIND>(a, e_q, e_nw, 0, e_idx0 + (next + rank - e_begin), st)) walk_store(e_S, e_K, st);
-        else active = true;
+        const int64_t widx = e_idx0 + (next + rank - e_begin);
+        steps = 0;
+        if (e_resume) {
+          // a walk finished in an earlier launch keeps its outputs
+          active = lane_load<T, N>(e_rec + widx * kLaneRecord, e_nw, widx, st);
+        } else if (walk_init<T, N, KIND>(a, e_q, e_nw, 0, widx, st)) {
+          walk_store(e_S, e_K, st);
+          if (e_rec) lane_save<T, N>(e_rec + widx * kLaneRecord, st, 1u);
+        } else {
+          active = true;
+        }
       }
       next += cnt;
     }
@@ -504,6 +565,12 @@ __global__ __launch_bounds__(256) void walk_lane_batch_kernel(WalkArgs a) {
     if (active) {
       if (walk_step<T, N, KIND, RICH>(a, st, e_seed, tab)) {
         walk_store(e_S, e_K, st);
+        if (e_rec) lane_save<T, N>(e_rec + st.idx * kLaneRecord, st, 1u);
+        active = false;
+      } else if (e_rec && ++steps >= a.step_budget) {
+        // the slice is used up: the walk continues in a later launch
+        lane_save<T, N>(e_rec + st.idx * kLaneRecord, st, 0u);
+        atomicAdd(e_pending, 1ull);
         active = false;
       }
     }

@@ -169,6 +169,29 @@ def test_server_serves_cloud_requests():
     m.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_server_slices_cloud_walks(prec):
+    """Served point-cloud walks whose radius varies per step (their length is
+    not known) run a fixed number of steps per launch and continue from
+    their records (walker position, weights, score, patch): the result
+    equals the solo solve bit for bit, with the same walk-steps, over many
+    launches."""
+    prob = cloud(12000, seed=41, tau_w=1e-5)
+    Q = inputs.torus_area_uniform(5, seed=42)
+    m = mpwos.Manifold(prob)
+    announce(f"cloud served time-sliced {prec}")
+    solo = mpwos.solve(prob, Q, 96, 6, manifold=m, precision=prec, walk_outputs=True)
+    srv = mpwos.Server(4 << 30)
+    out = srv.wait(srv.submit(m, prob, Q, 96, 6, precision=prec, persistent=1), 120_000)
+    st = srv.stats()
+    srv.close()
+    m.close()
+    assert np.array_equal(out["u"], solo["u"]) and np.array_equal(out["stderr"], solo["stderr"])
+    assert st["walk_steps"] == solo["stats"]["walk_steps"]
+    # 256 steps per launch: the longest walk took at least K_max / 256 launches
+    assert st["rounds"] >= int(solo["walk_K"].max()) // 256 >= 2, (st, int(solo["walk_K"].max()))
+
+
 def test_server_checks_cloud_queries_at_admission():
     """A served point-cloud request is checked on the device when it is
     admitted (submit does not wait for the device): one with a query far
