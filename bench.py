@@ -78,15 +78,15 @@ KERNEL_SOURCES = ["walk_lane.hip", "walk_group.hip", "walk_group_dev.h", "walk_g
 # (profiles/copy_kernel_hbm_probe.txt).  They apply to a run only when the
 # kernel sources hash to kernel_sha256 and the launch has the same form.
 PROFILED = {
-    "kernel_sha256": "3127f40f64703c74d99db73896f846bb400869fd110fcc63ef841b47e8980ea3",
+    "kernel_sha256": "65e67c5fc58112d91368fd96893e564e8637ea8806e68caac31e8099dc8bdabb",
     "kernels": {
-        "sphere": {"valu_per_walk_step": 161.45, "salu_per_walk_step": 31.28, "walk_steps": 2919235584, "fetch_kib": 469.3, "write_kib": 196608.0, "launch": {"persistent": 0, "block_size": 256}},
-        "cap": {"valu_per_walk_step": 320.68, "salu_per_walk_step": 115.64, "walk_steps": 478364826, "fetch_kib": 988.2, "write_kib": 287299.7, "launch": {"persistent": 1, "block_size": 256}},
-        "circle": {"valu_per_walk_step": 157.28, "salu_per_walk_step": 30.34, "walk_steps": 14848000, "fetch_kib": 92.8, "write_kib": 750.0, "launch": {"persistent": 0, "block_size": 0}},
-        "hyper100": {"valu_per_walk_step": 6907.66, "salu_per_walk_step": 897.24, "walk_steps": 2097152000, "fetch_kib": 8338.9, "write_kib": 268526.1, "launch": {"persistent": 0, "block_size": 0}},
-        "hyper1000": {"valu_per_walk_step": 56158.08, "salu_per_walk_step": 7217.6, "walk_steps": 419430400, "fetch_kib": 4355061.5, "write_kib": 17627274.4, "launch": {"persistent": 0, "block_size": 0}},
-        "torus": {"valu_per_walk_step": 520.53, "salu_per_walk_step": 68.97, "walk_steps": 13430161408, "fetch_kib": 836.3, "write_kib": 98304.0, "launch": {"persistent": 0, "block_size": 0}},
-        "cloud": {"valu_per_walk_step": 31579.42, "salu_per_walk_step": 19103.54, "walk_steps": 536870912, "fetch_kib": 3430616528.9, "write_kib": 99219.2, "launch": {"persistent": 1, "block_size": 0}},
+        "sphere": {"valu_per_walk_step": 161.45, "salu_per_walk_step": 31.28, "walk_steps": 2919235584, "fetch_kib": 469.9, "write_kib": 196608.0, "launch": {"persistent": 0, "block_size": 256}},
+        "cap": {"valu_per_walk_step": 320.69, "salu_per_walk_step": 115.65, "walk_steps": 478364826, "fetch_kib": 984.7, "write_kib": 287475.2, "launch": {"persistent": 1, "block_size": 256}},
+        "circle": {"valu_per_walk_step": 157.28, "salu_per_walk_step": 30.34, "walk_steps": 14848000, "fetch_kib": 95.8, "write_kib": 750.0, "launch": {"persistent": 0, "block_size": 0}},
+        "hyper100": {"valu_per_walk_step": 6907.66, "salu_per_walk_step": 897.24, "walk_steps": 2097152000, "fetch_kib": 8356.1, "write_kib": 274225.8, "launch": {"persistent": 0, "block_size": 0}},
+        "hyper1000": {"valu_per_walk_step": 56158.08, "salu_per_walk_step": 7217.6, "walk_steps": 419430400, "fetch_kib": 4357318.9, "write_kib": 17627505.7, "launch": {"persistent": 0, "block_size": 0}},
+        "torus": {"valu_per_walk_step": 520.53, "salu_per_walk_step": 68.97, "walk_steps": 13430161408, "fetch_kib": 843.8, "write_kib": 98304.0, "launch": {"persistent": 0, "block_size": 0}},
+        "cloud": {"valu_per_walk_step": 31579.42, "salu_per_walk_step": 19103.54, "walk_steps": 536870912, "fetch_kib": 3433330738.9, "write_kib": 99219.2, "launch": {"persistent": 1, "block_size": 0}},
     },
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
@@ -779,25 +779,31 @@ def served_mix(rate=200.0, window=30.0, seed=2, ms_range=(0.02, 20.0), q_range=(
 
 
 def backlog_growth(reqs, lat):
-    """Median latency of the requests that arrived in the last third of the
-    window over that of the first third, per manifold, the largest: near 1
-    while the server keeps up, growing with the backlog when it does not."""
+    """Growth of the latency over the window: each request's latency over the
+    median latency of its manifold (all arrivals), then the median of that
+    ratio over the last third of the arrivals over its median over the first
+    third.  Near 1 while the server keeps up, growing with the backlog when
+    it does not; normalising per manifold keeps the mix of manifolds that
+    arrive in each third from moving it."""
     t = np.array([r[0] for r in reqs])
+    kinds = np.array([r[1] for r in reqs])
+    norm = np.array(lat, dtype=float)
+    for name in set(kinds.tolist()):
+        sel = kinds == name
+        norm[sel] = norm[sel] / max(float(np.median(norm[sel])), 1e-12)
     lo, hi = np.percentile(t, 100 / 3), np.percentile(t, 200 / 3)
-    worst = 0.0
-    for name in SERVED_KINDS:
-        sel = np.array([r[1] == name for r in reqs])
-        a, b = lat[sel & (t <= lo)], lat[sel & (t >= hi)]
-        if len(a) >= 3 and len(b) >= 3:
-            worst = max(worst, float(np.median(b) / np.median(a)))
-    return worst
+    a, b = norm[t <= lo], norm[t >= hi]
+    if len(a) < 3 or len(b) < 3:
+        return 1.0
+    return float(np.median(b) / np.median(a))
 
 
 def served_sweep(rates, window=20.0):
     """The served mix at several arrival rates (no per-solve runs).  A rate is
-    stable when no manifold's median latency grows by more than a fifth from
-    the first third of the arrivals to the last (backlog_growth <= 1.2) and
-    the queue drains within a tenth of the window after the last arrival."""
+    stable when the latency, relative to each manifold's median, grows by no
+    more than a fifth from the first third of the arrivals to the last
+    (backlog_growth <= 1.2) and the queue drains within a tenth of the window
+    after the last arrival."""
     runs = []
     for r in rates:
         runs.append(served_mix(rate=r, window=window, fp64_sample=0))

@@ -73,14 +73,14 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 
 def test_backlog_growth_reads_a_growing_queue():
-    # per manifold: median latency of the last third of the arrivals over the
-    # first third, the worst manifold; steady latencies read 1, a queue whose
-    # latency grows with time reads the growth
+    # latency relative to each manifold's median, last third of the arrivals
+    # over the first: steady latencies read 1 whatever the manifolds' own
+    # levels, a queue whose latency grows with time reads the growth
     t = [i * 0.01 for i in range(300)]
     reqs = [(ti, "sphere" if i % 2 else "cap", None, 0, 0) for i, ti in enumerate(t)]
-    steady = [0.05] * 300
+    steady = [0.05 if r[1] == "sphere" else 2.0 for r in reqs]
     assert bench.backlog_growth(reqs, np.array(steady)) == pytest.approx(1.0)
-    growing = [0.05 + (ti if r[1] == "cap" else 0.0) for ti, r in zip(t, reqs)]
+    growing = [(0.05 if r[1] == "sphere" else 2.0) * (1 + ti) for ti, r in zip(t, reqs)]
     g = bench.backlog_growth(reqs, np.array(growing))
-    # cap: median of the first third about 0.05 + 0.5, of the last about 0.05 + 2.5
-    assert 4.0 < g < 6.0
+    # medians of (1 + t) over the thirds: about 1.5 and 3.5
+    assert 2.0 < g < 2.6
