@@ -224,9 +224,14 @@ def roofline_cloud(name, n_queries, n_walks, walk_steps, kernel_ms, launch):
            "launch_ms": kernel_ms,
            "note": "latency-bound: each projection is a depth-first KD-tree nearest-point search"}
     prof = profiled(name, launch)
+    if prof:
+        out["counted_launch"] = prof["launch"]
+        out["valu_issue_frac"] = prof["valu_per_walk_step"] * walk_steps / secs / PEAK_SLOTS
+        out["valu_per_walk_step_counted"] = prof["valu_per_walk_step"]
     if prof and prof.get("walk_steps") == walk_steps and "fetch_kib" in prof:
         out["traffic"] = 1024 * (prof["fetch_kib"] * FETCH_FACTOR + prof["write_kib"] * WRITE_FACTOR)
         out["traffic_unit"] = "HBM bytes per launch"
+        out["traffic_frac"] = out["traffic"] / secs / PEAK_HBM_BYTES
     return out
 
 
