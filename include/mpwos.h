@@ -370,12 +370,15 @@ typedef struct {
  * shared by the requests of its class, in three-dimensional walk-steps (0 =
  * about 9e7); a launch holds at least the walks that fill the device, or all
  * that its class has left, and at least one wavefront's walks per request.
- * Launches run on max(2, min(8, GPU_MAX_HW_QUEUES - 2)) streams (the
- * variable as read at creation, default 4), one hardware queue each when the
- * runtime has them; classes whose launches take above 20 ms of device time
- * run on half of them, and no launch is queued behind such a launch.  The
- * library allocates two launch tables of 512 entries per stream and 64 MiB of
- * pinned staging at creation; admission, uploads, reductions and copies out are
+ * Launches run on six to eight streams, each with a hardware queue of its
+ * own: ordinary streams, min(8, GPU_MAX_HW_QUEUES - 2) of them, when the
+ * variable (as read at creation, default 4) leaves queues for six beside the
+ * null and completion streams; otherwise six streams created with a CU mask
+ * of every CU, which the runtime gives queues of their own.  Classes whose
+ * launches take above 20 ms of device time run on half of them, and no
+ * launch is queued behind such a launch.  The library allocates two launch
+ * tables of 512 entries per stream and 64 MiB of pinned staging at creation;
+ * admission, uploads, reductions and copies out are
  * asynchronous (events), so the scheduling thread never waits for the
  * device.  A request whose staging does not fit waits for completions to
  * free it; one above 16 MiB takes pinned memory of its own. */

@@ -21,6 +21,7 @@
 // A walk's score depends only on (request, query, walk) through the Philox
 // counter, and the per-query reduction runs in a fixed order, so a served
 // result is bit-identical to the same solve run alone.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,6 +47,7 @@ namespace mpwos {
 namespace {
 
 constexpr int kMaxStreams = 8;            // walk streams at most
+constexpr int kMinStreams = 6;            // walk streams at least (CU-masked when the queues are fewer)
 constexpr int kDepth = 2;                  // launches in flight per stream
 constexpr int kSlots = kMaxStreams * kDepth;
 constexpr int kMaxBatch = 512;             // requests per launch
@@ -733,15 +735,37 @@ mpwos_status mpwos_server_create(size_t hbm_budget_bytes, int64_t slice_walk_ste
   if (e == hipSuccess) e = hipGetDeviceProperties(&prop, s->device);
   // The runtime shares hardware queues between streams beyond
   // GPU_MAX_HW_QUEUES (default 4), and kernels of streams that share a queue
-  // run one after another: the walk streams take what the null stream and
-  // the completion stream leave, two at least.
+  // run one after another.  With queues for at least six walk streams beside
+  // the null stream and the completion stream, the walk streams are ordinary
+  // ones (up to eight); with fewer, six streams are created with a CU mask
+  // covering every CU, which the runtime gives queues of their own.
   int hwq = 4;
   if (const char* v = std::getenv("GPU_MAX_HW_QUEUES"))
     if (std::atoi(v) > 0) hwq = std::atoi(v);
-  s->n_streams = std::max(2, std::min(kMaxStreams, hwq - 2));
+  bool masked = false;
+  if (hwq - 2 >= kMinStreams) {
+    s->n_streams = std::min(kMaxStreams, hwq - 2);
+    for (int i = 0; e == hipSuccess && i < s->n_streams; ++i)
+      e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
+  } else {
+    s->n_streams = kMinStreams;
+    uint32_t all[16];
+    for (uint32_t& w : all) w = 0xFFFFFFFFu;
+    masked = true;
+    for (int i = 0; masked && i < s->n_streams; ++i)
+      masked = hipExtStreamCreateWithCUMask(&s->streams[i], 16, all) == hipSuccess;
+    if (!masked) {
+      // ordinary streams on the queues there are
+      (void)hipGetLastError();
+      for (auto& st : s->streams)
+        if (st) (void)hipStreamDestroy(st);
+      for (auto& st : s->streams) st = nullptr;
+      s->n_streams = std::max(2, std::min(kMaxStreams, hwq - 2));
+      for (int i = 0; e == hipSuccess && i < s->n_streams; ++i)
+        e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
+    }
+  }
   s->n_long = std::max(1, s->n_streams / 2);
-  for (int i = 0; e == hipSuccess && i < s->n_streams; ++i)
-    e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->done_stream, hipStreamNonBlocking);
   for (int k = 0; e == hipSuccess && k < s->n_streams * kDepth; ++k) {
     Slot& sl = s->slots[k];
