@@ -40,8 +40,7 @@ __device__ __forceinline__ void cap_gamma_point(const WalkArgs& a, const T* y, T
 }
 
 template <class T, int N>
-__device__ __forceinline__ T cap_delta(const WalkArgs& a, const T* y) {
-  T yg[N];
+__device__ __forceinline__ T cap_delta(const WalkArgs& a, const T* y, T* yg) {
   cap_gamma_point<T, N>(a, y, yg);
   // r = y_Gamma - y splits into rn along the normal y_Gamma / R and the
   // tangential rest, |r^T|^2 = |r|^2 - rn^2 (rn^2 is the smaller term: no
@@ -64,11 +63,15 @@ __device__ __forceinline__ T cap_delta(const WalkArgs& a, const T* y) {
 
 // Membership of the boundary layer, in the walk's precision; dg receives
 // delta_Gamma(y) when y is above the cutting plane (the next step's radius
-// reuses it).
+// reuses it), yg the nearest point of Gamma when y is in the layer (the
+// boundary datum is taken there).
 template <class T, int N>
-__device__ __forceinline__ bool cap_in_layer(const WalkArgs& a, const T* y, T& dg) {
-  if (y[N - 1] <= (T)a.p[1]) return true;
-  dg = cap_delta<T, N>(a, y);
+__device__ __forceinline__ bool cap_in_layer(const WalkArgs& a, const T* y, T& dg, T* yg) {
+  if (y[N - 1] <= (T)a.p[1]) {
+    cap_gamma_point<T, N>(a, y, yg);
+    return true;
+  }
+  dg = cap_delta<T, N>(a, y, yg);
   return dg < (T)a.eps;
 }
 
@@ -119,25 +122,22 @@ __device__ __forceinline__ bool ct_in_layer(const WalkArgs& a, const T* y, T& dg
   return d < a.eps;
 }
 
-// boundary layer test and boundary datum, by manifold
+// Boundary layer test, by manifold: true when y is in the layer, with g the
+// boundary datum at y's nearest point of Gamma; dg as for the tests above.
 template <class T, int N, int KIND>
-__device__ __forceinline__ bool in_layer(const WalkArgs& a, const T* y, T& dg) {
-  if constexpr (KIND == kCutTorus) return ct_in_layer<T>(a, y, dg);
-  else return cap_in_layer<T, N>(a, y, dg);
-}
-
-template <class T, int N, int KIND>
-__device__ __forceinline__ double layer_value(const WalkArgs& a, const T* y) {
+__device__ __forceinline__ bool layer_stop(const WalkArgs& a, const T* y, T& dg, double& g) {
   T yg[N];
   if constexpr (KIND == kCutTorus) {
+    if (!ct_in_layer<T>(a, y, dg)) return false;
     const double yd[3] = {(double)y[0], (double)y[1], (double)y[2]};
     double gd[3], nd[3];
     ct_gamma_point(a, yd, gd, nd);
     for (int i = 0; i < 3; ++i) yg[i] = (T)gd[i];
   } else {
-    cap_gamma_point<T, N>(a, y, yg);
+    if (!cap_in_layer<T, N>(a, y, dg, yg)) return false;
   }
-  return boundary_value<T>(a, yg, N);
+  g = boundary_value<T>(a, yg, N);
+  return true;
 }
 
 // ---- closest point ----------------------------------------------------------
@@ -195,8 +195,9 @@ __device__ __forceinline__ bool walk_init(const WalkArgs& a, const double* queri
     if (!a.const_r) st.rg = (T)cloud_rho_geo(a, p);
   }
   if constexpr (KIND == kCap || KIND == kCutTorus) {
-    if (in_layer<T, N, KIND>(a, st.Y, st.rg)) {
-      st.S = layer_value<T, N, KIND>(a, st.Y);
+    double g;
+    if (layer_stop<T, N, KIND>(a, st.Y, st.rg, g)) {
+      st.S = g;
       return true;
     }
   }
@@ -364,8 +365,9 @@ __device__ __forceinline__ bool walk_step(const WalkArgs& a, LaneState<T, N>& st
   }
   st.k += 1;
   if constexpr (KIND == kCap || KIND == kCutTorus) {
-    if (in_layer<T, N, KIND>(a, st.Y, st.rg)) {
-      score_add<T>(st, st.W * layer_value<T, N, KIND>(a, st.Y));
+    double g;
+    if (layer_stop<T, N, KIND>(a, st.Y, st.rg, g)) {
+      score_add<T>(st, st.W * g);
       return true;
     }
   } else {
@@ -420,35 +422,50 @@ void walk_lane_kernel(WalkArgs a) {
     int64_t next = 0, end = 0;
     for (;;) {
       const uint64_t idle = __ballot(!active);
-      const bool refill = !exhausted && (__popcll(idle) >= kRefillIdle || idle == ~0ull);
-      for (; refill;) {
-        const uint64_t want = __ballot(!active);
-        if (want == 0 || exhausted) break;
-        if (next >= end) {
-          const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)want) - 1);
-          unsigned long long base = 0;
-          if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)a.chunk);
-          const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
-          const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
-          const int64_t b = (int64_t)(((uint64_t)hi << 32) | lo);
-          if (b >= total) {
-            exhausted = true;
-            break;
+      if (!exhausted && (__popcll(idle) >= kRefillIdle || idle == ~0ull)) {
+        // the idle lanes take their walk indices first (from the wave's chunk,
+        // and further chunks while it runs out), then start those walks
+        // together: the loop over chunks carries indices only, not the walk
+        // state.  A walk that starts in the boundary layer ends here; its lane
+        // waits for the next pass.
+        int64_t mine = -1;
+        bool need = !active;
+        for (;;) {
+          const uint64_t want = __ballot(need);
+          if (want == 0) break;
+          if (next >= end) {
+            const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)want) - 1);
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)a.chunk);
+            const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
+            const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
+            const int64_t b = (int64_t)(((uint64_t)hi << 32) | lo);
+            if (b >= total) {
+              exhausted = true;
+              break;
+            }
+            next = b;
+            end = b + a.chunk < total ? b + a.chunk : total;
           }
-          next = b;
-          end = b + a.chunk < total ? b + a.chunk : total;
+          const int rank = __popcll(want & lt_mask);
+          const int64_t avail = end - next;
+          const int64_t cnt = (int64_t)__popcll(want) < avail ? (int64_t)__popcll(want) : avail;
+          if (need && rank < cnt) {
+            mine = next + rank;
+            need = false;
+          }
+          next += cnt;
         }
-        const int rank = __popcll(want & lt_mask);
-        const int64_t avail = end - next;
-        const int64_t cnt = (int64_t)__popcll(want) < avail ? (int64_t)__popcll(want) : avail;
-        if (!active && rank < cnt) {
-          if (walk_init<T, N, KIND>(a, a.queries, a.nw, a.q_offset, a.idx_base + next + rank, st))
+        if (mine >= 0) {
+          if (walk_init<T, N, KIND>(a, a.queries, a.nw, a.q_offset, a.idx_base + mine, st))
             walk_store(a.walk_S, a.walk_K, st);
           else active = true;
         }
-        next += cnt;
       }
-      if (__ballot(active) == 0) break;
+      if (__ballot(active) == 0) {
+        if (exhausted) break;
+        continue;
+      }
       if (active) {
         if (walk_step<T, N, KIND, RICH>(a, st, seed, tab)) {
           walk_store(a.walk_S, a.walk_K, st);
