@@ -78,15 +78,15 @@ KERNEL_SOURCES = ["walk_lane.hip", "walk_group.hip", "walk_group_dev.h", "walk_g
 # (profiles/copy_kernel_hbm_probe.txt).  They apply to a run only when the
 # kernel sources hash to kernel_sha256 and the launch has the same form.
 PROFILED = {
-    "kernel_sha256": "65e67c5fc58112d91368fd96893e564e8637ea8806e68caac31e8099dc8bdabb",
+    "kernel_sha256": "96f6bdb3bcf75a454c40c7856e9fba748d18f40543f29be42c59316de06db0b9",
     "kernels": {
-        "sphere": {"valu_per_walk_step": 161.45, "salu_per_walk_step": 31.28, "walk_steps": 2919235584, "fetch_kib": 469.9, "write_kib": 196608.0, "launch": {"persistent": 0, "block_size": 256}},
-        "cap": {"valu_per_walk_step": 320.69, "salu_per_walk_step": 115.65, "walk_steps": 478364826, "fetch_kib": 984.7, "write_kib": 287475.2, "launch": {"persistent": 1, "block_size": 256}},
-        "circle": {"valu_per_walk_step": 157.28, "salu_per_walk_step": 30.34, "walk_steps": 14848000, "fetch_kib": 95.8, "write_kib": 750.0, "launch": {"persistent": 0, "block_size": 0}},
-        "hyper100": {"valu_per_walk_step": 6907.66, "salu_per_walk_step": 897.24, "walk_steps": 2097152000, "fetch_kib": 8356.1, "write_kib": 274225.8, "launch": {"persistent": 0, "block_size": 0}},
-        "hyper1000": {"valu_per_walk_step": 56158.08, "salu_per_walk_step": 7217.6, "walk_steps": 419430400, "fetch_kib": 4357318.9, "write_kib": 17627505.7, "launch": {"persistent": 0, "block_size": 0}},
-        "torus": {"valu_per_walk_step": 520.53, "salu_per_walk_step": 68.97, "walk_steps": 13430161408, "fetch_kib": 843.8, "write_kib": 98304.0, "launch": {"persistent": 0, "block_size": 0}},
-        "cloud": {"valu_per_walk_step": 31579.42, "salu_per_walk_step": 19103.54, "walk_steps": 536870912, "fetch_kib": 3433330738.9, "write_kib": 99219.2, "launch": {"persistent": 1, "block_size": 0}},
+        "sphere": {"valu_per_walk_step": 161.45, "salu_per_walk_step": 31.28, "walk_steps": 2919235584, "fetch_kib": 468.4, "write_kib": 196608.0, "launch": {"persistent": 0, "block_size": 256}},
+        "cap": {"valu_per_walk_step": 289.23, "salu_per_walk_step": 88.6, "walk_steps": 478364829, "fetch_kib": 976.2, "write_kib": 286481.0, "launch": {"persistent": 1, "block_size": 256}},
+        "circle": {"valu_per_walk_step": 157.28, "salu_per_walk_step": 30.34, "walk_steps": 14848000, "fetch_kib": 95.4, "write_kib": 750.0, "launch": {"persistent": 0, "block_size": 0}},
+        "hyper100": {"valu_per_walk_step": 6907.66, "salu_per_walk_step": 897.24, "walk_steps": 2097152000, "fetch_kib": 8315.8, "write_kib": 267554.0, "launch": {"persistent": 0, "block_size": 0}},
+        "hyper1000": {"valu_per_walk_step": 56158.08, "salu_per_walk_step": 7217.6, "walk_steps": 419430400, "fetch_kib": 4303006.6, "write_kib": 17631149.7, "launch": {"persistent": 0, "block_size": 0}},
+        "torus": {"valu_per_walk_step": 520.53, "salu_per_walk_step": 68.97, "walk_steps": 13430161408, "fetch_kib": 844.4, "write_kib": 98304.0, "launch": {"persistent": 0, "block_size": 0}},
+        "cloud": {"valu_per_walk_step": 31517.65, "salu_per_walk_step": 19070.85, "walk_steps": 536870912, "fetch_kib": 3434660673.7, "write_kib": 99219.2, "launch": {"persistent": 1, "block_size": 0}},
     },
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
