@@ -141,6 +141,31 @@ def test_persistent_and_block_size_do_not_change_results():
                 assert np.array_equal(base["u"], other["u"])
 
 
+def test_persistent_refill_with_walks_that_end_at_their_start():
+    # a walk whose query lies in the boundary layer ends when it starts and
+    # leaves its lane idle until the next refill pass: launches where every
+    # walk does so, and where every other query does, equal the plain launch
+    prob, Qi, _ = CASES["cap"]
+    t = np.linspace(0.0, 2.0 * math.pi, 48, endpoint=False)
+    c = math.cos(1e-4)
+    Ql = np.stack([c * np.cos(t), c * np.sin(t), np.full(48, math.sin(1e-4))], axis=1)
+    Qm = np.empty((96, 3))
+    Qm[0::2], Qm[1::2] = Ql, Qi
+    for Q, nw in ((Ql, 131), (Qm, 131), (Qm, 4099)):
+        for prec in ("fp64", "fp32"):
+            announce(f"refill {len(Q)}x{nw} {prec}")
+            base = mpwos.solve(prob, Q, nw, 3, walk_outputs=True, precision=prec)
+            for kw in (dict(persistent=1), dict(persistent=1, block_size=64)):
+                other = mpwos.solve(prob, Q, nw, 3, walk_outputs=True, precision=prec, **kw)
+                assert np.array_equal(base["walk_S"], other["walk_S"]), (len(Q), nw, prec, kw)
+                assert np.array_equal(base["walk_K"], other["walk_K"])
+            K = base["walk_K"].reshape(len(Q), nw)
+            if len(Q) == 48:
+                assert np.all(K == 0)
+            else:
+                assert np.all(K[0::2] == 0) and np.all(K[1::2] > 0)
+
+
 def test_group_kernel_persistent_matches_plain():
     prob = dict(inputs.hypersphere_problem(100), tau_w=1e-3)
     Q = inputs.hypersphere_queries(5, 100, seed=2)
