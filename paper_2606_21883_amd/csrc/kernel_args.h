@@ -159,9 +159,10 @@ struct WalkArgs {
   RadialLaw law;
   // FP32 walks whose radius varies per step: the screening series'
   // coefficients alpha_j in float (wcoef[0] unused) and the number of terms
-  // that can exceed 1e-10 over the solve's radii
+  // that can exceed 1e-10 over the solve's radii; w32n terms j = 1..w32n
+  // keep the first dropped term below 2^-30 of the leading one there
   float wcoef[kMaxJ];
-  int32_t wjs;
+  int32_t wjs, w32n;
   RadialFixed fixed;
   InvTable tab;
   CloudDev cloud;

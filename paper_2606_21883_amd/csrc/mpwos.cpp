@@ -785,6 +785,13 @@ mpwos_status prepare_solve(const mpwos_manifold* man, const mpwos_fn* f, const m
   }
   memset(a.wcoef, 0, sizeof(a.wcoef));
   for (int j = 1; j < a.wjs; ++j) a.wcoef[j] = (float)h.alpha[j];
+  // terms for FP32 relative accuracy: the series is alpha_1 X^2 (1 + ...),
+  // so the truncation error relative to s1 is about the first dropped term
+  // over the leading one
+  a.w32n = kMaxJ - 1;
+  for (int j = 1; j + 1 < kMaxJ; ++j) {
+    if (h.alpha[j + 1] / h.alpha[1] * std::pow(x2max, j) < 0x1p-30) { a.w32n = j; break; }
+  }
   a.const_r = (d.kind == MPWOS_SPHERE || d.kind == MPWOS_TORUS_IMPLICIT || d.kind == MPWOS_DUMBBELL ||
                d.kind == MPWOS_PRODUCT || cloud_bound)
                   ? 1 : 0;

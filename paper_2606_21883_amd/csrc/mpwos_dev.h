@@ -198,11 +198,14 @@ __device__ __forceinline__ void weights(const WalkArgs& a, double r, double& c, 
 // the hardware reciprocal (1 ulp).  All terms are positive, so the float sum
 // is accurate to a few ulps at any size.  W and S stay FP64.  For the lane
 // kernels' dimensions (n <= 3) the coefficients are compile-time constants
-// (alpha_j = 1/(4^j j! (nu+1)_j), nu = (n-2)/2) and the first kSeries32 of
-// them are always summed: that covers every solve whose series the host cut
-// at kSeries32 + 1 terms (alpha_j z^j below 1e-10), sigma r^2 up to about 5;
-// wider ones and lane groups take the solve's float coefficients.
+// (alpha_j = 1/(4^j j! (nu+1)_j), nu = (n-2)/2): the first kSeries32 of them
+// cover every solve whose series the host cut at kSeries32 + 1 terms
+// (alpha_j z^j below 1e-10), sigma r^2 up to about 5, and the first
+// kSeries32Short do when the solve's radii keep the first dropped term below
+// 2^-30 of the leading one (the cap: sigma r^2 up to 0.16); wider ones and
+// lane groups take the solve's float coefficients.
 constexpr int kSeries32 = 8;
+constexpr int kSeries32Short = 4;
 
 template <int N>
 struct SeriesCoef {
@@ -224,8 +227,13 @@ __device__ __forceinline__ void weights32(const WalkArgs& a, float r, float& c, 
   float t = 0.0f;
   if (N <= 3 && a.wjs <= kSeries32 + 1) {
     constexpr SeriesCoef<N> K;
+    if (a.w32n <= kSeries32Short) {
 #pragma unroll
-    for (int j = kSeries32; j >= 1; --j) t = fmaf(t, z, K.v[j]);
+      for (int j = kSeries32Short; j >= 1; --j) t = fmaf(t, z, K.v[j]);
+    } else {
+#pragma unroll
+      for (int j = kSeries32; j >= 1; --j) t = fmaf(t, z, K.v[j]);
+    }
   } else {
     for (int j = a.wjs - 1; j >= 1; --j) t = fmaf(t, z, a.wcoef[j]);
   }
@@ -334,19 +342,24 @@ __device__ __forceinline__ float table_guess32(const InvTable& t, float u, float
   int i = (int)pos;
   i = i < 0 ? 0 : (i > t.mu - 2 ? t.mu - 2 : i);
   const float fr = pos - (float)i;
+  // at most 17 x 2 x 1025 entries: 32-bit byte offsets from the table's
+  // (uniform) base, so the loads take the scalar base and a 32-bit offset
+  const char* base = (const char*)t.s32;
   if (t.mx == 1) {
-    const float* r = t.s32 + (up ? t.mu : 0);
-    return r[i] + fr * (r[i + 1] - r[i]);
+    const uint32_t o = (uint32_t)((up ? t.mu : 0) + i) * 4u;
+    const float a0 = *(const float*)(base + o), a1 = *(const float*)(base + o + 4u);
+    return a0 + fr * (a1 - a0);
   }
   const float xpos = X2 * (float)t.x2scale;
   int k = (int)xpos;
   k = k < 0 ? 0 : (k > t.mx - 2 ? t.mx - 2 : k);
   const float fx = xpos - (float)k;
-  // at most 17 x 2 x 1025 entries: 32-bit offsets
-  const float* ra = t.s32 + (uint32_t)((k * 2 + (up ? 1 : 0)) * t.mu);
-  const float* rb = ra + (uint32_t)(2 * t.mu);
-  const float ga = ra[i] + fr * (ra[i + 1] - ra[i]);
-  const float gb = rb[i] + fr * (rb[i + 1] - rb[i]);
+  const uint32_t oa = (uint32_t)((k * 2 + (up ? 1 : 0)) * t.mu + i) * 4u;
+  const uint32_t ob = oa + (uint32_t)(2 * t.mu) * 4u;
+  const float a0 = *(const float*)(base + oa), a1 = *(const float*)(base + oa + 4u);
+  const float b0 = *(const float*)(base + ob), b1 = *(const float*)(base + ob + 4u);
+  const float ga = a0 + fr * (a1 - a0);
+  const float gb = b0 + fr * (b1 - b0);
   return ga + fx * (gb - ga);
 }
 
