@@ -78,15 +78,15 @@ KERNEL_SOURCES = ["walk_lane.hip", "walk_group.hip", "walk_group_dev.h", "walk_g
 # (profiles/copy_kernel_hbm_probe.txt).  They apply to a run only when the
 # kernel sources hash to kernel_sha256 and the launch has the same form.
 PROFILED = {
-    "kernel_sha256": "96f6bdb3bcf75a454c40c7856e9fba748d18f40543f29be42c59316de06db0b9",
+    "kernel_sha256": "bb78bf3d228ab50d9417fd8be55d243e16cd9ed43c84817920578145c79a8eab",
     "kernels": {
-        "sphere": {"valu_per_walk_step": 161.45, "salu_per_walk_step": 31.28, "walk_steps": 2919235584, "fetch_kib": 468.4, "write_kib": 196608.0, "launch": {"persistent": 0, "block_size": 256}},
-        "cap": {"valu_per_walk_step": 289.23, "salu_per_walk_step": 88.6, "walk_steps": 478364829, "fetch_kib": 976.2, "write_kib": 286481.0, "launch": {"persistent": 1, "block_size": 256}},
-        "circle": {"valu_per_walk_step": 157.28, "salu_per_walk_step": 30.34, "walk_steps": 14848000, "fetch_kib": 95.4, "write_kib": 750.0, "launch": {"persistent": 0, "block_size": 0}},
-        "hyper100": {"valu_per_walk_step": 6907.66, "salu_per_walk_step": 897.24, "walk_steps": 2097152000, "fetch_kib": 8315.8, "write_kib": 267554.0, "launch": {"persistent": 0, "block_size": 0}},
-        "hyper1000": {"valu_per_walk_step": 56158.08, "salu_per_walk_step": 7217.6, "walk_steps": 419430400, "fetch_kib": 4303006.6, "write_kib": 17631149.7, "launch": {"persistent": 0, "block_size": 0}},
-        "torus": {"valu_per_walk_step": 520.53, "salu_per_walk_step": 68.97, "walk_steps": 13430161408, "fetch_kib": 844.4, "write_kib": 98304.0, "launch": {"persistent": 0, "block_size": 0}},
-        "cloud": {"valu_per_walk_step": 31517.65, "salu_per_walk_step": 19070.85, "walk_steps": 536870912, "fetch_kib": 3434660673.7, "write_kib": 99219.2, "launch": {"persistent": 1, "block_size": 0}},
+        "sphere": {"valu_per_walk_step": 157.45, "salu_per_walk_step": 31.26, "walk_steps": 2919235584, "fetch_kib": 463.7, "write_kib": 196608.0, "launch": {"persistent": 0, "block_size": 256}},
+        "cap": {"valu_per_walk_step": 280.16, "salu_per_walk_step": 92.0, "walk_steps": 478364829, "fetch_kib": 983.0, "write_kib": 290342.5, "launch": {"persistent": 1, "block_size": 256}},
+        "circle": {"valu_per_walk_step": 153.28, "salu_per_walk_step": 30.33, "walk_steps": 14848000, "fetch_kib": 94.8, "write_kib": 750.0, "launch": {"persistent": 0, "block_size": 0}},
+        "hyper100": {"valu_per_walk_step": 6859.68, "salu_per_walk_step": 897.22, "walk_steps": 2097152000, "fetch_kib": 9469.3, "write_kib": 535517.9, "launch": {"persistent": 0, "block_size": 0}},
+        "hyper1000": {"valu_per_walk_step": 55774.72, "salu_per_walk_step": 7216.96, "walk_steps": 419430400, "fetch_kib": 3415130.4, "write_kib": 17119615.4, "launch": {"persistent": 0, "block_size": 0}},
+        "torus": {"valu_per_walk_step": 516.53, "salu_per_walk_step": 68.97, "walk_steps": 13430161408, "fetch_kib": 843.9, "write_kib": 98304.0, "launch": {"persistent": 0, "block_size": 0}},
+        "cloud": {"valu_per_walk_step": 31512.65, "salu_per_walk_step": 19070.85, "walk_steps": 536870912, "fetch_kib": 3433032280.4, "write_kib": 99219.2, "launch": {"persistent": 1, "block_size": 0}},
     },
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
