@@ -220,7 +220,11 @@ mpwos_status mpwos_manifold_destroy(mpwos_manifold* m);
  *   queries: n_queries x n doubles, each on M (within 1e-9 (1 + |q|)); on a
  *            POINT_CLOUD each within two local spacings of the reconstructed
  *            surface, and the walk starts from its projection cp_h(q), the
- *            point the estimate refers to.  EOFFMANIFOLD otherwise.
+ *            point the estimate refers to.  EOFFMANIFOLD otherwise.  Device
+ *            queries (opt->device_io) on SPHERE, SPHERE_CAP, TORUS_IMPLICIT
+ *            and CUT_TORUS are checked on the device beside the walks:
+ *            EOFFMANIFOLD then comes after them, with u_out and stderr_out
+ *            left unwritten.
  *   n_walks: paths per query, >= 1.
  *   eps: boundary-layer width (eq. boundary_layer), > 0 on SPHERE_CAP, ignored when closed.
  *   seed: key of the Philox4x32-10 stream; walk w of query q at step k draws

@@ -44,6 +44,12 @@ mpwos_status check_queries_host(const mpwos_manifold* man, const WalkArgs& a, co
 // distance to its FP64 projection and the local spacing there (2 doubles).
 hipError_t launch_cloud_check(const WalkArgs& a, const double* dq, double* out, int64_t nq, hipStream_t s);
 
+// query_check.hip: the analytic manifolds' query check on the device; slot
+// (zeroed by the caller) ends at n_q - (first failing query), or 0
+bool device_query_check(int kind);
+hipError_t launch_query_check(const mpwos_manifold_desc& d, const double* q, int64_t nq, unsigned long long* slot,
+                              hipStream_t s);
+
 // khist.hip: histogram of the per-walk K^i (exact below kKHistExact, then
 // 128 bins per octave up to 2^31) and its nearest-rank p50 / p99
 constexpr int kKHistExact = 2048;

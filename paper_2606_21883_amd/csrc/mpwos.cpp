@@ -59,6 +59,9 @@ struct Context {
   hipStream_t stream = nullptr;
   hipEvent_t ev[4] = {};
   DevBuf queries, walkS, walkK, u, se, stats, tmp, khist;
+  // pinned host words for a solve's read-back: the statistics words, then
+  // the K histogram
+  unsigned long long* hpin = nullptr;
   bool ready = false;
 };
 
@@ -87,6 +90,7 @@ static mpwos_status context_init(Context& c) {
   c.n_cu = prop.multiProcessorCount;
   HIP_TRY(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
   for (auto& e : c.ev) HIP_TRY(hipEventCreate(&e));
+  HIP_TRY(hipHostMalloc((void**)&c.hpin, (8 + kKHistBins) * sizeof(unsigned long long), hipHostMallocDefault));
   c.ready = true;
   return MPWOS_OK;
 }
@@ -899,16 +903,19 @@ extern "C" mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_
   const int n = d.n;
   hipStream_t s = o.stream ? (hipStream_t)o.stream : g_ctx.stream;
 
-  // host view of the queries for validation
+  // host view of the queries for validation; device queries on an analytic
+  // manifold are checked on the device instead, beside the walks, and the
+  // solve returns EOFFMANIFOLD before writing any output
+  const bool dev_check = o.device_io && device_query_check(d.kind);
   std::vector<double> hq;
   const double* qhost = queries;
-  if (o.device_io) {
+  if (o.device_io && !dev_check) {
     hq.resize((size_t)n_queries * n);
     HIP_TRY(hipMemcpyAsync(hq.data(), queries, hq.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     qhost = hq.data();
   }
-  if (d.kind != MPWOS_POINT_CLOUD) {
+  if (d.kind != MPWOS_POINT_CLOUD && !dev_check) {
     for (int64_t q = 0; q < n_queries; ++q)
       if (!query_on_manifold(d, qhost + q * n))
         return fail(MPWOS_EOFFMANIFOLD, "query " + std::to_string(q) + " is not on the manifold");
@@ -946,6 +953,7 @@ extern "C" mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_
   }
   unsigned long long* dstat = (unsigned long long*)g_ctx.stats.p;
   HIP_TRY(launch_zero_u64(dstat, 8, s));
+  if (dev_check) HIP_TRY(launch_query_check(d, dq, n_queries, dstat + 7, s));
   // the K histogram, for the statistics only
   unsigned long long* dhist = nullptr;
   if (stats) {
@@ -989,13 +997,22 @@ extern "C" mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_
     reduce_ms += ms2;
   }
   const hipMemcpyKind dk = o.device_io ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  HIP_TRY(hipMemcpyAsync(u_out, du, (size_t)n_queries * sizeof(double), dk, s));
-  if (stderr_out) HIP_TRY(hipMemcpyAsync(stderr_out, dse, (size_t)n_queries * sizeof(double), dk, s));
-  unsigned long long hs[8];
-  HIP_TRY(hipMemcpyAsync(hs, dstat, sizeof(hs), hipMemcpyDeviceToHost, s));
-  std::vector<unsigned long long> hh(dhist ? kKHistBins : 0);
-  if (dhist) HIP_TRY(hipMemcpyAsync(hh.data(), dhist, hh.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  if (!dev_check) {
+    HIP_TRY(hipMemcpyAsync(u_out, du, (size_t)n_queries * sizeof(double), dk, s));
+    if (stderr_out) HIP_TRY(hipMemcpyAsync(stderr_out, dse, (size_t)n_queries * sizeof(double), dk, s));
+  }
+  unsigned long long* hs = g_ctx.hpin;
+  unsigned long long* hh = g_ctx.hpin + 8;
+  HIP_TRY(hipMemcpyAsync(hs, dstat, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  if (dhist) HIP_TRY(hipMemcpyAsync(hh, dhist, kKHistBins * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (dev_check) {
+    if (hs[7])
+      return fail(MPWOS_EOFFMANIFOLD, "query " + std::to_string(n_queries - (int64_t)hs[7]) + " is not on the manifold");
+    HIP_TRY(hipMemcpyAsync(u_out, du, (size_t)n_queries * sizeof(double), dk, s));
+    if (stderr_out) HIP_TRY(hipMemcpyAsync(stderr_out, dse, (size_t)n_queries * sizeof(double), dk, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   const int64_t ksum = (int64_t)hs[0];
   const int32_t kmax = (int32_t)(uint32_t)hs[1];
   const int64_t ntr = (int64_t)hs[2];
@@ -1006,7 +1023,7 @@ extern "C" mpwos_status mpwos_solve(const mpwos_manifold* manifold, const mpwos_
     stats->k_mean = (double)ksum / ((double)n_queries * (double)n_walks);
     stats->kernel_ms = kernel_ms;
     stats->reduce_ms = reduce_ms;
-    khist_quantiles(hh.data(), stats->k_p50, stats->k_p99);
+    khist_quantiles(hh, stats->k_p50, stats->k_p99);
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return ntr ? MPWOS_WTRUNC : MPWOS_OK;

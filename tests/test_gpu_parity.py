@@ -384,6 +384,53 @@ def test_invalid_arguments():
         mpwos.Manifold(dict(manifold="sphere", n=1, p=[1.0]))
 
 
+def test_device_queries_are_checked_on_the_device():
+    # device-resident queries on the analytic manifolds: the on-manifold rule
+    # runs on the device beside the walks; a good set gives the host-query
+    # solve's bits, a set with failing queries returns EOFFMANIFOLD naming the
+    # first and leaves the outputs unwritten
+    import torch
+    cut = dict(inputs.cut_torus_problem(n_v=2), eps=1e-3)
+    cases = {
+        "sphere": (inputs.sphere_problem(), inputs.sphere_uniform(40, 3, seed=4)),
+        "cap": (inputs.cap_problem(), inputs.cap_uniform(40, 3, 0.0, seed=4)),
+        "torus": (inputs.torus_problem(), inputs.torus_area_uniform(40, seed=4)),
+        "cut_torus": (cut, inputs.cut_torus_points(40, seed=4, s_margin=0.1)),
+    }
+    for name, (prob, Q) in cases.items():
+        announce(f"device query check {name}")
+        m = mpwos.Manifold(prob)
+        ref = mpwos.solve(prob, Q, 16, 3, manifold=m, precision="fp32")
+
+        def dev(Qd):
+            dq = torch.from_numpy(np.ascontiguousarray(Qd)).to("cuda")
+            u = torch.full((len(Qd),), float("nan"), dtype=torch.float64, device="cuda")
+            se = torch.full((len(Qd),), float("nan"), dtype=torch.float64, device="cuda")
+            st = mpwos.solve_device(m, prob, dq.data_ptr(), len(Qd), 16, 3, u.data_ptr(), se.data_ptr(),
+                                    torch.cuda.current_stream().cuda_stream, precision="fp32")
+            torch.cuda.synchronize()
+            return st, u.cpu().numpy(), se.cpu().numpy()
+
+        st, u, se = dev(Q)
+        assert np.array_equal(u, ref["u"]) and np.array_equal(se, ref["stderr"]), name
+        assert st["walk_steps"] == ref["stats"]["walk_steps"]
+        bad = Q.copy()
+        bad[[7, 29]] *= 1.001
+        if name == "cap":
+            bad[7] = Q[7] * np.array([1.0, 1.0, -1.0])
+        if name == "cut_torus":
+            # the mirror image across the cutting plane: on the torus, off Omega
+            c, s_ = math.cos(0.35 * math.pi), math.sin(0.35 * math.pi)
+            y = Q[7]
+            t = y[0] * s_ - y[1] * c
+            bad[7] = y + 2.0 * t * np.array([-s_, c, 0.0])
+        with pytest.raises(mpwos.MpwosError) as e:
+            dev(bad)
+        assert e.value.status == mpwos.EOFFMANIFOLD and "query 7 " in str(e.value), (name, str(e.value))
+        _, u, se = dev(Q)
+        assert np.array_equal(u, ref["u"])
+
+
 def test_seed_changes_the_stream_and_is_reproducible():
     prob, Q, nw = CASES["sphere"]
     a = mpwos.solve(prob, Q, nw, 1, walk_outputs=True)
