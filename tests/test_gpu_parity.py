@@ -429,6 +429,25 @@ def test_device_queries_are_checked_on_the_device():
         assert e.value.status == mpwos.EOFFMANIFOLD and "query 7 " in str(e.value), (name, str(e.value))
         _, u, se = dev(Q)
         assert np.array_equal(u, ref["u"])
+        if name in ("sphere", "torus"):
+            # the tolerance 1e-9 (1 + |q|) along the normal: half of it passes
+            # and twice it fails, on the device and on the host alike
+            if name == "sphere":
+                nrm = Q / np.linalg.norm(Q, axis=1, keepdims=True)
+            else:
+                rho = np.hypot(Q[:, 0], Q[:, 1])
+                core = np.stack([Q[:, 0] / rho, Q[:, 1] / rho, np.zeros(len(Q))], axis=1) * prob["p"][0]
+                nrm = (Q - core) / np.linalg.norm(Q - core, axis=1, keepdims=True)
+            tol = 1e-9 * (1.0 + np.linalg.norm(Q, axis=1, keepdims=True))
+            dev(Q + 0.5 * tol * nrm)
+            mpwos.solve(prob, Q + 0.5 * tol * nrm, 16, 3, manifold=m, precision="fp32")
+            for side in (Q + 2.0 * tol * nrm, Q - 2.0 * tol * nrm):
+                with pytest.raises(mpwos.MpwosError) as e:
+                    dev(side)
+                assert "query 0 " in str(e.value)
+                with pytest.raises(mpwos.MpwosError) as e:
+                    mpwos.solve(prob, side, 16, 3, manifold=m, precision="fp32")
+                assert "query 0 " in str(e.value)
 
 
 def test_seed_changes_the_stream_and_is_reproducible():
