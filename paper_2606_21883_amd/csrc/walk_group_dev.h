@@ -379,35 +379,8 @@ __device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB
   const T rT = (T)r;
   const T R = (T)a.p[0];
   uint32_t dummy = 0;
-  // sphere sample and projection: Theta = Y + r g/|g|, Y' = cp(Theta) (the
-  // sphere: R Theta/|Theta|; the dumbbell: Newton in the profile parameter)
-  T Yn[4 * MB];
-  {
-    T g[4 * MB];
-    group_normals<T, L, MB>(a, rs, st.k, 0, gl, g, false, dummy);
-    T gg = (T)0;
-#pragma unroll
-    for (int i = 0; i < 4 * MB; ++i) gg += g[i] * g[i];
-    gg = group_sum<L>(gg);
-    const T ig = rsqrt_(gg);
-    T tt = (T)0;
-#pragma unroll
-    for (int i = 0; i < 4 * MB; ++i) {
-      Yn[i] = st.Y[i] + rT * (g[i] * ig);
-      tt += Yn[i] * Yn[i];
-    }
-    if constexpr (KIND == kDumbbell) {
-      db_project<T, L, MB>(a, Yn, gl);
-    } else if constexpr (KIND == kProduct) {
-      pr_project<T, L, MB>(a, Yn, gl);
-    } else {
-      tt = group_sum<L>(tt);
-      const T f = R * rsqrt_(tt);
-#pragma unroll
-      for (int i = 0; i < 4 * MB; ++i) Yn[i] *= f;
-    }
-  }
-  // Green samples
+  // Green samples first: they read Y only, so the next point Y' need not be
+  // live beside their vectors (registers)
   T Fsum = (T)0;
   for (int l = 1; l <= a.n_v; ++l) {
     T g[4 * MB];
@@ -450,6 +423,34 @@ __device__ __forceinline__ bool group_step(const WalkArgs& a, GroupWalk<T, L, MB
       v = (T)0;
     }
     Fsum += v;
+  }
+  // sphere sample and projection: Theta = Y + r g/|g|, Y' = cp(Theta) (the
+  // sphere: R Theta/|Theta|; the dumbbell: Newton in the profile parameter)
+  T Yn[4 * MB];
+  {
+    T g[4 * MB];
+    group_normals<T, L, MB>(a, rs, st.k, 0, gl, g, false, dummy);
+    T gg = (T)0;
+#pragma unroll
+    for (int i = 0; i < 4 * MB; ++i) gg += g[i] * g[i];
+    gg = group_sum<L>(gg);
+    const T ig = rsqrt_(gg);
+    T tt = (T)0;
+#pragma unroll
+    for (int i = 0; i < 4 * MB; ++i) {
+      Yn[i] = st.Y[i] + rT * (g[i] * ig);
+      tt += Yn[i] * Yn[i];
+    }
+    if constexpr (KIND == kDumbbell) {
+      db_project<T, L, MB>(a, Yn, gl);
+    } else if constexpr (KIND == kProduct) {
+      pr_project<T, L, MB>(a, Yn, gl);
+    } else {
+      tt = group_sum<L>(tt);
+      const T f = R * rsqrt_(tt);
+#pragma unroll
+      for (int i = 0; i < 4 * MB; ++i) Yn[i] *= f;
+    }
   }
   const double F = (double)Fsum * a.inv_nv;
   if constexpr (sizeof(T) == 8) kahan_add(st.S, st.C, (st.W * a.om0) * F);
